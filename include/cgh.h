@@ -1,0 +1,165 @@
+/*
+ * cgh.h -- C ABI of libcgh, MI355X (gfx950) progressive saliency-guided
+ * hologram generation.
+ *
+ * Method: "Progressive hologram generation based on object saliency"
+ * (arXiv 2211.09938).  An object is decomposed by a multi-level Haar DWT
+ * (Sec. 2, Eq. 2, algorithm step 1); the coarsest approximation is rendered
+ * for every block and the detail coefficients of level l only in blocks whose
+ * block-maximum saliency exceeds that level's threshold (steps 2-5, Sec. 3
+ * thresholds); every coefficient is scaled onto the fringe of its basis block
+ * and superposed on the hologram plane (Eq. 3).  The fringe is the point-source
+ * object wave of Eq. 1 in Fresnel form,
+ *     kernel(dy, dx) = exp(i*pi*pitch^2*(dx^2 + dy^2) / (lambda*z)),
+ * object and hologram sharing one pixel grid of pitch `pitch`.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers unless marked [host].  Images are
+ *    row-major, index [y][x], y = row (ny rows, nx columns).
+ *  - Complex arrays are interleaved (re, im) float pairs, i.e. the memory
+ *    layout of C99 float complex / torch.complex64; `float* h` holds 2*ny*nx
+ *    floats.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call only enqueues work on `stream`; none synchronises it.
+ *  - The caller owns every buffer.  The library never allocates, frees or
+ *    retains caller memory; scratch memory comes from the caller's
+ *    `workspace`, sized by cgh_workspace_size().
+ *  - Every argument is validated on the host before anything is enqueued.
+ *    On an error return nothing has been enqueued and no output is touched.
+ *    A failed launch returns CGH_ERROR_HIP; cgh_last_hip_error() gives the
+ *    hipError_t of the calling thread's last such failure.
+ *  - Limits: 1 <= levels <= 3 (the paper uses three levels: 8x8, 4x4, 2x2
+ *    and 1x1 block fringes); ny and nx divisible by 2^levels and at most
+ *    CGH_MAX_SIDE; 1 <= n_layers <= 256.  ny == 0 or nx == 0 is an empty
+ *    problem: success, nothing enqueued.
+ */
+#ifndef CGH_H
+#define CGH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CGH_MAX_SIDE 16384
+#define CGH_MAX_LAYERS 256
+#define CGH_MAX_LEVELS 3
+
+typedef enum {
+    CGH_SUCCESS = 0,
+    CGH_ERROR_INVALID_VALUE = 1, /* NULL required pointer, non-finite/non-positive optics, bad flag */
+    CGH_ERROR_SHAPE = 2,         /* side not divisible by 2^levels, too large, levels out of range */
+    CGH_ERROR_UNSUPPORTED = 3,   /* a valid request this build does not implement */
+    CGH_ERROR_OUT_OF_MEMORY = 4, /* plan creation could not allocate */
+    CGH_ERROR_WORKSPACE = 5,     /* workspace NULL or smaller than cgh_workspace_size() */
+    CGH_ERROR_HIP = 6            /* a HIP runtime call or launch failed */
+} cgh_status;
+
+/* Arithmetic of the two dense contractions (the coefficient stage and the
+ * fringe look-up tables are always built from FP64 phases). */
+typedef enum {
+    CGH_FP32 = 0,       /* FP32 operands, FP32 MFMA, FP32 accumulate            */
+    CGH_BF16_SPLIT = 1, /* each operand v = hi + lo, hi = bf16(v), lo = bf16(v-hi);
+                           products hi*hi + hi*lo + lo*hi on bf16 MFMA, FP32 acc  */
+    CGH_FP16_SPLIT = 2  /* same with fp16 halves                                */
+} cgh_precision;
+
+enum {
+    CGH_FLAG_ACCUMULATE = 1u,   /* hologram += result instead of hologram = result */
+    CGH_FLAG_EQ1_PREFACTOR = 2u /* multiply layer d by exp(i*2*pi*z_d/lambda)/z_d,
+                                   the constant of Eq. 1's paraxial expansion     */
+};
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char* cgh_status_string(int status);
+
+/* hipError_t of this thread's last CGH_ERROR_HIP return (0 if none). */
+int cgh_last_hip_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int cgh_version(void);
+
+/*
+ * Multi-level 2D averaging Haar analysis (Sec. 2, Eq. 2; algorithm step 1).
+ * Per axis lo = (a+b)/2, hi = (a-b)/2, x first then y, recursing on LL.
+ * Output in Mallat layout: inside the top-left (2h x 2w) square of each level,
+ * [0:h,0:w] LL, [0:h,w:2w] V (lo_y hi_x), [h:2h,0:w] H (hi_y lo_x),
+ * [h:2h,w:2w] D (hi_y hi_x).  The level-`levels` LL is the 2^levels-block mean.
+ * x: ny*nx floats (input), coeffs: ny*nx floats (output, must not alias x).
+ * Bit-exact with the FP64 definition whenever the input values are dyadic.
+ */
+int cgh_haar_dwt(const float* x, int ny, int nx, int levels, float* coeffs, void* stream);
+
+/* Inverse of cgh_haar_dwt: a = lo + hi, b = lo - hi, y first then x per level. */
+int cgh_haar_idwt(const float* coeffs, int ny, int nx, int levels, float* x, void* stream);
+
+/*
+ * Bytes of device workspace that cgh_progressive_hologram,
+ * cgh_hologram_backward and cgh_fresnel_backpropagate need for this problem.
+ * bytes: [host] output.
+ */
+int cgh_workspace_size(int ny, int nx, int n_layers, int levels, int precision, size_t* bytes);
+
+/*
+ * Progressive saliency-guided hologram (Sec. 2, Eqs. 1-3, steps 1-5):
+ *   A_d    = object * [layer_index == d]                     (3D extension, Sec. 2)
+ *   C_d    = W(A_d) with level-l details zeroed where maxpool_{2^l}(saliency) <= t_l
+ *   H      = sum_d P_d * sum_coefficients C_d * (fringe of the coefficient's basis block)
+ * which equals the Fresnel sum of the masked reconstruction S(C_d) of every layer.
+ *
+ *  object       ny*nx float amplitudes.
+ *  layer_index  ny*nx uint8 in [0, n_layers), or NULL: every pixel in layer 0
+ *               (then n_layers must be 1).  Values >= n_layers belong to no layer.
+ *  z            [host] n_layers distances in metres, finite and > 0.
+ *  saliency     ny*nx floats, or NULL: every block salient.
+ *  thresholds   [host] `levels` floats in [0,1], t_1 (finest details) first, or
+ *               NULL: (0.9, 0.7, 0.5) for 3 levels (Sec. 3), 0.5 per level otherwise.
+ *               A level-l detail is kept iff its block maximum is strictly greater.
+ *  lambda, pitch  metres, finite and > 0.
+ *  precision    cgh_precision.   flags: CGH_FLAG_*.
+ *  workspace    device scratch of at least cgh_workspace_size() bytes.
+ *  hologram     2*ny*nx floats (complex64 interleaved), overwritten (or
+ *               accumulated into with CGH_FLAG_ACCUMULATE).  Must not alias inputs.
+ */
+int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, int n_layers,
+                             const double* z, const float* saliency, const float* thresholds,
+                             double lambda, double pitch, int ny, int nx, int levels,
+                             int precision, unsigned flags, void* workspace,
+                             size_t workspace_bytes, float* hologram, void* stream);
+
+/*
+ * Adjoint of cgh_progressive_hologram with respect to the object amplitudes.
+ * grad_hologram: 2*ny*nx floats, G = dL/dRe(H) + i dL/dIm(H) (the cotangent
+ * torch hands to a complex output).  Writes grad_object (ny*nx floats):
+ *   dL/dA[q,p] = [ S M W ( Re( P_d * sum_{y,x} conj(G[y,x]) kernel_d(y-q, x-p) ) ) ][q,p],
+ *   d = layer_index[q,p]   (zero for pixels in no layer),
+ * using that the masked averaging-Haar reconstruction S M W is self-adjoint.
+ * Other arguments as for cgh_progressive_hologram (CGH_FLAG_ACCUMULATE is
+ * rejected).
+ */
+int cgh_hologram_backward(const float* grad_hologram, const uint8_t* layer_index, int n_layers,
+                          const double* z, const float* saliency, const float* thresholds,
+                          double lambda, double pitch, int ny, int nx, int levels, int precision,
+                          unsigned flags, void* workspace, size_t workspace_bytes,
+                          float* grad_object, void* stream);
+
+/*
+ * Fresnel back-propagation of a hologram to the object plane at distance z
+ * (numerical reconstruction, Sec. 2 last paragraph, here with the same Fresnel
+ * kernel as the forward pass):
+ *   adjoint == 0:  out[q,p] = 1/(ny*nx) * sum_{y,x} conj(kernel(y-q, x-p)) * in[y,x]
+ *   adjoint != 0:  out[y,x] = 1/(ny*nx) * sum_{q,p} kernel(y-q, x-p) * in[q,p]
+ * field_in, field_out: 2*ny*nx floats complex, must not alias.  The workspace
+ * is sized by cgh_workspace_size(ny, nx, 1, 1, precision, ...).
+ */
+int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lambda, double pitch,
+                              double z, int precision, int adjoint, void* workspace,
+                              size_t workspace_bytes, float* field_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGH_H */

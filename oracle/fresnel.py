@@ -22,11 +22,17 @@ from multiprocessing import get_context
 import numpy as np
 
 
-def kernel_2d(dy, dx, lam, pitch, z):
-    """exp(i pi pitch^2 (dx^2 + dy^2) / (lambda z)) for integer pixel offsets."""
+def phase_2d(dy, dx, lam, pitch, z):
+    """pi pitch^2 (dx^2 + dy^2) / (lambda z) for integer pixel offsets (radians)."""
     dy = np.asarray(dy, dtype=np.float64)
     dx = np.asarray(dx, dtype=np.float64)
-    return np.exp(1j * np.pi * pitch * pitch * (dx * dx + dy * dy) / (lam * z))
+    return np.pi * pitch * pitch * (dx * dx + dy * dy) / (lam * z)
+
+
+def kernel_2d(dy, dx, lam, pitch, z):
+    """exp(i pi pitch^2 (dx^2 + dy^2) / (lambda z)) for integer pixel offsets."""
+    th = phase_2d(dy, dx, lam, pitch, z)
+    return np.cos(th) + 1j * np.sin(th)
 
 
 def prefactor(lam, z):
@@ -37,15 +43,34 @@ def prefactor(lam, z):
 def _chunk_sum(args):
     ys, xs, qs, ps, amps, lam, pitch, z = args
     out = np.zeros(ys.shape[0], dtype=np.complex128)
-    step = max(1, 2_000_000 // max(1, qs.shape[0]))
+    # work in blocks of ~256k terms (pixels x points) to stay cache- and allocator-friendly
+    pstep = min(qs.shape[0], 131072)
+    step = max(1, 131072 // pstep)
+    a_re = np.ascontiguousarray(np.real(amps))
+    a_im = np.ascontiguousarray(np.imag(amps)) if np.iscomplexobj(amps) else None
     for s in range(0, ys.shape[0], step):
-        dy = ys[s:s + step, None] - qs[None, :]
-        dx = xs[s:s + step, None] - ps[None, :]
-        out[s:s + step] = (kernel_2d(dy, dx, lam, pitch, z) * amps[None, :]).sum(axis=1)
+        for t in range(0, qs.shape[0], pstep):
+            th = phase_2d(ys[s:s + step, None] - qs[None, t:t + pstep],
+                          xs[s:s + step, None] - ps[None, t:t + pstep], lam, pitch, z)
+            # sum_i a_i exp(i th_i) with exp(i th) = cos th + i sin th
+            c, sn = np.cos(th), np.sin(th)
+            ar = a_re[t:t + pstep]
+            if a_im is None:
+                out[s:s + step] += c @ ar + 1j * (sn @ ar)
+            else:
+                ai = a_im[t:t + pstep]
+                out[s:s + step] += (c @ ar - sn @ ai) + 1j * (c @ ai + sn @ ar)
     return out
 
 
 def worker_count():
+    """Processes for the direct sum: the host's CPU share, at most 16.
+
+    ``ORACLE_WORKERS`` overrides it (GPU test runs keep the pool small).
+    """
+    env = os.environ.get("ORACLE_WORKERS")
+    if env:
+        return max(1, int(env))
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:  # pragma: no cover

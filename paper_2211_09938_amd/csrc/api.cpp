@@ -1,0 +1,316 @@
+// C ABI of libcgh: argument validation, workspace layout and stream-ordered
+// dispatch of the kernels.  Every check happens on the host before the first
+// HIP call, so an invalid request never enqueues work or touches an output.
+#include <cmath>
+#include <cstring>
+#include <exception>
+
+#include "../../include/cgh.h"
+#include "common.h"
+#include "gemm.h"
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int hip_status(hipError_t e) {
+    if (e == hipSuccess) return CGH_SUCCESS;
+    g_last_hip_error = (int)e;
+    return CGH_ERROR_HIP;
+}
+
+int check_shape(int ny, int nx, int levels) {
+    if (levels < 1) return CGH_ERROR_SHAPE;
+    if (levels > CGH_MAX_LEVELS) return CGH_ERROR_UNSUPPORTED;
+    if (ny < 0 || nx < 0 || ny > CGH_MAX_SIDE || nx > CGH_MAX_SIDE) return CGH_ERROR_SHAPE;
+    const int b = 1 << levels;
+    if (ny % b || nx % b) return CGH_ERROR_SHAPE;
+    return CGH_SUCCESS;
+}
+
+int check_precision(int precision) {
+    if (precision < CGH_FP32 || precision > CGH_FP16_SPLIT) return CGH_ERROR_INVALID_VALUE;
+    if (precision != CGH_FP32) return CGH_ERROR_UNSUPPORTED;
+    return CGH_SUCCESS;
+}
+
+int choose_split(int ny, int nx, int levels, int layers) {
+    const int tiles = ((ny + cgh::kTileM - 1) / cgh::kTileM) * ((nx + cgh::kTileN - 1) / cgh::kTileN);
+    const int target = 512;  // two resident workgroups on each of 256 CUs
+    int split = (target + tiles - 1) / tiles;
+    const int kt = cgh::second_stage_ktiles(ny, levels, layers);
+    if (split > kt / 4) split = kt / 4;
+    if (split > 16) split = 16;
+    if (split < 1) split = 1;
+    return split;
+}
+
+cgh::Layout make_layout(int ny, int nx, int layers, int levels) {
+    cgh::Layout lo{};
+    const size_t plane = (size_t)ny * nx;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
+    lo.coef = take((size_t)layers * plane * 4);
+    lo.coef_lo = lo.coef + (size_t)layers * plane * 2;
+    const size_t nlut_x = (size_t)layers * levels * 4 * cgh::lut_len(nx);
+    const size_t nlut_y = (size_t)layers * levels * 4 * cgh::lut_len(ny);
+    lo.lut_x = take(nlut_x * 4);
+    lo.lut_x_lo = lo.lut_x + nlut_x * 2;
+    lo.lut_y = take(nlut_y * 4);
+    lo.lut_y_lo = lo.lut_y + nlut_y * 2;
+    lo.lut0 = take((size_t)(2 * cgh::lut_len(nx) + 2 * cgh::lut_len(ny)) * 4);
+    lo.t_layer = 0;
+    lo.flags_layer = 0;
+    for (int l = 1; l <= levels; ++l) {
+        lo.t_layer += (size_t)cgh::band_side(ny, l) * nx;
+        lo.flags_layer += (size_t)cgh::band_side(ny, l) + cgh::band_side(nx, l);
+    }
+    // the back-propagation reuses T as its ny x nx intermediate
+    size_t t_elems = (size_t)layers * lo.t_layer;
+    if (t_elems < plane) t_elems = plane;
+    lo.t = take(t_elems * 8);
+    lo.t_lo = lo.t;
+    lo.flags = take((size_t)layers * lo.flags_layer);
+    lo.n_ktiles = cgh::second_stage_ktiles(ny, levels, layers);
+    lo.ktiles = take((size_t)(1 + lo.n_ktiles) * 4);
+    lo.split_k = choose_split(ny, nx, levels, layers);
+    lo.partial = take(lo.split_k > 1 ? (size_t)lo.split_k * plane * 8 : 0);
+    lo.total = off;
+    return lo;
+}
+
+struct Optics {
+    double c[CGH_MAX_LAYERS];
+    double pre_re[CGH_MAX_LAYERS], pre_im[CGH_MAX_LAYERS];
+    double one_re[CGH_MAX_LAYERS], one_im[CGH_MAX_LAYERS];
+};
+
+void make_optics(Optics& o, int layers, const double* z, double lambda, double pitch, bool eq1) {
+    for (int d = 0; d < layers; ++d) {
+        o.c[d] = pitch * pitch / (2.0 * lambda * z[d]);
+        o.one_re[d] = 1.0;
+        o.one_im[d] = 0.0;
+        if (eq1) {
+            // exp(i k z) / z with k z = 2 pi z / lambda, reduced to a fraction of a cycle
+            const double cyc = z[d] / lambda;
+            const double fr = cyc - std::floor(cyc);
+            o.pre_re[d] = std::cos(2.0 * M_PI * fr) / z[d];
+            o.pre_im[d] = std::sin(2.0 * M_PI * fr) / z[d];
+        } else {
+            o.pre_re[d] = 1.0;
+            o.pre_im[d] = 0.0;
+        }
+    }
+}
+
+int check_common(int n_layers, const uint8_t* layer_index, const double* z, const float* thresholds,
+                 double lambda, double pitch, int ny, int nx, int levels, int precision,
+                 unsigned flags, float* thr_out) {
+    int st = check_shape(ny, nx, levels);
+    if (st) return st;
+    if (n_layers < 1 || n_layers > CGH_MAX_LAYERS) return CGH_ERROR_INVALID_VALUE;
+    if (!layer_index && n_layers != 1) return CGH_ERROR_INVALID_VALUE;
+    if (!z) return CGH_ERROR_INVALID_VALUE;
+    for (int d = 0; d < n_layers; ++d)
+        if (!finite_pos(z[d])) return CGH_ERROR_INVALID_VALUE;
+    if (!finite_pos(lambda) || !finite_pos(pitch)) return CGH_ERROR_INVALID_VALUE;
+    if (flags & ~(unsigned)(CGH_FLAG_ACCUMULATE | CGH_FLAG_EQ1_PREFACTOR)) return CGH_ERROR_INVALID_VALUE;
+    for (int l = 0; l < CGH_MAX_LEVELS; ++l) thr_out[l] = 0.5f;
+    if (thresholds) {
+        for (int l = 0; l < levels; ++l) {
+            const float t = thresholds[l];
+            if (!(t >= 0.0f && t <= 1.0f)) return CGH_ERROR_INVALID_VALUE;
+            thr_out[l] = t;
+        }
+    } else if (levels == 3) {
+        thr_out[0] = 0.9f;
+        thr_out[1] = 0.7f;
+        thr_out[2] = 0.5f;
+    }
+    return check_precision(precision);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cgh_status_string(int status) {
+    switch (status) {
+        case CGH_SUCCESS: return "CGH_SUCCESS";
+        case CGH_ERROR_INVALID_VALUE: return "CGH_ERROR_INVALID_VALUE: invalid argument value";
+        case CGH_ERROR_SHAPE: return "CGH_ERROR_SHAPE: sides must be divisible by 2^levels and within limits";
+        case CGH_ERROR_UNSUPPORTED: return "CGH_ERROR_UNSUPPORTED: valid request not implemented by this build";
+        case CGH_ERROR_OUT_OF_MEMORY: return "CGH_ERROR_OUT_OF_MEMORY";
+        case CGH_ERROR_WORKSPACE: return "CGH_ERROR_WORKSPACE: workspace missing or too small";
+        case CGH_ERROR_HIP: return "CGH_ERROR_HIP: HIP runtime or launch failure";
+        default: return "CGH_ERROR_UNKNOWN";
+    }
+}
+
+int cgh_last_hip_error(void) { return g_last_hip_error; }
+
+int cgh_version(void) { return 100; }
+
+int cgh_haar_dwt(const float* x, int ny, int nx, int levels, float* coeffs, void* stream) {
+    try {
+        int st = check_shape(ny, nx, levels);
+        if (st) return st;
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        if (!x || !coeffs || (const void*)x == (const void*)coeffs) return CGH_ERROR_INVALID_VALUE;
+        const float thr[3] = {0.f, 0.f, 0.f};
+        return hip_status(cgh::launch_dwt_mask(x, nullptr, nullptr, ny, nx, 1, levels, thr,
+                                               cgh::P_FP32, coeffs, nullptr, nullptr, 0,
+                                               (hipStream_t)stream));
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
+int cgh_haar_idwt(const float* coeffs, int ny, int nx, int levels, float* x, void* stream) {
+    try {
+        int st = check_shape(ny, nx, levels);
+        if (st) return st;
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        if (!x || !coeffs || (const void*)x == (const void*)coeffs) return CGH_ERROR_INVALID_VALUE;
+        return hip_status(cgh::launch_idwt(coeffs, ny, nx, levels, x, (hipStream_t)stream));
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
+int cgh_workspace_size(int ny, int nx, int n_layers, int levels, int precision, size_t* bytes) {
+    if (!bytes) return CGH_ERROR_INVALID_VALUE;
+    int st = check_shape(ny, nx, levels);
+    if (st) return st;
+    if (n_layers < 1 || n_layers > CGH_MAX_LAYERS) return CGH_ERROR_INVALID_VALUE;
+    if (precision < CGH_FP32 || precision > CGH_FP16_SPLIT) return CGH_ERROR_INVALID_VALUE;
+    *bytes = (ny == 0 || nx == 0) ? 0 : make_layout(ny, nx, n_layers, levels).total;
+    return CGH_SUCCESS;
+}
+
+int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, int n_layers,
+                             const double* z, const float* saliency, const float* thresholds,
+                             double lambda, double pitch, int ny, int nx, int levels,
+                             int precision, unsigned flags, void* workspace,
+                             size_t workspace_bytes, float* hologram, void* stream) {
+    try {
+        float thr[CGH_MAX_LEVELS];
+        int st = check_common(n_layers, layer_index, z, thresholds, lambda, pitch, ny, nx, levels,
+                              precision, flags, thr);
+        if (st) return st;
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        if (!object || !hologram) return CGH_ERROR_INVALID_VALUE;
+        const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
+        if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+
+        hipStream_t s = (hipStream_t)stream;
+        char* ws = static_cast<char*>(workspace);
+        Optics op;
+        make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
+        uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
+
+        hipError_t e = cgh::launch_fill_u8(fl, (size_t)n_layers * lo.flags_layer, s);
+        if (e == hipSuccess)
+            e = cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels, thr,
+                                     precision, ws + lo.coef, ws + lo.coef_lo, fl, lo.flags_layer, s);
+        if (e == hipSuccess)
+            e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im, precision,
+                                 ws + lo.lut_x, ws + lo.lut_x_lo, s);
+        if (e == hipSuccess)
+            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im, precision,
+                                 ws + lo.lut_y, ws + lo.lut_y_lo, s);
+        if (e == hipSuccess) {
+            cgh::GemmShape sh{ny, nx, n_layers, levels, lo.split_k, lo.t_layer, lo.flags_layer};
+            e = cgh::launch_forward_f32(
+                sh, reinterpret_cast<const float*>(ws + lo.coef),
+                reinterpret_cast<const float*>(ws + lo.lut_x),
+                reinterpret_cast<const float*>(ws + lo.lut_y), reinterpret_cast<float2*>(ws + lo.t),
+                fl, reinterpret_cast<int*>(ws + lo.ktiles), reinterpret_cast<float2*>(ws + lo.partial),
+                reinterpret_cast<float2*>(hologram), (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0, 1, s);
+        }
+        return hip_status(e);
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
+int cgh_hologram_backward(const float* grad_hologram, const uint8_t* layer_index, int n_layers,
+                          const double* z, const float* saliency, const float* thresholds,
+                          double lambda, double pitch, int ny, int nx, int levels, int precision,
+                          unsigned flags, void* workspace, size_t workspace_bytes,
+                          float* grad_object, void* stream) {
+    try {
+        float thr[CGH_MAX_LEVELS];
+        int st = check_common(n_layers, layer_index, z, thresholds, lambda, pitch, ny, nx, levels,
+                              precision, flags, thr);
+        if (st) return st;
+        if (flags & CGH_FLAG_ACCUMULATE) return CGH_ERROR_INVALID_VALUE;
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        if (!grad_hologram || !grad_object) return CGH_ERROR_INVALID_VALUE;
+        const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
+        if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+
+        hipStream_t s = (hipStream_t)stream;
+        char* ws = static_cast<char*>(workspace);
+        Optics op;
+        make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
+        hipError_t e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
+                                        cgh::P_FP32, ws + lo.lut_x, nullptr, s);
+        if (e == hipSuccess)
+            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im, cgh::P_FP32,
+                                 ws + lo.lut_y, nullptr, s);
+        if (e == hipSuccess) {
+            cgh::GemmShape sh{ny, nx, n_layers, levels, 1, lo.t_layer, lo.flags_layer};
+            e = cgh::launch_backward_f32(sh, reinterpret_cast<const float2*>(grad_hologram),
+                                         reinterpret_cast<const float*>(ws + lo.lut_x),
+                                         reinterpret_cast<const float*>(ws + lo.lut_y),
+                                         reinterpret_cast<float2*>(ws + lo.t),
+                                         reinterpret_cast<float*>(ws + lo.coef), s);
+        }
+        if (e == hipSuccess)
+            e = cgh::launch_grad_synthesis(reinterpret_cast<const float*>(ws + lo.coef), layer_index,
+                                           saliency, ny, nx, n_layers, levels, thr, grad_object, s);
+        return hip_status(e);
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
+int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lambda, double pitch,
+                              double z, int precision, int adjoint, void* workspace,
+                              size_t workspace_bytes, float* field_out, void* stream) {
+    try {
+        int st = check_shape(ny, nx, 1);
+        if (st) return st;
+        if (!finite_pos(lambda) || !finite_pos(pitch) || !finite_pos(z)) return CGH_ERROR_INVALID_VALUE;
+        if ((st = check_precision(precision))) return st;
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        if (!field_in || !field_out || field_in == field_out) return CGH_ERROR_INVALID_VALUE;
+        const cgh::Layout lo = make_layout(ny, nx, 1, 1);
+        if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        hipStream_t s = (hipStream_t)stream;
+        char* ws = static_cast<char*>(workspace);
+        const double c = pitch * pitch / (2.0 * lambda * z), one = 1.0, zero = 0.0;
+        float* lut0_x = reinterpret_cast<float*>(ws + lo.lut0);
+        float* lut0_y = lut0_x + 2 * cgh::lut_len(nx);
+        hipError_t e = cgh::launch_luts(nx, 1, 1, 0, &c, &one, &zero, cgh::P_FP32, lut0_x, nullptr, s);
+        if (e == hipSuccess)
+            e = cgh::launch_luts(ny, 1, 1, 0, &c, &one, &zero, cgh::P_FP32, lut0_y, nullptr, s);
+        if (e == hipSuccess)
+            e = cgh::launch_backprop_f32(ny, nx, lut0_x, lut0_y,
+                                         reinterpret_cast<const float2*>(field_in),
+                                         reinterpret_cast<float2*>(ws + lo.t),
+                                         reinterpret_cast<float2*>(field_out), adjoint ? 1 : 0,
+                                         (float)(1.0 / ((double)ny * (double)nx)), s);
+        return hip_status(e);
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Internal declarations shared by the libcgh HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cgh {
+
+constexpr int kMaxLevels = 3;
+
+// Operand representation of the contractions (values of cgh_precision).
+enum Prec { P_FP32 = 0, P_BF16 = 1, P_FP16 = 2 };
+constexpr int kLayerChunk = 64;  // layers per fringe-table launch (kernel-argument budget)
+
+// Side length of the level-l square of Mallat coefficients along one axis
+// (l >= 1): both subband halves, 2 * (n >> l).
+__host__ __device__ inline int band_side(int n, int l) { return n >> (l - 1); }
+
+// Fringe table of one axis: entry i holds g[m] for m = i - n_pix, i in [0, 2 n_pix).
+__host__ __device__ inline int lut_len(int n_pix) { return 2 * n_pix; }
+
+// Table index of (layer d, level l >= 1, band b, part) for `levels` levels.
+__host__ __device__ inline size_t lut_table(int d, int l, int band, int part, int levels) {
+    return ((size_t)(d * levels + (l - 1)) * 2 + band) * 2 + part;
+}
+
+// Offsets (in rows of s(l) for T, in bytes for flags) of level l inside one layer.
+__host__ __device__ inline size_t t_level_rows(int ny, int l) {
+    size_t rows = 0;
+    for (int k = 1; k < l; ++k) rows += band_side(ny, k);
+    return rows;
+}
+__host__ __device__ inline size_t flag_level_off(int ny, int nx, int l) {
+    size_t off = 0;
+    for (int k = 1; k < l; ++k) off += band_side(ny, k) + band_side(nx, k);
+    return off;
+}
+
+struct LayerConsts {
+    double c[kLayerChunk];       // pitch^2 / (2 lambda z_d): kernel phase in cycles per px^2
+    double pre_re[kLayerChunk];  // per-layer complex constant (1, or exp(i k z)/z)
+    double pre_im[kLayerChunk];
+};
+
+// Byte offsets of every region inside the caller's workspace.
+struct Layout {
+    size_t coef, coef_lo;        // masked Mallat coefficients, D * ny * nx (fp32, or hi/lo halves)
+    size_t lut_x, lut_y;         // fringe tables (fp32, or hi halves)
+    size_t lut_x_lo, lut_y_lo;   // lo halves (split precision)
+    size_t lut0;                 // level-0 table pair (x then y) for back-propagation
+    size_t t, t_lo;              // first-stage products, D * sum_l s_y(l) * nx complex
+    size_t flags;                // per layer: rows then cols of every level, bytes
+    size_t ktiles;               // int count + int list of active second-stage K tiles
+    size_t partial;              // split-K partial holograms
+    size_t total;
+    size_t t_layer;              // complex elements of T per layer
+    size_t flags_layer;          // flag bytes per layer
+    int n_ktiles;                // candidate second-stage K tiles
+    int split_k;
+};
+
+struct Launch;  // forward declaration for the host dispatcher
+
+// ------------------------------------------------------------ launchers (host)
+hipError_t launch_fill_u8(uint8_t* p, size_t n, hipStream_t s);
+hipError_t launch_dwt_mask(const float* obj, const uint8_t* layer, const float* sal, int ny, int nx,
+                           int layers, int levels, const float* thr, int precision, void* coef,
+                           void* coef_lo, uint8_t* flags, size_t flags_layer, hipStream_t s);
+hipError_t launch_idwt(const float* coef, int ny, int nx, int levels, float* out, hipStream_t s);
+hipError_t launch_grad_synthesis(const float* gcoef, const uint8_t* layer, const float* sal, int ny,
+                                 int nx, int layers, int levels, const float* thr, float* grad,
+                                 hipStream_t s);
+hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double* c,
+                       const double* pre_re, const double* pre_im, int precision, void* hi,
+                       void* lo, hipStream_t s);
+
+}  // namespace cgh

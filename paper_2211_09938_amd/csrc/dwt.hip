@@ -1,0 +1,347 @@
+// Block-local kernels of the coefficient stage:
+//  * fused layer split + multi-level averaging Haar analysis + saliency
+//    block-max quantisation + detail masking (Sec. 2 Eq. 2, algorithm step 1,
+//    detail selection of steps 3-5), one thread per 2^L x 2^L block;
+//  * plain Haar synthesis;
+//  * gradient synthesis (transpose of the masked analysis, with the layer gather).
+//
+// The averaging Haar transform of 2^L levels never mixes pixels of different
+// aligned 2^L blocks, so every block is independent: no halo, one pass over HBM.
+#include "common.h"
+#include "split.h"
+
+namespace cgh {
+
+namespace {
+
+template <int B>
+struct Pool {
+    float s1[B / 2][B / 2];
+    float s2[(B >= 4) ? B / 4 : 1][(B >= 4) ? B / 4 : 1];
+    float s3[(B >= 8) ? B / 8 : 1][(B >= 8) ? B / 8 : 1];
+};
+
+template <int L>
+__device__ __forceinline__ void pool_saliency(const float* __restrict__ sal, int nx, int by, int bx,
+                                              Pool<(1 << L)>& p) {
+    constexpr int B = 1 << L;
+    float s[B][B];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c) s[r][c] = sal[(size_t)(by * B + r) * nx + bx * B + c];
+#pragma unroll
+    for (int j = 0; j < B / 2; ++j)
+#pragma unroll
+        for (int i = 0; i < B / 2; ++i)
+            p.s1[j][i] = fmaxf(fmaxf(s[2 * j][2 * i], s[2 * j][2 * i + 1]),
+                               fmaxf(s[2 * j + 1][2 * i], s[2 * j + 1][2 * i + 1]));
+    if constexpr (L >= 2) {
+#pragma unroll
+        for (int j = 0; j < B / 4; ++j)
+#pragma unroll
+            for (int i = 0; i < B / 4; ++i)
+                p.s2[j][i] = fmaxf(fmaxf(p.s1[2 * j][2 * i], p.s1[2 * j][2 * i + 1]),
+                                   fmaxf(p.s1[2 * j + 1][2 * i], p.s1[2 * j + 1][2 * i + 1]));
+    }
+    if constexpr (L >= 3) {
+        p.s3[0][0] = fmaxf(fmaxf(p.s2[0][0], p.s2[0][1]), fmaxf(p.s2[1][0], p.s2[1][1]));
+    }
+}
+
+template <int B>
+__device__ __forceinline__ float pooled(const Pool<B>& p, int lev, int j, int i) {
+    if (lev == 1) return p.s1[j][i];
+    if (lev == 2) return p.s2[(B >= 4) ? j : 0][(B >= 4) ? i : 0];
+    return p.s3[0][0];
+}
+
+// One thread per 2^L x 2^L block; threads along x are adjacent blocks.
+template <int L, int P>
+__global__ __launch_bounds__(256) void dwt_mask_kernel(
+    const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
+    int ny, int nx, int layers, float t1, float t2, float t3, void* __restrict__ coef,
+    void* __restrict__ coef_lo, uint8_t* __restrict__ flags, size_t flags_layer) {
+    constexpr int B = 1 << L;
+    const int nbx = nx >> L;
+    const int bx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int by = blockIdx.y;
+    if (bx >= nbx) return;
+
+    float a[B][B];
+    uint8_t li[B][B];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            const size_t g = (size_t)(by * B + r) * nx + bx * B + c;
+            a[r][c] = obj[g];
+            li[r][c] = layer ? layer[g] : 0;
+        }
+    Pool<B> pool;
+    if (sal) pool_saliency<L>(sal, nx, by, bx, pool);
+    const float thr[3] = {t1, t2, t3};
+    const size_t plane = (size_t)ny * nx;
+
+    for (int d = 0; d < layers; ++d) {
+        float cur[B][B];
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+                cur[r][c] = (li[r][c] == d) ? a[r][c] : 0.0f;
+                any |= (li[r][c] == d);
+            }
+        const size_t base = (size_t)d * plane;
+        uint8_t* fl = flags ? flags + (size_t)d * flags_layer : nullptr;
+#pragma unroll
+        for (int lev = 1; lev <= L; ++lev) {
+            const int h = B >> lev;
+            const int nyl = ny >> lev, nxl = nx >> lev;
+            uint8_t* frow = fl ? fl + flag_level_off(ny, nx, lev) : nullptr;
+            uint8_t* fcol = frow ? frow + band_side(ny, lev) : nullptr;
+            float lo[B][B / 2], hi[B][B / 2];
+#pragma unroll
+            for (int r = 0; r < 2 * h; ++r)
+#pragma unroll
+                for (int i = 0; i < h; ++i) {
+                    lo[r][i] = (cur[r][2 * i] + cur[r][2 * i + 1]) * 0.5f;
+                    hi[r][i] = (cur[r][2 * i] - cur[r][2 * i + 1]) * 0.5f;
+                }
+#pragma unroll
+            for (int j = 0; j < h; ++j)
+#pragma unroll
+                for (int i = 0; i < h; ++i) {
+                    const float ll = (lo[2 * j][i] + lo[2 * j + 1][i]) * 0.5f;
+                    const float hh = (lo[2 * j][i] - lo[2 * j + 1][i]) * 0.5f;
+                    const float vv = (hi[2 * j][i] + hi[2 * j + 1][i]) * 0.5f;
+                    const float dd = (hi[2 * j][i] - hi[2 * j + 1][i]) * 0.5f;
+                    const bool keep = !sal || pooled<B>(pool, lev, j, i) > thr[lev - 1];
+                    const float v = keep ? vv : 0.0f;
+                    const float hv = keep ? hh : 0.0f;
+                    const float dv = keep ? dd : 0.0f;
+                    const int gy = by * h + j, gx = bx * h + i;
+                    store_val<P>(coef, coef_lo, base + (size_t)gy * nx + nxl + gx, v);
+                    store_val<P>(coef, coef_lo, base + (size_t)(nyl + gy) * nx + gx, hv);
+                    store_val<P>(coef, coef_lo, base + (size_t)(nyl + gy) * nx + nxl + gx, dv);
+                    if (frow) {
+                        if (v != 0.0f) { frow[gy] = 1; fcol[nxl + gx] = 1; }
+                        if (hv != 0.0f) { frow[nyl + gy] = 1; fcol[gx] = 1; }
+                        if (dv != 0.0f) { frow[nyl + gy] = 1; fcol[nxl + gx] = 1; }
+                    }
+                    cur[j][i] = ll;
+                }
+        }
+        store_val<P>(coef, coef_lo, base + (size_t)by * nx + bx, cur[0][0]);
+        if (fl && cur[0][0] != 0.0f) {
+            uint8_t* frow = fl + flag_level_off(ny, nx, L);
+            frow[by] = 1;
+            frow[band_side(ny, L) + bx] = 1;
+        }
+        (void)any;
+    }
+}
+
+// Synthesis of one block from Mallat coefficients (inverse of the analysis above).
+template <int L>
+__device__ __forceinline__ void synth_block(const float* __restrict__ c, int ny, int nx, int by,
+                                            int bx, const float (*scale)[2], float out[1 << L][1 << L]) {
+    constexpr int B = 1 << L;
+    float cur[B][B];
+    cur[0][0] = c[(size_t)by * nx + bx] * scale[L][0];
+#pragma unroll
+    for (int lev = L; lev >= 1; --lev) {
+        const int h = B >> lev;
+        const int nyl = ny >> lev, nxl = nx >> lev;
+        float nxt[B][B];
+#pragma unroll
+        for (int j = 0; j < h; ++j)
+#pragma unroll
+            for (int i = 0; i < h; ++i) {
+                const int gy = by * h + j, gx = bx * h + i;
+                const float s = scale[lev][1];
+                const float vv = c[(size_t)gy * nx + nxl + gx] * s;
+                const float hh = c[(size_t)(nyl + gy) * nx + gx] * s;
+                const float dd = c[(size_t)(nyl + gy) * nx + nxl + gx] * s;
+                const float lo0 = cur[j][i] + hh, lo1 = cur[j][i] - hh;
+                const float hi0 = vv + dd, hi1 = vv - dd;
+                nxt[2 * j][2 * i] = lo0 + hi0;
+                nxt[2 * j][2 * i + 1] = lo0 - hi0;
+                nxt[2 * j + 1][2 * i] = lo1 + hi1;
+                nxt[2 * j + 1][2 * i + 1] = lo1 - hi1;
+            }
+#pragma unroll
+        for (int r = 0; r < 2 * h; ++r)
+#pragma unroll
+            for (int q = 0; q < 2 * h; ++q) cur[r][q] = nxt[r][q];
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int q = 0; q < B; ++q) out[r][q] = cur[r][q];
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void idwt_kernel(const float* __restrict__ coef, int ny, int nx,
+                                                   float* __restrict__ out) {
+    constexpr int B = 1 << L;
+    const int bx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int by = blockIdx.y;
+    if (bx >= (nx >> L)) return;
+    const float one[4][2] = {{1.f, 1.f}, {1.f, 1.f}, {1.f, 1.f}, {1.f, 1.f}};
+    float px[B][B];
+    synth_block<L>(coef, ny, nx, by, bx, one, px);
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int q = 0; q < B; ++q) out[(size_t)(by * B + r) * nx + bx * B + q] = px[r][q];
+}
+
+// grad[p] = sum_d [layer[p] == d] * S( Lambda M gcoef_d )[p], Lambda = 4^-level per coefficient.
+template <int L>
+__global__ __launch_bounds__(256) void grad_synthesis_kernel(
+    const float* __restrict__ gcoef, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
+    int ny, int nx, int layers, float t1, float t2, float t3, float* __restrict__ grad) {
+    constexpr int B = 1 << L;
+    const int bx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int by = blockIdx.y;
+    if (bx >= (nx >> L)) return;
+    Pool<B> pool;
+    if (sal) pool_saliency<L>(sal, nx, by, bx, pool);
+    const float thr[3] = {t1, t2, t3};
+    uint8_t li[B][B];
+    float acc[B][B];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            li[r][q] = layer ? layer[(size_t)(by * B + r) * nx + bx * B + q] : 0;
+            acc[r][q] = 0.0f;
+        }
+    const size_t plane = (size_t)ny * nx;
+    // Masked, scaled copy of this block's coefficients, then plain synthesis.
+    for (int d = 0; d < layers; ++d) {
+        bool present = false;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int q = 0; q < B; ++q) present |= (li[r][q] == d);
+        if (!present) continue;
+        const float* c = gcoef + (size_t)d * plane;
+        float cur[B][B];
+        cur[0][0] = c[(size_t)by * nx + bx] * (1.0f / (float)(1 << (2 * L)));
+#pragma unroll
+        for (int lev = L; lev >= 1; --lev) {
+            const int h = B >> lev;
+            const int nyl = ny >> lev, nxl = nx >> lev;
+            const float s = 1.0f / (float)(1 << (2 * lev));
+            float nxt[B][B];
+#pragma unroll
+            for (int j = 0; j < h; ++j)
+#pragma unroll
+                for (int i = 0; i < h; ++i) {
+                    const int gy = by * h + j, gx = bx * h + i;
+                    const bool keep = !sal || pooled<B>(pool, lev, j, i) > thr[lev - 1];
+                    const float k = keep ? s : 0.0f;
+                    const float vv = c[(size_t)gy * nx + nxl + gx] * k;
+                    const float hh = c[(size_t)(nyl + gy) * nx + gx] * k;
+                    const float dd = c[(size_t)(nyl + gy) * nx + nxl + gx] * k;
+                    const float lo0 = cur[j][i] + hh, lo1 = cur[j][i] - hh;
+                    const float hi0 = vv + dd, hi1 = vv - dd;
+                    nxt[2 * j][2 * i] = lo0 + hi0;
+                    nxt[2 * j][2 * i + 1] = lo0 - hi0;
+                    nxt[2 * j + 1][2 * i] = lo1 + hi1;
+                    nxt[2 * j + 1][2 * i + 1] = lo1 - hi1;
+                }
+#pragma unroll
+            for (int r = 0; r < 2 * h; ++r)
+#pragma unroll
+                for (int q = 0; q < 2 * h; ++q) cur[r][q] = nxt[r][q];
+        }
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int q = 0; q < B; ++q) acc[r][q] += (li[r][q] == d) ? cur[r][q] : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int q = 0; q < B; ++q) grad[(size_t)(by * B + r) * nx + bx * B + q] = acc[r][q];
+}
+
+__global__ void fill_u8_kernel(uint8_t* p, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_fill_u8(uint8_t* p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int threads = 256;
+    size_t blocks = (n + threads - 1) / threads;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, p, n);
+    return hipGetLastError();
+}
+
+template <int L, int P>
+static void dwt_launch(const float* obj, const uint8_t* layer, const float* sal, int ny, int nx,
+                       int layers, const float* thr, void* coef, void* coef_lo, uint8_t* flags,
+                       size_t flags_layer, hipStream_t s) {
+    const int nbx = nx >> L;
+    dim3 grid((nbx + 255) / 256, ny >> L);
+    hipLaunchKernelGGL((dwt_mask_kernel<L, P>), grid, dim3(256), 0, s, obj, layer, sal, ny, nx,
+                       layers, thr[0], L >= 2 ? thr[1] : 0.f, L >= 3 ? thr[2] : 0.f, coef, coef_lo,
+                       flags, flags_layer);
+}
+
+hipError_t launch_dwt_mask(const float* obj, const uint8_t* layer, const float* sal, int ny, int nx,
+                           int layers, int levels, const float* thr, int precision, void* coef,
+                           void* coef_lo, uint8_t* flags, size_t flags_layer, hipStream_t s) {
+#define CGH_DWT_CASE(LV, PR)                                                                 \
+    if (levels == LV && precision == PR) {                                                   \
+        dwt_launch<LV, PR>(obj, layer, sal, ny, nx, layers, thr, coef, coef_lo, flags,       \
+                           flags_layer, s);                                                  \
+        return hipGetLastError();                                                            \
+    }
+    CGH_DWT_CASE(1, P_FP32) CGH_DWT_CASE(2, P_FP32) CGH_DWT_CASE(3, P_FP32)
+    CGH_DWT_CASE(1, P_BF16) CGH_DWT_CASE(2, P_BF16) CGH_DWT_CASE(3, P_BF16)
+    CGH_DWT_CASE(1, P_FP16) CGH_DWT_CASE(2, P_FP16) CGH_DWT_CASE(3, P_FP16)
+#undef CGH_DWT_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_idwt(const float* coef, int ny, int nx, int levels, float* out, hipStream_t s) {
+    const int nbx = nx >> levels;
+    dim3 grid((nbx + 255) / 256, ny >> levels);
+    if (levels == 1) hipLaunchKernelGGL(idwt_kernel<1>, grid, dim3(256), 0, s, coef, ny, nx, out);
+    else if (levels == 2) hipLaunchKernelGGL(idwt_kernel<2>, grid, dim3(256), 0, s, coef, ny, nx, out);
+    else if (levels == 3) hipLaunchKernelGGL(idwt_kernel<3>, grid, dim3(256), 0, s, coef, ny, nx, out);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_synthesis(const float* gcoef, const uint8_t* layer, const float* sal, int ny,
+                                 int nx, int layers, int levels, const float* thr, float* grad,
+                                 hipStream_t s) {
+    const int nbx = nx >> levels;
+    dim3 grid((nbx + 255) / 256, ny >> levels);
+    const float t1 = thr[0], t2 = levels >= 2 ? thr[1] : 0.f, t3 = levels >= 3 ? thr[2] : 0.f;
+    if (levels == 1)
+        hipLaunchKernelGGL(grad_synthesis_kernel<1>, grid, dim3(256), 0, s, gcoef, layer, sal, ny,
+                           nx, layers, t1, t2, t3, grad);
+    else if (levels == 2)
+        hipLaunchKernelGGL(grad_synthesis_kernel<2>, grid, dim3(256), 0, s, gcoef, layer, sal, ny,
+                           nx, layers, t1, t2, t3, grad);
+    else if (levels == 3)
+        hipLaunchKernelGGL(grad_synthesis_kernel<3>, grid, dim3(256), 0, s, gcoef, layer, sal, ny,
+                           nx, layers, t1, t2, t3, grad);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace cgh

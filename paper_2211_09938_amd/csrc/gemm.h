@@ -1,0 +1,33 @@
+// Host-side interface of the contraction kernels (internal).
+#pragma once
+
+#include "common.h"
+
+namespace cgh {
+
+constexpr int kTileM = 128;  // output tile rows
+constexpr int kTileN = 128;  // output tile columns (complex)
+constexpr int kTileK = 16;   // K tile
+
+struct GemmShape {
+    int ny, nx, layers, levels, split_k;
+    size_t t_layer;      // complex elements of T per layer
+    size_t flags_layer;  // flag bytes per layer
+};
+
+// Candidate K tiles of the second forward stage (list capacity).
+int second_stage_ktiles(int ny, int levels, int layers);
+
+hipError_t launch_forward_f32(const GemmShape& sh, const float* coef, const float* lut_x,
+                              const float* lut_y, float2* t, const uint8_t* flags, int* klist,
+                              float2* partial, float2* out, int accumulate, int use_flags,
+                              hipStream_t s);
+
+hipError_t launch_backward_f32(const GemmShape& sh, const float2* grad_h, const float* lut_x,
+                               const float* lut_y, float2* q, float* gcoef, hipStream_t s);
+
+hipError_t launch_backprop_f32(int ny, int nx, const float* lut0_x, const float* lut0_y,
+                               const float2* in, float2* tmp, float2* out, int adjoint, float scale,
+                               hipStream_t s);
+
+}  // namespace cgh

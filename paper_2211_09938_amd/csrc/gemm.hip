@@ -1,0 +1,696 @@
+// Dense complex contractions of the hologram on CDNA4 matrix cores (FP32 path).
+//
+// Per depth layer d and Haar level l the hologram contribution factors as
+//     H_{d,l} = Fy_{d,l} * Cb_{d,l} * Fx_{d,l}^T                        (Eq. 3, separable Eq. 1)
+// where Cb is the level-l square of Mallat coefficients (its LL quadrant empty
+// for l < L) and F[pix, j] = g_band(j)[pix - (j mod n_l) * 2^l] is the
+// strided-Toeplitz matrix of the 1D block fringes (lut.hip).  Two stages:
+//     stage 1:  T_{d,l} = Cb_{d,l} * Fx_{d,l}^T          (real x complex)
+//     stage 2:  H       = sum_{d,l} Fy_{d,l} * T_{d,l}  (complex x complex, one long K)
+// Fringe operands are never materialised: each K tile gathers its window of the
+// 1D table (a few KB, cache resident) straight into LDS.
+//
+// The backward pass and the Fresnel back-propagation reuse the same kernel
+// with other operand loaders (conjugated / transposed fringes, dense complex).
+//
+// Kernel: 256 threads = 4 waves in a 2x2 grid, output tile 128 x 128 complex,
+// each wave 64 x 64 complex as 2 x 2 blocks of v_mfma_f32_32x32x2f32, 4M complex
+// products (re*re - im*im, re*im + im*re) reusing every operand fragment twice.
+// K tiles of 16 are staged global -> registers -> LDS, the next tile's global
+// loads in flight while the current one is multiplied.
+#include "common.h"
+#include "gemm.h"
+
+namespace cgh {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+namespace {
+
+constexpr int BM = kTileM, BN = kTileN, BK = kTileK, NT = 256, PAD = 4;
+constexpr int LDA = BM + PAD, LDB = BN + PAD;
+
+__device__ __forceinline__ float2 cz() { return make_float2(0.f, 0.f); }
+
+__device__ __forceinline__ floatx16 mfma(float a, float b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// Flat grid over (layer, level, row tile, col tile), level 1 (largest) first.
+struct FlatGrid {
+    int levels;
+    int cum[kMaxLevels + 1];   // cumulative tiles per layer up to level l
+    int ctl[kMaxLevels + 1];   // column tiles of level l
+    __device__ __forceinline__ void decode(int bid, int& d, int& l, int& m0, int& n0) const {
+        const int per = cum[levels];
+        d = bid / per;
+        int r = bid - d * per;
+        l = 1;
+        while (l < levels && r >= cum[l]) ++l;
+        r -= cum[l - 1];
+        m0 = (r / ctl[l]) * BM;
+        n0 = (r % ctl[l]) * BN;
+    }
+};
+
+// ------------------------------------------------------------------ kernel
+template <class Pb>
+__global__ __launch_bounds__(NT, 2) void cgemm_f32_kernel(Pb pb) {
+    __shared__ float As[2][BK][LDA];
+    __shared__ float Bs[2][BK][LDB];
+    typename Pb::Ctx cx;
+    if (!pb.setup(cx)) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int l32 = lane & 31;
+
+    floatx16 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) { cr[i][j][r] = 0.f; ci[i][j][r] = 0.f; }
+
+    float2 ra[8], rb[8];
+    const int nk = pb.nk(cx);
+
+    auto load = [&](int kt) {
+        const typename Pb::KT kd = pb.kt(cx, kt);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            int m, k;
+            if (Pb::A_KFAST) { k = tid & 15; m = (tid >> 4) + 16 * e; }
+            else { m = tid & 127; k = (tid >> 7) + 2 * e; }
+            ra[e] = pb.a(cx, kd, m, k);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            int n, k;
+            if (Pb::B_KFAST) { k = tid & 15; n = (tid >> 4) + 16 * e; }
+            else { n = tid & 127; k = (tid >> 7) + 2 * e; }
+            rb[e] = pb.b(cx, kd, k, n);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            int m, k;
+            if (Pb::A_KFAST) { k = tid & 15; m = (tid >> 4) + 16 * e; }
+            else { m = tid & 127; k = (tid >> 7) + 2 * e; }
+            As[0][k][m] = ra[e].x;
+            if (Pb::A_CPLX) As[1][k][m] = ra[e].y;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            int n, k;
+            if (Pb::B_KFAST) { k = tid & 15; n = (tid >> 4) + 16 * e; }
+            else { n = tid & 127; k = (tid >> 7) + 2 * e; }
+            Bs[0][k][n] = rb[e].x;
+            if (Pb::B_CPLX) Bs[1][k][n] = rb[e].y;
+        }
+    };
+
+    if (nk > 0) {
+        load(0);
+        stash();
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load(kt + 1);
+#pragma unroll
+        for (int ks = 0; ks < BK / 2; ++ks) {
+            const int kk = 2 * ks + (lane >> 5);
+            float ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                ar[b] = As[0][kk][wm + 32 * b + l32];
+                ai[b] = Pb::A_CPLX ? As[1][kk][wm + 32 * b + l32] : 0.f;
+                br[b] = Bs[0][kk][wn + 32 * b + l32];
+                bi[b] = Pb::B_CPLX ? Bs[1][kk][wn + 32 * b + l32] : 0.f;
+            }
+            if constexpr (Pb::A_CPLX && Pb::B_CPLX) {
+                float nai[2] = {-ai[0], -ai[1]};
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) cr[i][j] = mfma(ar[i], br[j], cr[i][j]);
+                if constexpr (!Pb::OUT_REAL) {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) ci[i][j] = mfma(ar[i], bi[j], ci[i][j]);
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) cr[i][j] = mfma(nai[i], bi[j], cr[i][j]);
+                if constexpr (!Pb::OUT_REAL) {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) ci[i][j] = mfma(ai[i], br[j], ci[i][j]);
+                }
+            } else if constexpr (Pb::A_CPLX) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        cr[i][j] = mfma(ar[i], br[j], cr[i][j]);
+                        ci[i][j] = mfma(ai[i], br[j], ci[i][j]);
+                    }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        cr[i][j] = mfma(ar[i], br[j], cr[i][j]);
+                        ci[i][j] = mfma(ar[i], bi[j], ci[i][j]);
+                    }
+            }
+        }
+        __syncthreads();
+        if (kt + 1 < nk) stash();
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int n = wn + 32 * j + l32;
+                pb.store(cx, m, n, cr[i][j][r], ci[i][j][r]);
+            }
+}
+
+// ------------------------------------------------------------ operand helpers
+// Fringe table entry for pixel `pix` of coefficient column/row `coef` of a level
+// with n_l coefficients per band: band = coef >= n_l, offset pix - (coef mod n_l) 2^l.
+__device__ __forceinline__ float2 fringe(const float* __restrict__ lut_level, int len, int n_pix,
+                                         int nl, int l, int pix, int coef, bool conj) {
+    const int band = coef >= nl;
+    const int c = coef - band * nl;
+    const float* tb = lut_level + (size_t)band * 2 * len;
+    const int idx = pix - (c << l) + n_pix;
+    const float re = tb[idx], im = tb[len + idx];
+    return make_float2(re, conj ? -im : im);
+}
+
+// ---------------------------------------------------------- forward, stage 1
+// T_{d,l}[r, x] = sum_j Cb_{d,l}[r, j] * Fx_{d,l}[x, j]
+struct FwdS1 {
+    static constexpr bool A_CPLX = false, B_CPLX = true, OUT_REAL = false;
+    static constexpr bool A_KFAST = true, B_KFAST = false;
+    const float* coef;
+    const float* lut;
+    float2* t;
+    const uint8_t* flags;
+    int ny, nx, L;
+    size_t t_layer, flags_layer;
+    FlatGrid g;
+    struct Ctx {
+        int d, l, m0, n0, sy, sx, nyl, nxl, k0;
+        const float* c;
+        const float* lut;
+        float2* t;
+    };
+    struct KT { int j0; };
+    __device__ bool setup(Ctx& cx) const {
+        g.decode(blockIdx.x, cx.d, cx.l, cx.m0, cx.n0);
+        const int l = cx.l;
+        cx.sy = band_side(ny, l);
+        cx.sx = band_side(nx, l);
+        cx.nyl = ny >> l;
+        cx.nxl = nx >> l;
+        const uint8_t* fr = flags + (size_t)cx.d * flags_layer + flag_level_off(ny, nx, l);
+        const int row = cx.m0 + (int)threadIdx.x;
+        const int busy = (threadIdx.x < BM && row < cx.sy) ? fr[row] : 0;
+        if (!__syncthreads_or(busy)) return false;  // all rows zero: T rows stay unwritten
+        cx.k0 = (l < L && cx.m0 + BM <= cx.nyl) ? cx.nxl / BK : 0;
+        cx.c = coef + (size_t)cx.d * ny * nx;
+        cx.lut = lut + lut_table(cx.d, l, 0, 0, L) * lut_len(nx);
+        cx.t = t + (size_t)cx.d * t_layer + t_level_rows(ny, l) * nx;
+        return true;
+    }
+    __device__ int nk(const Ctx& cx) const { return (cx.sx + BK - 1) / BK - cx.k0; }
+    __device__ KT kt(const Ctx& cx, int i) const { return KT{(cx.k0 + i) * BK}; }
+    __device__ float2 a(const Ctx& cx, const KT& kd, int m, int k) const {
+        const int r = cx.m0 + m, j = kd.j0 + k;
+        if (r < cx.sy && j < cx.sx && !(cx.l < L && r < cx.nyl && j < cx.nxl))
+            return make_float2(cx.c[(size_t)r * nx + j], 0.f);
+        return cz();
+    }
+    __device__ float2 b(const Ctx& cx, const KT& kd, int k, int n) const {
+        const int j = kd.j0 + k, x = cx.n0 + n;
+        if (j < cx.sx && x < nx) return fringe(cx.lut, lut_len(nx), nx, cx.nxl, cx.l, x, j, false);
+        return cz();
+    }
+    __device__ void store(const Ctx& cx, int m, int n, float re, float im) const {
+        const int r = cx.m0 + m, x = cx.n0 + n;
+        if (r < cx.sy && x < nx) cx.t[(size_t)r * nx + x] = make_float2(re, im);
+    }
+};
+
+// ---------------------------------------------------------- forward, stage 2
+// H[y, x] = sum over active K tiles (d, l, band, j) of Fy_{d,l}[y, j] * T_{d,l}[j, x]
+struct FwdS2 {
+    static constexpr bool A_CPLX = true, B_CPLX = true, OUT_REAL = false;
+    static constexpr bool A_KFAST = false, B_KFAST = false;
+    const float* lut;
+    const float2* t;
+    const uint8_t* flags;
+    const int* klist;  // [0] = count, then codes
+    float2* out;
+    float2* partial;
+    int ny, nx, L, split, accumulate, ctiles;
+    size_t t_layer, flags_layer;
+    struct Ctx { int m0, n0, s, kbeg, kend; };
+    struct KT {
+        int l, nyl, j0;
+        const float* lut;
+        const float2* trow;
+        const uint8_t* rf;
+    };
+    __device__ bool setup(Ctx& cx) const {
+        const int tile = blockIdx.x;
+        cx.m0 = (tile / ctiles) * BM;
+        cx.n0 = (tile % ctiles) * BN;
+        cx.s = blockIdx.y;
+        const int count = klist[0];
+        const int chunk = (count + split - 1) / split;
+        cx.kbeg = cx.s * chunk;
+        cx.kend = min(count, cx.kbeg + chunk);
+        return true;
+    }
+    __device__ int nk(const Ctx& cx) const { return max(0, cx.kend - cx.kbeg); }
+    __device__ KT kt(const Ctx& cx, int i) const {
+        const int code = klist[1 + cx.kbeg + i];
+        const int seg = code >> 16, tile = code & 0xffff;
+        const int d = seg / (2 * L);
+        const int l = ((seg >> 1) % L) + 1;
+        const int band = seg & 1;
+        KT kd;
+        kd.l = l;
+        kd.nyl = ny >> l;
+        kd.j0 = tile * BK;
+        kd.lut = lut + lut_table(d, l, band, 0, L) * lut_len(ny);
+        kd.trow = t + (size_t)d * t_layer + (t_level_rows(ny, l) + (size_t)band * kd.nyl) * nx;
+        kd.rf = flags + (size_t)d * flags_layer + flag_level_off(ny, nx, l) + band * kd.nyl;
+        return kd;
+    }
+    __device__ float2 a(const Ctx& cx, const KT& kd, int m, int k) const {
+        const int y = cx.m0 + m, j = kd.j0 + k;
+        if (y < ny && j < kd.nyl) {
+            const int len = lut_len(ny);
+            const int idx = y - (j << kd.l) + ny;
+            return make_float2(kd.lut[idx], kd.lut[len + idx]);
+        }
+        return cz();
+    }
+    __device__ float2 b(const Ctx& cx, const KT& kd, int k, int n) const {
+        const int j = kd.j0 + k, x = cx.n0 + n;
+        if (j < kd.nyl && x < nx && kd.rf[j]) return kd.trow[(size_t)j * nx + x];
+        return cz();
+    }
+    __device__ void store(const Ctx& cx, int m, int n, float re, float im) const {
+        const int y = cx.m0 + m, x = cx.n0 + n;
+        if (y >= ny || x >= nx) return;
+        const size_t i = (size_t)y * nx + x;
+        if (split == 1) {
+            float2 v = make_float2(re, im);
+            if (accumulate) { const float2 o = out[i]; v.x += o.x; v.y += o.y; }
+            out[i] = v;
+        } else {
+            partial[(size_t)cx.s * ny * nx + i] = make_float2(re, im);
+        }
+    }
+};
+
+// --------------------------------------------------------- backward, stage 1
+// Q_{d,l}[r, x] = sum_y conj(Fy_{d,l}[y, r]) * G[y, x]
+struct BwdS1 {
+    static constexpr bool A_CPLX = true, B_CPLX = true, OUT_REAL = false;
+    static constexpr bool A_KFAST = true, B_KFAST = false;
+    const float* lut;
+    const float2* g_in;
+    float2* q;
+    int ny, nx, L;
+    size_t t_layer;
+    FlatGrid g;
+    struct Ctx { int d, l, m0, n0, sy, nyl; const float* lut; float2* q; };
+    struct KT { int y0; };
+    __device__ bool setup(Ctx& cx) const {
+        g.decode(blockIdx.x, cx.d, cx.l, cx.m0, cx.n0);
+        cx.sy = band_side(ny, cx.l);
+        cx.nyl = ny >> cx.l;
+        cx.lut = lut + lut_table(cx.d, cx.l, 0, 0, L) * lut_len(ny);
+        cx.q = q + (size_t)cx.d * t_layer + t_level_rows(ny, cx.l) * nx;
+        return true;
+    }
+    __device__ int nk(const Ctx&) const { return (ny + BK - 1) / BK; }
+    __device__ KT kt(const Ctx&, int i) const { return KT{i * BK}; }
+    __device__ float2 a(const Ctx& cx, const KT& kd, int m, int k) const {
+        const int r = cx.m0 + m, y = kd.y0 + k;
+        if (r < cx.sy && y < ny) return fringe(cx.lut, lut_len(ny), ny, cx.nyl, cx.l, y, r, true);
+        return cz();
+    }
+    __device__ float2 b(const Ctx& cx, const KT& kd, int k, int n) const {
+        const int y = kd.y0 + k, x = cx.n0 + n;
+        if (y < ny && x < nx) return g_in[(size_t)y * nx + x];
+        return cz();
+    }
+    __device__ void store(const Ctx& cx, int m, int n, float re, float im) const {
+        const int r = cx.m0 + m, x = cx.n0 + n;
+        if (r < cx.sy && x < nx) cx.q[(size_t)r * nx + x] = make_float2(re, im);
+    }
+};
+
+// --------------------------------------------------------- backward, stage 2
+// gC_{d,l}[r, j] = Re( sum_x Q_{d,l}[r, x] * conj(Fx_{d,l}[x, j]) ), at level-l positions only
+struct BwdS2 {
+    static constexpr bool A_CPLX = true, B_CPLX = true, OUT_REAL = true;
+    static constexpr bool A_KFAST = true, B_KFAST = true;
+    const float* lut;
+    const float2* q;
+    float* gcoef;
+    int ny, nx, L;
+    size_t t_layer;
+    FlatGrid g;
+    struct Ctx { int d, l, m0, n0, sy, sx, nyl, nxl; const float* lut; const float2* q; float* gc; };
+    struct KT { int x0; };
+    __device__ bool setup(Ctx& cx) const {
+        g.decode(blockIdx.x, cx.d, cx.l, cx.m0, cx.n0);
+        const int l = cx.l;
+        cx.sy = band_side(ny, l);
+        cx.sx = band_side(nx, l);
+        cx.nyl = ny >> l;
+        cx.nxl = nx >> l;
+        if (l < L && cx.m0 + BM <= cx.nyl && cx.n0 + BN <= cx.nxl) return false;  // coarser level's square
+        cx.lut = lut + lut_table(cx.d, l, 0, 0, L) * lut_len(nx);
+        cx.q = q + (size_t)cx.d * t_layer + t_level_rows(ny, l) * nx;
+        cx.gc = gcoef + (size_t)cx.d * ny * nx;
+        return true;
+    }
+    __device__ int nk(const Ctx&) const { return (nx + BK - 1) / BK; }
+    __device__ KT kt(const Ctx&, int i) const { return KT{i * BK}; }
+    __device__ float2 a(const Ctx& cx, const KT& kd, int m, int k) const {
+        const int r = cx.m0 + m, x = kd.x0 + k;
+        if (r < cx.sy && x < nx) return cx.q[(size_t)r * nx + x];
+        return cz();
+    }
+    __device__ float2 b(const Ctx& cx, const KT& kd, int k, int n) const {
+        const int x = kd.x0 + k, j = cx.n0 + n;
+        if (j < cx.sx && x < nx) return fringe(cx.lut, lut_len(nx), nx, cx.nxl, cx.l, x, j, true);
+        return cz();
+    }
+    __device__ void store(const Ctx& cx, int m, int n, float re, float) const {
+        const int r = cx.m0 + m, j = cx.n0 + n;
+        if (r < cx.sy && j < cx.sx && !(cx.l < L && r < cx.nyl && j < cx.nxl))
+            cx.gc[(size_t)r * nx + j] = re;
+    }
+};
+
+// ------------------------------------------------- Fresnel back-propagation
+// stage 1: V[q, x] = sum_y k*(y - q) H[y, x]      (k* = conj(k), or k for the adjoint)
+// stage 2: U[q, p] = s * sum_x V[q, x] k*(x - p)
+struct PropS1 {
+    static constexpr bool A_CPLX = true, B_CPLX = true, OUT_REAL = false;
+    static constexpr bool A_KFAST = true, B_KFAST = false;
+    const float* lut_y;  // level-0 table of the y axis (re then im)
+    const float2* in;
+    float2* v;
+    int ny, nx, conj, ctiles;
+    struct Ctx { int m0, n0; };
+    struct KT { int y0; };
+    __device__ bool setup(Ctx& cx) const {
+        cx.m0 = (blockIdx.x / ctiles) * BM;
+        cx.n0 = (blockIdx.x % ctiles) * BN;
+        return true;
+    }
+    __device__ int nk(const Ctx&) const { return (ny + BK - 1) / BK; }
+    __device__ KT kt(const Ctx&, int i) const { return KT{i * BK}; }
+    __device__ float2 a(const Ctx& cx, const KT& kd, int m, int k) const {
+        const int qq = cx.m0 + m, y = kd.y0 + k;
+        if (qq < ny && y < ny) {
+            const int len = lut_len(ny), idx = y - qq + ny;
+            return make_float2(lut_y[idx], conj ? -lut_y[len + idx] : lut_y[len + idx]);
+        }
+        return cz();
+    }
+    __device__ float2 b(const Ctx& cx, const KT& kd, int k, int n) const {
+        const int y = kd.y0 + k, x = cx.n0 + n;
+        if (y < ny && x < nx) return in[(size_t)y * nx + x];
+        return cz();
+    }
+    __device__ void store(const Ctx& cx, int m, int n, float re, float im) const {
+        const int qq = cx.m0 + m, x = cx.n0 + n;
+        if (qq < ny && x < nx) v[(size_t)qq * nx + x] = make_float2(re, im);
+    }
+};
+
+struct PropS2 {
+    static constexpr bool A_CPLX = true, B_CPLX = true, OUT_REAL = false;
+    static constexpr bool A_KFAST = true, B_KFAST = true;
+    const float* lut_x;
+    const float2* v;
+    float2* out;
+    int ny, nx, conj, ctiles;
+    float scale;
+    struct Ctx { int m0, n0; };
+    struct KT { int x0; };
+    __device__ bool setup(Ctx& cx) const {
+        cx.m0 = (blockIdx.x / ctiles) * BM;
+        cx.n0 = (blockIdx.x % ctiles) * BN;
+        return true;
+    }
+    __device__ int nk(const Ctx&) const { return (nx + BK - 1) / BK; }
+    __device__ KT kt(const Ctx&, int i) const { return KT{i * BK}; }
+    __device__ float2 a(const Ctx& cx, const KT& kd, int m, int k) const {
+        const int qq = cx.m0 + m, x = kd.x0 + k;
+        if (qq < ny && x < nx) return v[(size_t)qq * nx + x];
+        return cz();
+    }
+    __device__ float2 b(const Ctx& cx, const KT& kd, int k, int n) const {
+        const int x = kd.x0 + k, p = cx.n0 + n;
+        if (x < nx && p < nx) {
+            const int len = lut_len(nx), idx = x - p + nx;
+            return make_float2(lut_x[idx], conj ? -lut_x[len + idx] : lut_x[len + idx]);
+        }
+        return cz();
+    }
+    __device__ void store(const Ctx& cx, int m, int n, float re, float im) const {
+        const int qq = cx.m0 + m, p = cx.n0 + n;
+        if (qq < ny && p < nx) out[(size_t)qq * nx + p] = make_float2(re * scale, im * scale);
+    }
+};
+
+// --------------------------------------------------------------- K-tile list
+// Deterministic compaction (one workgroup) of the second-stage K tiles whose
+// rows of T hold at least one nonzero coefficient row.
+__global__ __launch_bounds__(1024) void ktile_list_kernel(const uint8_t* __restrict__ flags, int ny,
+                                                          int nx, int L, int D,
+                                                          size_t flags_layer, int use_flags,
+                                                          int* __restrict__ klist) {
+    __shared__ int scan[1024];
+    __shared__ int base_s;
+    int per_layer = 0;
+    for (int l = 1; l <= L; ++l) per_layer += 2 * (((ny >> l) + BK - 1) / BK);
+    const int total = D * per_layer;
+    if (threadIdx.x == 0) base_s = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < total; c0 += 1024) {
+        const int c = c0 + (int)threadIdx.x;
+        int active = 0, code = 0;
+        if (c < total) {
+            const int d = c / per_layer;
+            int r = c - d * per_layer;
+            int l = 1;
+            for (;;) {
+                const int tl = ((ny >> l) + BK - 1) / BK;
+                if (r < 2 * tl || l == L) break;
+                r -= 2 * tl;
+                ++l;
+            }
+            const int tl = ((ny >> l) + BK - 1) / BK;
+            const int band = r / tl, tile = r - band * tl;
+            const int nyl = ny >> l;
+            if (use_flags) {
+                const uint8_t* rf = flags + (size_t)d * flags_layer + flag_level_off(ny, nx, l) + band * nyl;
+                for (int q = tile * BK; q < min(nyl, tile * BK + BK); ++q) active |= rf[q];
+            } else {
+                active = 1;
+            }
+            code = (((d * L + (l - 1)) * 2 + band) << 16) | tile;
+        }
+        scan[threadIdx.x] = active;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int v = (threadIdx.x >= (unsigned)off) ? scan[threadIdx.x - off] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += v;
+            __syncthreads();
+        }
+        const int base = base_s;
+        if (active) klist[1 + base + scan[threadIdx.x] - 1] = code;
+        __syncthreads();
+        if (threadIdx.x == 1023) base_s = base + scan[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) klist[0] = base_s;
+}
+
+__global__ __launch_bounds__(256) void reduce_partial_kernel(const float2* __restrict__ partial,
+                                                             int split, size_t n, int accumulate,
+                                                             float2* __restrict__ out) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) {
+        float2 v = accumulate ? out[i] : make_float2(0.f, 0.f);
+        for (int s = 0; s < split; ++s) {
+            const float2 p = partial[(size_t)s * n + i];
+            v.x += p.x;
+            v.y += p.y;
+        }
+        out[i] = v;
+    }
+}
+
+template <class Pb>
+hipError_t run(const Pb& pb, dim3 grid, hipStream_t s) {
+    if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
+    hipLaunchKernelGGL(cgemm_f32_kernel<Pb>, grid, dim3(NT), 0, s, pb);
+    return hipGetLastError();
+}
+
+FlatGrid make_grid(int ny, int levels, const int* cols_per_level) {
+    FlatGrid g{};
+    g.levels = levels;
+    g.cum[0] = 0;
+    for (int l = 1; l <= levels; ++l) {
+        const int rows = (band_side(ny, l) + BM - 1) / BM;
+        g.ctl[l] = (cols_per_level[l] + BN - 1) / BN;
+        g.cum[l] = g.cum[l - 1] + rows * g.ctl[l];
+    }
+    return g;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- launchers
+int second_stage_ktiles(int ny, int levels, int layers) {
+    int per = 0;
+    for (int l = 1; l <= levels; ++l) per += 2 * (((ny >> l) + BK - 1) / BK);
+    return per * layers;
+}
+
+hipError_t launch_forward_f32(const GemmShape& sh, const float* coef, const float* lut_x,
+                              const float* lut_y, float2* t, const uint8_t* flags, int* klist,
+                              float2* partial, float2* out, int accumulate, int use_flags,
+                              hipStream_t s) {
+    int cols[kMaxLevels + 1];
+    for (int l = 1; l <= sh.levels; ++l) cols[l] = sh.nx;
+    FwdS1 p1{};
+    p1.coef = coef;
+    p1.lut = lut_x;
+    p1.t = t;
+    p1.flags = flags;
+    p1.ny = sh.ny;
+    p1.nx = sh.nx;
+    p1.L = sh.levels;
+    p1.t_layer = sh.t_layer;
+    p1.flags_layer = sh.flags_layer;
+    p1.g = make_grid(sh.ny, sh.levels, cols);
+    hipError_t e = run(p1, dim3(p1.g.cum[sh.levels] * sh.layers), s);
+    if (e != hipSuccess) return e;
+
+    hipLaunchKernelGGL(ktile_list_kernel, dim3(1), dim3(1024), 0, s, flags, sh.ny, sh.nx,
+                       sh.levels, sh.layers, sh.flags_layer, use_flags, klist);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    FwdS2 p2{};
+    p2.lut = lut_y;
+    p2.t = t;
+    p2.flags = flags;
+    p2.klist = klist;
+    p2.out = out;
+    p2.partial = partial;
+    p2.ny = sh.ny;
+    p2.nx = sh.nx;
+    p2.L = sh.levels;
+    p2.split = sh.split_k;
+    p2.accumulate = accumulate;
+    p2.ctiles = (sh.nx + BN - 1) / BN;
+    p2.t_layer = sh.t_layer;
+    p2.flags_layer = sh.flags_layer;
+    const int tiles = ((sh.ny + BM - 1) / BM) * p2.ctiles;
+    e = run(p2, dim3(tiles, sh.split_k), s);
+    if (e != hipSuccess) return e;
+    if (sh.split_k > 1) {
+        const size_t n = (size_t)sh.ny * sh.nx;
+        size_t blocks = (n + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(reduce_partial_kernel, dim3((unsigned)blocks), dim3(256), 0, s, partial,
+                           sh.split_k, n, accumulate, out);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t launch_backward_f32(const GemmShape& sh, const float2* grad_h, const float* lut_x,
+                               const float* lut_y, float2* q, float* gcoef, hipStream_t s) {
+    int cols[kMaxLevels + 1];
+    for (int l = 1; l <= sh.levels; ++l) cols[l] = sh.nx;
+    BwdS1 p1{};
+    p1.lut = lut_y;
+    p1.g_in = grad_h;
+    p1.q = q;
+    p1.ny = sh.ny;
+    p1.nx = sh.nx;
+    p1.L = sh.levels;
+    p1.t_layer = sh.t_layer;
+    p1.g = make_grid(sh.ny, sh.levels, cols);
+    hipError_t e = run(p1, dim3(p1.g.cum[sh.levels] * sh.layers), s);
+    if (e != hipSuccess) return e;
+    for (int l = 1; l <= sh.levels; ++l) cols[l] = band_side(sh.nx, l);
+    BwdS2 p2{};
+    p2.lut = lut_x;
+    p2.q = q;
+    p2.gcoef = gcoef;
+    p2.ny = sh.ny;
+    p2.nx = sh.nx;
+    p2.L = sh.levels;
+    p2.t_layer = sh.t_layer;
+    p2.g = make_grid(sh.ny, sh.levels, cols);
+    return run(p2, dim3(p2.g.cum[sh.levels] * sh.layers), s);
+}
+
+hipError_t launch_backprop_f32(int ny, int nx, const float* lut0_x, const float* lut0_y,
+                               const float2* in, float2* tmp, float2* out, int adjoint, float scale,
+                               hipStream_t s) {
+    PropS1 p1{};
+    p1.lut_y = lut0_y;
+    p1.in = in;
+    p1.v = tmp;
+    p1.ny = ny;
+    p1.nx = nx;
+    p1.conj = adjoint ? 0 : 1;
+    p1.ctiles = (nx + BN - 1) / BN;
+    hipError_t e = run(p1, dim3(((ny + BM - 1) / BM) * p1.ctiles), s);
+    if (e != hipSuccess) return e;
+    PropS2 p2{};
+    p2.lut_x = lut0_x;
+    p2.v = tmp;
+    p2.out = out;
+    p2.ny = ny;
+    p2.nx = nx;
+    p2.conj = adjoint ? 0 : 1;
+    p2.ctiles = (nx + BN - 1) / BN;
+    p2.scale = scale;
+    return run(p2, dim3(((ny + BM - 1) / BM) * p2.ctiles), s);
+}
+
+}  // namespace cgh

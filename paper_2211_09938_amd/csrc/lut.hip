@@ -1,0 +1,94 @@
+// Fringe tables of the block basis functions, one 1D table per axis.
+//
+// Under the Fresnel form of Eq. 1 the kernel of an integer pixel offset (dy, dx)
+// factors as k(dy) k(dx) with k(m) = exp(i pi pitch^2 m^2 / (lambda z)).  The
+// hologram of a Haar basis block (Sec. 2: a level-l coefficient spreads over a
+// 2^l x 2^l block of points, each with its own fringe) therefore factors into
+// 1D sums over the block's columns and rows:
+//     lo band:  g_lo[m] = sum_{u <  2^l}     k(m - u)
+//     hi band:  g_hi[m] = sum_{u <  2^(l-1)} k(m - u) - sum_{2^(l-1) <= u < 2^l} k(m - u)
+// which are the separable rows of the paper's 2^l x 2^l look-up-table blocks.
+//
+// Phase evaluation: m^2 is formed exactly as a 64-bit integer, the phase in
+// cycles is m^2 * c with c = pitch^2 / (2 lambda z) in FP64, its fractional
+// part is taken in FP64 and sin/cos come from the HIP device library's FP64
+// sincospi.  Only then is the sum rounded to the operand precision.
+#include "common.h"
+#include "split.h"
+
+namespace cgh {
+
+namespace {
+
+template <int P>
+__global__ __launch_bounds__(256) void lut_kernel(int n_pix, int d0, int levels, int lmin,
+                                                  LayerConsts lc, void* __restrict__ hi,
+                                                  void* __restrict__ lo) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int len = lut_len(n_pix);
+    if (idx >= len) return;
+    const int combo = blockIdx.y;
+    const int lev = (lmin == 0) ? 0 : 1 + combo / 2;
+    const int band = (lmin == 0) ? 0 : combo % 2;
+    const int dl = blockIdx.z;
+    const int d = d0 + dl;
+    const int m = idx - n_pix;
+    const int bsz = 1 << lev;
+    double re = 0.0, im = 0.0;
+    if (m >= -(n_pix - bsz) && m <= n_pix - 1) {
+        const double c = lc.c[dl];
+        for (int u = 0; u < bsz; ++u) {
+            const long long mm = (long long)(m - u);
+            const double cyc_full = (double)(mm * mm) * c;
+            const double cyc = cyc_full - floor(cyc_full);
+            double s, co;
+            sincospi(2.0 * cyc, &s, &co);
+            const double sign = (band == 0 || u < (bsz >> 1)) ? 1.0 : -1.0;
+            re += sign * co;
+            im += sign * s;
+        }
+        const double pr = lc.pre_re[dl], pi = lc.pre_im[dl];
+        const double r2 = re * pr - im * pi;
+        const double i2 = re * pi + im * pr;
+        re = r2;
+        im = i2;
+    }
+    const size_t t_re = (lmin == 0) ? (size_t)(d * 2 + 0) : lut_table(d, lev, band, 0, levels);
+    const size_t t_im = (lmin == 0) ? (size_t)(d * 2 + 1) : lut_table(d, lev, band, 1, levels);
+    store_val<P>(hi, lo, t_re * len + idx, (float)re);
+    store_val<P>(hi, lo, t_im * len + idx, (float)im);
+}
+
+}  // namespace
+
+hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double* c,
+                       const double* pre_re, const double* pre_im, int precision, void* hi,
+                       void* lo, hipStream_t s) {
+    const int len = lut_len(n_pix);
+    const int combos = (lmin == 0) ? 1 : 2 * levels;
+    for (int d0 = 0; d0 < layers; d0 += kLayerChunk) {
+        const int nd = (layers - d0 < kLayerChunk) ? layers - d0 : kLayerChunk;
+        LayerConsts lc;
+        for (int k = 0; k < kLayerChunk; ++k) {
+            const int d = d0 + (k < nd ? k : 0);
+            lc.c[k] = c[d];
+            lc.pre_re[k] = pre_re[d];
+            lc.pre_im[k] = pre_im[d];
+        }
+        dim3 grid((len + 255) / 256, combos, nd);
+        if (precision == P_FP32)
+            hipLaunchKernelGGL(lut_kernel<P_FP32>, grid, dim3(256), 0, s, n_pix, d0, levels, lmin,
+                               lc, hi, lo);
+        else if (precision == P_BF16)
+            hipLaunchKernelGGL(lut_kernel<P_BF16>, grid, dim3(256), 0, s, n_pix, d0, levels, lmin,
+                               lc, hi, lo);
+        else
+            hipLaunchKernelGGL(lut_kernel<P_FP16>, grid, dim3(256), 0, s, n_pix, d0, levels, lmin,
+                               lc, hi, lo);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace cgh

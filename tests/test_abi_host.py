@@ -1,0 +1,134 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every function that include/cgh.h declares, and
+reject invalid arguments on the host before anything is enqueued -- which is why
+these calls work without a GPU: validation never reaches a HIP call.
+"""
+
+import ctypes
+import os
+
+import pytest
+
+from paper_2211_09938_amd import cgh
+
+pytestmark = pytest.mark.skipif(not os.path.exists(cgh.LIB_PATH), reason="libcgh.so not built")
+
+OK, INVALID, SHAPE, UNSUP, OOM, WS, HIP = range(7)
+P = ctypes.c_void_p
+BOGUS = P(0x1000)  # never dereferenced: validation fails first
+
+
+def test_every_declared_function_is_exported():
+    lib = cgh.lib()
+    names = cgh.header_functions()
+    assert "cgh_progressive_hologram" in names and "cgh_hologram_backward" in names
+    assert "cgh_haar_dwt" in names
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in cgh.SIGNATURES, name
+
+
+def test_status_strings():
+    lib = cgh.lib()
+    for code in range(7):
+        assert lib.cgh_status_string(code).decode().startswith(cgh.STATUS[code])
+    assert lib.cgh_status_string(99) == b"CGH_ERROR_UNKNOWN"
+    assert lib.cgh_version() >= 100
+
+
+def ws_size(ny, nx, layers=1, levels=3, prec=0):
+    out = ctypes.c_size_t(0)
+    st = cgh.lib().cgh_workspace_size(ny, nx, layers, levels, prec, ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_size_rules():
+    st, b = ws_size(128, 128)
+    assert st == OK and b > 128 * 128 * 8
+    st2, b2 = ws_size(2048, 2048, 8)
+    assert st2 == OK and b2 > b
+    assert ws_size(0, 64)[0] == OK and ws_size(0, 64)[1] == 0
+    assert ws_size(100, 64)[0] == SHAPE          # 100 not divisible by 8
+    assert ws_size(64, 64, 1, 0)[0] == SHAPE     # levels < 1
+    assert ws_size(64, 64, 1, 4)[0] == UNSUP     # more levels than implemented
+    assert ws_size(64, 64, 0)[0] == INVALID      # no layer
+    assert ws_size(64, 64, 257)[0] == INVALID
+    assert ws_size(64, 64, 1, 3, 7)[0] == INVALID
+    assert ws_size(32768, 64)[0] == SHAPE        # beyond the side limit
+    assert cgh.lib().cgh_workspace_size(64, 64, 1, 3, 0, None) == INVALID
+
+
+def call_forward(**over):
+    z = (ctypes.c_double * 1)(0.2)
+    args = dict(obj=BOGUS, layer=None, n_layers=1, z=z, sal=None, thr=None, lam=532e-9,
+                pitch=8e-6, ny=64, nx=64, levels=3, prec=0, flags=0, ws=BOGUS, ws_bytes=1 << 40,
+                out=BOGUS)
+    args.update(over)
+    return cgh.lib().cgh_progressive_hologram(
+        args["obj"], args["layer"], args["n_layers"], args["z"], args["sal"], args["thr"],
+        args["lam"], args["pitch"], args["ny"], args["nx"], args["levels"], args["prec"],
+        args["flags"], args["ws"], args["ws_bytes"], args["out"], None)
+
+
+@pytest.mark.parametrize("over,code", [
+    (dict(obj=None), INVALID),
+    (dict(out=None), INVALID),
+    (dict(z=None), INVALID),
+    (dict(z=(ctypes.c_double * 1)(-0.2)), INVALID),
+    (dict(z=(ctypes.c_double * 1)(float("nan"))), INVALID),
+    (dict(lam=0.0), INVALID),
+    (dict(lam=float("inf")), INVALID),
+    (dict(pitch=-1.0), INVALID),
+    (dict(n_layers=2), INVALID),                      # two layers need a layer map
+    (dict(n_layers=0), INVALID),
+    (dict(thr=(ctypes.c_float * 3)(0.9, 1.5, 0.5)), INVALID),
+    (dict(thr=(ctypes.c_float * 3)(0.9, float("nan"), 0.5)), INVALID),
+    (dict(flags=8), INVALID),
+    (dict(prec=5), INVALID),
+    (dict(ny=60), SHAPE),
+    (dict(levels=0), SHAPE),
+    (dict(levels=4), UNSUP),
+    (dict(ny=32768), SHAPE),
+    (dict(ws=None), WS),
+    (dict(ws_bytes=1024), WS),
+])
+def test_forward_rejects_invalid_arguments(over, code):
+    assert call_forward(**over) == code
+
+
+def test_forward_empty_problem_is_a_no_op():
+    assert call_forward(ny=0, obj=None, out=None, ws=None, ws_bytes=0) == OK
+    assert call_forward(nx=0, obj=None, out=None, ws=None, ws_bytes=0) == OK
+
+
+def test_backward_and_backprop_validation():
+    lib = cgh.lib()
+    z = (ctypes.c_double * 1)(0.2)
+    base = [BOGUS, None, 1, z, None, None, 532e-9, 8e-6, 64, 64, 3, 0, 0, BOGUS, 1 << 40, BOGUS, None]
+    a = list(base)
+    a[12] = 1  # accumulate is meaningless for a gradient
+    assert lib.cgh_hologram_backward(*a) == INVALID
+    a = list(base)
+    a[0] = None
+    assert lib.cgh_hologram_backward(*a) == INVALID
+    a = list(base)
+    a[14] = 16
+    assert lib.cgh_hologram_backward(*a) == WS
+    assert lib.cgh_fresnel_backpropagate(BOGUS, 64, 64, 532e-9, 8e-6, 0.0, 0, 0, BOGUS, 1 << 40,
+                                         BOGUS, None) == INVALID
+    assert lib.cgh_fresnel_backpropagate(BOGUS, 64, 63, 532e-9, 8e-6, 0.2, 0, 0, BOGUS, 1 << 40,
+                                         BOGUS, None) == SHAPE
+    assert lib.cgh_fresnel_backpropagate(BOGUS, 64, 64, 532e-9, 8e-6, 0.2, 0, 0, BOGUS, 16,
+                                         P(0x2000), None) == WS
+    assert lib.cgh_fresnel_backpropagate(BOGUS, 64, 64, 532e-9, 8e-6, 0.2, 0, 0, BOGUS, 1 << 40,
+                                         BOGUS, None) == INVALID  # in-place is rejected
+
+
+def test_haar_validation():
+    lib = cgh.lib()
+    assert lib.cgh_haar_dwt(BOGUS, 64, 60, 3, BOGUS, None) == SHAPE
+    assert lib.cgh_haar_dwt(None, 64, 64, 3, BOGUS, None) == INVALID
+    assert lib.cgh_haar_dwt(BOGUS, 64, 64, 3, BOGUS, None) == INVALID  # aliasing in/out
+    assert lib.cgh_haar_idwt(BOGUS, 64, 64, 0, P(0x2000), None) == SHAPE
+    assert lib.cgh_haar_dwt(None, 0, 64, 3, None, None) == OK
