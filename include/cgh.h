@@ -158,6 +158,50 @@ int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lamb
                               double z, int precision, int adjoint, void* workspace,
                               size_t workspace_bytes, float* field_out, void* stream);
 
+/* ------------------------------------------------------------ diagnostics */
+
+/* Stages of cgh_progressive_hologram, in launch order. */
+enum {
+    CGH_STAGE_COEF = 0,    /* flag clear + fused layer split / Haar / saliency / masking */
+    CGH_STAGE_LUT = 1,     /* FP64 fringe tables, both axes                               */
+    CGH_STAGE_FIRST = 2,   /* first contraction  T_{d,l} = Cb_{d,l} Fx_{d,l}^T            */
+    CGH_STAGE_LIST = 3,    /* compaction of the second contraction's active K tiles       */
+    CGH_STAGE_SECOND = 4,  /* second contraction H = sum_{d,l} Fy_{d,l} T_{d,l}           */
+    CGH_STAGE_REDUCE = 5,  /* split-K partial sum (only when the K range is split)        */
+    CGH_STAGE_COUNT = 6
+};
+
+/* Per-stage timing of cgh_progressive_hologram: on != 0 makes every later
+ * call record a HIP event pair around each stage, on the call's own stream
+ * (events come from a library-owned pool).  Process-wide, thread-safe. */
+int cgh_profile_enable(int on);
+
+/* Waits for every recorded event pair, adds the elapsed times to per-stage
+ * totals and returns them: ms[CGH_STAGE_COUNT] milliseconds and
+ * launches[CGH_STAGE_COUNT] event pairs, both [host], either may be NULL.
+ * reset != 0 clears the totals after reading. */
+int cgh_profile_read(double* ms, long long* launches, int reset);
+
+/* Work counts of the last cgh_progressive_hologram that used `workspace`. */
+typedef struct {
+    long long coef_rows_active;  /* nonzero rows of every layer's and level's coefficient square:
+                                    the K extent of the second contraction                    */
+    long long coef_rows_total;
+    long long ktiles_active;     /* K tiles the second contraction issued                     */
+    long long ktiles_total;
+    int ktile_rows;              /* rows per K tile                                            */
+    int split_k;                 /* K-range split of the second contraction                    */
+    double flops_first;          /* algorithmic real flops, first contraction (active rows)    */
+    double flops_second;         /* algorithmic real flops, second contraction:
+                                    8 * ny * nx * coef_rows_active                             */
+    double flops_second_issued;  /* 8 * ny * nx * ktiles_active * ktile_rows                   */
+} cgh_stats;
+
+/* Reads the occupancy flags back from `workspace` (same problem arguments as
+ * the forward call) and fills *stats [host].  Synchronises `stream`. */
+int cgh_workspace_stats(const void* workspace, int ny, int nx, int n_layers, int levels,
+                        int precision, cgh_stats* stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,20 @@ def worker_count():
     return max(1, min(n, 16))
 
 
+_SHARED = None  # (ys, xs, qs, ps, amps, lam, pitch, z) inherited by forked workers
+
+
+def _shared_chunk(bounds):
+    a, b = bounds
+    ys, xs, qs, ps, amps, lam, pitch, z = _SHARED
+    try:  # one BLAS thread per worker process: the pool already fills the cores
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        return _chunk_sum((ys[a:b], xs[a:b], qs, ps, amps, lam, pitch, z))
+    with threadpool_limits(limits=1):
+        return _chunk_sum((ys[a:b], xs[a:b], qs, ps, amps, lam, pitch, z))
+
+
 def direct_sum(amp, lam, pitch, z, ys, xs, workers=None):
     """Hologram values at pixels (ys[k], xs[k]) of the object field ``amp``.
 
@@ -85,6 +99,7 @@ def direct_sum(amp, lam, pitch, z, ys, xs, workers=None):
     pixel grid; returns complex128 of len(ys).  Points with zero amplitude
     contribute nothing and are skipped.
     """
+    global _SHARED
     amp = np.asarray(amp)
     amp = amp.astype(np.complex128 if np.iscomplexobj(amp) else np.float64)
     qs, ps = np.nonzero(amp)
@@ -101,10 +116,14 @@ def direct_sum(amp, lam, pitch, z, ys, xs, workers=None):
         return _chunk_sum((ys, xs, qs, ps, amps, lam, pitch, z))
     n_chunks = min(ys.shape[0], workers * 4)
     bounds = np.linspace(0, ys.shape[0], n_chunks + 1).astype(np.int64)
-    jobs = [(ys[a:b], xs[a:b], qs, ps, amps, lam, pitch, z)
-            for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
-    with get_context("fork").Pool(workers) as pool:
-        parts = pool.map(_chunk_sum, jobs)
+    jobs = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    # the point arrays reach the workers through fork, not through pickling
+    _SHARED = (ys, xs, qs, ps, amps, lam, pitch, z)
+    try:
+        with get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_shared_chunk, jobs)
+    finally:
+        _SHARED = None
     return np.concatenate(parts)
 
 

@@ -55,7 +55,32 @@ SIGNATURES = {
                                        _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp, _vp]),
     "cgh_fresnel_backpropagate": (_c_int, [_vp, _c_int, _c_int, _c_double, _c_double, _c_double,
                                            _c_int, _c_int, _vp, _sz, _vp, _vp]),
+    "cgh_profile_enable": (_c_int, [_c_int]),
+    "cgh_profile_read": (_c_int, [ctypes.POINTER(_c_double), ctypes.POINTER(ctypes.c_longlong),
+                                  _c_int]),
+    "cgh_workspace_stats": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp]),
 }
+
+STAGES = ("coef", "lut", "first", "list", "second", "reduce")
+
+
+class Stats(ctypes.Structure):
+    """Mirror of cgh_stats."""
+
+    _fields_ = [
+        ("coef_rows_active", ctypes.c_longlong),
+        ("coef_rows_total", ctypes.c_longlong),
+        ("ktiles_active", ctypes.c_longlong),
+        ("ktiles_total", ctypes.c_longlong),
+        ("ktile_rows", ctypes.c_int),
+        ("split_k", ctypes.c_int),
+        ("flops_first", ctypes.c_double),
+        ("flops_second", ctypes.c_double),
+        ("flops_second_issued", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class CghError(RuntimeError):
@@ -236,6 +261,28 @@ def fresnel_backpropagate(field, lam, pitch, z, adjoint=False, precision="fp32",
         ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out.data_ptr()), _stream()),
         "cgh_fresnel_backpropagate")
     return out
+
+
+# -------------------------------------------------------------- diagnostics
+
+def profile_enable(on=True):
+    _check(lib().cgh_profile_enable(1 if on else 0), "cgh_profile_enable")
+
+
+def profile_read(reset=True):
+    """{stage: (total ms, event pairs)} of the forward stages since the last reset."""
+    ms = (ctypes.c_double * len(STAGES))()
+    n = (ctypes.c_longlong * len(STAGES))()
+    _check(lib().cgh_profile_read(ms, n, 1 if reset else 0), "cgh_profile_read")
+    return {name: (ms[i], n[i]) for i, name in enumerate(STAGES)}
+
+
+def workspace_stats(workspace, ny, nx, n_layers=1, levels=3, precision="fp32"):
+    st = Stats()
+    _check(lib().cgh_workspace_stats(ctypes.c_void_p(workspace.data_ptr()), ny, nx, n_layers, levels,
+                                     _precision(precision), ctypes.byref(st), _stream()),
+           "cgh_workspace_stats")
+    return st.as_dict()
 
 
 # ----------------------------------------------------------------- autograd

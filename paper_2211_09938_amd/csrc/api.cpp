@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
+#include <vector>
 
 #include "../../include/cgh.h"
 #include "common.h"
@@ -135,6 +137,72 @@ int check_common(int n_layers, const uint8_t* layer_index, const double* z, cons
     return check_precision(precision);
 }
 
+
+// Per-stage HIP event timing of the forward call (diagnostics).
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    struct Pair { int stage; hipEvent_t a, b; };
+    std::vector<Pair> pending;
+    double ms[CGH_STAGE_COUNT] = {};
+    long long launches[CGH_STAGE_COUNT] = {};
+
+    hipEvent_t take() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+Profiler& profiler() {
+    static Profiler p;
+    return p;
+}
+
+// Records an event pair around one stage when profiling is on.
+struct StageTimer {
+    hipStream_t s;
+    int stage;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageTimer(hipStream_t st, int stg) : s(st), stage(stg) {
+        Profiler& p = profiler();
+        std::lock_guard<std::mutex> g(p.mu);
+        if (!p.on) return;
+        a = p.take();
+        b = p.take();
+        if (a && b && hipEventRecord(a, s) == hipSuccess) return;
+        if (a) p.pool.push_back(a);
+        if (b) p.pool.push_back(b);
+        a = b = nullptr;
+    }
+    void done() {
+        if (!a || !b) return;
+        if (hipEventRecord(b, s) != hipSuccess) return;  // destructor returns both to the pool
+        Profiler& p = profiler();
+        std::lock_guard<std::mutex> g(p.mu);
+        p.pending.push_back({stage, a, b});
+        a = b = nullptr;
+    }
+    ~StageTimer() {
+        if (a || b) {  // stage failed before done(): give the events back unrecorded
+            Profiler& p = profiler();
+            std::lock_guard<std::mutex> g(p.mu);
+            if (a) p.pool.push_back(a);
+            if (b) p.pool.push_back(b);
+        }
+    }
+};
+
+template <class F>
+hipError_t timed(hipStream_t s, int stage, F&& f) {
+    StageTimer t(s, stage);
+    hipError_t e = f();
+    if (e == hipSuccess) t.done();
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -214,25 +282,45 @@ int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, in
         make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
         uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
 
-        hipError_t e = cgh::launch_fill_u8(fl, (size_t)n_layers * lo.flags_layer, s);
+        const int acc = (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0;
+        const cgh::GemmShape sh{ny, nx, n_layers, levels, lo.split_k, lo.t_layer, lo.flags_layer};
+        float2* t = reinterpret_cast<float2*>(ws + lo.t);
+        int* klist = reinterpret_cast<int*>(ws + lo.ktiles);
+        float2* partial = reinterpret_cast<float2*>(ws + lo.partial);
+        float2* out = reinterpret_cast<float2*>(hologram);
+
+        hipError_t e = timed(s, CGH_STAGE_COEF, [&] {
+            hipError_t r = cgh::launch_fill_u8(fl, (size_t)n_layers * lo.flags_layer, s);
+            if (r != hipSuccess) return r;
+            return cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels,
+                                        thr, precision, ws + lo.coef, ws + lo.coef_lo, fl,
+                                        lo.flags_layer, s);
+        });
         if (e == hipSuccess)
-            e = cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels, thr,
-                                     precision, ws + lo.coef, ws + lo.coef_lo, fl, lo.flags_layer, s);
+            e = timed(s, CGH_STAGE_LUT, [&] {
+                hipError_t r = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
+                                                precision, ws + lo.lut_x, ws + lo.lut_x_lo, s);
+                if (r != hipSuccess) return r;
+                return cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im,
+                                        precision, ws + lo.lut_y, ws + lo.lut_y_lo, s);
+            });
         if (e == hipSuccess)
-            e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im, precision,
-                                 ws + lo.lut_x, ws + lo.lut_x_lo, s);
+            e = timed(s, CGH_STAGE_FIRST, [&] {
+                return cgh::launch_forward_stage1_f32(
+                    sh, reinterpret_cast<const float*>(ws + lo.coef),
+                    reinterpret_cast<const float*>(ws + lo.lut_x), t, fl, s);
+            });
         if (e == hipSuccess)
-            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im, precision,
-                                 ws + lo.lut_y, ws + lo.lut_y_lo, s);
-        if (e == hipSuccess) {
-            cgh::GemmShape sh{ny, nx, n_layers, levels, lo.split_k, lo.t_layer, lo.flags_layer};
-            e = cgh::launch_forward_f32(
-                sh, reinterpret_cast<const float*>(ws + lo.coef),
-                reinterpret_cast<const float*>(ws + lo.lut_x),
-                reinterpret_cast<const float*>(ws + lo.lut_y), reinterpret_cast<float2*>(ws + lo.t),
-                fl, reinterpret_cast<int*>(ws + lo.ktiles), reinterpret_cast<float2*>(ws + lo.partial),
-                reinterpret_cast<float2*>(hologram), (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0, 1, s);
-        }
+            e = timed(s, CGH_STAGE_LIST, [&] { return cgh::launch_ktile_list(sh, fl, 1, klist, s); });
+        if (e == hipSuccess)
+            e = timed(s, CGH_STAGE_SECOND, [&] {
+                return cgh::launch_forward_stage2_f32(
+                    sh, reinterpret_cast<const float*>(ws + lo.lut_y), t, fl, klist, partial, out,
+                    acc, s);
+            });
+        if (e == hipSuccess && lo.split_k > 1)
+            e = timed(s, CGH_STAGE_REDUCE,
+                      [&] { return cgh::launch_reduce_partial(sh, partial, out, acc, s); });
         return hip_status(e);
     } catch (...) {
         return CGH_ERROR_HIP;
@@ -308,6 +396,91 @@ int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lamb
                                          reinterpret_cast<float2*>(field_out), adjoint ? 1 : 0,
                                          (float)(1.0 / ((double)ny * (double)nx)), s);
         return hip_status(e);
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
+int cgh_profile_enable(int on) {
+    Profiler& p = profiler();
+    std::lock_guard<std::mutex> g(p.mu);
+    p.on = on != 0;
+    return CGH_SUCCESS;
+}
+
+int cgh_profile_read(double* ms, long long* launches, int reset) {
+    try {
+        Profiler& p = profiler();
+        std::lock_guard<std::mutex> g(p.mu);
+        int status = CGH_SUCCESS;
+        for (auto& pr : p.pending) {
+            float t = 0.f;
+            hipError_t e = hipEventSynchronize(pr.b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, pr.a, pr.b);
+            if (e != hipSuccess) {
+                status = hip_status(e);
+            } else {
+                p.ms[pr.stage] += t;
+                p.launches[pr.stage] += 1;
+            }
+            p.pool.push_back(pr.a);
+            p.pool.push_back(pr.b);
+        }
+        p.pending.clear();
+        for (int k = 0; k < CGH_STAGE_COUNT; ++k) {
+            if (ms) ms[k] = p.ms[k];
+            if (launches) launches[k] = p.launches[k];
+            if (reset) { p.ms[k] = 0.0; p.launches[k] = 0; }
+        }
+        return status;
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
+int cgh_workspace_stats(const void* workspace, int ny, int nx, int n_layers, int levels,
+                        int precision, cgh_stats* stats, void* stream) {
+    try {
+        int st = check_shape(ny, nx, levels);
+        if (st) return st;
+        if (!stats || !workspace || n_layers < 1 || n_layers > CGH_MAX_LAYERS) return CGH_ERROR_INVALID_VALUE;
+        if ((st = check_precision(precision))) return st;
+        std::memset(stats, 0, sizeof(*stats));
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
+        hipStream_t s = (hipStream_t)stream;
+        const char* ws = static_cast<const char*>(workspace);
+        std::vector<uint8_t> fl((size_t)n_layers * lo.flags_layer);
+        int count = 0;
+        hipError_t e = hipMemcpyAsync(fl.data(), ws + lo.flags, fl.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&count, ws + lo.ktiles, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e);
+        long long rows = 0, rows_total = 0;
+        double k1 = 0.0;
+        for (int d = 0; d < n_layers; ++d) {
+            for (int l = 1; l <= levels; ++l) {
+                const uint8_t* fr = fl.data() + (size_t)d * lo.flags_layer + cgh::flag_level_off(ny, nx, l);
+                const int sy = cgh::band_side(ny, l), sx = cgh::band_side(nx, l);
+                const int nyl = ny >> l, nxl = nx >> l;
+                for (int r = 0; r < sy; ++r) {
+                    rows_total += 1;
+                    if (!fr[r]) continue;
+                    rows += 1;
+                    k1 += (l < levels && r < nyl) ? (double)(sx - nxl) : (double)sx;
+                }
+            }
+        }
+        stats->coef_rows_active = rows;
+        stats->coef_rows_total = rows_total;
+        stats->ktiles_active = count;
+        stats->ktiles_total = lo.n_ktiles;
+        stats->ktile_rows = cgh::kTileK;
+        stats->split_k = lo.split_k;
+        stats->flops_first = 4.0 * (double)nx * k1;
+        stats->flops_second = 8.0 * (double)ny * (double)nx * (double)rows;
+        stats->flops_second_issued = 8.0 * (double)ny * (double)nx * (double)count * cgh::kTileK;
+        return CGH_SUCCESS;
     } catch (...) {
         return CGH_ERROR_HIP;
     }

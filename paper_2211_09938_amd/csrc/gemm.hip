@@ -587,10 +587,8 @@ int second_stage_ktiles(int ny, int levels, int layers) {
     return per * layers;
 }
 
-hipError_t launch_forward_f32(const GemmShape& sh, const float* coef, const float* lut_x,
-                              const float* lut_y, float2* t, const uint8_t* flags, int* klist,
-                              float2* partial, float2* out, int accumulate, int use_flags,
-                              hipStream_t s) {
+hipError_t launch_forward_stage1_f32(const GemmShape& sh, const float* coef, const float* lut_x,
+                                     float2* t, const uint8_t* flags, hipStream_t s) {
     int cols[kMaxLevels + 1];
     for (int l = 1; l <= sh.levels; ++l) cols[l] = sh.nx;
     FwdS1 p1{};
@@ -604,13 +602,19 @@ hipError_t launch_forward_f32(const GemmShape& sh, const float* coef, const floa
     p1.t_layer = sh.t_layer;
     p1.flags_layer = sh.flags_layer;
     p1.g = make_grid(sh.ny, sh.levels, cols);
-    hipError_t e = run(p1, dim3(p1.g.cum[sh.levels] * sh.layers), s);
-    if (e != hipSuccess) return e;
+    return run(p1, dim3(p1.g.cum[sh.levels] * sh.layers), s);
+}
 
+hipError_t launch_ktile_list(const GemmShape& sh, const uint8_t* flags, int use_flags, int* klist,
+                             hipStream_t s) {
     hipLaunchKernelGGL(ktile_list_kernel, dim3(1), dim3(1024), 0, s, flags, sh.ny, sh.nx,
                        sh.levels, sh.layers, sh.flags_layer, use_flags, klist);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipGetLastError();
+}
 
+hipError_t launch_forward_stage2_f32(const GemmShape& sh, const float* lut_y, const float2* t,
+                                     const uint8_t* flags, const int* klist, float2* partial,
+                                     float2* out, int accumulate, hipStream_t s) {
     FwdS2 p2{};
     p2.lut = lut_y;
     p2.t = t;
@@ -627,17 +631,18 @@ hipError_t launch_forward_f32(const GemmShape& sh, const float* coef, const floa
     p2.t_layer = sh.t_layer;
     p2.flags_layer = sh.flags_layer;
     const int tiles = ((sh.ny + BM - 1) / BM) * p2.ctiles;
-    e = run(p2, dim3(tiles, sh.split_k), s);
-    if (e != hipSuccess) return e;
-    if (sh.split_k > 1) {
-        const size_t n = (size_t)sh.ny * sh.nx;
-        size_t blocks = (n + 255) / 256;
-        if (blocks > 8192) blocks = 8192;
-        hipLaunchKernelGGL(reduce_partial_kernel, dim3((unsigned)blocks), dim3(256), 0, s, partial,
-                           sh.split_k, n, accumulate, out);
-        e = hipGetLastError();
-    }
-    return e;
+    return run(p2, dim3(tiles, sh.split_k), s);
+}
+
+hipError_t launch_reduce_partial(const GemmShape& sh, const float2* partial, float2* out,
+                                 int accumulate, hipStream_t s) {
+    if (sh.split_k <= 1) return hipSuccess;
+    const size_t n = (size_t)sh.ny * sh.nx;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(reduce_partial_kernel, dim3((unsigned)blocks), dim3(256), 0, s, partial,
+                       sh.split_k, n, accumulate, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_backward_f32(const GemmShape& sh, const float2* grad_h, const float* lut_x,
