@@ -157,7 +157,8 @@ def main():
         "gpoint_pixel_per_s": holo_s * points * points / 1e9,
         "roofline": {
             "bound": "mfma",
-            "kernel": "second contraction (cgemm_f32_kernel<FwdS2>)",
+            "kernel": ("second contraction (cgemm_f32_kernel<FwdS2>)" if args.precision == "fp32"
+                       else "second contraction (cgemm_split_kernel<FwdS2>)"),
             "achieved": achieved,
             "peak": peak,
             "unit": "TFLOP/s",

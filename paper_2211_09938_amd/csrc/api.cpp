@@ -37,7 +37,6 @@ int check_shape(int ny, int nx, int levels) {
 
 int check_precision(int precision) {
     if (precision < CGH_FP32 || precision > CGH_FP16_SPLIT) return CGH_ERROR_INVALID_VALUE;
-    if (precision != CGH_FP32) return CGH_ERROR_UNSUPPORTED;
     return CGH_SUCCESS;
 }
 
@@ -283,7 +282,8 @@ int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, in
         uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
 
         const int acc = (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0;
-        const cgh::GemmShape sh{ny, nx, n_layers, levels, lo.split_k, lo.t_layer, lo.flags_layer};
+        const cgh::GemmShape sh{ny, nx, n_layers, levels, lo.split_k, precision, lo.t_layer,
+                                 lo.flags_layer};
         float2* t = reinterpret_cast<float2*>(ws + lo.t);
         int* klist = reinterpret_cast<int*>(ws + lo.ktiles);
         float2* partial = reinterpret_cast<float2*>(ws + lo.partial);
@@ -293,20 +293,20 @@ int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, in
             hipError_t r = cgh::launch_fill_u8(fl, (size_t)n_layers * lo.flags_layer, s);
             if (r != hipSuccess) return r;
             return cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels,
-                                        thr, precision, ws + lo.coef, ws + lo.coef_lo, fl,
+                                        thr, cgh::P_FP32, ws + lo.coef, nullptr, fl,
                                         lo.flags_layer, s);
         });
         if (e == hipSuccess)
             e = timed(s, CGH_STAGE_LUT, [&] {
                 hipError_t r = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
-                                                precision, ws + lo.lut_x, ws + lo.lut_x_lo, s);
+                                                cgh::P_FP32, ws + lo.lut_x, nullptr, s);
                 if (r != hipSuccess) return r;
                 return cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im,
-                                        precision, ws + lo.lut_y, ws + lo.lut_y_lo, s);
+                                        cgh::P_FP32, ws + lo.lut_y, nullptr, s);
             });
         if (e == hipSuccess)
             e = timed(s, CGH_STAGE_FIRST, [&] {
-                return cgh::launch_forward_stage1_f32(
+                return cgh::launch_forward_stage1(
                     sh, reinterpret_cast<const float*>(ws + lo.coef),
                     reinterpret_cast<const float*>(ws + lo.lut_x), t, fl, s);
             });
@@ -314,7 +314,7 @@ int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, in
             e = timed(s, CGH_STAGE_LIST, [&] { return cgh::launch_ktile_list(sh, fl, 1, klist, s); });
         if (e == hipSuccess)
             e = timed(s, CGH_STAGE_SECOND, [&] {
-                return cgh::launch_forward_stage2_f32(
+                return cgh::launch_forward_stage2(
                     sh, reinterpret_cast<const float*>(ws + lo.lut_y), t, fl, klist, partial, out,
                     acc, s);
             });
@@ -353,8 +353,8 @@ int cgh_hologram_backward(const float* grad_hologram, const uint8_t* layer_index
             e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im, cgh::P_FP32,
                                  ws + lo.lut_y, nullptr, s);
         if (e == hipSuccess) {
-            cgh::GemmShape sh{ny, nx, n_layers, levels, 1, lo.t_layer, lo.flags_layer};
-            e = cgh::launch_backward_f32(sh, reinterpret_cast<const float2*>(grad_hologram),
+            cgh::GemmShape sh{ny, nx, n_layers, levels, 1, precision, lo.t_layer, lo.flags_layer};
+            e = cgh::launch_backward(sh, reinterpret_cast<const float2*>(grad_hologram),
                                          reinterpret_cast<const float*>(ws + lo.lut_x),
                                          reinterpret_cast<const float*>(ws + lo.lut_y),
                                          reinterpret_cast<float2*>(ws + lo.t),
@@ -390,11 +390,11 @@ int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lamb
         if (e == hipSuccess)
             e = cgh::launch_luts(ny, 1, 1, 0, &c, &one, &zero, cgh::P_FP32, lut0_y, nullptr, s);
         if (e == hipSuccess)
-            e = cgh::launch_backprop_f32(ny, nx, lut0_x, lut0_y,
+            e = cgh::launch_backprop(ny, nx, lut0_x, lut0_y,
                                          reinterpret_cast<const float2*>(field_in),
                                          reinterpret_cast<float2*>(ws + lo.t),
                                          reinterpret_cast<float2*>(field_out), adjoint ? 1 : 0,
-                                         (float)(1.0 / ((double)ny * (double)nx)), s);
+                                         (float)(1.0 / ((double)ny * (double)nx)), precision, s);
         return hip_status(e);
     } catch (...) {
         return CGH_ERROR_HIP;

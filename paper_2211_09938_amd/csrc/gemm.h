@@ -11,6 +11,7 @@ constexpr int kTileK = 16;   // K tile
 
 struct GemmShape {
     int ny, nx, layers, levels, split_k;
+    int precision;       // cgh_precision of both contractions
     size_t t_layer;      // complex elements of T per layer
     size_t flags_layer;  // flag bytes per layer
 };
@@ -18,21 +19,21 @@ struct GemmShape {
 // Candidate K tiles of the second forward stage (list capacity).
 int second_stage_ktiles(int ny, int levels, int layers);
 
-hipError_t launch_forward_stage1_f32(const GemmShape& sh, const float* coef, const float* lut_x,
+hipError_t launch_forward_stage1(const GemmShape& sh, const float* coef, const float* lut_x,
                                      float2* t, const uint8_t* flags, hipStream_t s);
 hipError_t launch_ktile_list(const GemmShape& sh, const uint8_t* flags, int use_flags, int* klist,
                              hipStream_t s);
-hipError_t launch_forward_stage2_f32(const GemmShape& sh, const float* lut_y, const float2* t,
+hipError_t launch_forward_stage2(const GemmShape& sh, const float* lut_y, const float2* t,
                                      const uint8_t* flags, const int* klist, float2* partial,
                                      float2* out, int accumulate, hipStream_t s);
 hipError_t launch_reduce_partial(const GemmShape& sh, const float2* partial, float2* out,
                                  int accumulate, hipStream_t s);
 
-hipError_t launch_backward_f32(const GemmShape& sh, const float2* grad_h, const float* lut_x,
+hipError_t launch_backward(const GemmShape& sh, const float2* grad_h, const float* lut_x,
                                const float* lut_y, float2* q, float* gcoef, hipStream_t s);
 
-hipError_t launch_backprop_f32(int ny, int nx, const float* lut0_x, const float* lut0_y,
-                               const float2* in, float2* tmp, float2* out, int adjoint, float scale,
-                               hipStream_t s);
+hipError_t launch_backprop(int ny, int nx, const float* lut0_x, const float* lut0_y,
+                           const float2* in, float2* tmp, float2* out, int adjoint, float scale,
+                           int precision, hipStream_t s);
 
 }  // namespace cgh

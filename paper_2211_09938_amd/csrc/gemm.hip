@@ -187,6 +187,201 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f32_kernel(Pb pb) {
             }
 }
 
+// ------------------------------------------------------ split-precision kernel
+// Same tiles, loaders and epilogue as the FP32 kernel; every staged FP32 operand
+// value v is split into hi = round16(v) and lo = round16(v - hi) (bf16 or fp16,
+// round to nearest even) and each real product a*b is formed as
+// a_hi*b_hi + a_hi*b_lo + a_lo*b_hi on v_mfma_f32_32x32x16_{bf16,f16} with FP32
+// accumulation.  LDS holds, per component (re_hi, re_lo, im_hi, im_lo), a
+// [row][k] tile with k contiguous so that each MFMA fragment (8 consecutive k
+// of one row) is one 16-byte LDS read.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int P>
+__device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
+    if constexpr (P == P_BF16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                        __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(halfx8, a),
+                                                       __builtin_bit_cast(halfx8, b), c, 0, 0, 0);
+}
+
+template <int P>
+__device__ __forceinline__ void split_pair(float v, unsigned& hi, unsigned& lo) {
+    if constexpr (P == P_BF16) {
+        const __bf16 h = (__bf16)v;
+        const __bf16 l = (__bf16)(v - (float)h);
+        hi = __builtin_bit_cast(unsigned short, h);
+        lo = __builtin_bit_cast(unsigned short, l);
+    } else {
+        const _Float16 h = (_Float16)v;
+        const _Float16 l = (_Float16)(v - (float)h);
+        hi = __builtin_bit_cast(unsigned short, h);
+        lo = __builtin_bit_cast(unsigned short, l);
+    }
+}
+
+// 8 values -> packed hi and lo halves (4 x 32-bit each).
+template <int P>
+__device__ __forceinline__ void split8(const float* v, u32x4& hi, u32x4& lo) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        unsigned h0, l0, h1, l1;
+        split_pair<P>(v[2 * q], h0, l0);
+        split_pair<P>(v[2 * q + 1], h1, l1);
+        hi[q] = h0 | (h1 << 16);
+        lo[q] = l0 | (l1 << 16);
+    }
+}
+
+constexpr int SRS = 24;  // LDS row stride in 16-bit elements (16 k + 8 pad = 48 bytes)
+
+template <class Pb, int P>
+__global__ __launch_bounds__(NT) void cgemm_split_kernel(Pb pb) {
+    constexpr int NCA = Pb::A_CPLX ? 4 : 2;
+    constexpr int NCB = Pb::B_CPLX ? 4 : 2;
+    __shared__ __attribute__((aligned(16))) uint16_t As[NCA][BM][SRS];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[NCB][BN][SRS];
+    typename Pb::Ctx cx;
+    if (!pb.setup(cx)) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int l32 = lane & 31, kq = 8 * (lane >> 5);
+
+    floatx16 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) { cr[i][j][r] = 0.f; ci[i][j][r] = 0.f; }
+
+    // staging: each thread owns 8 consecutive k of one row of A and of B
+    const int ra_row = Pb::A_KFAST ? (tid >> 1) : (tid & 127);
+    const int ra_k = Pb::A_KFAST ? 8 * (tid & 1) : 8 * (tid >> 7);
+    const int rb_row = Pb::B_KFAST ? (tid >> 1) : (tid & 127);
+    const int rb_k = Pb::B_KFAST ? 8 * (tid & 1) : 8 * (tid >> 7);
+    float2 ra[8], rb[8];
+    const int nk = pb.nk(cx);
+
+    auto load = [&](int kt) {
+        const typename Pb::KT kd = pb.kt(cx, kt);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ra[e] = pb.a(cx, kd, ra_row, ra_k + e);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) rb[e] = pb.b(cx, kd, rb_k + e, rb_row);
+    };
+    auto stash = [&]() {
+        float v[8];
+        u32x4 hi, lo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = ra[e].x;
+        split8<P>(v, hi, lo);
+        *reinterpret_cast<u32x4*>(&As[0][ra_row][ra_k]) = hi;
+        *reinterpret_cast<u32x4*>(&As[1][ra_row][ra_k]) = lo;
+        if constexpr (Pb::A_CPLX) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = ra[e].y;
+            split8<P>(v, hi, lo);
+            *reinterpret_cast<u32x4*>(&As[2][ra_row][ra_k]) = hi;
+            *reinterpret_cast<u32x4*>(&As[3][ra_row][ra_k]) = lo;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = rb[e].x;
+        split8<P>(v, hi, lo);
+        *reinterpret_cast<u32x4*>(&Bs[0][rb_row][rb_k]) = hi;
+        *reinterpret_cast<u32x4*>(&Bs[1][rb_row][rb_k]) = lo;
+        if constexpr (Pb::B_CPLX) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = rb[e].y;
+            split8<P>(v, hi, lo);
+            *reinterpret_cast<u32x4*>(&Bs[2][rb_row][rb_k]) = hi;
+            *reinterpret_cast<u32x4*>(&Bs[3][rb_row][rb_k]) = lo;
+        }
+    };
+
+    if (nk > 0) {
+        load(0);
+        stash();
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) load(kt + 1);
+        u32x4 a[2][NCA], b[2][NCB];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int c = 0; c < NCA; ++c)
+                a[i][c] = *reinterpret_cast<const u32x4*>(&As[c][wm + 32 * i + l32][kq]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int c = 0; c < NCB; ++c)
+                b[j][c] = *reinterpret_cast<const u32x4*>(&Bs[c][wn + 32 * j + l32][kq]);
+        // three-term product of split operands: x_hi*y_hi + x_hi*y_lo + x_lo*y_hi
+        auto prod3 = [&](floatx16 acc, const u32x4& xh, const u32x4& xl, const u32x4& yh,
+                         const u32x4& yl) {
+            acc = mfma16<P>(xh, yh, acc);
+            acc = mfma16<P>(xh, yl, acc);
+            acc = mfma16<P>(xl, yh, acc);
+            return acc;
+        };
+        if constexpr (Pb::A_CPLX && Pb::B_CPLX) {
+            u32x4 nah[2], nal[2];  // -A_im: flip the sign bit of every half
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                nah[i] = a[i][2] ^ 0x80008000u;
+                nal[i] = a[i][3] ^ 0x80008000u;
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    cr[i][j] = prod3(cr[i][j], a[i][0], a[i][1], b[j][0], b[j][1]);
+                    cr[i][j] = prod3(cr[i][j], nah[i], nal[i], b[j][2], b[j][3]);
+                    if constexpr (!Pb::OUT_REAL) {
+                        ci[i][j] = prod3(ci[i][j], a[i][0], a[i][1], b[j][2], b[j][3]);
+                        ci[i][j] = prod3(ci[i][j], a[i][2], a[i][3], b[j][0], b[j][1]);
+                    }
+                }
+        } else if constexpr (Pb::A_CPLX) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    cr[i][j] = prod3(cr[i][j], a[i][0], a[i][1], b[j][0], b[j][1]);
+                    ci[i][j] = prod3(ci[i][j], a[i][2], a[i][3], b[j][0], b[j][1]);
+                }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    cr[i][j] = prod3(cr[i][j], a[i][0], a[i][1], b[j][0], b[j][1]);
+                    ci[i][j] = prod3(ci[i][j], a[i][0], a[i][1], b[j][2], b[j][3]);
+                }
+        }
+        __syncthreads();
+        if (kt + 1 < nk) stash();
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int n = wn + 32 * j + l32;
+                pb.store(cx, m, n, cr[i][j][r], ci[i][j][r]);
+            }
+}
+
 // ------------------------------------------------------------ operand helpers
 // Fringe table entry for pixel `pix` of coefficient column/row `coef` of a level
 // with n_l coefficients per band: band = coef >= n_l, offset pix - (coef mod n_l) 2^l.
@@ -560,9 +755,14 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const float2* __res
 }
 
 template <class Pb>
-hipError_t run(const Pb& pb, dim3 grid, hipStream_t s) {
+hipError_t run(const Pb& pb, dim3 grid, hipStream_t s, int precision = P_FP32) {
     if (grid.x == 0 || grid.y == 0 || grid.z == 0) return hipSuccess;
-    hipLaunchKernelGGL(cgemm_f32_kernel<Pb>, grid, dim3(NT), 0, s, pb);
+    if (precision == P_BF16)
+        hipLaunchKernelGGL((cgemm_split_kernel<Pb, P_BF16>), grid, dim3(NT), 0, s, pb);
+    else if (precision == P_FP16)
+        hipLaunchKernelGGL((cgemm_split_kernel<Pb, P_FP16>), grid, dim3(NT), 0, s, pb);
+    else
+        hipLaunchKernelGGL(cgemm_f32_kernel<Pb>, grid, dim3(NT), 0, s, pb);
     return hipGetLastError();
 }
 
@@ -587,7 +787,7 @@ int second_stage_ktiles(int ny, int levels, int layers) {
     return per * layers;
 }
 
-hipError_t launch_forward_stage1_f32(const GemmShape& sh, const float* coef, const float* lut_x,
+hipError_t launch_forward_stage1(const GemmShape& sh, const float* coef, const float* lut_x,
                                      float2* t, const uint8_t* flags, hipStream_t s) {
     int cols[kMaxLevels + 1];
     for (int l = 1; l <= sh.levels; ++l) cols[l] = sh.nx;
@@ -602,7 +802,7 @@ hipError_t launch_forward_stage1_f32(const GemmShape& sh, const float* coef, con
     p1.t_layer = sh.t_layer;
     p1.flags_layer = sh.flags_layer;
     p1.g = make_grid(sh.ny, sh.levels, cols);
-    return run(p1, dim3(p1.g.cum[sh.levels] * sh.layers), s);
+    return run(p1, dim3(p1.g.cum[sh.levels] * sh.layers), s, sh.precision);
 }
 
 hipError_t launch_ktile_list(const GemmShape& sh, const uint8_t* flags, int use_flags, int* klist,
@@ -612,7 +812,7 @@ hipError_t launch_ktile_list(const GemmShape& sh, const uint8_t* flags, int use_
     return hipGetLastError();
 }
 
-hipError_t launch_forward_stage2_f32(const GemmShape& sh, const float* lut_y, const float2* t,
+hipError_t launch_forward_stage2(const GemmShape& sh, const float* lut_y, const float2* t,
                                      const uint8_t* flags, const int* klist, float2* partial,
                                      float2* out, int accumulate, hipStream_t s) {
     FwdS2 p2{};
@@ -631,7 +831,7 @@ hipError_t launch_forward_stage2_f32(const GemmShape& sh, const float* lut_y, co
     p2.t_layer = sh.t_layer;
     p2.flags_layer = sh.flags_layer;
     const int tiles = ((sh.ny + BM - 1) / BM) * p2.ctiles;
-    return run(p2, dim3(tiles, sh.split_k), s);
+    return run(p2, dim3(tiles, sh.split_k), s, sh.precision);
 }
 
 hipError_t launch_reduce_partial(const GemmShape& sh, const float2* partial, float2* out,
@@ -645,7 +845,7 @@ hipError_t launch_reduce_partial(const GemmShape& sh, const float2* partial, flo
     return hipGetLastError();
 }
 
-hipError_t launch_backward_f32(const GemmShape& sh, const float2* grad_h, const float* lut_x,
+hipError_t launch_backward(const GemmShape& sh, const float2* grad_h, const float* lut_x,
                                const float* lut_y, float2* q, float* gcoef, hipStream_t s) {
     int cols[kMaxLevels + 1];
     for (int l = 1; l <= sh.levels; ++l) cols[l] = sh.nx;
@@ -658,7 +858,7 @@ hipError_t launch_backward_f32(const GemmShape& sh, const float2* grad_h, const 
     p1.L = sh.levels;
     p1.t_layer = sh.t_layer;
     p1.g = make_grid(sh.ny, sh.levels, cols);
-    hipError_t e = run(p1, dim3(p1.g.cum[sh.levels] * sh.layers), s);
+    hipError_t e = run(p1, dim3(p1.g.cum[sh.levels] * sh.layers), s, sh.precision);
     if (e != hipSuccess) return e;
     for (int l = 1; l <= sh.levels; ++l) cols[l] = band_side(sh.nx, l);
     BwdS2 p2{};
@@ -670,12 +870,12 @@ hipError_t launch_backward_f32(const GemmShape& sh, const float2* grad_h, const 
     p2.L = sh.levels;
     p2.t_layer = sh.t_layer;
     p2.g = make_grid(sh.ny, sh.levels, cols);
-    return run(p2, dim3(p2.g.cum[sh.levels] * sh.layers), s);
+    return run(p2, dim3(p2.g.cum[sh.levels] * sh.layers), s, sh.precision);
 }
 
-hipError_t launch_backprop_f32(int ny, int nx, const float* lut0_x, const float* lut0_y,
-                               const float2* in, float2* tmp, float2* out, int adjoint, float scale,
-                               hipStream_t s) {
+hipError_t launch_backprop(int ny, int nx, const float* lut0_x, const float* lut0_y,
+                           const float2* in, float2* tmp, float2* out, int adjoint, float scale,
+                           int precision, hipStream_t s) {
     PropS1 p1{};
     p1.lut_y = lut0_y;
     p1.in = in;
@@ -684,7 +884,7 @@ hipError_t launch_backprop_f32(int ny, int nx, const float* lut0_x, const float*
     p1.nx = nx;
     p1.conj = adjoint ? 0 : 1;
     p1.ctiles = (nx + BN - 1) / BN;
-    hipError_t e = run(p1, dim3(((ny + BM - 1) / BM) * p1.ctiles), s);
+    hipError_t e = run(p1, dim3(((ny + BM - 1) / BM) * p1.ctiles), s, precision);
     if (e != hipSuccess) return e;
     PropS2 p2{};
     p2.lut_x = lut0_x;
@@ -695,7 +895,7 @@ hipError_t launch_backprop_f32(int ny, int nx, const float* lut0_x, const float*
     p2.conj = adjoint ? 0 : 1;
     p2.ctiles = (nx + BN - 1) / BN;
     p2.scale = scale;
-    return run(p2, dim3(((ny + BM - 1) / BM) * p2.ctiles), s);
+    return run(p2, dim3(((ny + BM - 1) / BM) * p2.ctiles), s, precision);
 }
 
 }  // namespace cgh

@@ -114,3 +114,20 @@ def test_autograd_loss_gradient_matches_oracle_chain():
                                                 s.pitch, 3, s.saliency.astype(np.float64))
     assert abs(float(loss) - ref_loss) <= CHAIN_TOL * ref_loss
     assert rel_l2(obj.grad.cpu().numpy(), ref_grad) <= CHAIN_TOL
+
+
+@pytest.mark.parametrize("precision", ["bf16_split", "fp16_split"])
+def test_split_precision_backward_and_backprop(precision):
+    import torch
+
+    s = scenes.random_scene(310, 40, 56, planes=2)
+    g = _cot(5, 40, 56)
+    ga = cgh().hologram_backward(to_dev(g), s.z, s.lam, s.pitch, 3, to_dev(s.saliency),
+                                 to_dev(s.layer), precision=precision)
+    u = cgh().fresnel_backpropagate(to_dev(g), s.lam, s.pitch, 0.2, precision=precision)
+    torch.cuda.synchronize()
+    ref = gradient.grad_object(g.astype(np.complex128), s.z, s.lam, s.pitch, 3,
+                               s.saliency.astype(np.float64), s.layer)
+    ref_u = gradient.fresnel_backpropagate(g.astype(np.complex128), s.lam, s.pitch, 0.2)
+    assert rel_l2(ga.cpu().numpy(), ref) <= 1e-3
+    assert rel_l2(u.cpu().numpy(), ref_u) <= 1e-3

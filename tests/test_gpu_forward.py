@@ -177,3 +177,39 @@ def test_invalid_workspace_leaves_output_untouched():
     assert st == 5  # CGH_ERROR_WORKSPACE
     torch.cuda.synchronize()
     assert torch.all(out == (3.0 + 1.0j))
+
+
+# ------------------------------------------------------------ split precision
+SPLIT_TOL = 1e-3  # the stated bar for the BF16/FP16 split forms
+
+
+@pytest.mark.parametrize("precision", ["bf16_split", "fp16_split"])
+@pytest.mark.parametrize("case", ["tiny", "ragged", "plane1024", "depth2048"])
+def test_split_precision_parity(precision, case):
+    if case == "tiny":
+        s = scenes.tiny()
+        pix = None
+    elif case == "ragged":
+        s = scenes.random_scene(120, 72, 136, planes=2)
+        pix = None
+    elif case == "plane1024":
+        s = scenes.plane_1024()
+        pix = sample_pixels(1024, 1024, seed=2, n_random=96)
+    else:
+        s = scenes.depth_2048()
+        pix = sample_pixels(2048, 2048, seed=3, n_random=64, crop=8)
+    h = gpu_hologram(s, precision=precision)
+    ref = oracle_hologram(s, pixels=pix)
+    got = h if pix is None else h[pix[0], pix[1]]
+    err = rel_l2(got, ref)
+    print(f"{precision} {case}: rel-L2 {err:.3e}")
+    assert err <= SPLIT_TOL
+
+
+@pytest.mark.parametrize("precision", ["bf16_split", "fp16_split"])
+def test_split_precision_edge_cases(precision):
+    s = scenes.random_scene(16, 40, 24, planes=1, levels=2)
+    assert rel_l2(gpu_hologram(s, precision=precision), oracle_hologram(s)) <= SPLIT_TOL
+    z = scenes.random_scene(17, 64, 64)
+    z.obj[:] = 0
+    assert np.all(gpu_hologram(z, precision=precision) == 0)
