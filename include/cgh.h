@@ -162,12 +162,12 @@ int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lamb
 
 /* Stages of cgh_progressive_hologram, in launch order. */
 enum {
-    CGH_STAGE_COEF = 0,    /* flag clear + fused layer split / Haar / saliency / masking */
-    CGH_STAGE_LUT = 1,     /* FP64 fringe tables, both axes                               */
-    CGH_STAGE_FIRST = 2,   /* first contraction  T_{d,l} = Cb_{d,l} Fx_{d,l}^T            */
-    CGH_STAGE_LIST = 3,    /* compaction of the second contraction's active K tiles       */
-    CGH_STAGE_SECOND = 4,  /* second contraction H = sum_{d,l} Fy_{d,l} T_{d,l}           */
-    CGH_STAGE_REDUCE = 5,  /* split-K partial sum (only when the K range is split)        */
+    CGH_STAGE_COEF = 0,    /* flag clear + fused layer split / Haar / saliency / masking   */
+    CGH_STAGE_LUT = 1,     /* FP64 fringe tables, both axes                                 */
+    CGH_STAGE_PLAN = 2,    /* active row/column lists, plan, K-contiguous operand panels    */
+    CGH_STAGE_FIRST = 3,   /* first contraction  T_{d,l} = Cb_{d,l} Fx_{d,l}^T (active rows) */
+    CGH_STAGE_SECOND = 4,  /* second contraction H = sum_{d,l} Fy_{d,l} T_{d,l}             */
+    CGH_STAGE_REDUCE = 5,  /* split-K partial sum (only when the K range is split)          */
     CGH_STAGE_COUNT = 6
 };
 
@@ -187,18 +187,19 @@ typedef struct {
     long long coef_rows_active;  /* nonzero rows of every layer's and level's coefficient square:
                                     the K extent of the second contraction                    */
     long long coef_rows_total;
-    long long ktiles_active;     /* K tiles the second contraction issued                     */
-    long long ktiles_total;
-    int ktile_rows;              /* rows per K tile                                            */
+    long long k_padded;          /* K the second contraction ran over (segments padded to 16)  */
+    long long k_total;           /* K of the dense form (every row of every level and layer)   */
+    int k_tile;                  /* K tile of the contractions                                 */
     int split_k;                 /* K-range split of the second contraction                    */
-    double flops_first;          /* algorithmic real flops, first contraction (active rows)    */
+    double flops_first;          /* algorithmic real flops, first contraction:
+                                    4 * nx * sum over (layer, level) of active rows x columns  */
     double flops_second;         /* algorithmic real flops, second contraction:
                                     8 * ny * nx * coef_rows_active                             */
-    double flops_second_issued;  /* 8 * ny * nx * ktiles_active * ktile_rows                   */
+    double flops_second_issued;  /* 8 * ny * nx * k_padded                                     */
 } cgh_stats;
 
-/* Reads the occupancy flags back from `workspace` (same problem arguments as
- * the forward call) and fills *stats [host].  Synchronises `stream`. */
+/* Reads the plan back from `workspace` (same problem arguments as the forward
+ * call) and fills *stats [host].  Synchronises `stream`. */
 int cgh_workspace_stats(const void* workspace, int ny, int nx, int n_layers, int levels,
                         int precision, cgh_stats* stats, void* stream);
 

@@ -61,7 +61,7 @@ SIGNATURES = {
     "cgh_workspace_stats": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp]),
 }
 
-STAGES = ("coef", "lut", "first", "list", "second", "reduce")
+STAGES = ("coef", "lut", "plan", "first", "second", "reduce")
 
 
 class Stats(ctypes.Structure):
@@ -70,9 +70,9 @@ class Stats(ctypes.Structure):
     _fields_ = [
         ("coef_rows_active", ctypes.c_longlong),
         ("coef_rows_total", ctypes.c_longlong),
-        ("ktiles_active", ctypes.c_longlong),
-        ("ktiles_total", ctypes.c_longlong),
-        ("ktile_rows", ctypes.c_int),
+        ("k_padded", ctypes.c_longlong),
+        ("k_total", ctypes.c_longlong),
+        ("k_tile", ctypes.c_int),
         ("split_k", ctypes.c_int),
         ("flops_first", ctypes.c_double),
         ("flops_second", ctypes.c_double),

@@ -10,6 +10,7 @@
 #include "../../include/cgh.h"
 #include "common.h"
 #include "gemm.h"
+#include "nt.h"
 
 namespace {
 
@@ -41,10 +42,11 @@ int check_precision(int precision) {
 }
 
 int choose_split(int ny, int nx, int levels, int layers) {
-    const int tiles = ((ny + cgh::kTileM - 1) / cgh::kTileM) * ((nx + cgh::kTileN - 1) / cgh::kTileN);
+    const int tiles = ((ny + cgh::kNtTile - 1) / cgh::kNtTile) * ((nx + cgh::kNtTile - 1) / cgh::kNtTile);
     const int target = 512;  // two resident workgroups on each of 256 CUs
     int split = (target + tiles - 1) / tiles;
-    const int kt = cgh::second_stage_ktiles(ny, levels, layers);
+    // keep at least four K tiles per split of the dense K range
+    const int kt = (int)(cgh::nt_sizes(ny, nx, layers, levels).kmax / cgh::kKT);
     if (split > kt / 4) split = kt / 4;
     if (split > 16) split = 16;
     if (split < 1) split = 1;
@@ -54,16 +56,12 @@ int choose_split(int ny, int nx, int levels, int layers) {
 cgh::Layout make_layout(int ny, int nx, int layers, int levels) {
     cgh::Layout lo{};
     const size_t plane = (size_t)ny * nx;
+    const int n_dl = layers * levels;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
     lo.coef = take((size_t)layers * plane * 4);
-    lo.coef_lo = lo.coef + (size_t)layers * plane * 2;
-    const size_t nlut_x = (size_t)layers * levels * 4 * cgh::lut_len(nx);
-    const size_t nlut_y = (size_t)layers * levels * 4 * cgh::lut_len(ny);
-    lo.lut_x = take(nlut_x * 4);
-    lo.lut_x_lo = lo.lut_x + nlut_x * 2;
-    lo.lut_y = take(nlut_y * 4);
-    lo.lut_y_lo = lo.lut_y + nlut_y * 2;
+    lo.lut_x = take((size_t)layers * levels * 4 * cgh::lut_len(nx) * 4);
+    lo.lut_y = take((size_t)layers * levels * 4 * cgh::lut_len(ny) * 4);
     lo.lut0 = take((size_t)(2 * cgh::lut_len(nx) + 2 * cgh::lut_len(ny)) * 4);
     lo.t_layer = 0;
     lo.flags_layer = 0;
@@ -71,18 +69,57 @@ cgh::Layout make_layout(int ny, int nx, int layers, int levels) {
         lo.t_layer += (size_t)cgh::band_side(ny, l) * nx;
         lo.flags_layer += (size_t)cgh::band_side(ny, l) + cgh::band_side(nx, l);
     }
-    // the back-propagation reuses T as its ny x nx intermediate
-    size_t t_elems = (size_t)layers * lo.t_layer;
-    if (t_elems < plane) t_elems = plane;
-    lo.t = take(t_elems * 8);
-    lo.t_lo = lo.t;
     lo.flags = take((size_t)layers * lo.flags_layer);
-    lo.n_ktiles = cgh::second_stage_ktiles(ny, levels, layers);
-    lo.ktiles = take((size_t)(1 + lo.n_ktiles) * 4);
+    const cgh::NtSizes z = cgh::nt_sizes(ny, nx, layers, levels);
+    lo.rowlist = take(z.rowlist * 4);
+    lo.collist = take(z.collist * 4);
+    lo.cnt_row = take((size_t)n_dl * 4);
+    lo.cnt_col = take((size_t)n_dl * 4);
+    lo.seg_row = take((size_t)n_dl * 4);
+    lo.hdr = take(sizeof(cgh::PlanHeader));
+    lo.entries = take((size_t)(n_dl + 1) * sizeof(cgh::NtEntry));
+    lo.first_tiles_max = z.first_tiles_max;
+    // backward: T (complex, >= one plane for the back-propagation intermediate);
+    // forward: the operand panels, 8 bytes per complex element in every precision
+    size_t t_bytes = (size_t)layers * lo.t_layer * 8;
+    if (t_bytes < plane * 8) t_bytes = plane * 8;
+    const size_t fx_b = align_up(z.fx_plane * 8), cb_b = align_up(z.cb_plane * 4);
+    const size_t fy_b = align_up(z.fy_plane * 8), tc_b = align_up(z.tc_plane * 8);
+    const size_t panels = fx_b + cb_b + fy_b + tc_b;
+    lo.big = take(t_bytes > panels ? t_bytes : panels);
+    lo.t = lo.big;
+    lo.fx = lo.big;
+    lo.cb = lo.fx + fx_b;
+    lo.fy = lo.cb + cb_b;
+    lo.tc = lo.fy + fy_b;
+    lo.fx_ps = z.fx_plane;
+    lo.cb_ps = z.cb_plane;
+    lo.fy_ps = z.fy_plane;
+    lo.tc_ps = z.tc_plane;
     lo.split_k = choose_split(ny, nx, levels, layers);
     lo.partial = take(lo.split_k > 1 ? (size_t)lo.split_k * plane * 8 : 0);
     lo.total = off;
     return lo;
+}
+
+cgh::NtBuffers nt_buffers(char* ws, const cgh::Layout& lo) {
+    cgh::NtBuffers b{};
+    b.rowlist = reinterpret_cast<int*>(ws + lo.rowlist);
+    b.collist = reinterpret_cast<int*>(ws + lo.collist);
+    b.cnt_row = reinterpret_cast<int*>(ws + lo.cnt_row);
+    b.cnt_col = reinterpret_cast<int*>(ws + lo.cnt_col);
+    b.seg_row = reinterpret_cast<int*>(ws + lo.seg_row);
+    b.hdr = reinterpret_cast<cgh::PlanHeader*>(ws + lo.hdr);
+    b.entries = reinterpret_cast<cgh::NtEntry*>(ws + lo.entries);
+    b.fx = ws + lo.fx;
+    b.cb = ws + lo.cb;
+    b.fy = ws + lo.fy;
+    b.tc = ws + lo.tc;
+    b.fx_ps = lo.fx_ps;
+    b.cb_ps = lo.cb_ps;
+    b.fy_ps = lo.fy_ps;
+    b.tc_ps = lo.tc_ps;
+    return b;
 }
 
 struct Optics {
@@ -283,9 +320,11 @@ int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, in
 
         const int acc = (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0;
         const cgh::GemmShape sh{ny, nx, n_layers, levels, lo.split_k, precision, lo.t_layer,
-                                 lo.flags_layer};
-        float2* t = reinterpret_cast<float2*>(ws + lo.t);
-        int* klist = reinterpret_cast<int*>(ws + lo.ktiles);
+                                lo.flags_layer};
+        const cgh::NtBuffers nb = nt_buffers(ws, lo);
+        const float* coef = reinterpret_cast<const float*>(ws + lo.coef);
+        const float* lut_x = reinterpret_cast<const float*>(ws + lo.lut_x);
+        const float* lut_y = reinterpret_cast<const float*>(ws + lo.lut_y);
         float2* partial = reinterpret_cast<float2*>(ws + lo.partial);
         float2* out = reinterpret_cast<float2*>(hologram);
 
@@ -305,18 +344,21 @@ int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, in
                                         cgh::P_FP32, ws + lo.lut_y, nullptr, s);
             });
         if (e == hipSuccess)
-            e = timed(s, CGH_STAGE_FIRST, [&] {
-                return cgh::launch_forward_stage1(
-                    sh, reinterpret_cast<const float*>(ws + lo.coef),
-                    reinterpret_cast<const float*>(ws + lo.lut_x), t, fl, s);
+            e = timed(s, CGH_STAGE_PLAN, [&] {
+                hipError_t r = cgh::launch_nt_plan(fl, ny, nx, n_layers, levels, lo.flags_layer, nb, s);
+                if (r != hipSuccess) return r;
+                return cgh::launch_nt_materialize(coef, lut_x, lut_y, ny, nx, n_layers, levels,
+                                                  precision, nb, s);
             });
         if (e == hipSuccess)
-            e = timed(s, CGH_STAGE_LIST, [&] { return cgh::launch_ktile_list(sh, fl, 1, klist, s); });
+            e = timed(s, CGH_STAGE_FIRST, [&] {
+                return cgh::launch_nt_first(ny, nx, n_layers, levels, precision, nb,
+                                            lo.first_tiles_max, s);
+            });
         if (e == hipSuccess)
             e = timed(s, CGH_STAGE_SECOND, [&] {
-                return cgh::launch_forward_stage2(
-                    sh, reinterpret_cast<const float*>(ws + lo.lut_y), t, fl, klist, partial, out,
-                    acc, s);
+                return cgh::launch_nt_second(ny, nx, n_layers, levels, precision, lo.split_k, nb,
+                                             partial, out, acc, s);
             });
         if (e == hipSuccess && lo.split_k > 1)
             e = timed(s, CGH_STAGE_REDUCE,
@@ -450,36 +492,28 @@ int cgh_workspace_stats(const void* workspace, int ny, int nx, int n_layers, int
         const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
         hipStream_t s = (hipStream_t)stream;
         const char* ws = static_cast<const char*>(workspace);
-        std::vector<uint8_t> fl((size_t)n_layers * lo.flags_layer);
-        int count = 0;
-        hipError_t e = hipMemcpyAsync(fl.data(), ws + lo.flags, fl.size(), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(&count, ws + lo.ktiles, sizeof(int), hipMemcpyDeviceToHost, s);
+        const int n_dl = n_layers * levels;
+        std::vector<int> cr(n_dl), cc(n_dl);
+        cgh::PlanHeader hdr{};
+        hipError_t e = hipMemcpyAsync(cr.data(), ws + lo.cnt_row, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(cc.data(), ws + lo.cnt_col, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hdr, ws + lo.hdr, sizeof(hdr), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_status(e);
-        long long rows = 0, rows_total = 0;
-        double k1 = 0.0;
-        for (int d = 0; d < n_layers; ++d) {
-            for (int l = 1; l <= levels; ++l) {
-                const uint8_t* fr = fl.data() + (size_t)d * lo.flags_layer + cgh::flag_level_off(ny, nx, l);
-                const int sy = cgh::band_side(ny, l), sx = cgh::band_side(nx, l);
-                const int nyl = ny >> l, nxl = nx >> l;
-                for (int r = 0; r < sy; ++r) {
-                    rows_total += 1;
-                    if (!fr[r]) continue;
-                    rows += 1;
-                    k1 += (l < levels && r < nyl) ? (double)(sx - nxl) : (double)sx;
-                }
-            }
-        }
-        stats->coef_rows_active = rows;
-        stats->coef_rows_total = rows_total;
-        stats->ktiles_active = count;
-        stats->ktiles_total = lo.n_ktiles;
-        stats->ktile_rows = cgh::kTileK;
+        double rc = 0.0;
+        for (int k = 0; k < n_dl; ++k) rc += (double)cr[k] * (double)cc[k];
+        long long total = 0;
+        for (int l = 1; l <= levels; ++l) total += cgh::band_side(ny, l);
+        total *= n_layers;
+        stats->coef_rows_active = hdr.rows_active;
+        stats->coef_rows_total = total;
+        stats->k_padded = hdr.kpad;
+        stats->k_total = total;
+        stats->k_tile = cgh::kKT;
         stats->split_k = lo.split_k;
-        stats->flops_first = 4.0 * (double)nx * k1;
-        stats->flops_second = 8.0 * (double)ny * (double)nx * (double)rows;
-        stats->flops_second_issued = 8.0 * (double)ny * (double)nx * (double)count * cgh::kTileK;
+        stats->flops_first = 4.0 * (double)nx * rc;
+        stats->flops_second = 8.0 * (double)ny * (double)nx * (double)hdr.rows_active;
+        stats->flops_second_issued = 8.0 * (double)ny * (double)nx * (double)hdr.kpad;
         return CGH_SUCCESS;
     } catch (...) {
         return CGH_ERROR_HIP;

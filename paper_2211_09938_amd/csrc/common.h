@@ -45,18 +45,22 @@ struct LayerConsts {
 
 // Byte offsets of every region inside the caller's workspace.
 struct Layout {
-    size_t coef, coef_lo;        // masked Mallat coefficients, D * ny * nx (fp32, or hi/lo halves)
-    size_t lut_x, lut_y;         // fringe tables (fp32, or hi halves)
-    size_t lut_x_lo, lut_y_lo;   // lo halves (split precision)
+    size_t coef;                 // masked Mallat coefficients, D * ny * nx floats
+    size_t lut_x, lut_y;         // FP32 fringe tables
     size_t lut0;                 // level-0 table pair (x then y) for back-propagation
-    size_t t, t_lo;              // first-stage products, D * sum_l s_y(l) * nx complex
     size_t flags;                // per layer: rows then cols of every level, bytes
-    size_t ktiles;               // int count + int list of active second-stage K tiles
+    size_t rowlist, collist;     // active row / column indices per (layer, level)
+    size_t cnt_row, cnt_col, seg_row;  // per (layer, level) counts and k' offsets
+    size_t hdr, entries;         // device plan header and GEMM problem table
+    size_t big;                  // shared region: backward T, or the forward panels
+    size_t t;                    // backward / back-propagation intermediate (complex)
+    size_t fx, cb, fy, tc;       // forward operand panels (inside `big`)
+    size_t fx_ps, cb_ps, fy_ps, tc_ps;  // their plane strides, elements
     size_t partial;              // split-K partial holograms
     size_t total;
     size_t t_layer;              // complex elements of T per layer
     size_t flags_layer;          // flag bytes per layer
-    int n_ktiles;                // candidate second-stage K tiles
+    int first_tiles_max;
     int split_k;
 };
 

@@ -16,16 +16,6 @@ struct GemmShape {
     size_t flags_layer;  // flag bytes per layer
 };
 
-// Candidate K tiles of the second forward stage (list capacity).
-int second_stage_ktiles(int ny, int levels, int layers);
-
-hipError_t launch_forward_stage1(const GemmShape& sh, const float* coef, const float* lut_x,
-                                     float2* t, const uint8_t* flags, hipStream_t s);
-hipError_t launch_ktile_list(const GemmShape& sh, const uint8_t* flags, int use_flags, int* klist,
-                             hipStream_t s);
-hipError_t launch_forward_stage2(const GemmShape& sh, const float* lut_y, const float2* t,
-                                     const uint8_t* flags, const int* klist, float2* partial,
-                                     float2* out, int accumulate, hipStream_t s);
 hipError_t launch_reduce_partial(const GemmShape& sh, const float2* partial, float2* out,
                                  int accumulate, hipStream_t s);
 

@@ -1,17 +1,15 @@
-// Dense complex contractions of the hologram on CDNA4 matrix cores (FP32 path).
+// Complex contractions of the adjoint and of the Fresnel back-propagation on
+// CDNA4 matrix cores (the forward pass uses the compacted kernels of ntgemm.hip).
 //
 // Per depth layer d and Haar level l the hologram contribution factors as
 //     H_{d,l} = Fy_{d,l} * Cb_{d,l} * Fx_{d,l}^T                        (Eq. 3, separable Eq. 1)
 // where Cb is the level-l square of Mallat coefficients (its LL quadrant empty
 // for l < L) and F[pix, j] = g_band(j)[pix - (j mod n_l) * 2^l] is the
-// strided-Toeplitz matrix of the 1D block fringes (lut.hip).  Two stages:
-//     stage 1:  T_{d,l} = Cb_{d,l} * Fx_{d,l}^T          (real x complex)
-//     stage 2:  H       = sum_{d,l} Fy_{d,l} * T_{d,l}  (complex x complex, one long K)
-// Fringe operands are never materialised: each K tile gathers its window of the
-// 1D table (a few KB, cache resident) straight into LDS.
-//
-// The backward pass and the Fresnel back-propagation reuse the same kernel
-// with other operand loaders (conjugated / transposed fringes, dense complex).
+// strided-Toeplitz matrix of the 1D block fringes (lut.hip).  The adjoint is
+//     Q_{d,l}  = Fy_{d,l}^H * G,   gC_{d,l} = Re(Q_{d,l} * conj(Fx_{d,l}))
+// and the back-propagation uses the level-0 fringe (the kernel itself).
+// Fringe operands are never materialised: each K tile gathers its elements of
+// the 1D table (a few KB, cache resident) straight into LDS.
 //
 // Kernel: 256 threads = 4 waves in a 2x2 grid, output tile 128 x 128 complex,
 // each wave 64 x 64 complex as 2 x 2 blocks of v_mfma_f32_32x32x2f32, 4M complex
@@ -395,136 +393,6 @@ __device__ __forceinline__ float2 fringe(const float* __restrict__ lut_level, in
     return make_float2(re, conj ? -im : im);
 }
 
-// ---------------------------------------------------------- forward, stage 1
-// T_{d,l}[r, x] = sum_j Cb_{d,l}[r, j] * Fx_{d,l}[x, j]
-struct FwdS1 {
-    static constexpr bool A_CPLX = false, B_CPLX = true, OUT_REAL = false;
-    static constexpr bool A_KFAST = true, B_KFAST = false;
-    const float* coef;
-    const float* lut;
-    float2* t;
-    const uint8_t* flags;
-    int ny, nx, L;
-    size_t t_layer, flags_layer;
-    FlatGrid g;
-    struct Ctx {
-        int d, l, m0, n0, sy, sx, nyl, nxl, k0;
-        const float* c;
-        const float* lut;
-        float2* t;
-    };
-    struct KT { int j0; };
-    __device__ bool setup(Ctx& cx) const {
-        g.decode(blockIdx.x, cx.d, cx.l, cx.m0, cx.n0);
-        const int l = cx.l;
-        cx.sy = band_side(ny, l);
-        cx.sx = band_side(nx, l);
-        cx.nyl = ny >> l;
-        cx.nxl = nx >> l;
-        const uint8_t* fr = flags + (size_t)cx.d * flags_layer + flag_level_off(ny, nx, l);
-        const int row = cx.m0 + (int)threadIdx.x;
-        const int busy = (threadIdx.x < BM && row < cx.sy) ? fr[row] : 0;
-        if (!__syncthreads_or(busy)) return false;  // all rows zero: T rows stay unwritten
-        cx.k0 = (l < L && cx.m0 + BM <= cx.nyl) ? cx.nxl / BK : 0;
-        cx.c = coef + (size_t)cx.d * ny * nx;
-        cx.lut = lut + lut_table(cx.d, l, 0, 0, L) * lut_len(nx);
-        cx.t = t + (size_t)cx.d * t_layer + t_level_rows(ny, l) * nx;
-        return true;
-    }
-    __device__ int nk(const Ctx& cx) const { return (cx.sx + BK - 1) / BK - cx.k0; }
-    __device__ KT kt(const Ctx& cx, int i) const { return KT{(cx.k0 + i) * BK}; }
-    __device__ float2 a(const Ctx& cx, const KT& kd, int m, int k) const {
-        const int r = cx.m0 + m, j = kd.j0 + k;
-        if (r < cx.sy && j < cx.sx && !(cx.l < L && r < cx.nyl && j < cx.nxl))
-            return make_float2(cx.c[(size_t)r * nx + j], 0.f);
-        return cz();
-    }
-    __device__ float2 b(const Ctx& cx, const KT& kd, int k, int n) const {
-        const int j = kd.j0 + k, x = cx.n0 + n;
-        if (j < cx.sx && x < nx) return fringe(cx.lut, lut_len(nx), nx, cx.nxl, cx.l, x, j, false);
-        return cz();
-    }
-    __device__ void store(const Ctx& cx, int m, int n, float re, float im) const {
-        const int r = cx.m0 + m, x = cx.n0 + n;
-        if (r < cx.sy && x < nx) cx.t[(size_t)r * nx + x] = make_float2(re, im);
-    }
-};
-
-// ---------------------------------------------------------- forward, stage 2
-// H[y, x] = sum over active K tiles (d, l, band, j) of Fy_{d,l}[y, j] * T_{d,l}[j, x]
-struct FwdS2 {
-    static constexpr bool A_CPLX = true, B_CPLX = true, OUT_REAL = false;
-    static constexpr bool A_KFAST = false, B_KFAST = false;
-    const float* lut;
-    const float2* t;
-    const uint8_t* flags;
-    const int* klist;  // [0] = count, then codes
-    float2* out;
-    float2* partial;
-    int ny, nx, L, split, accumulate, ctiles;
-    size_t t_layer, flags_layer;
-    struct Ctx { int m0, n0, s, kbeg, kend; };
-    struct KT {
-        int l, nyl, j0;
-        const float* lut;
-        const float2* trow;
-        const uint8_t* rf;
-    };
-    __device__ bool setup(Ctx& cx) const {
-        const int tile = blockIdx.x;
-        cx.m0 = (tile / ctiles) * BM;
-        cx.n0 = (tile % ctiles) * BN;
-        cx.s = blockIdx.y;
-        const int count = klist[0];
-        const int chunk = (count + split - 1) / split;
-        cx.kbeg = cx.s * chunk;
-        cx.kend = min(count, cx.kbeg + chunk);
-        return true;
-    }
-    __device__ int nk(const Ctx& cx) const { return max(0, cx.kend - cx.kbeg); }
-    __device__ KT kt(const Ctx& cx, int i) const {
-        const int code = klist[1 + cx.kbeg + i];
-        const int seg = code >> 16, tile = code & 0xffff;
-        const int d = seg / (2 * L);
-        const int l = ((seg >> 1) % L) + 1;
-        const int band = seg & 1;
-        KT kd;
-        kd.l = l;
-        kd.nyl = ny >> l;
-        kd.j0 = tile * BK;
-        kd.lut = lut + lut_table(d, l, band, 0, L) * lut_len(ny);
-        kd.trow = t + (size_t)d * t_layer + (t_level_rows(ny, l) + (size_t)band * kd.nyl) * nx;
-        kd.rf = flags + (size_t)d * flags_layer + flag_level_off(ny, nx, l) + band * kd.nyl;
-        return kd;
-    }
-    __device__ float2 a(const Ctx& cx, const KT& kd, int m, int k) const {
-        const int y = cx.m0 + m, j = kd.j0 + k;
-        if (y < ny && j < kd.nyl) {
-            const int len = lut_len(ny);
-            const int idx = y - (j << kd.l) + ny;
-            return make_float2(kd.lut[idx], kd.lut[len + idx]);
-        }
-        return cz();
-    }
-    __device__ float2 b(const Ctx& cx, const KT& kd, int k, int n) const {
-        const int j = kd.j0 + k, x = cx.n0 + n;
-        if (j < kd.nyl && x < nx && kd.rf[j]) return kd.trow[(size_t)j * nx + x];
-        return cz();
-    }
-    __device__ void store(const Ctx& cx, int m, int n, float re, float im) const {
-        const int y = cx.m0 + m, x = cx.n0 + n;
-        if (y >= ny || x >= nx) return;
-        const size_t i = (size_t)y * nx + x;
-        if (split == 1) {
-            float2 v = make_float2(re, im);
-            if (accumulate) { const float2 o = out[i]; v.x += o.x; v.y += o.y; }
-            out[i] = v;
-        } else {
-            partial[(size_t)cx.s * ny * nx + i] = make_float2(re, im);
-        }
-    }
-};
-
 // --------------------------------------------------------- backward, stage 1
 // Q_{d,l}[r, x] = sum_y conj(Fy_{d,l}[y, r]) * G[y, x]
 struct BwdS1 {
@@ -683,61 +551,6 @@ struct PropS2 {
     }
 };
 
-// --------------------------------------------------------------- K-tile list
-// Deterministic compaction (one workgroup) of the second-stage K tiles whose
-// rows of T hold at least one nonzero coefficient row.
-__global__ __launch_bounds__(1024) void ktile_list_kernel(const uint8_t* __restrict__ flags, int ny,
-                                                          int nx, int L, int D,
-                                                          size_t flags_layer, int use_flags,
-                                                          int* __restrict__ klist) {
-    __shared__ int scan[1024];
-    __shared__ int base_s;
-    int per_layer = 0;
-    for (int l = 1; l <= L; ++l) per_layer += 2 * (((ny >> l) + BK - 1) / BK);
-    const int total = D * per_layer;
-    if (threadIdx.x == 0) base_s = 0;
-    __syncthreads();
-    for (int c0 = 0; c0 < total; c0 += 1024) {
-        const int c = c0 + (int)threadIdx.x;
-        int active = 0, code = 0;
-        if (c < total) {
-            const int d = c / per_layer;
-            int r = c - d * per_layer;
-            int l = 1;
-            for (;;) {
-                const int tl = ((ny >> l) + BK - 1) / BK;
-                if (r < 2 * tl || l == L) break;
-                r -= 2 * tl;
-                ++l;
-            }
-            const int tl = ((ny >> l) + BK - 1) / BK;
-            const int band = r / tl, tile = r - band * tl;
-            const int nyl = ny >> l;
-            if (use_flags) {
-                const uint8_t* rf = flags + (size_t)d * flags_layer + flag_level_off(ny, nx, l) + band * nyl;
-                for (int q = tile * BK; q < min(nyl, tile * BK + BK); ++q) active |= rf[q];
-            } else {
-                active = 1;
-            }
-            code = (((d * L + (l - 1)) * 2 + band) << 16) | tile;
-        }
-        scan[threadIdx.x] = active;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const int v = (threadIdx.x >= (unsigned)off) ? scan[threadIdx.x - off] : 0;
-            __syncthreads();
-            scan[threadIdx.x] += v;
-            __syncthreads();
-        }
-        const int base = base_s;
-        if (active) klist[1 + base + scan[threadIdx.x] - 1] = code;
-        __syncthreads();
-        if (threadIdx.x == 1023) base_s = base + scan[1023];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) klist[0] = base_s;
-}
-
 __global__ __launch_bounds__(256) void reduce_partial_kernel(const float2* __restrict__ partial,
                                                              int split, size_t n, int accumulate,
                                                              float2* __restrict__ out) {
@@ -781,59 +594,6 @@ FlatGrid make_grid(int ny, int levels, const int* cols_per_level) {
 }  // namespace
 
 // --------------------------------------------------------------- launchers
-int second_stage_ktiles(int ny, int levels, int layers) {
-    int per = 0;
-    for (int l = 1; l <= levels; ++l) per += 2 * (((ny >> l) + BK - 1) / BK);
-    return per * layers;
-}
-
-hipError_t launch_forward_stage1(const GemmShape& sh, const float* coef, const float* lut_x,
-                                     float2* t, const uint8_t* flags, hipStream_t s) {
-    int cols[kMaxLevels + 1];
-    for (int l = 1; l <= sh.levels; ++l) cols[l] = sh.nx;
-    FwdS1 p1{};
-    p1.coef = coef;
-    p1.lut = lut_x;
-    p1.t = t;
-    p1.flags = flags;
-    p1.ny = sh.ny;
-    p1.nx = sh.nx;
-    p1.L = sh.levels;
-    p1.t_layer = sh.t_layer;
-    p1.flags_layer = sh.flags_layer;
-    p1.g = make_grid(sh.ny, sh.levels, cols);
-    return run(p1, dim3(p1.g.cum[sh.levels] * sh.layers), s, sh.precision);
-}
-
-hipError_t launch_ktile_list(const GemmShape& sh, const uint8_t* flags, int use_flags, int* klist,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(ktile_list_kernel, dim3(1), dim3(1024), 0, s, flags, sh.ny, sh.nx,
-                       sh.levels, sh.layers, sh.flags_layer, use_flags, klist);
-    return hipGetLastError();
-}
-
-hipError_t launch_forward_stage2(const GemmShape& sh, const float* lut_y, const float2* t,
-                                     const uint8_t* flags, const int* klist, float2* partial,
-                                     float2* out, int accumulate, hipStream_t s) {
-    FwdS2 p2{};
-    p2.lut = lut_y;
-    p2.t = t;
-    p2.flags = flags;
-    p2.klist = klist;
-    p2.out = out;
-    p2.partial = partial;
-    p2.ny = sh.ny;
-    p2.nx = sh.nx;
-    p2.L = sh.levels;
-    p2.split = sh.split_k;
-    p2.accumulate = accumulate;
-    p2.ctiles = (sh.nx + BN - 1) / BN;
-    p2.t_layer = sh.t_layer;
-    p2.flags_layer = sh.flags_layer;
-    const int tiles = ((sh.ny + BM - 1) / BM) * p2.ctiles;
-    return run(p2, dim3(tiles, sh.split_k), s, sh.precision);
-}
-
 hipError_t launch_reduce_partial(const GemmShape& sh, const float2* partial, float2* out,
                                  int accumulate, hipStream_t s) {
     if (sh.split_k <= 1) return hipSuccess;

@@ -1,0 +1,320 @@
+// Planning and operand-panel kernels of the compacted forward contractions.
+//
+//  * lists:  per (layer, level), the active rows and columns of the level's
+//            coefficient square (deterministic wave-ballot compaction);
+//  * plan:   padded counts, k' segment offsets and the GEMM problem table;
+//  * panels: K-contiguous operand panels in the operand precision --
+//            Fy_c[y][k'] and Fx_c[x][c'] gathered from the 1D fringe tables,
+//            Cb_c[r'][c'] gathered from the masked Mallat coefficients.
+#include "nt.h"
+#include "split.h"
+
+namespace cgh {
+
+namespace {
+
+// Appends, in index order, every i in [0, n) with f[i] != 0 to out; returns the count.
+__device__ int block_compact(const uint8_t* __restrict__ f, int n, int* __restrict__ out,
+                             int* s_wave) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int running = 0;
+    for (int base = 0; base < n; base += blockDim.x) {
+        const int i = base + (int)threadIdx.x;
+        const bool pred = i < n && f[i] != 0;
+        const unsigned long long m = __ballot(pred);
+        const int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wave[w] = __popcll(m);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int k = 0; k < nw; ++k) {
+            if (k < w) off += s_wave[k];
+            tot += s_wave[k];
+        }
+        if (pred) out[running + off + pre] = i;
+        running += tot;
+        __syncthreads();
+    }
+    return running;
+}
+
+__global__ __launch_bounds__(1024) void lists_kernel(const uint8_t* __restrict__ flags, int ny,
+                                                     int nx, int levels, size_t flags_layer,
+                                                     int* __restrict__ rowlist,
+                                                     int* __restrict__ collist,
+                                                     int* __restrict__ cnt_row,
+                                                     int* __restrict__ cnt_col) {
+    __shared__ int s_wave[16];
+    const int dl = blockIdx.x;
+    const int d = dl / levels, l = dl % levels + 1;
+    const uint8_t* fr = flags + (size_t)d * flags_layer + flag_level_off(ny, nx, l);
+    const int sy = band_side(ny, l), sx = band_side(nx, l);
+    const int nr = block_compact(fr, sy, rowlist + dl_rows_off(ny, levels, d, l), s_wave);
+    const int nc = block_compact(fr + sy, sx, collist + dl_cols_off(nx, levels, d, l), s_wave);
+    if (threadIdx.x == 0) {
+        cnt_row[dl] = nr;
+        cnt_col[dl] = nc;
+    }
+}
+
+// Inclusive Hillis-Steele scan over the block (blockDim.x == 1024).
+__device__ int block_scan_incl(int v, int* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        const int add = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const int r = sh[threadIdx.x];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(1024) void plan_kernel(int ny, int nx, int layers, int levels,
+                                                    const int* __restrict__ cnt_row,
+                                                    const int* __restrict__ cnt_col,
+                                                    int* __restrict__ seg_row,
+                                                    PlanHeader* __restrict__ hdr,
+                                                    NtEntry* __restrict__ entries) {
+    __shared__ int sh[1024];
+    __shared__ int last[3];
+    const int n_dl = layers * levels;
+    const int tn = (nx + kNtTile - 1) / kNtTile;
+    int total_k = 0, total_t = 0, total_r = 0;
+    for (int base = 0; base < n_dl; base += 1024) {
+        const int t = base + (int)threadIdx.x;
+        int cr = 0, cc = 0, pr = 0, tiles = 0;
+        if (t < n_dl) {
+            cr = cnt_row[t];
+            cc = cnt_col[t];
+            pr = pad_kt(cr);
+            tiles = cr > 0 ? ((cr + kNtTile - 1) / kNtTile) * tn : 0;
+        }
+        const int ik = block_scan_incl(pr, sh);
+        const int it = block_scan_incl(tiles, sh);
+        const int ir = block_scan_incl(cr, sh);
+        if (t < n_dl) {
+            const int d = t / levels, l = t % levels + 1;
+            const int seg = total_k + ik - pr;
+            seg_row[t] = seg;
+            NtEntry e;
+            e.M = cr;
+            e.N = nx;
+            e.K = pad_kt(cc);
+            e.lda = e.K;
+            e.ldb = e.K;
+            e.a_off = (long long)dl_cb_off(ny, nx, levels, d, l);
+            e.b_off = (long long)dl_fx_off(nx, levels, d, l);
+            e.out_off = seg;
+            e.tiles_n = tn;
+            e.tile_begin = total_t + it - tiles;
+            entries[t] = e;
+        }
+        // totals of this chunk come from the last thread's inclusive values
+        if (threadIdx.x == blockDim.x - 1) {
+            last[0] = ik;
+            last[1] = it;
+            last[2] = ir;
+        }
+        __syncthreads();
+        total_k += last[0];
+        total_t += last[1];
+        total_r += last[2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        hdr->kpad = total_k;
+        hdr->first_tiles = total_t;
+        hdr->rows_active = total_r;
+        hdr->second_tiles = ((ny + kNtTile - 1) / kNtTile) * tn;
+        NtEntry e;
+        e.M = ny;
+        e.N = nx;
+        e.K = total_k;
+        e.lda = total_k;
+        e.ldb = total_k;
+        e.a_off = 0;
+        e.b_off = 0;
+        e.out_off = 0;
+        e.tiles_n = tn;
+        e.tile_begin = 0;
+        entries[n_dl] = e;
+    }
+}
+
+// Complex value -> planes (FP32: re, im; split: re_hi, re_lo, im_hi, im_lo).
+template <int P>
+__device__ __forceinline__ void put_c(void* base, size_t ps, size_t off, float re, float im) {
+    if constexpr (P == P_FP32) {
+        float* b = static_cast<float*>(base);
+        b[off] = re;
+        b[ps + off] = im;
+    } else {
+        uint16_t* b = static_cast<uint16_t*>(base);
+        uint16_t h, l;
+        split16<P>(re, h, l);
+        b[off] = h;
+        b[ps + off] = l;
+        split16<P>(im, h, l);
+        b[2 * ps + off] = h;
+        b[3 * ps + off] = l;
+    }
+}
+
+// Real value -> planes (FP32: one plane; split: hi, lo).
+template <int P>
+__device__ __forceinline__ void put_r(void* base, size_t ps, size_t off, float v) {
+    if constexpr (P == P_FP32) {
+        static_cast<float*>(base)[off] = v;
+    } else {
+        uint16_t* b = static_cast<uint16_t*>(base);
+        uint16_t h, l;
+        split16<P>(v, h, l);
+        b[off] = h;
+        b[ps + off] = l;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void fy_kernel(const float* __restrict__ lut_y,
+                                                 const int* __restrict__ rowlist,
+                                                 const int* __restrict__ cnt_row,
+                                                 const int* __restrict__ seg_row,
+                                                 const PlanHeader* __restrict__ hdr, int ny,
+                                                 int levels, void* fy, size_t ps) {
+    const int dl = blockIdx.y;
+    const int d = dl / levels, l = dl % levels + 1;
+    const int cr = cnt_row[dl], pr = pad_kt(cr);
+    if (pr == 0) return;
+    const int seg = seg_row[dl], kpad = hdr->kpad;
+    const int nyl = ny >> l, len = lut_len(ny);
+    const int* rl = rowlist + dl_rows_off(ny, levels, d, l);
+    const float* lutl = lut_y + lut_table(d, l, 0, 0, levels) * len;
+    const long long total = (long long)ny * pr;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int y = (int)(e / pr), i = (int)(e - (long long)y * pr);
+        float re = 0.f, im = 0.f;
+        if (i < cr) {
+            const int r = rl[i];
+            const int band = r >= nyl, j = r - band * nyl;
+            const float* tb = lutl + (size_t)band * 2 * len;
+            const int idx = y - (j << l) + ny;
+            re = tb[idx];
+            im = tb[len + idx];
+        }
+        put_c<P>(fy, ps, (size_t)y * kpad + seg + i, re, im);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void fx_kernel(const float* __restrict__ lut_x,
+                                                 const int* __restrict__ collist,
+                                                 const int* __restrict__ cnt_row,
+                                                 const int* __restrict__ cnt_col, int nx,
+                                                 int levels, void* fx, size_t ps) {
+    const int dl = blockIdx.y;
+    const int d = dl / levels, l = dl % levels + 1;
+    const int cc = cnt_col[dl], pc = pad_kt(cc);
+    if (pc == 0 || cnt_row[dl] == 0) return;
+    const int nxl = nx >> l, len = lut_len(nx);
+    const int* cl = collist + dl_cols_off(nx, levels, d, l);
+    const float* lutl = lut_x + lut_table(d, l, 0, 0, levels) * len;
+    const size_t base = dl_fx_off(nx, levels, d, l);
+    const long long total = (long long)nx * pc;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(e / pc), c = (int)(e - (long long)x * pc);
+        float re = 0.f, im = 0.f;
+        if (c < cc) {
+            const int j = cl[c];
+            const int band = j >= nxl, jj = j - band * nxl;
+            const float* tb = lutl + (size_t)band * 2 * len;
+            const int idx = x - (jj << l) + nx;
+            re = tb[idx];
+            im = tb[len + idx];
+        }
+        put_c<P>(fx, ps, base + (size_t)x * pc + c, re, im);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void cb_kernel(const float* __restrict__ coef,
+                                                 const int* __restrict__ rowlist,
+                                                 const int* __restrict__ collist,
+                                                 const int* __restrict__ cnt_row,
+                                                 const int* __restrict__ cnt_col, int ny, int nx,
+                                                 int levels, void* cb, size_t ps) {
+    const int dl = blockIdx.y;
+    const int d = dl / levels, l = dl % levels + 1;
+    const int cr = cnt_row[dl], cc = cnt_col[dl], pc = pad_kt(cc);
+    if (cr == 0 || pc == 0) return;
+    const int nyl = ny >> l, nxl = nx >> l;
+    const int* rl = rowlist + dl_rows_off(ny, levels, d, l);
+    const int* cl = collist + dl_cols_off(nx, levels, d, l);
+    const float* cd = coef + (size_t)d * ny * nx;
+    const size_t base = dl_cb_off(ny, nx, levels, d, l);
+    const long long total = (long long)cr * pc;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int rr = (int)(e / pc), c = (int)(e - (long long)rr * pc);
+        float v = 0.f;
+        if (c < cc) {
+            const int r = rl[rr], j = cl[c];
+            // the LL quadrant of a level below the top belongs to the coarser levels
+            if (!(l < levels && r < nyl && j < nxl)) v = cd[(size_t)r * nx + j];
+        }
+        put_r<P>(cb, ps, base + (size_t)rr * pc + c, v);
+    }
+}
+
+int grid_for(long long elems) {
+    long long g = (elems + 256 * 8 - 1) / (256 * 8);
+    if (g < 1) g = 1;
+    if (g > 512) g = 512;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int levels,
+                          size_t flags_layer, const NtBuffers& b, hipStream_t s) {
+    const int n_dl = layers * levels;
+    hipLaunchKernelGGL(lists_kernel, dim3(n_dl), dim3(1024), 0, s, flags, ny, nx, levels,
+                       flags_layer, b.rowlist, b.collist, b.cnt_row, b.cnt_col);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, ny, nx, layers, levels, b.cnt_row,
+                       b.cnt_col, b.seg_row, b.hdr, b.entries);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t materialize(const float* coef, const float* lut_x, const float* lut_y, int ny,
+                              int nx, int layers, int levels, const NtBuffers& b, hipStream_t s) {
+    const int n_dl = layers * levels;
+    const long long big_y = (long long)ny * pad_kt(band_side(ny, 1));
+    const long long big_x = (long long)nx * pad_kt(band_side(nx, 1));
+    const long long big_c = (long long)band_side(ny, 1) * pad_kt(band_side(nx, 1));
+    hipLaunchKernelGGL(fy_kernel<P>, dim3(grid_for(big_y), n_dl), dim3(256), 0, s, lut_y,
+                       b.rowlist, b.cnt_row, b.seg_row, b.hdr, ny, levels, b.fy, b.fy_ps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fx_kernel<P>, dim3(grid_for(big_x), n_dl), dim3(256), 0, s, lut_x,
+                       b.collist, b.cnt_row, b.cnt_col, nx, levels, b.fx, b.fx_ps);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(cb_kernel<P>, dim3(grid_for(big_c), n_dl), dim3(256), 0, s, coef,
+                       b.rowlist, b.collist, b.cnt_row, b.cnt_col, ny, nx, levels, b.cb, b.cb_ps);
+    return hipGetLastError();
+}
+
+hipError_t launch_nt_materialize(const float* coef, const float* lut_x, const float* lut_y, int ny,
+                                 int nx, int layers, int levels, int precision,
+                                 const NtBuffers& b, hipStream_t s) {
+    if (precision == P_BF16) return materialize<P_BF16>(coef, lut_x, lut_y, ny, nx, layers, levels, b, s);
+    if (precision == P_FP16) return materialize<P_FP16>(coef, lut_x, lut_y, ny, nx, layers, levels, b, s);
+    return materialize<P_FP32>(coef, lut_x, lut_y, ny, nx, layers, levels, b, s);
+}
+
+}  // namespace cgh
