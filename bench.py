@@ -52,7 +52,22 @@ def parse():
     ap.add_argument("--cpu-pixels", type=int, default=1536,
                     help="hologram pixels the oracle evaluates for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times "
+                         "(reference for scaling hardware byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": n * 4, "launches": 5}), flush=True)
 
 
 def cpu_baseline(scene, n_pixels, seed=12345):
@@ -88,6 +103,9 @@ def cpu_baseline(scene, n_pixels, seed=12345):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the hologram would shard by column bands, see DESIGN.md)", file=sys.stderr)
