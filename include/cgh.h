@@ -158,6 +158,64 @@ int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lamb
                               double z, int precision, int adjoint, void* workspace,
                               size_t workspace_bytes, float* field_out, void* stream);
 
+/* ---------------------------------------------------------- batched plans */
+
+/*
+ * One scene of a batch: the arguments of cgh_progressive_hologram that vary per
+ * scene.  Device pointers as there; z is [host] and is copied at plan creation.
+ * The device buffers must stay valid (and unmoved) for the plan's lifetime:
+ * the plan's captured graph reads and writes them on every execution.
+ */
+typedef struct {
+    const float* object;         /* ny*nx */
+    const uint8_t* layer_index;  /* ny*nx, or NULL (then n_layers == 1) */
+    int n_layers;
+    const double* z;             /* [host] n_layers distances in metres */
+    const float* saliency;       /* ny*nx, or NULL */
+    int ny, nx;
+    float* hologram;             /* 2*ny*nx floats (complex64), overwritten */
+} cgh_scene;
+
+typedef struct cgh_plan cgh_plan;
+
+/*
+ * Plans many scenes of uneven size as one unit (the batched form of
+ * cgh_progressive_hologram; same method, same arguments per scene).  The plan
+ * owns device memory for every scene's workspace, merges the contraction
+ * problems of all scenes into one table per contraction, runs each contraction
+ * as one persistent launch whose workgroups pull tiles from a shared counter,
+ * and captures the whole batch into a HIP graph.  Tile shapes come from an
+ * autotuner that times the candidates on this batch and caches the winners, as
+ * JSON lines keyed by GPU architecture, precision and batch signature, in
+ * tune_cache_path (NULL: no cache; the file is created if missing).
+ * Plan creation synchronises `stream` (it runs the batch while tuning).
+ * Errors: as cgh_progressive_hologram per scene, CGH_ERROR_OUT_OF_MEMORY if
+ * the device memory cannot be allocated.  *plan is NULL on error.
+ */
+int cgh_plan_create(const cgh_scene* scenes /* [host] */, int n_scenes, int levels, double lambda,
+                    double pitch, const float* thresholds, int precision, unsigned flags,
+                    const char* tune_cache_path, void* stream, cgh_plan** plan /* [host] */);
+
+/* Launches the captured graph on `stream`: every scene's hologram is
+ * recomputed from the current contents of its input buffers. */
+int cgh_plan_execute(cgh_plan* plan, void* stream);
+
+/* Frees the plan (waits for nothing: the caller synchronises first). */
+int cgh_plan_destroy(cgh_plan* plan);
+
+typedef struct {
+    int n_scenes;
+    int first_tile[2];     /* rows, cols of the first contraction's tile  */
+    int second_tile[2];    /* rows, cols of the second contraction's tile */
+    int from_cache;        /* tile shapes read from the tune cache         */
+    int persistent_grid;   /* workgroups of each persistent launch         */
+    double tune_ms_first;  /* measured time of the chosen first contraction (ms, 0 if cached) */
+    double tune_ms_second;
+    size_t device_bytes;   /* device memory the plan owns                  */
+} cgh_plan_info;
+
+int cgh_plan_get_info(const cgh_plan* plan, cgh_plan_info* info /* [host] */);
+
 /* ------------------------------------------------------------ diagnostics */
 
 /* Stages of cgh_progressive_hologram, in launch order. */

@@ -59,7 +59,42 @@ SIGNATURES = {
     "cgh_profile_read": (_c_int, [ctypes.POINTER(_c_double), ctypes.POINTER(ctypes.c_longlong),
                                   _c_int]),
     "cgh_workspace_stats": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp]),
+    "cgh_plan_create": (_c_int, [_vp, _c_int, _c_int, _c_double, _c_double, _vp, _c_int, _c_uint,
+                                 ctypes.c_char_p, _vp, ctypes.POINTER(_vp)]),
+    "cgh_plan_execute": (_c_int, [_vp, _vp]),
+    "cgh_plan_destroy": (_c_int, [_vp]),
+    "cgh_plan_get_info": (_c_int, [_vp, _vp]),
 }
+
+
+class SceneDesc(ctypes.Structure):
+    """Mirror of cgh_scene."""
+
+    _fields_ = [
+        ("object", _vp),
+        ("layer_index", _vp),
+        ("n_layers", _c_int),
+        ("z", ctypes.POINTER(_c_double)),
+        ("saliency", _vp),
+        ("ny", _c_int),
+        ("nx", _c_int),
+        ("hologram", _vp),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    """Mirror of cgh_plan_info."""
+
+    _fields_ = [
+        ("n_scenes", _c_int),
+        ("first_tile", _c_int * 2),
+        ("second_tile", _c_int * 2),
+        ("from_cache", _c_int),
+        ("persistent_grid", _c_int),
+        ("tune_ms_first", _c_double),
+        ("tune_ms_second", _c_double),
+        ("device_bytes", _sz),
+    ]
 
 STAGES = ("coef", "lut", "plan", "first", "second", "reduce")
 
@@ -283,6 +318,73 @@ def workspace_stats(workspace, ny, nx, n_layers=1, levels=3, precision="fp32"):
                                      _precision(precision), ctypes.byref(st), _stream()),
            "cgh_workspace_stats")
     return st.as_dict()
+
+
+# ------------------------------------------------------------ batched plans
+
+class Plan:
+    """A batch of scenes planned, tuned and graph-captured once (cgh_plan_*).
+
+    ``scenes`` is a list of dicts with keys ``obj`` (float32 GPU tensor),
+    ``z`` (distances), and optionally ``saliency`` and ``layer_index``.  The
+    input tensors are referenced by the captured graph and must stay alive and
+    unmodified in place only as the caller intends; ``holograms`` holds one
+    complex64 output per scene, refreshed by every :meth:`execute`.
+    """
+
+    def __init__(self, scenes, lam, pitch, levels=3, thresholds=None, precision="fp32",
+                 eq1_prefactor=False, tune_cache=None):
+        torch = _torch()
+        self._keep = []
+        self.holograms = []
+        descs = (SceneDesc * len(scenes))()
+        for i, sc in enumerate(scenes):
+            obj = sc["obj"]
+            ny, nx = obj.shape
+            zs = list(np.atleast_1d(np.asarray(sc["z"], dtype=np.float64)))
+            sal, lay = sc.get("saliency"), sc.get("layer_index")
+            out = torch.empty((ny, nx), dtype=torch.complex64, device=obj.device)
+            zarr = _host_doubles(zs)
+            descs[i].object = _dev_tensor(obj, torch.float32, "object")
+            descs[i].layer_index = None if lay is None else _dev_tensor(lay, torch.uint8, "layer_index", (ny, nx))
+            descs[i].n_layers = len(zs)
+            descs[i].z = ctypes.cast(zarr, ctypes.POINTER(_c_double))
+            descs[i].saliency = None if sal is None else _dev_tensor(sal, torch.float32, "saliency", (ny, nx))
+            descs[i].ny = ny
+            descs[i].nx = nx
+            descs[i].hologram = ctypes.c_void_p(out.data_ptr())
+            self._keep += [obj, sal, lay, zarr]
+            self.holograms.append(out)
+        flags = FLAG_EQ1_PREFACTOR if eq1_prefactor else 0
+        handle = ctypes.c_void_p()
+        cache = None if tune_cache is None else os.fsencode(tune_cache)
+        _check(lib().cgh_plan_create(descs, len(scenes), levels, float(lam), float(pitch),
+                                     _host_floats(thresholds), _precision(precision), flags, cache,
+                                     _stream(), ctypes.byref(handle)), "cgh_plan_create")
+        self._handle = handle
+
+    def execute(self):
+        _check(lib().cgh_plan_execute(self._handle, _stream()), "cgh_plan_execute")
+        return self.holograms
+
+    def info(self):
+        inf = PlanInfo()
+        _check(lib().cgh_plan_get_info(self._handle, ctypes.byref(inf)), "cgh_plan_get_info")
+        return {"n_scenes": inf.n_scenes, "first_tile": tuple(inf.first_tile),
+                "second_tile": tuple(inf.second_tile), "from_cache": bool(inf.from_cache),
+                "persistent_grid": inf.persistent_grid, "tune_ms_first": inf.tune_ms_first,
+                "tune_ms_second": inf.tune_ms_second, "device_bytes": inf.device_bytes}
+
+    def close(self):
+        if getattr(self, "_handle", None):
+            _check(lib().cgh_plan_destroy(self._handle), "cgh_plan_destroy")
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------- autograd

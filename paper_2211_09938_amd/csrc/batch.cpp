@@ -1,0 +1,367 @@
+// Batched plans: many scenes of uneven size planned, tuned and captured as one
+// unit.  Every scene runs the same per-scene stages as cgh_progressive_hologram
+// (coefficients, fringe tables, active lists and panels); the contraction
+// problems of all scenes are then merged into one table per contraction and
+// each contraction runs as a single persistent launch over that table.  Tile
+// shapes come from an autotuner (timed on this batch, cached as JSON lines).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <string>
+#include <vector>
+
+#include "host.h"
+
+using namespace cgh::host;
+
+struct cgh_plan {
+    struct Scene {
+        cgh_scene s;
+        std::vector<double> z;
+        size_t ws_off;
+        cgh::Layout lo;
+        int first_off;
+    };
+    int levels = 3, precision = 0;
+    unsigned flags = 0;
+    double lambda = 0, pitch = 0;
+    float thr[CGH_MAX_LEVELS] = {};
+    std::vector<Scene> scenes;  // execution order: largest first
+    char* mem = nullptr;
+    size_t bytes = 0;
+    cgh::NtEntry* first = nullptr;
+    cgh::NtEntry* second = nullptr;
+    int n_first = 0;
+    cgh::PlanHeader* hdrs = nullptr;
+    int* first_off = nullptr;
+    int* counts = nullptr;
+    int* queues = nullptr;
+    int tiles[4] = {cgh::kNtTile, cgh::kNtTile, cgh::kNtTile, cgh::kNtTile};
+    int grid = 512;
+    int from_cache = 0;
+    double ms_first = 0, ms_second = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr int kMaxScenes = 4096;
+constexpr int kCandidates[4][2] = {{128, 128}, {64, 128}, {128, 64}, {64, 64}};
+
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr, c = nullptr;
+};
+
+// Enqueues the whole batch on `s` with the given tile shapes; records ev (if
+// given) before the first contraction, between the two, and after the second.
+hipError_t enqueue(const cgh_plan& p, hipStream_t s, const int* tiles, const Events* ev) {
+    Optics op;
+    for (size_t i = 0; i < p.scenes.size(); ++i) {
+        const cgh_plan::Scene& sc = p.scenes[i];
+        const cgh::Layout& lo = sc.lo;
+        char* ws = p.mem + sc.ws_off;
+        const int ny = sc.s.ny, nx = sc.s.nx, nl = sc.s.n_layers;
+        make_optics(op, nl, sc.z.data(), p.lambda, p.pitch, (p.flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
+        uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
+        cgh::NtBuffers nb = nt_buffers(ws, lo);
+        nb.first = p.first + sc.first_off;
+        nb.second = p.second + i;
+        nb.hdr = p.hdrs + i;
+        const cgh::NtOutput o{reinterpret_cast<float2*>(sc.s.hologram), nullptr, 0};
+        hipError_t e = cgh::launch_fill_u8(fl, (size_t)nl * lo.flags_layer, s);
+        if (e == hipSuccess)
+            e = cgh::launch_dwt_mask(sc.s.object, sc.s.layer_index, sc.s.saliency, ny, nx, nl,
+                                     p.levels, p.thr, cgh::P_FP32, ws + lo.coef, nullptr, fl,
+                                     lo.flags_layer, s);
+        if (e == hipSuccess)
+            e = cgh::launch_luts(nx, nl, p.levels, 1, op.c, op.one_re, op.one_im, cgh::P_FP32,
+                                 ws + lo.lut_x, nullptr, s);
+        if (e == hipSuccess)
+            e = cgh::launch_luts(ny, nl, p.levels, 1, op.c, op.pre_re, op.pre_im, cgh::P_FP32,
+                                 ws + lo.lut_y, nullptr, s);
+        if (e == hipSuccess)
+            e = cgh::launch_nt_plan(fl, ny, nx, nl, p.levels, lo.flags_layer, p.precision, tiles, nb,
+                                    o, s);
+        if (e == hipSuccess)
+            e = cgh::launch_nt_materialize(reinterpret_cast<const float*>(ws + lo.coef),
+                                           reinterpret_cast<const float*>(ws + lo.lut_x),
+                                           reinterpret_cast<const float*>(ws + lo.lut_y), ny, nx,
+                                           nl, p.levels, p.precision, nb, s);
+        if (e != hipSuccess) return e;
+    }
+    const int n = (int)p.scenes.size();
+    hipError_t e = cgh::launch_batch_prefix(p.hdrs, n, p.first_off, p.first, p.second, p.counts,
+                                            p.queues, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev->a, s);
+    if (e == hipSuccess)
+        e = cgh::launch_nt_persistent(false, p.precision, tiles[0], tiles[1], p.first, p.n_first,
+                                      p.counts, p.queues, p.grid, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev->b, s);
+    if (e == hipSuccess)
+        e = cgh::launch_nt_persistent(true, p.precision, tiles[2], tiles[3], p.second, n,
+                                      p.counts + 1, p.queues + 1, p.grid, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev->c, s);
+    return e;
+}
+
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+// Batch signature: architecture, precision, levels and the sorted scene shapes.
+std::string tune_key(const cgh_plan& p) {
+    std::vector<std::string> shapes;
+    for (const auto& sc : p.scenes)
+        shapes.push_back(std::to_string(sc.s.ny) + "x" + std::to_string(sc.s.nx) + "x" +
+                         std::to_string(sc.s.n_layers));
+    std::sort(shapes.begin(), shapes.end());
+    std::string k = arch_name() + "/p" + std::to_string(p.precision) + "/L" + std::to_string(p.levels) + "/";
+    for (size_t i = 0; i < shapes.size(); ++i) k += (i ? "," : "") + shapes[i];
+    return k;
+}
+
+// Cache file: one JSON object per line,
+// {"key": "...", "first": [tm, tn], "second": [tm, tn], "ms_first": x, "ms_second": y}
+bool cache_lookup(const char* path, const std::string& key, int* tiles) {
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    const std::string want = "\"key\": \"" + key + "\"";
+    while (std::getline(f, line)) {
+        if (line.find(want) == std::string::npos) continue;
+        const size_t a = line.find("\"first\": [");
+        const size_t b = line.find("\"second\": [");
+        if (a == std::string::npos || b == std::string::npos) continue;
+        int t[4];
+        if (std::sscanf(line.c_str() + a, "\"first\": [%d, %d]", &t[0], &t[1]) != 2) continue;
+        if (std::sscanf(line.c_str() + b, "\"second\": [%d, %d]", &t[2], &t[3]) != 2) continue;
+        bool ok = true;
+        for (int q = 0; q < 2; ++q) {
+            bool found = false;
+            for (const auto& c : kCandidates) found |= (c[0] == t[2 * q] && c[1] == t[2 * q + 1]);
+            ok &= found;
+        }
+        if (!ok) continue;
+        for (int q = 0; q < 4; ++q) tiles[q] = t[q];
+        return true;
+    }
+    return false;
+}
+
+void cache_store(const char* path, const std::string& key, const int* tiles, double ms1, double ms2) {
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    char buf[160];
+    std::snprintf(buf, sizeof(buf),
+                  "\", \"first\": [%d, %d], \"second\": [%d, %d], \"ms_first\": %.4f, \"ms_second\": %.4f}\n",
+                  tiles[0], tiles[1], tiles[2], tiles[3], ms1, ms2);
+    f << "{\"key\": \"" << key << buf;
+}
+
+// Times every candidate shape on this batch and keeps the fastest per contraction.
+hipError_t autotune(cgh_plan& p, hipStream_t s) {
+    Events ev;
+    hipError_t e = hipEventCreate(&ev.a);
+    if (e == hipSuccess) e = hipEventCreate(&ev.b);
+    if (e == hipSuccess) e = hipEventCreate(&ev.c);
+    double best1 = 1e30, best2 = 1e30;
+    for (const auto& c : kCandidates) {
+        if (e != hipSuccess) break;
+        const int tiles[4] = {c[0], c[1], c[0], c[1]};
+        double t1 = 1e30, t2 = 1e30;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // first run warms up
+            e = enqueue(p, s, tiles, &ev);
+            if (e == hipSuccess) e = hipEventSynchronize(ev.c);
+            float m1 = 0.f, m2 = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&m1, ev.a, ev.b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&m2, ev.b, ev.c);
+            if (rep > 0) {
+                t1 = std::min(t1, (double)m1);
+                t2 = std::min(t2, (double)m2);
+            }
+        }
+        if (t1 < best1) { best1 = t1; p.tiles[0] = c[0]; p.tiles[1] = c[1]; }
+        if (t2 < best2) { best2 = t2; p.tiles[2] = c[0]; p.tiles[3] = c[1]; }
+    }
+    if (ev.a) (void)hipEventDestroy(ev.a);
+    if (ev.b) (void)hipEventDestroy(ev.b);
+    if (ev.c) (void)hipEventDestroy(ev.c);
+    p.ms_first = best1;
+    p.ms_second = best2;
+    return e;
+}
+
+void release(cgh_plan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->mem) (void)hipFree(p->mem);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double lambda, double pitch,
+                    const float* thresholds, int precision, unsigned flags,
+                    const char* tune_cache_path, void* stream, cgh_plan** plan) {
+    if (!plan) return CGH_ERROR_INVALID_VALUE;
+    *plan = nullptr;
+    try {
+        if (!scenes || n_scenes < 1 || n_scenes > kMaxScenes) return CGH_ERROR_INVALID_VALUE;
+        if (flags & CGH_FLAG_ACCUMULATE) return CGH_ERROR_INVALID_VALUE;
+        cgh_plan* p = new cgh_plan();
+        p->levels = levels;
+        p->precision = precision;
+        p->flags = flags;
+        p->lambda = lambda;
+        p->pitch = pitch;
+        // validate every scene on the host before touching the device
+        for (int i = 0; i < n_scenes; ++i) {
+            const cgh_scene& sc = scenes[i];
+            int st = check_common(sc.n_layers, sc.layer_index, sc.z, thresholds, lambda, pitch,
+                                  sc.ny, sc.nx, levels, precision, flags, p->thr);
+            if (!st && (sc.ny == 0 || sc.nx == 0)) continue;  // empty scene: nothing to do
+            if (!st && (!sc.object || !sc.hologram)) st = CGH_ERROR_INVALID_VALUE;
+            if (st) {
+                delete p;
+                return st;
+            }
+            cgh_plan::Scene rec{};
+            rec.s = sc;
+            rec.z.assign(sc.z, sc.z + sc.n_layers);
+            rec.lo = make_layout(sc.ny, sc.nx, sc.n_layers, levels, false);
+            p->scenes.push_back(rec);
+        }
+        if (p->scenes.empty()) {
+            delete p;
+            return CGH_ERROR_INVALID_VALUE;
+        }
+        // largest scenes first: their tiles enter the work queues early
+        std::stable_sort(p->scenes.begin(), p->scenes.end(), [](const auto& a, const auto& b) {
+            const double ca = (double)a.s.ny * a.s.nx * (a.s.ny + a.s.nx) * a.s.n_layers;
+            const double cb = (double)b.s.ny * b.s.nx * (b.s.ny + b.s.nx) * b.s.n_layers;
+            return ca > cb;
+        });
+        size_t off = 0;
+        int n_first = 0;
+        for (auto& sc : p->scenes) {
+            sc.ws_off = off;
+            off = align_up(off + sc.lo.total);
+            sc.first_off = n_first;
+            n_first += sc.s.n_layers * levels;
+        }
+        const int n = (int)p->scenes.size();
+        p->n_first = n_first;
+        const size_t first_b = align_up((size_t)n_first * sizeof(cgh::NtEntry));
+        const size_t second_b = align_up((size_t)n * sizeof(cgh::NtEntry));
+        const size_t hdr_b = align_up((size_t)n * sizeof(cgh::PlanHeader));
+        const size_t off_b = align_up((size_t)(n + 1) * sizeof(int));
+        p->bytes = off + first_b + second_b + hdr_b + off_b + align_up(4 * sizeof(int));
+
+        const char* fail = std::getenv("CGH_TEST_FAIL_ALLOC");  // host-forced failure for tests
+        if (fail && fail[0] == '1') {
+            delete p;
+            return CGH_ERROR_OUT_OF_MEMORY;
+        }
+        if (hipMalloc(reinterpret_cast<void**>(&p->mem), p->bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            p->mem = nullptr;
+            release(p);
+            return CGH_ERROR_OUT_OF_MEMORY;
+        }
+        char* m = p->mem + off;
+        p->first = reinterpret_cast<cgh::NtEntry*>(m);
+        m += first_b;
+        p->second = reinterpret_cast<cgh::NtEntry*>(m);
+        m += second_b;
+        p->hdrs = reinterpret_cast<cgh::PlanHeader*>(m);
+        m += hdr_b;
+        p->first_off = reinterpret_cast<int*>(m);
+        m += off_b;
+        p->counts = reinterpret_cast<int*>(m);
+        p->queues = p->counts + 2;
+
+        hipStream_t s = (hipStream_t)stream;
+        std::vector<int> fo(n + 1);
+        for (int i = 0; i < n; ++i) fo[i] = p->scenes[i].first_off;
+        fo[n] = n_first;
+        hipError_t e = hipMemcpyAsync(p->first_off, fo.data(), (n + 1) * sizeof(int),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+        if (e == hipSuccess) p->grid = 2 * prop.multiProcessorCount;  // two resident per CU
+
+        const std::string key = tune_key(*p);
+        if (e == hipSuccess) {
+            if (cache_lookup(tune_cache_path, key, p->tiles)) {
+                p->from_cache = 1;
+            } else {
+                e = autotune(*p, s);
+                if (e == hipSuccess) cache_store(tune_cache_path, key, p->tiles, p->ms_first, p->ms_second);
+            }
+        }
+        // capture the batch on a private stream and instantiate it
+        hipStream_t cs = nullptr;
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            hipError_t ee = enqueue(*p, cs, p->tiles, nullptr);
+            e = hipStreamEndCapture(cs, &p->graph);
+            if (ee != hipSuccess) e = ee;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            const int st = hip_status(e);
+            release(p);
+            return st;
+        }
+        *plan = p;
+        return CGH_SUCCESS;
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
+int cgh_plan_execute(cgh_plan* plan, void* stream) {
+    if (!plan || !plan->exec) return CGH_ERROR_INVALID_VALUE;
+    return hip_status(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+}
+
+int cgh_plan_destroy(cgh_plan* plan) {
+    if (!plan) return CGH_ERROR_INVALID_VALUE;
+    release(plan);
+    return CGH_SUCCESS;
+}
+
+int cgh_plan_get_info(const cgh_plan* plan, cgh_plan_info* info) {
+    if (!plan || !info) return CGH_ERROR_INVALID_VALUE;
+    info->n_scenes = (int)plan->scenes.size();
+    info->first_tile[0] = plan->tiles[0];
+    info->first_tile[1] = plan->tiles[1];
+    info->second_tile[0] = plan->tiles[2];
+    info->second_tile[1] = plan->tiles[3];
+    info->from_cache = plan->from_cache;
+    info->persistent_grid = plan->grid;
+    info->tune_ms_first = plan->from_cache ? 0.0 : plan->ms_first;
+    info->tune_ms_second = plan->from_cache ? 0.0 : plan->ms_second;
+    info->device_bytes = plan->bytes;
+    return CGH_SUCCESS;
+}
+
+}  // extern "C"

@@ -50,7 +50,7 @@ struct Layout {
     size_t lut0;                 // level-0 table pair (x then y) for back-propagation
     size_t flags;                // per layer: rows then cols of every level, bytes
     size_t rowlist, collist;     // active row / column indices per (layer, level)
-    size_t cnt_row, cnt_col, seg_row;  // per (layer, level) counts and k' offsets
+    size_t cnt_row, cnt_col, seg_row, tbeg;  // per (layer, level) counts, k' and tile offsets
     size_t hdr, entries;         // device plan header and GEMM problem table
     size_t big;                  // shared region: backward T, or the forward panels
     size_t t;                    // backward / back-propagation intermediate (complex)
@@ -60,6 +60,7 @@ struct Layout {
     size_t total;
     size_t t_layer;              // complex elements of T per layer
     size_t flags_layer;          // flag bytes per layer
+    int entries_n;               // problems in the table: one per (layer, level), then one
     int first_tiles_max;
     int split_k;
 };

@@ -1,0 +1,176 @@
+// Host-side helpers shared by the C ABI translation units (internal):
+// argument checks, workspace layout, optics constants.
+#pragma once
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/cgh.h"
+#include "common.h"
+#include "gemm.h"
+#include "nt.h"
+
+namespace cgh {
+namespace host {
+
+constexpr size_t kAlign = 256;  // workspace region alignment (bytes)
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Maps a HIP error to a status code, remembering it for cgh_last_hip_error().
+int hip_status(hipError_t e);
+
+inline int check_shape(int ny, int nx, int levels) {
+    if (levels < 1) return CGH_ERROR_SHAPE;
+    if (levels > CGH_MAX_LEVELS) return CGH_ERROR_UNSUPPORTED;
+    if (ny < 0 || nx < 0 || ny > CGH_MAX_SIDE || nx > CGH_MAX_SIDE) return CGH_ERROR_SHAPE;
+    const int b = 1 << levels;
+    if (ny % b || nx % b) return CGH_ERROR_SHAPE;
+    return CGH_SUCCESS;
+}
+
+inline int check_precision(int precision) {
+    if (precision < CGH_FP32 || precision > CGH_FP16_SPLIT) return CGH_ERROR_INVALID_VALUE;
+    return CGH_SUCCESS;
+}
+
+inline int choose_split(int ny, int nx, int levels, int layers) {
+    const int tiles = ((ny + cgh::kNtTile - 1) / cgh::kNtTile) * ((nx + cgh::kNtTile - 1) / cgh::kNtTile);
+    const int target = 512;  // two resident workgroups on each of 256 CUs
+    int split = (target + tiles - 1) / tiles;
+    // keep at least four K tiles per split of the dense K range
+    const int kt = (int)(cgh::nt_sizes(ny, nx, layers, levels).kmax / cgh::kKT);
+    if (split > kt / 4) split = kt / 4;
+    if (split > 16) split = 16;
+    if (split < 1) split = 1;
+    return split;
+}
+
+// with_partial: reserve split-K partial holograms (single-scene calls only).
+inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with_partial = true) {
+    cgh::Layout lo{};
+    const size_t plane = (size_t)ny * nx;
+    const int n_dl = layers * levels;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
+    lo.coef = take((size_t)layers * plane * 4);
+    lo.lut_x = take((size_t)layers * levels * 4 * cgh::lut_len(nx) * 4);
+    lo.lut_y = take((size_t)layers * levels * 4 * cgh::lut_len(ny) * 4);
+    lo.lut0 = take((size_t)(2 * cgh::lut_len(nx) + 2 * cgh::lut_len(ny)) * 4);
+    lo.t_layer = 0;
+    lo.flags_layer = 0;
+    for (int l = 1; l <= levels; ++l) {
+        lo.t_layer += (size_t)cgh::band_side(ny, l) * nx;
+        lo.flags_layer += (size_t)cgh::band_side(ny, l) + cgh::band_side(nx, l);
+    }
+    lo.flags = take((size_t)layers * lo.flags_layer);
+    const cgh::NtSizes z = cgh::nt_sizes(ny, nx, layers, levels);
+    lo.rowlist = take(z.rowlist * 4);
+    lo.collist = take(z.collist * 4);
+    lo.cnt_row = take((size_t)n_dl * 4);
+    lo.cnt_col = take((size_t)n_dl * 4);
+    lo.seg_row = take((size_t)n_dl * 4);
+    lo.tbeg = take((size_t)n_dl * 4);
+    lo.hdr = take(sizeof(cgh::PlanHeader));
+    lo.entries = take((size_t)(n_dl + 1) * sizeof(cgh::NtEntry));
+    lo.entries_n = n_dl + 1;
+    lo.first_tiles_max = z.first_tiles_max;
+    // backward: T (complex, >= one plane for the back-propagation intermediate);
+    // forward: the operand panels, 8 bytes per complex element in every precision
+    size_t t_bytes = (size_t)layers * lo.t_layer * 8;
+    if (t_bytes < plane * 8) t_bytes = plane * 8;
+    const size_t fx_b = align_up(z.fx_plane * 8), cb_b = align_up(z.cb_plane * 4);
+    const size_t fy_b = align_up(z.fy_plane * 8), tc_b = align_up(z.tc_plane * 8);
+    const size_t panels = fx_b + cb_b + fy_b + tc_b;
+    lo.big = take(t_bytes > panels ? t_bytes : panels);
+    lo.t = lo.big;
+    lo.fx = lo.big;
+    lo.cb = lo.fx + fx_b;
+    lo.fy = lo.cb + cb_b;
+    lo.tc = lo.fy + fy_b;
+    lo.fx_ps = z.fx_plane;
+    lo.cb_ps = z.cb_plane;
+    lo.fy_ps = z.fy_plane;
+    lo.tc_ps = z.tc_plane;
+    lo.split_k = with_partial ? choose_split(ny, nx, levels, layers) : 1;
+    lo.partial = take(lo.split_k > 1 ? (size_t)lo.split_k * plane * 8 : 0);
+    lo.total = off;
+    return lo;
+}
+
+inline cgh::NtBuffers nt_buffers(char* ws, const cgh::Layout& lo) {
+    cgh::NtBuffers b{};
+    b.rowlist = reinterpret_cast<int*>(ws + lo.rowlist);
+    b.collist = reinterpret_cast<int*>(ws + lo.collist);
+    b.cnt_row = reinterpret_cast<int*>(ws + lo.cnt_row);
+    b.cnt_col = reinterpret_cast<int*>(ws + lo.cnt_col);
+    b.seg_row = reinterpret_cast<int*>(ws + lo.seg_row);
+    b.tbeg = reinterpret_cast<int*>(ws + lo.tbeg);
+    b.hdr = reinterpret_cast<cgh::PlanHeader*>(ws + lo.hdr);
+    b.first = reinterpret_cast<cgh::NtEntry*>(ws + lo.entries);
+    b.second = b.first + (lo.entries_n - 1);
+    b.fx = ws + lo.fx;
+    b.cb = ws + lo.cb;
+    b.fy = ws + lo.fy;
+    b.tc = ws + lo.tc;
+    b.fx_ps = lo.fx_ps;
+    b.cb_ps = lo.cb_ps;
+    b.fy_ps = lo.fy_ps;
+    b.tc_ps = lo.tc_ps;
+    return b;
+}
+
+struct Optics {
+    double c[CGH_MAX_LAYERS];
+    double pre_re[CGH_MAX_LAYERS], pre_im[CGH_MAX_LAYERS];
+    double one_re[CGH_MAX_LAYERS], one_im[CGH_MAX_LAYERS];
+};
+
+inline void make_optics(Optics& o, int layers, const double* z, double lambda, double pitch, bool eq1) {
+    for (int d = 0; d < layers; ++d) {
+        o.c[d] = pitch * pitch / (2.0 * lambda * z[d]);
+        o.one_re[d] = 1.0;
+        o.one_im[d] = 0.0;
+        if (eq1) {
+            // exp(i k z) / z with k z = 2 pi z / lambda, reduced to a fraction of a cycle
+            const double cyc = z[d] / lambda;
+            const double fr = cyc - std::floor(cyc);
+            o.pre_re[d] = std::cos(2.0 * M_PI * fr) / z[d];
+            o.pre_im[d] = std::sin(2.0 * M_PI * fr) / z[d];
+        } else {
+            o.pre_re[d] = 1.0;
+            o.pre_im[d] = 0.0;
+        }
+    }
+}
+
+inline int check_common(int n_layers, const uint8_t* layer_index, const double* z, const float* thresholds,
+                 double lambda, double pitch, int ny, int nx, int levels, int precision,
+                 unsigned flags, float* thr_out) {
+    int st = check_shape(ny, nx, levels);
+    if (st) return st;
+    if (n_layers < 1 || n_layers > CGH_MAX_LAYERS) return CGH_ERROR_INVALID_VALUE;
+    if (!layer_index && n_layers != 1) return CGH_ERROR_INVALID_VALUE;
+    if (!z) return CGH_ERROR_INVALID_VALUE;
+    for (int d = 0; d < n_layers; ++d)
+        if (!finite_pos(z[d])) return CGH_ERROR_INVALID_VALUE;
+    if (!finite_pos(lambda) || !finite_pos(pitch)) return CGH_ERROR_INVALID_VALUE;
+    if (flags & ~(unsigned)(CGH_FLAG_ACCUMULATE | CGH_FLAG_EQ1_PREFACTOR)) return CGH_ERROR_INVALID_VALUE;
+    for (int l = 0; l < CGH_MAX_LEVELS; ++l) thr_out[l] = 0.5f;
+    if (thresholds) {
+        for (int l = 0; l < levels; ++l) {
+            const float t = thresholds[l];
+            if (!(t >= 0.0f && t <= 1.0f)) return CGH_ERROR_INVALID_VALUE;
+            thr_out[l] = t;
+        }
+    } else if (levels == 3) {
+        thr_out[0] = 0.9f;
+        thr_out[1] = 0.7f;
+        thr_out[2] = 0.5f;
+    }
+    return check_precision(precision);
+}
+
+}  // namespace host
+}  // namespace cgh

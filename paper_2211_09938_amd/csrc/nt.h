@@ -21,15 +21,22 @@ constexpr int kNtTile = 128;  // output tile rows and columns
 
 __host__ __device__ inline int pad_kt(int v) { return (v + kKT - 1) / kKT * kKT; }
 
-// One GEMM problem of the batched NT kernel.
+// One GEMM problem of the batched NT kernel (self-contained, so problems of
+// different scenes can share one launch).
 struct NtEntry {
-    int M, N, K;           // output rows, output columns (complex), reduction length
-    int lda, ldb;          // row strides of the A and B panels (elements)
-    long long a_off;       // element offset of A's row 0 inside its planes
-    long long b_off;       // element offset of B's row 0 inside its planes
-    long long out_off;     // first contraction: k' segment offset of this problem
-    int tiles_n;           // ceil(N / kNtTile)
-    int tile_begin;        // exclusive prefix of tiles over the entries
+    const void* a;          // A panel: plane 0, row 0, k 0
+    const void* b;          // B panel: plane 0, row 0, k 0
+    void* out;              // first: T_c plane 0 at this problem's k' segment; second: hologram
+    float2* partial;        // second: split-K partial holograms (single-scene calls), else null
+    long long a_ps, b_ps;   // plane strides of A and B (elements)
+    long long out_ps;       // first: plane stride of T_c (elements)
+    int M, N, K;            // output rows, output columns (complex), reduction length
+    int lda, ldb;           // row strides of the A and B panels (elements)
+    int out_ld;             // first: row stride of T_c (the scene's kpad); second: nx
+    int tiles_n;            // column tiles
+    int tile_begin;         // exclusive prefix of tiles over the table
+    int accumulate;         // second: hologram += result
+    int tile_m, tile_n;     // tile shape the table was planned for
 };
 
 // Device-side plan written by the planning kernels (lives in the workspace).
@@ -47,7 +54,7 @@ struct NtSizes {
     size_t cb_plane;          // elements per plane of Cb_c
     size_t kmax;              // upper bound of kpad
     size_t fy_plane, tc_plane;
-    int first_tiles_max;
+    int first_tiles_max;  // upper bound over every tile shape
 };
 
 inline NtSizes nt_sizes(int ny, int nx, int layers, int levels) {
@@ -61,7 +68,7 @@ inline NtSizes nt_sizes(int ny, int nx, int layers, int levels) {
         fx += (size_t)nx * pad_kt(sxl);
         cb += (size_t)syl * pad_kt(sxl);
         kmax += pad_kt(syl);
-        tiles += ((syl + kNtTile - 1) / kNtTile) * ((nx + kNtTile - 1) / kNtTile);
+        tiles += ((syl + 63) / 64) * ((nx + 63) / 64);  // bound for the smallest tile shape
     }
     z.rowlist = sy * layers;
     z.collist = sx * layers;
@@ -114,22 +121,47 @@ struct NtBuffers {
     int* cnt_row;   // [D*L]
     int* cnt_col;   // [D*L]
     int* seg_row;   // [D*L]
+    int* tbeg;      // [D*L] tile prefix (first contraction, local to the scene)
     PlanHeader* hdr;
-    NtEntry* entries;  // [D*L] first contraction, then 1 for the second
+    NtEntry* first;   // [D*L] first-contraction problems of this scene
+    NtEntry* second;  // [1] second-contraction problem of this scene
     // panels (element type by precision), plane strides in elements
     void* fx; void* cb; void* fy; void* tc;
     size_t fx_ps, cb_ps, fy_ps, tc_ps;
 };
 
+// Output of the second contraction of one scene.
+struct NtOutput {
+    float2* hologram;
+    float2* partial;   // split-K partials or null
+    int accumulate;
+};
+
+// tiles: {rows, cols} of the first contraction's tile, then of the second's.
 hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int levels,
-                          size_t flags_layer, const NtBuffers& b, hipStream_t s);
+                          size_t flags_layer, int precision, const int* tiles,
+                          const NtBuffers& b, const NtOutput& o, hipStream_t s);
 hipError_t launch_nt_materialize(const float* coef, const float* lut_x, const float* lut_y, int ny,
                                  int nx, int layers, int levels, int precision,
                                  const NtBuffers& b, hipStream_t s);
-hipError_t launch_nt_first(int ny, int nx, int layers, int levels, int precision,
-                           const NtBuffers& b, int max_tiles, hipStream_t s);
-hipError_t launch_nt_second(int ny, int nx, int layers, int levels, int precision, int split,
-                            const NtBuffers& b, float2* partial, float2* out, int accumulate,
+// Direct launches over one scene's table (tile 128 x 128; split-K for the second).
+hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffers& b,
+                           int max_tiles, hipStream_t s);
+hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBuffers& b,
                             hipStream_t s);
+// Persistent launch over a batched table: `grid` workgroups pull tiles from
+// *queue (zeroed by the caller) until *tile_count is reached.
+hipError_t launch_nt_persistent(bool second, int precision, int tile_m, int tile_n,
+                                const NtEntry* entries, int n_entries, const int* tile_count,
+                                int* queue, int grid, hipStream_t s);
+// Adds each scene's tile offset to its problems in the batched tables, writes
+// the two tile totals to counts[0..1] and zeroes queues[0..1].
+hipError_t launch_batch_prefix(const PlanHeader* hdrs, int n_scenes, const int* first_off,
+                               NtEntry* first, NtEntry* second, int* counts, int* queues,
+                               hipStream_t s);
+// Tiles of a problem with M rows and N columns under a tile shape.
+__host__ __device__ inline int nt_tiles(int M, int N, int tm, int tn) {
+    return ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
+}
 
 }  // namespace cgh

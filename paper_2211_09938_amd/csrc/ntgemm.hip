@@ -1,13 +1,17 @@
 // Batched NT complex GEMM on CDNA4 matrix cores for the compacted forward pass.
 //
 // C[m][n] = sum_k A[m][k] * B[n][k], A real or complex, B complex, both panels
-// K-contiguous in the operand precision.  One workgroup computes a 128 x 128
-// complex tile with 4 waves (2 x 2, 64 x 64 complex each, 2 x 2 blocks of
-// 32 x 32 MFMA).  A device-resident problem table (NtEntry) describes every GEMM
-// of a launch; blockIdx.x picks (problem, tile) by binary search over the
-// tiles' prefix, and a K split.  Per K tile of 16 each thread moves four
-// 16-byte chunks of A and four of B global -> registers -> LDS, the next tile's
-// loads in flight during the current tile's MFMAs.
+// K-contiguous in the operand precision.  A workgroup of 4 waves (2 x 2)
+// computes a TM x TN complex tile (TM, TN in {64, 128}); each wave owns
+// (TM/64) x (TN/64) blocks of 32 x 32 MFMA output.  A device-resident table of
+// self-contained problems (NtEntry) describes every GEMM of a launch; a tile
+// index selects (problem, tile) by binary search over the tiles' prefix.
+// Direct schedule: one workgroup per (tile, K split).  Persistent schedule:
+// a grid sized to the machine pulls tiles from an atomic counter until the
+// table is exhausted, so problems of very different sizes balance themselves.
+// Per K tile of 16 each thread moves 16-byte chunks of A and B
+// global -> registers -> LDS, the next tile's loads in flight during the
+// current tile's MFMAs.
 //
 //  FP32:  v_mfma_f32_32x32x2f32; a lane's 16-byte LDS read gives it the
 //         operands of 4 consecutive MFMAs (lane half g supplies k = 4g + t).
@@ -27,8 +31,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 namespace {
-
-constexpr int T = kNtTile;  // 128
 
 template <int P>
 struct Fmt {
@@ -73,39 +75,21 @@ __device__ __forceinline__ int find_entry(const NtEntry* __restrict__ en, int n,
     return lo;
 }
 
-// Block id -> (K split s, tile t): split-major, block id = s * count + t.
-// (Handing each XCD a contiguous range of tiles was measured to be no faster:
-// the operand panels stay resident in the 256 MB Infinity Cache.)
-__device__ __forceinline__ bool logical_tile(int bid, int count, int split, int& s, int& t) {
-    if (bid >= count * split) return false;
-    s = bid / count;
-    t = bid - s * count;
-    return true;
-}
-
-// Tile `local` of a problem -> its output origin (row-major over tiles).
-__device__ __forceinline__ void tile_origin(const NtEntry& e, int local, int& m0, int& n0) {
-    m0 = (local / e.tiles_n) * T;
-    n0 = (local % e.tiles_n) * T;
-}
-
-// Stage-1 output: T_c[x][seg + r'] in the operand precision (transposed store).
+// First contraction output: T_c[x][k'] (transposed, operand precision);
+// m is the first of 4 consecutive rows k', n the column x.
 template <int P>
 struct FirstEpi {
-    void* tc;
-    size_t ps;
-    const PlanHeader* hdr;
-    __device__ void store4(const NtEntry& e, int s, int m, int n, const float* re,
-                           const float* im) const {
-        (void)s;
+    __device__ static void store4(const NtEntry& e, int, int, int m, int n, const float* re,
+                                  const float* im) {
         if (m >= pad_kt(e.M) || n >= e.N) return;
-        const size_t off = (size_t)n * hdr->kpad + e.out_off + m;
+        const size_t off = (size_t)n * e.out_ld + m;
+        const size_t ps = (size_t)e.out_ps;
         if constexpr (P == P_FP32) {
-            float* b = static_cast<float*>(tc);
+            float* b = static_cast<float*>(e.out);
             *reinterpret_cast<floatx4*>(b + off) = floatx4{re[0], re[1], re[2], re[3]};
             *reinterpret_cast<floatx4*>(b + ps + off) = floatx4{im[0], im[1], im[2], im[3]};
         } else {
-            uint16_t* b = static_cast<uint16_t*>(tc);
+            uint16_t* b = static_cast<uint16_t*>(e.out);
             unsigned rh[4], rl[4], ih[4], il[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -125,96 +109,75 @@ struct FirstEpi {
     }
 };
 
-// Stage-2 output: complex64 hologram (or a split-K partial).
+// Second contraction output: complex64 hologram rows m..m+3, column n (or a
+// split-K partial).
 struct SecondEpi {
-    float2* out;
-    float2* partial;
-    int ny, nx, split, accumulate;
-    __device__ void store4(const NtEntry&, int s, int m, int n, const float* re,
-                           const float* im) const {
-        if (n >= nx) return;
+    __device__ static void store4(const NtEntry& e, int s, int split, int m, int n,
+                                  const float* re, const float* im) {
+        if (n >= e.N) return;
+        float2* out = static_cast<float2*>(e.out);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int y = m + q;
-            if (y >= ny) continue;
-            const size_t i = (size_t)y * nx + n;
+            if (y >= e.M) continue;
+            const size_t i = (size_t)y * e.out_ld + n;
             float2 v = make_float2(re[q], im[q]);
             if (split == 1) {
-                if (accumulate) {
+                if (e.accumulate) {
                     const float2 o = out[i];
                     v.x += o.x;
                     v.y += o.y;
                 }
                 out[i] = v;
             } else {
-                partial[(size_t)s * ny * nx + i] = v;
+                e.partial[(size_t)s * e.M * e.N + i] = v;
             }
         }
     }
 };
 
-template <int P, bool A_CPLX, class Epi>
-__global__ __launch_bounds__(256, 2) void nt_kernel(const NtEntry* __restrict__ entries,
-                                                    int n_entries,
-                                                    const int* __restrict__ tile_count,
-                                                    int split, const void* __restrict__ A,
-                                                    size_t a_ps, const void* __restrict__ B,
-                                                    size_t b_ps, Epi epi) {
+// One output tile (m0, n0) of problem e over K tiles [kb, ke).
+template <int P, bool A_CPLX, class Epi, int TM, int TN>
+__device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb, int ke, int s,
+                                        int split, unsigned char* As, unsigned char* Bs) {
     using F = Fmt<P>;
     constexpr int NPA = A_CPLX ? F::PC : F::PR;
     constexpr int NPB = F::PC;
-    constexpr int PLANE = T * F::PITCH;
-    __shared__ __attribute__((aligned(16))) unsigned char As[NPA * PLANE];
-    __shared__ __attribute__((aligned(16))) unsigned char Bs[NPB * PLANE];
+    constexpr int BI = TM / 64, BJ = TN / 64;  // 32 x 32 blocks per wave
+    constexpr int APLANE = TM * F::PITCH, BPLANE = TN * F::PITCH;
+    constexpr int QA = NPA * TM * F::CPR / 256;
+    constexpr int QB = NPB * TN * F::CPR / 256;
+    static_assert(QA >= 1 && QB >= 1, "tile too small for the staging layout");
 
-    int s, t;
-    if (!logical_tile(blockIdx.x, *tile_count, split, s, t)) return;
-    const int ei = find_entry(entries, n_entries, t);
-    const NtEntry e = entries[ei];
-    int m0, n0;
-    tile_origin(e, t - e.tile_begin, m0, n0);
-    const int chunk = pad_kt((e.K + split - 1) / split);
-    const int kb = s * chunk;
-    const int ke = min(e.K, kb + chunk);
     const int nk = ke > kb ? (ke - kb) / kKT : 0;
-
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TN / 2);
     const int l32 = lane & 31, g = lane >> 5;
 
-    floatx16 cr[2][2], ci[2][2];
+    floatx16 cr[BI][BJ], ci[BI][BJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < BJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) { cr[i][j][r] = 0.f; ci[i][j][r] = 0.f; }
-
-    // chunk q -> (plane, row, c); A has NPA * T * CPR chunks, B has NPB * T * CPR.
-    constexpr int QA = NPA * T * F::CPR / 256;
-    constexpr int QB = NPB * T * F::CPR / 256;
-    u32x4 ra[QA], rb[QB];
-    const unsigned char* Ab = static_cast<const unsigned char*>(A);
-    const unsigned char* Bb = static_cast<const unsigned char*>(B);
 
     // chunk q of an operand tile -> (plane, row, 16-byte chunk c of the row);
     // neighbouring threads read neighbouring chunks of a row (a row-fastest
     // assignment avoids LDS store conflicts but was measured 20% slower)
-    auto decomp = [](int q, int& plane, int& row, int& c) {
-        c = q % F::CPR;
-        row = (q / F::CPR) % T;
-        plane = q / (F::CPR * T);
-    };
+    u32x4 ra[QA], rb[QB];
+    const unsigned char* Ab = static_cast<const unsigned char*>(e.a);
+    const unsigned char* Bb = static_cast<const unsigned char*>(e.b);
     auto load = [&](int kt) {
         const int k0 = kb + kt * kKT;
 #pragma unroll
         for (int u = 0; u < QA; ++u) {
-            int plane, row, c;
-            decomp(tid + 256 * u, plane, row, c);
+            const int q = tid + 256 * u;
+            const int c = q % F::CPR, row = (q / F::CPR) % TM, plane = q / (F::CPR * TM);
             const int m = m0 + row;
             if (m < e.M) {
-                const size_t el = (size_t)plane * a_ps + (size_t)e.a_off + (size_t)m * e.lda + k0;
+                const size_t el = (size_t)plane * e.a_ps + (size_t)m * e.lda + k0;
                 ra[u] = *reinterpret_cast<const u32x4*>(Ab + el * F::ES + c * 16);
             } else {
                 ra[u] = u32x4{0u, 0u, 0u, 0u};
@@ -222,11 +185,11 @@ __global__ __launch_bounds__(256, 2) void nt_kernel(const NtEntry* __restrict__ 
         }
 #pragma unroll
         for (int u = 0; u < QB; ++u) {
-            int plane, row, c;
-            decomp(tid + 256 * u, plane, row, c);
+            const int q = tid + 256 * u;
+            const int c = q % F::CPR, row = (q / F::CPR) % TN, plane = q / (F::CPR * TN);
             const int n = n0 + row;
             if (n < e.N) {
-                const size_t el = (size_t)plane * b_ps + (size_t)e.b_off + (size_t)n * e.ldb + k0;
+                const size_t el = (size_t)plane * e.b_ps + (size_t)n * e.ldb + k0;
                 rb[u] = *reinterpret_cast<const u32x4*>(Bb + el * F::ES + c * 16);
             } else {
                 rb[u] = u32x4{0u, 0u, 0u, 0u};
@@ -236,15 +199,15 @@ __global__ __launch_bounds__(256, 2) void nt_kernel(const NtEntry* __restrict__ 
     auto stash = [&]() {
 #pragma unroll
         for (int u = 0; u < QA; ++u) {
-            int plane, row, c;
-            decomp(tid + 256 * u, plane, row, c);
-            *reinterpret_cast<u32x4*>(As + plane * PLANE + row * F::PITCH + c * 16) = ra[u];
+            const int q = tid + 256 * u;
+            const int c = q % F::CPR, row = (q / F::CPR) % TM, plane = q / (F::CPR * TM);
+            *reinterpret_cast<u32x4*>(As + plane * APLANE + row * F::PITCH + c * 16) = ra[u];
         }
 #pragma unroll
         for (int u = 0; u < QB; ++u) {
-            int plane, row, c;
-            decomp(tid + 256 * u, plane, row, c);
-            *reinterpret_cast<u32x4*>(Bs + plane * PLANE + row * F::PITCH + c * 16) = rb[u];
+            const int q = tid + 256 * u;
+            const int c = q % F::CPR, row = (q / F::CPR) % TN, plane = q / (F::CPR * TN);
+            *reinterpret_cast<u32x4*>(Bs + plane * BPLANE + row * F::PITCH + c * 16) = rb[u];
         }
     };
 
@@ -258,90 +221,71 @@ __global__ __launch_bounds__(256, 2) void nt_kernel(const NtEntry* __restrict__ 
         if constexpr (P == P_FP32) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                floatx4 fa[2][NPA], fb[2][NPB];
+                floatx4 fa[BI][NPA], fb[BJ][NPB];
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < BI; ++i)
 #pragma unroll
                     for (int c = 0; c < NPA; ++c)
                         fa[i][c] = *reinterpret_cast<const floatx4*>(
-                            As + c * PLANE + (wm + 32 * i + l32) * F::PITCH + (8 * h + 4 * g) * 4);
+                            As + c * APLANE + (wm + 32 * i + l32) * F::PITCH + (8 * h + 4 * g) * 4);
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < BJ; ++j)
 #pragma unroll
                     for (int c = 0; c < NPB; ++c)
                         fb[j][c] = *reinterpret_cast<const floatx4*>(
-                            Bs + c * PLANE + (wn + 32 * j + l32) * F::PITCH + (8 * h + 4 * g) * 4);
+                            Bs + c * BPLANE + (wn + 32 * j + l32) * F::PITCH + (8 * h + 4 * g) * 4);
 #pragma unroll
                 for (int tt = 0; tt < 4; ++tt) {
+#pragma unroll
+                    for (int i = 0; i < BI; ++i)
+#pragma unroll
+                        for (int j = 0; j < BJ; ++j) {
+                            cr[i][j] = mfma32(fa[i][0][tt], fb[j][0][tt], cr[i][j]);
+                            ci[i][j] = mfma32(fa[i][0][tt], fb[j][1][tt], ci[i][j]);
+                        }
                     if constexpr (A_CPLX) {
 #pragma unroll
-                        for (int i = 0; i < 2; ++i)
+                        for (int i = 0; i < BI; ++i)
 #pragma unroll
-                            for (int j = 0; j < 2; ++j) {
-                                cr[i][j] = mfma32(fa[i][0][tt], fb[j][0][tt], cr[i][j]);
-                                ci[i][j] = mfma32(fa[i][0][tt], fb[j][1][tt], ci[i][j]);
-                            }
-#pragma unroll
-                        for (int i = 0; i < 2; ++i)
-#pragma unroll
-                            for (int j = 0; j < 2; ++j) {
+                            for (int j = 0; j < BJ; ++j) {
                                 cr[i][j] = mfma32(-fa[i][1][tt], fb[j][1][tt], cr[i][j]);
                                 ci[i][j] = mfma32(fa[i][1][tt], fb[j][0][tt], ci[i][j]);
-                            }
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < 2; ++i)
-#pragma unroll
-                            for (int j = 0; j < 2; ++j) {
-                                cr[i][j] = mfma32(fa[i][0][tt], fb[j][0][tt], cr[i][j]);
-                                ci[i][j] = mfma32(fa[i][0][tt], fb[j][1][tt], ci[i][j]);
                             }
                     }
                 }
             }
         } else {
-            u32x4 a[2][NPA], b[2][NPB];
+            u32x4 a[BI][NPA], b[BJ][NPB];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < BI; ++i)
 #pragma unroll
                 for (int c = 0; c < NPA; ++c)
                     a[i][c] = *reinterpret_cast<const u32x4*>(
-                        As + c * PLANE + (wm + 32 * i + l32) * F::PITCH + g * 16);
+                        As + c * APLANE + (wm + 32 * i + l32) * F::PITCH + g * 16);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < BJ; ++j)
 #pragma unroll
                 for (int c = 0; c < NPB; ++c)
                     b[j][c] = *reinterpret_cast<const u32x4*>(
-                        Bs + c * PLANE + (wn + 32 * j + l32) * F::PITCH + g * 16);
-            if constexpr (A_CPLX) {
-                u32x4 nah[2], nal[2];  // -A_im: flip the sign bit of every 16-bit half
+                        Bs + c * BPLANE + (wn + 32 * j + l32) * F::PITCH + g * 16);
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    nah[i] = a[i][2] ^ 0x80008000u;
-                    nal[i] = a[i][3] ^ 0x80008000u;
+            for (int i = 0; i < BI; ++i)
+#pragma unroll
+                for (int j = 0; j < BJ; ++j) {
+                    cr[i][j] = prod3<P>(cr[i][j], a[i][0], a[i][1], b[j][0], b[j][1]);
+                    ci[i][j] = prod3<P>(ci[i][j], a[i][0], a[i][1], b[j][2], b[j][3]);
                 }
+            if constexpr (A_CPLX) {
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < BI; ++i) {
+                    // -A_im: flip the sign bit of every 16-bit half
+                    const u32x4 nah = a[i][2] ^ 0x80008000u, nal = a[i][3] ^ 0x80008000u;
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        cr[i][j] = prod3<P>(cr[i][j], a[i][0], a[i][1], b[j][0], b[j][1]);
-                        ci[i][j] = prod3<P>(ci[i][j], a[i][0], a[i][1], b[j][2], b[j][3]);
-                    }
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        cr[i][j] = prod3<P>(cr[i][j], nah[i], nal[i], b[j][2], b[j][3]);
+                    for (int j = 0; j < BJ; ++j) {
+                        cr[i][j] = prod3<P>(cr[i][j], nah, nal, b[j][2], b[j][3]);
                         ci[i][j] = prod3<P>(ci[i][j], a[i][2], a[i][3], b[j][0], b[j][1]);
                     }
-            } else {
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        cr[i][j] = prod3<P>(cr[i][j], a[i][0], a[i][1], b[j][0], b[j][1]);
-                        ci[i][j] = prod3<P>(ci[i][j], a[i][0], a[i][1], b[j][2], b[j][3]);
-                    }
+                }
             }
         }
         __syncthreads();
@@ -350,9 +294,9 @@ __global__ __launch_bounds__(256, 2) void nt_kernel(const NtEntry* __restrict__ 
     }
 
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < BJ; ++j)
 #pragma unroll
             for (int qd = 0; qd < 4; ++qd) {
                 float re[4], im[4];
@@ -361,50 +305,137 @@ __global__ __launch_bounds__(256, 2) void nt_kernel(const NtEntry* __restrict__ 
                     re[q] = cr[i][j][4 * qd + q];
                     im[q] = ci[i][j][4 * qd + q];
                 }
-                epi.store4(e, s, m0 + wm + 32 * i + 8 * qd + 4 * g, n0 + wn + 32 * j + l32, re, im);
+                Epi::store4(e, s, split, m0 + wm + 32 * i + 8 * qd + 4 * g,
+                            n0 + wn + 32 * j + l32, re, im);
             }
 }
 
+template <int P, bool A_CPLX, int TM, int TN>
+struct Smem {
+    static constexpr int NPA = A_CPLX ? Fmt<P>::PC : Fmt<P>::PR;
+    static constexpr int A = NPA * TM * Fmt<P>::PITCH;
+    static constexpr int B = Fmt<P>::PC * TN * Fmt<P>::PITCH;
+};
+
+// Resolves tile t of the table and runs it (K range of split s).
+template <int P, bool A_CPLX, class Epi, int TM, int TN>
+__device__ __forceinline__ void run_tile(const NtEntry* __restrict__ entries, int n_entries,
+                                         int t, int s, int split, unsigned char* As,
+                                         unsigned char* Bs) {
+    const NtEntry e = entries[find_entry(entries, n_entries, t)];
+    const int local = t - e.tile_begin;
+    const int m0 = (local / e.tiles_n) * TM;
+    const int n0 = (local % e.tiles_n) * TN;
+    const int chunk = pad_kt((e.K + split - 1) / split);
+    const int kb = s * chunk;
+    const int ke = min(e.K, kb + chunk);
+    nt_tile<P, A_CPLX, Epi, TM, TN>(e, m0, n0, kb, ke, s, split, As, Bs);
+}
+
+// Direct schedule: block id = s * count + t.
+template <int P, bool A_CPLX, class Epi, int TM, int TN>
+__global__ __launch_bounds__(256, 2) void nt_direct_kernel(const NtEntry* __restrict__ entries,
+                                                           int n_entries,
+                                                           const int* __restrict__ tile_count,
+                                                           int split) {
+    using S = Smem<P, A_CPLX, TM, TN>;
+    __shared__ __attribute__((aligned(16))) unsigned char As[S::A];
+    __shared__ __attribute__((aligned(16))) unsigned char Bs[S::B];
+    const int count = *tile_count;
+    const int bid = blockIdx.x;
+    if (bid >= count * split) return;
+    const int s = bid / count;
+    run_tile<P, A_CPLX, Epi, TM, TN>(entries, n_entries, bid - s * count, s, split, As, Bs);
+}
+
+// Persistent schedule: pull tiles from *queue until *tile_count is reached;
+// every workgroup exits once the counter passes the end of the table.
+template <int P, bool A_CPLX, class Epi, int TM, int TN>
+__global__ __launch_bounds__(256, 2) void nt_persistent_kernel(
+    const NtEntry* __restrict__ entries, int n_entries, const int* __restrict__ tile_count,
+    int* __restrict__ queue) {
+    using S = Smem<P, A_CPLX, TM, TN>;
+    __shared__ __attribute__((aligned(16))) unsigned char As[S::A];
+    __shared__ __attribute__((aligned(16))) unsigned char Bs[S::B];
+    __shared__ int s_next;
+    const int count = *tile_count;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = atomicAdd(queue, 1);
+        __syncthreads();
+        const int t = s_next;
+        __syncthreads();
+        if (t >= count) break;
+        run_tile<P, A_CPLX, Epi, TM, TN>(entries, n_entries, t, 0, 1, As, Bs);
+    }
+}
+
+template <int P, bool SECOND, int TM, int TN>
+hipError_t persistent(const NtEntry* entries, int n_entries, const int* count, int* queue,
+                      int grid, hipStream_t s) {
+    if (SECOND)
+        hipLaunchKernelGGL((nt_persistent_kernel<P, true, SecondEpi, TM, TN>), dim3(grid),
+                           dim3(256), 0, s, entries, n_entries, count, queue);
+    else
+        hipLaunchKernelGGL((nt_persistent_kernel<P, false, FirstEpi<P>, TM, TN>), dim3(grid),
+                           dim3(256), 0, s, entries, n_entries, count, queue);
+    return hipGetLastError();
+}
+
+template <int P, bool SECOND>
+hipError_t persistent_shape(int tm, int tn, const NtEntry* entries, int n_entries,
+                            const int* count, int* queue, int grid, hipStream_t s) {
+    if (tm == 128 && tn == 128) return persistent<P, SECOND, 128, 128>(entries, n_entries, count, queue, grid, s);
+    if (tm == 64 && tn == 128) return persistent<P, SECOND, 64, 128>(entries, n_entries, count, queue, grid, s);
+    if (tm == 128 && tn == 64) return persistent<P, SECOND, 128, 64>(entries, n_entries, count, queue, grid, s);
+    if (tm == 64 && tn == 64) return persistent<P, SECOND, 64, 64>(entries, n_entries, count, queue, grid, s);
+    return hipErrorInvalidValue;
+}
+
 template <int P>
-hipError_t first(int ny, int nx, int layers, int levels, const NtBuffers& b, int max_tiles,
-                 hipStream_t s) {
+hipError_t first_direct(int layers, int levels, const NtBuffers& b, int max_tiles, hipStream_t s) {
     if (max_tiles <= 0) return hipSuccess;
-    FirstEpi<P> epi{b.tc, b.tc_ps, b.hdr};
-    const int* count = &b.hdr->first_tiles;
-    hipLaunchKernelGGL((nt_kernel<P, false, FirstEpi<P>>), dim3(max_tiles), dim3(256), 0, s,
-                       b.entries, layers * levels, count, 1, b.cb, b.cb_ps, b.fx, b.fx_ps, epi);
+    hipLaunchKernelGGL((nt_direct_kernel<P, false, FirstEpi<P>, 128, 128>), dim3(max_tiles),
+                       dim3(256), 0, s, b.first, layers * levels, &b.hdr->first_tiles, 1);
     return hipGetLastError();
 }
 
 template <int P>
-hipError_t second(int ny, int nx, int layers, int levels, int split, const NtBuffers& b,
-                  float2* partial, float2* out, int accumulate, hipStream_t s) {
-    SecondEpi epi{out, partial, ny, nx, split, accumulate};
-    const int* count = &b.hdr->second_tiles;
-    const int tiles = ((ny + T - 1) / T) * ((nx + T - 1) / T);
-    hipLaunchKernelGGL((nt_kernel<P, true, SecondEpi>), dim3(tiles * split), dim3(256), 0, s,
-                       b.entries + layers * levels, 1, count, split, b.fy, b.fy_ps, b.tc, b.tc_ps,
-                       epi);
+hipError_t second_direct(int ny, int nx, int split, const NtBuffers& b, hipStream_t s) {
+    const int tiles = nt_tiles(ny, nx, 128, 128);
+    hipLaunchKernelGGL((nt_direct_kernel<P, true, SecondEpi, 128, 128>), dim3(tiles * split),
+                       dim3(256), 0, s, b.second, 1, &b.hdr->second_tiles, split);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_nt_first(int ny, int nx, int layers, int levels, int precision,
-                           const NtBuffers& b, int max_tiles, hipStream_t s) {
-    if (precision == P_BF16) return first<P_BF16>(ny, nx, layers, levels, b, max_tiles, s);
-    if (precision == P_FP16) return first<P_FP16>(ny, nx, layers, levels, b, max_tiles, s);
-    return first<P_FP32>(ny, nx, layers, levels, b, max_tiles, s);
+hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffers& b,
+                           int max_tiles, hipStream_t s) {
+    if (precision == P_BF16) return first_direct<P_BF16>(layers, levels, b, max_tiles, s);
+    if (precision == P_FP16) return first_direct<P_FP16>(layers, levels, b, max_tiles, s);
+    return first_direct<P_FP32>(layers, levels, b, max_tiles, s);
 }
 
-hipError_t launch_nt_second(int ny, int nx, int layers, int levels, int precision, int split,
-                            const NtBuffers& b, float2* partial, float2* out, int accumulate,
+hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBuffers& b,
                             hipStream_t s) {
-    if (precision == P_BF16)
-        return second<P_BF16>(ny, nx, layers, levels, split, b, partial, out, accumulate, s);
-    if (precision == P_FP16)
-        return second<P_FP16>(ny, nx, layers, levels, split, b, partial, out, accumulate, s);
-    return second<P_FP32>(ny, nx, layers, levels, split, b, partial, out, accumulate, s);
+    if (precision == P_BF16) return second_direct<P_BF16>(ny, nx, split, b, s);
+    if (precision == P_FP16) return second_direct<P_FP16>(ny, nx, split, b, s);
+    return second_direct<P_FP32>(ny, nx, split, b, s);
+}
+
+hipError_t launch_nt_persistent(bool second, int precision, int tile_m, int tile_n,
+                                const NtEntry* entries, int n_entries, const int* tile_count,
+                                int* queue, int grid, hipStream_t s) {
+    if (grid <= 0 || n_entries <= 0) return hipSuccess;
+#define CGH_PERSIST(PR)                                                                          \
+    return second ? persistent_shape<PR, true>(tile_m, tile_n, entries, n_entries, tile_count,  \
+                                               queue, grid, s)                                   \
+                  : persistent_shape<PR, false>(tile_m, tile_n, entries, n_entries, tile_count, \
+                                                queue, grid, s);
+    if (precision == P_BF16) { CGH_PERSIST(P_BF16) }
+    if (precision == P_FP16) { CGH_PERSIST(P_FP16) }
+    CGH_PERSIST(P_FP32)
+#undef CGH_PERSIST
 }
 
 }  // namespace cgh

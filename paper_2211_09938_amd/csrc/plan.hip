@@ -71,47 +71,48 @@ __device__ int block_scan_incl(int v, int* sh) {
     return r;
 }
 
-__global__ __launch_bounds__(1024) void plan_kernel(int ny, int nx, int layers, int levels,
-                                                    const int* __restrict__ cnt_row,
-                                                    const int* __restrict__ cnt_col,
-                                                    int* __restrict__ seg_row,
-                                                    PlanHeader* __restrict__ hdr,
-                                                    NtEntry* __restrict__ entries) {
+struct PlanArgs {
+    int ny, nx, layers, levels, esize;
+    int tm1, tn1, tm2, tn2;  // tile shapes of the first and second contraction
+    const int* cnt_row;
+    const int* cnt_col;
+    int* seg_row;
+    int* tbeg;
+    PlanHeader* hdr;
+    NtEntry* first;
+    NtEntry* second;
+    const void* cb;
+    const void* fx;
+    const void* fy;
+    void* tc;
+    long long cb_ps, fx_ps, fy_ps, tc_ps;
+    float2* hologram;
+    float2* partial;
+    int accumulate;
+};
+
+__global__ __launch_bounds__(1024) void plan_kernel(PlanArgs a) {
     __shared__ int sh[1024];
     __shared__ int last[3];
-    const int n_dl = layers * levels;
-    const int tn = (nx + kNtTile - 1) / kNtTile;
+    const int n_dl = a.layers * a.levels;
+    const int tn1 = (a.nx + a.tn1 - 1) / a.tn1;
     int total_k = 0, total_t = 0, total_r = 0;
+    // pass 1: padded row counts -> k' segment offsets, tile counts -> tile prefix
     for (int base = 0; base < n_dl; base += 1024) {
         const int t = base + (int)threadIdx.x;
-        int cr = 0, cc = 0, pr = 0, tiles = 0;
+        int cr = 0, pr = 0, tiles = 0;
         if (t < n_dl) {
-            cr = cnt_row[t];
-            cc = cnt_col[t];
+            cr = a.cnt_row[t];
             pr = pad_kt(cr);
-            tiles = cr > 0 ? ((cr + kNtTile - 1) / kNtTile) * tn : 0;
+            tiles = cr > 0 ? ((cr + a.tm1 - 1) / a.tm1) * tn1 : 0;
         }
         const int ik = block_scan_incl(pr, sh);
         const int it = block_scan_incl(tiles, sh);
         const int ir = block_scan_incl(cr, sh);
         if (t < n_dl) {
-            const int d = t / levels, l = t % levels + 1;
-            const int seg = total_k + ik - pr;
-            seg_row[t] = seg;
-            NtEntry e;
-            e.M = cr;
-            e.N = nx;
-            e.K = pad_kt(cc);
-            e.lda = e.K;
-            e.ldb = e.K;
-            e.a_off = (long long)dl_cb_off(ny, nx, levels, d, l);
-            e.b_off = (long long)dl_fx_off(nx, levels, d, l);
-            e.out_off = seg;
-            e.tiles_n = tn;
-            e.tile_begin = total_t + it - tiles;
-            entries[t] = e;
+            a.seg_row[t] = total_k + ik - pr;
+            a.tbeg[t] = total_t + it - tiles;
         }
-        // totals of this chunk come from the last thread's inclusive values
         if (threadIdx.x == blockDim.x - 1) {
             last[0] = ik;
             last[1] = it;
@@ -123,23 +124,101 @@ __global__ __launch_bounds__(1024) void plan_kernel(int ny, int nx, int layers, 
         total_r += last[2];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        hdr->kpad = total_k;
-        hdr->first_tiles = total_t;
-        hdr->rows_active = total_r;
-        hdr->second_tiles = ((ny + kNtTile - 1) / kNtTile) * tn;
+    const int kpad = total_k;
+    // pass 2: the problem table
+    const char* cb = static_cast<const char*>(a.cb);
+    const char* fx = static_cast<const char*>(a.fx);
+    char* tc = static_cast<char*>(a.tc);
+    for (int t = threadIdx.x; t < n_dl; t += blockDim.x) {
+        const int d = t / a.levels, l = t % a.levels + 1;
         NtEntry e;
-        e.M = ny;
-        e.N = nx;
-        e.K = total_k;
-        e.lda = total_k;
-        e.ldb = total_k;
-        e.a_off = 0;
-        e.b_off = 0;
-        e.out_off = 0;
-        e.tiles_n = tn;
+        e.a = cb + dl_cb_off(a.ny, a.nx, a.levels, d, l) * a.esize;
+        e.b = fx + dl_fx_off(a.nx, a.levels, d, l) * a.esize;
+        e.out = tc + (size_t)a.seg_row[t] * a.esize;
+        e.partial = nullptr;
+        e.a_ps = a.cb_ps;
+        e.b_ps = a.fx_ps;
+        e.out_ps = a.tc_ps;
+        e.M = a.cnt_row[t];
+        e.N = a.nx;
+        e.K = pad_kt(a.cnt_col[t]);
+        e.lda = e.K;
+        e.ldb = e.K;
+        e.out_ld = kpad;
+        e.tiles_n = tn1;
+        e.tile_begin = a.tbeg[t];
+        e.accumulate = 0;
+        e.tile_m = a.tm1;
+        e.tile_n = a.tn1;
+        a.first[t] = e;
+    }
+    if (threadIdx.x == 0) {
+        a.hdr->kpad = kpad;
+        a.hdr->first_tiles = total_t;
+        a.hdr->rows_active = total_r;
+        a.hdr->second_tiles = nt_tiles(a.ny, a.nx, a.tm2, a.tn2);
+        NtEntry e;
+        e.a = a.fy;
+        e.b = a.tc;
+        e.out = a.hologram;
+        e.partial = a.partial;
+        e.a_ps = a.fy_ps;
+        e.b_ps = a.tc_ps;
+        e.out_ps = 0;
+        e.M = a.ny;
+        e.N = a.nx;
+        e.K = kpad;
+        e.lda = kpad;
+        e.ldb = kpad;
+        e.out_ld = a.nx;
+        e.tiles_n = (a.nx + a.tn2 - 1) / a.tn2;
         e.tile_begin = 0;
-        entries[n_dl] = e;
+        e.accumulate = a.accumulate;
+        e.tile_m = a.tm2;
+        e.tile_n = a.tn2;
+        a.second[0] = e;
+    }
+}
+
+// Merges the per-scene problem tables of a batch: scene i's first-contraction
+// entries (first_off[i] .. first_off[i+1]) and its second-contraction entry get
+// the tile offset of every scene before it; writes the batch tile totals and
+// clears the two work-queue counters.
+__global__ __launch_bounds__(1024) void batch_prefix_kernel(const PlanHeader* __restrict__ hdrs,
+                                                            int n_scenes,
+                                                            const int* __restrict__ first_off,
+                                                            NtEntry* __restrict__ first,
+                                                            NtEntry* __restrict__ second,
+                                                            int* __restrict__ counts,
+                                                            int* __restrict__ queues) {
+    __shared__ int sh[1024];
+    __shared__ int last[2];
+    int run1 = 0, run2 = 0;
+    for (int base = 0; base < n_scenes; base += 1024) {
+        const int i = base + (int)threadIdx.x;
+        const int v1 = i < n_scenes ? hdrs[i].first_tiles : 0;
+        const int v2 = i < n_scenes ? hdrs[i].second_tiles : 0;
+        const int c1 = block_scan_incl(v1, sh);
+        const int c2 = block_scan_incl(v2, sh);
+        if (i < n_scenes) {
+            const int o1 = run1 + c1 - v1;
+            for (int e = first_off[i]; e < first_off[i + 1]; ++e) first[e].tile_begin += o1;
+            second[i].tile_begin = run2 + c2 - v2;
+        }
+        if (threadIdx.x == blockDim.x - 1) {
+            last[0] = c1;
+            last[1] = c2;
+        }
+        __syncthreads();
+        run1 += last[0];
+        run2 += last[1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        counts[0] = run1;
+        counts[1] = run2;
+        queues[0] = 0;
+        queues[1] = 0;
     }
 }
 
@@ -279,14 +358,42 @@ int grid_for(long long elems) {
 }  // namespace
 
 hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int levels,
-                          size_t flags_layer, const NtBuffers& b, hipStream_t s) {
+                          size_t flags_layer, int precision, const int* tiles,
+                          const NtBuffers& b, const NtOutput& o, hipStream_t s) {
     const int n_dl = layers * levels;
     hipLaunchKernelGGL(lists_kernel, dim3(n_dl), dim3(1024), 0, s, flags, ny, nx, levels,
                        flags_layer, b.rowlist, b.collist, b.cnt_row, b.cnt_col);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, ny, nx, layers, levels, b.cnt_row,
-                       b.cnt_col, b.seg_row, b.hdr, b.entries);
+    PlanArgs a{};
+    a.ny = ny;
+    a.nx = nx;
+    a.layers = layers;
+    a.levels = levels;
+    a.esize = precision == P_FP32 ? 4 : 2;
+    a.tm1 = tiles[0];
+    a.tn1 = tiles[1];
+    a.tm2 = tiles[2];
+    a.tn2 = tiles[3];
+    a.cnt_row = b.cnt_row;
+    a.cnt_col = b.cnt_col;
+    a.seg_row = b.seg_row;
+    a.tbeg = b.tbeg;
+    a.hdr = b.hdr;
+    a.first = b.first;
+    a.second = b.second;
+    a.cb = b.cb;
+    a.fx = b.fx;
+    a.fy = b.fy;
+    a.tc = b.tc;
+    a.cb_ps = (long long)b.cb_ps;
+    a.fx_ps = (long long)b.fx_ps;
+    a.fy_ps = (long long)b.fy_ps;
+    a.tc_ps = (long long)b.tc_ps;
+    a.hologram = o.hologram;
+    a.partial = o.partial;
+    a.accumulate = o.accumulate;
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 
@@ -306,6 +413,14 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(cb_kernel<P>, dim3(grid_for(big_c), n_dl), dim3(256), 0, s, coef,
                        b.rowlist, b.collist, b.cnt_row, b.cnt_col, ny, nx, levels, b.cb, b.cb_ps);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_prefix(const PlanHeader* hdrs, int n_scenes, const int* first_off,
+                               NtEntry* first, NtEntry* second, int* counts, int* queues,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(batch_prefix_kernel, dim3(1), dim3(1024), 0, s, hdrs, n_scenes, first_off,
+                       first, second, counts, queues);
     return hipGetLastError();
 }
 

@@ -65,11 +65,10 @@ def ellipse_mask(rng, ny, nx, fraction, count=1, tol=0.01):
     cx = rng.uniform(0.3 * nx, 0.7 * nx, count)
     th = rng.uniform(0.0, np.pi, count)
     ratio = rng.uniform(0.5, 1.0, count)
-    yy = np.arange(ny, dtype=np.float64)[:, None] + 0.5
-    xx = np.arange(nx, dtype=np.float64)[None, :] + 0.5
-
-    def union(scale):
-        m = np.zeros((ny, nx), dtype=bool)
+    def union(scale, step):
+        yy = np.arange(0, ny, step, dtype=np.float64)[:, None] + 0.5
+        xx = np.arange(0, nx, step, dtype=np.float64)[None, :] + 0.5
+        m = np.zeros((yy.shape[0], xx.shape[1]), dtype=bool)
         for i in range(count):
             dy, dx = yy - cy[i], xx - cx[i]
             u = dx * np.cos(th[i]) + dy * np.sin(th[i])
@@ -79,19 +78,21 @@ def ellipse_mask(rng, ny, nx, fraction, count=1, tol=0.01):
             m |= (u / a) ** 2 + (v / b) ** 2 <= 1.0
         return m
 
+    # bisect the common scale on a grid of at most ~256 x 256 samples, then
+    # draw the mask at full resolution with the scale found
+    step = max(1, max(ny, nx) // 256)
     lo, hi = 0.0, 2.0 * max(ny, nx)
-    m = union(hi)
+    mid = hi
     for _ in range(60):
         mid = 0.5 * (lo + hi)
-        m = union(mid)
-        f = m.mean()
+        f = union(mid, step).mean()
         if abs(f - fraction) <= tol:
             break
         if f < fraction:
             lo = mid
         else:
             hi = mid
-    return m.astype(np.float32)
+    return union(mid, 1).astype(np.float32)
 
 
 def smooth_depth_layers(rng, ny, nx, planes, z_range=(0.1, 0.3)):

@@ -132,3 +132,51 @@ def test_haar_validation():
     assert lib.cgh_haar_dwt(BOGUS, 64, 64, 3, BOGUS, None) == INVALID  # aliasing in/out
     assert lib.cgh_haar_idwt(BOGUS, 64, 64, 0, P(0x2000), None) == SHAPE
     assert lib.cgh_haar_dwt(None, 0, 64, 3, None, None) == OK
+
+
+def _scene_array(n=1, **over):
+    arr = (cgh.SceneDesc * n)()
+    z = (ctypes.c_double * 1)(0.2)
+    for i in range(n):
+        arr[i].object = BOGUS
+        arr[i].layer_index = None
+        arr[i].n_layers = 1
+        arr[i].z = ctypes.cast(z, ctypes.POINTER(ctypes.c_double))
+        arr[i].saliency = None
+        arr[i].ny = 64
+        arr[i].nx = 64
+        arr[i].hologram = P(0x2000)
+        for k, v in over.items():
+            setattr(arr[i], k, v)
+    return arr, z
+
+
+def plan_create(arr, n, levels=3, lam=532e-9, pitch=8e-6, prec=0, flags=0):
+    handle = ctypes.c_void_p()
+    st = cgh.lib().cgh_plan_create(arr, n, levels, lam, pitch, None, prec, flags, None, None,
+                                   ctypes.byref(handle))
+    return st, handle
+
+
+def test_plan_validation_and_forced_allocation_failure(monkeypatch):
+    lib = cgh.lib()
+    arr, z = _scene_array(3)
+    assert lib.cgh_plan_create(None, 3, 3, 532e-9, 8e-6, None, 0, 0, None, None,
+                               ctypes.byref(ctypes.c_void_p())) == INVALID
+    assert lib.cgh_plan_create(arr, 3, 3, 532e-9, 8e-6, None, 0, 0, None, None, None) == INVALID
+    assert plan_create(arr, 0)[0] == INVALID
+    assert plan_create(arr, 3, flags=1)[0] == INVALID        # accumulate is per call, not per plan
+    assert plan_create(arr, 3, lam=-1.0)[0] == INVALID
+    assert plan_create(arr, 3, levels=4)[0] == UNSUP
+    bad, z2 = _scene_array(2, ny=60)
+    assert plan_create(bad, 2)[0] == SHAPE
+    bad, z3 = _scene_array(2, object=None)
+    assert plan_create(bad, 2)[0] == INVALID
+    bad, z4 = _scene_array(2, n_layers=2)                    # two layers need a layer map
+    assert plan_create(bad, 2)[0] == INVALID
+    monkeypatch.setenv("CGH_TEST_FAIL_ALLOC", "1")
+    st, h = plan_create(arr, 3)
+    assert st == OOM and not h.value
+    assert lib.cgh_plan_execute(None, None) == INVALID
+    assert lib.cgh_plan_destroy(None) == INVALID
+    assert lib.cgh_plan_get_info(None, None) == INVALID

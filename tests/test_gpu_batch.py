@@ -1,0 +1,141 @@
+"""GPU tests of the batched plan (cgh_plan_*): one persistent, graph-captured
+launch per contraction over scenes of uneven size.
+
+Each scene of a batch must match its own single-scene call (same method; only
+the tile schedule and the K split differ, so agreement is to FP32 rounding,
+rel-L2 <= 1e-6) and the FP64 oracle on sampled pixels (rel-L2 <= 1e-5 for FP32,
+1e-3 for the split forms).  Graph replays are checked against the eager result
+with unrelated eager work and synchronisations between the replays.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from paper_2211_09938_amd import scenes
+
+from helpers import oracle_hologram, rel_l2, sample_pixels, to_dev
+
+pytestmark = pytest.mark.gpu
+os.environ.setdefault("ORACLE_WORKERS", "8")
+
+
+def cgh():
+    from paper_2211_09938_amd import cgh as m
+
+    return m
+
+
+def make_batch(seed=7, sides=(64, 128, 136, 256, 392), n=8):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        ny = int(rng.choice(sides))
+        nx = int(rng.choice(sides))
+        planes = int(rng.integers(1, 4))
+        frac = float(rng.uniform(0.05, 0.6))
+        out.append(scenes.random_scene(1000 + i, ny, nx, planes=planes, fraction=frac,
+                                       z_range=(0.05, 0.3)))
+    return out
+
+
+def dev_scene(s):
+    d = {"obj": to_dev(s.obj), "z": s.z, "saliency": to_dev(s.saliency)}
+    if s.layer is not None:
+        d["layer_index"] = to_dev(s.layer)
+    return d
+
+
+def single(s, precision):
+    import torch
+
+    d = dev_scene(s)
+    h = cgh().progressive_hologram(d["obj"], s.z, s.lam, s.pitch, 3, d["saliency"],
+                                   d.get("layer_index"), precision=precision)
+    torch.cuda.synchronize()
+    return h.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16_split"])
+def test_batch_matches_single_scene_calls_and_oracle(precision, tmp_path):
+    import torch
+
+    batch = make_batch()
+    plan = cgh().Plan([dev_scene(s) for s in batch], scenes.WAVELENGTH, scenes.PITCH,
+                      precision=precision, tune_cache=str(tmp_path / "tune.jsonl"))
+    plan.execute()
+    torch.cuda.synchronize()
+    hs = [h.cpu().numpy() for h in plan.holograms]
+    for s, h in zip(batch, hs):
+        assert rel_l2(h, single(s, precision)) <= 1e-6
+    tol = 1e-5 if precision == "fp32" else 1e-3
+    for k in (0, 3, 6):
+        s = batch[k]
+        ys, xs = sample_pixels(*s.shape, seed=k, n_random=48)
+        assert rel_l2(hs[k][ys, xs], oracle_hologram(s, pixels=(ys, xs))) <= tol
+    info = plan.info()
+    assert info["n_scenes"] == len(batch) and not info["from_cache"]
+    plan.close()
+
+
+def test_graph_replays_with_eager_work_between(tmp_path):
+    import torch
+
+    batch = make_batch(seed=11, n=6)
+    devs = [dev_scene(s) for s in batch]
+    plan = cgh().Plan(devs, scenes.WAVELENGTH, scenes.PITCH, tune_cache=str(tmp_path / "t.jsonl"))
+    plan.execute()
+    torch.cuda.synchronize()
+    first = [h.cpu().numpy().copy() for h in plan.holograms]
+    eager = [single(s, "fp32") for s in batch]
+    for rep in range(3):
+        # unrelated eager work on the same stream, then a replay
+        junk = single(batch[rep], "fp32")
+        assert junk.shape == batch[rep].shape
+        plan.execute()
+        torch.cuda.synchronize()
+        for h, f, e in zip(plan.holograms, first, eager):
+            got = h.cpu().numpy()
+            assert np.array_equal(got, f)
+            assert rel_l2(got, e) <= 1e-6
+    # the graph reads the inputs' current contents: scaling every object scales every hologram
+    for d in devs:
+        d["obj"].mul_(0.5)
+    plan.execute()
+    torch.cuda.synchronize()
+    for h, f in zip(plan.holograms, first):
+        assert rel_l2(h.cpu().numpy(), 0.5 * f) <= 1e-6
+    plan.close()
+
+
+def test_tune_cache_is_reused(tmp_path):
+    batch = make_batch(seed=13, n=4)
+    cache = str(tmp_path / "tune.jsonl")
+    p1 = cgh().Plan([dev_scene(s) for s in batch], scenes.WAVELENGTH, scenes.PITCH,
+                    precision="bf16_split", tune_cache=cache)
+    i1 = p1.info()
+    p1.close()
+    p2 = cgh().Plan([dev_scene(s) for s in batch], scenes.WAVELENGTH, scenes.PITCH,
+                    precision="bf16_split", tune_cache=cache)
+    i2 = p2.info()
+    p2.close()
+    assert not i1["from_cache"] and i2["from_cache"]
+    assert i1["first_tile"] == i2["first_tile"] and i1["second_tile"] == i2["second_tile"]
+    with open(cache) as f:
+        lines = [ln for ln in f if ln.strip()]
+    assert len(lines) == 1 and '"first": [' in lines[0]
+
+
+def test_empty_and_single_scene_batches():
+    import torch
+
+    s = scenes.random_scene(77, 64, 64)
+    d = dev_scene(s)
+    empty = {"obj": torch.zeros((0, 64), device="cuda"), "z": [0.2]}
+    plan = cgh().Plan([empty, d], scenes.WAVELENGTH, scenes.PITCH)
+    plan.execute()
+    torch.cuda.synchronize()
+    assert rel_l2(plan.holograms[1].cpu().numpy(), single(s, "fp32")) <= 1e-6
+    assert plan.info()["n_scenes"] == 1
+    plan.close()
