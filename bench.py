@@ -2,10 +2,13 @@
 """Throughput of the progressive saliency-guided hologram on one MI355X.
 
 One step = one full hot-path pass (fused DWT/saliency/masking, FP64 fringe
-tables, both contractions, optional split-K reduce) producing one complex64
-hologram from inputs already resident in HBM.  Default workload: a 2048 x 2048
-object with a smooth depth map quantised to 8 planes (z = 0.1-0.3 m), ~20%
-saliency, 3 Haar levels, lambda 532 nm, pitch 8 um (seeded, synthetic).
+tables, active lists and operand panels, both contractions, optional split-K
+reduce) producing one complex64 hologram per scene from inputs already resident
+in HBM.  Default workload: a 2048 x 2048 object with a smooth depth map
+quantised to 8 planes (z = 0.1-0.3 m), ~20% saliency, 3 Haar levels,
+lambda 532 nm, pitch 8 um (seeded, synthetic).  The headline is the FP32 form;
+the BF16 and FP16 split forms are measured on the same inputs in the same run
+(``forms``), each with its relative L2 error against the FP64 oracle sample.
 
 Prints one JSON line: holograms/s, ms per step, the dominant kernel's roofline
 (second contraction: algorithmic flops per launch over its average duration,
@@ -28,6 +31,9 @@ import numpy as np  # noqa: E402
 from paper_2211_09938_amd import scenes  # noqa: E402
 
 PEAKS_TFLOPS = {"fp32": 157.3, "bf16_split": 2516.6, "fp16_split": 2516.6}
+# real MFMA products issued per algorithmic real product
+ISSUE_FACTOR = {"fp32": 1.0, "bf16_split": 3.0, "fp16_split": 3.0}
+DTYPES = {"fp32": "f32", "bf16_split": "bf16x3-split/f32-acc", "fp16_split": "f16x3-split/f32-acc"}
 METRIC = "holograms/sec and Gpoint*pixel/s at 2048^2, FP32 vs BF16-split at stated rel-L2"
 
 WORKLOADS = {
@@ -39,6 +45,10 @@ WORKLOADS = {
                   "3 Haar levels, lambda 532 nm, pitch 8 um"),
     "tiny128": (scenes.tiny,
                 "128x128 object, one plane z=0.2 m, ~25% saliency, 3 Haar levels"),
+    "batch64": (scenes.batched,
+                "64 scenes, sides uniform in {256,512,768,1024,1536,2048}, 1-4 depth planes, "
+                "saliency 5-60% from 1-3 ellipses, 3 Haar levels; one batched plan "
+                "(persistent contractions, autotuned tiles, HIP graph)"),
 }
 
 
@@ -47,11 +57,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="fp32", choices=sorted(PEAKS_TFLOPS))
+    ap.add_argument("--precision", default="fp32", choices=sorted(PEAKS_TFLOPS),
+                    help="form reported as the headline value")
+    ap.add_argument("--forms", default="all", choices=["all", "one"],
+                    help="also measure the other precision forms (all) or only --precision")
     ap.add_argument("--workload", default="depth2048x8", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-pixels", type=int, default=1536,
                     help="hologram pixels the oracle evaluates for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-cache", default=None, help="tile-shape cache for batched plans")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference for scaling hardware byte counters) and exit")
@@ -101,6 +115,121 @@ def cpu_baseline(scene, n_pixels, seed=12345):
     }
 
 
+def roofline(stats, prec, avg_ms, kernel):
+    """Second contraction: algorithmic flops per launch / average launch time."""
+    achieved = stats["flops_second"] / (avg_ms * 1e-3) / 1e12
+    peak = PEAKS_TFLOPS[prec]
+    issued = achieved * ISSUE_FACTOR[prec] * stats["flops_second_issued"] / max(1.0, stats["flops_second"])
+    return {
+        "bound": "mfma",
+        "kernel": kernel,
+        "achieved": achieved,
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": achieved / peak,
+        "traffic": None,
+        "flops_per_launch": stats["flops_second"],
+        "avg_launch_ms": avg_ms,
+        "issued_mfma_frac": issued / peak,
+    }
+
+
+def run_single(scene, prec, steps, warmup):
+    import torch
+
+    from paper_2211_09938_amd import cgh
+
+    dev = torch.device("cuda:0")
+    ny, nx = scene.shape
+    obj = torch.from_numpy(scene.obj).to(dev)
+    sal = None if scene.saliency is None else torch.from_numpy(scene.saliency).to(dev)
+    lay = None if scene.layer is None else torch.from_numpy(scene.layer).to(dev)
+    n_layers = len(scene.z)
+    ws = torch.empty(cgh.workspace_size(ny, nx, n_layers, scene.levels, prec), dtype=torch.uint8,
+                     device=dev)
+    out = torch.empty((ny, nx), dtype=torch.complex64, device=dev)
+
+    def step():
+        cgh.progressive_hologram(obj, scene.z, scene.lam, scene.pitch, scene.levels, sal, lay,
+                                 precision=prec, out=out, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    cgh.profile_enable(True)
+    cgh.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = cgh.profile_read(reset=True)
+    cgh.profile_enable(False)
+    stats = cgh.workspace_stats(ws, ny, nx, n_layers, scene.levels, prec)
+    sec_ms, sec_n = prof["second"]
+    kernel = f"second contraction (nt_direct_kernel<{prec}, complex A, 128x128>)"
+    return {
+        "value": steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "stages_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
+        "work": stats,
+        "roofline": roofline(stats, prec, sec_ms / max(1, sec_n), kernel),
+        "_out": out.cpu().numpy(),
+    }
+
+
+def run_batch(batch, prec, steps, warmup, tune_cache):
+    import torch
+
+    from paper_2211_09938_amd import cgh
+
+    dev = torch.device("cuda:0")
+    descs = []
+    for s in batch:
+        d = {"obj": torch.from_numpy(s.obj).to(dev), "z": s.z,
+             "saliency": torch.from_numpy(s.saliency).to(dev)}
+        if s.layer is not None:
+            d["layer_index"] = torch.from_numpy(s.layer).to(dev)
+        descs.append(d)
+    t_plan = time.perf_counter()
+    plan = cgh.Plan(descs, scenes.WAVELENGTH, scenes.PITCH, precision=prec, tune_cache=tune_cache)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t_plan
+    for _ in range(warmup):
+        plan.execute()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # per-kernel durations: the same kernels launched eagerly with stage events
+    cgh.profile_enable(True)
+    cgh.profile_read(reset=True)
+    for _ in range(3):
+        plan.execute()
+    torch.cuda.synchronize()
+    prof = cgh.profile_read(reset=True)
+    cgh.profile_enable(False)
+    stats = plan.stats()
+    info = plan.info()
+    sec_ms, sec_n = prof["second"]
+    n = len(batch)
+    res = {
+        "value": n * steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "stages_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
+        "work": stats,
+        "roofline": roofline(stats, prec, sec_ms / max(1, sec_n),
+                             f"second contraction (nt_persistent_kernel<{prec}, "
+                             f"{info['second_tile'][0]}x{info['second_tile'][1]}>)"),
+        "plan": dict(info, create_s=t_plan),
+    }
+    plan.close()
+    return res
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -111,87 +240,67 @@ def main():
               "(the hologram would shard by column bands, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     make, desc = WORKLOADS[args.workload]
-    scene = make()
-    ny, nx = scene.shape
+    work = make()
+    batch = isinstance(work, list)
+    scene = work[0] if batch else work
 
-    base = None if args.no_cpu_baseline else cpu_baseline(scene, args.cpu_pixels)
+    base = None if (args.no_cpu_baseline or batch) else cpu_baseline(scene, args.cpu_pixels)
 
     import torch
 
-    from paper_2211_09938_amd import cgh
-
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a GPU")
-    dev = torch.device("cuda:0")
-    obj = torch.from_numpy(scene.obj).to(dev)
-    sal = None if scene.saliency is None else torch.from_numpy(scene.saliency).to(dev)
-    lay = None if scene.layer is None else torch.from_numpy(scene.layer).to(dev)
-    n_layers = len(scene.z)
-    ws = torch.empty(cgh.workspace_size(ny, nx, n_layers, scene.levels, args.precision),
-                     dtype=torch.uint8, device=dev)
-    out = torch.empty((ny, nx), dtype=torch.complex64, device=dev)
-
-    def step():
-        cgh.progressive_hologram(obj, scene.z, scene.lam, scene.pitch, scene.levels, sal, lay,
-                                 precision=args.precision, out=out, workspace=ws)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    cgh.profile_enable(True)
-    cgh.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = cgh.profile_read(reset=True)
-    cgh.profile_enable(False)
-    stats = cgh.workspace_stats(ws, ny, nx, n_layers, scene.levels, args.precision)
-
-    holo_s = args.steps / elapsed
-    sec_ms, sec_n = prof["second"]
-    avg_ms = sec_ms / max(1, sec_n)
-    achieved = stats["flops_second"] / (avg_ms * 1e-3) / 1e12
-    peak = PEAKS_TFLOPS[args.precision]
-    points = float(ny * nx)
+    precs = [args.precision]
+    if args.forms == "all":
+        precs += [p for p in ("fp32", "bf16_split", "fp16_split") if p != args.precision]
+    forms = {}
+    for prec in precs:
+        if batch:
+            forms[prec] = run_batch(work, prec, args.steps, args.warmup, args.tune_cache)
+        else:
+            forms[prec] = run_single(scene, prec, args.steps, args.warmup)
+        out = forms[prec].pop("_out", None)
+        if base is not None and out is not None:
+            ys, xs, vals = base["_pixels"]
+            got = out[ys, xs].astype(np.complex128)
+            forms[prec]["rel_l2_vs_oracle"] = float(np.linalg.norm(got - vals) / np.linalg.norm(vals))
+        forms[prec]["dtype"] = DTYPES[prec]
+    head = forms[args.precision]
+    if batch:
+        points_pixels = sum(float(s.obj.size) ** 2 for s in work) / len(work)
+        config = {"workload": args.workload, "description": desc, "scenes": len(work),
+                  "sides": sorted({s.shape[0] for s in work}), "precision": args.precision}
+    else:
+        points_pixels = float(scene.obj.size) ** 2
+        config = {"workload": args.workload, "description": desc, "ny": scene.shape[0],
+                  "nx": scene.shape[1], "planes": len(scene.z), "levels": scene.levels,
+                  "precision": args.precision}
     line = {
         "metric": METRIC,
-        "value": holo_s,
+        "value": head["value"],
         "unit": "holograms/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16_split": "bf16x3-split/f32-acc",
-                  "fp16_split": "f16x3-split/f32-acc"}[args.precision],
+        "dtype": DTYPES[args.precision],
         "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "ny": ny, "nx": nx,
-                   "planes": n_layers, "levels": scene.levels, "precision": args.precision},
-        "gpoint_pixel_per_s": holo_s * points * points / 1e9,
-        "roofline": {
-            "bound": "mfma",
-            "kernel": ("second contraction (cgemm_f32_kernel<FwdS2>)" if args.precision == "fp32"
-                       else "second contraction (cgemm_split_kernel<FwdS2>)"),
-            "achieved": achieved,
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": achieved / peak,
-            "traffic": None,
-            "flops_per_launch": stats["flops_second"],
-            "avg_launch_ms": avg_ms,
-        },
-        "stages_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
-        "work": stats,
+        "config": config,
+        "gpoint_pixel_per_s": head["value"] * points_pixels / 1e9,
+        "roofline": head["roofline"],
+        "stages_ms_per_step": head["stages_ms_per_step"],
+        "work": head["work"],
     }
+    if "rel_l2_vs_oracle" in head:
+        line["rel_l2_vs_oracle"] = head["rel_l2_vs_oracle"]
+    if batch:
+        line["plan"] = head["plan"]
+    line["forms"] = {p: {k: v for k, v in f.items() if k != "work"} for p, f in forms.items()}
     if base is not None:
-        ys, xs, vals = base.pop("_pixels")
-        got = out.cpu().numpy()[ys, xs].astype(np.complex128)
-        line["rel_l2_vs_oracle"] = float(np.linalg.norm(got - vals) / np.linalg.norm(vals))
+        base.pop("_pixels")
         line["cpu_baseline"] = base
     print(json.dumps(line), flush=True)
 

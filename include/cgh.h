@@ -197,7 +197,10 @@ int cgh_plan_create(const cgh_scene* scenes /* [host] */, int n_scenes, int leve
                     const char* tune_cache_path, void* stream, cgh_plan** plan /* [host] */);
 
 /* Launches the captured graph on `stream`: every scene's hologram is
- * recomputed from the current contents of its input buffers. */
+ * recomputed from the current contents of its input buffers.  While stage
+ * profiling is on (cgh_profile_enable) the same kernels are launched eagerly
+ * instead, with event pairs around the per-scene stages (CGH_STAGE_PLAN) and
+ * the two persistent contractions (CGH_STAGE_FIRST, CGH_STAGE_SECOND). */
 int cgh_plan_execute(cgh_plan* plan, void* stream);
 
 /* Frees the plan (waits for nothing: the caller synchronises first). */
@@ -215,6 +218,10 @@ typedef struct {
 } cgh_plan_info;
 
 int cgh_plan_get_info(const cgh_plan* plan, cgh_plan_info* info /* [host] */);
+
+/* Work counts of the plan's last execution, summed over its scenes (the
+ * cgh_stats of every scene added up; split_k = 1).  Synchronises `stream`. */
+int cgh_plan_get_stats(const cgh_plan* plan, struct cgh_stats_s* stats /* [host] */, void* stream);
 
 /* ------------------------------------------------------------ diagnostics */
 
@@ -241,7 +248,7 @@ int cgh_profile_enable(int on);
 int cgh_profile_read(double* ms, long long* launches, int reset);
 
 /* Work counts of the last cgh_progressive_hologram that used `workspace`. */
-typedef struct {
+typedef struct cgh_stats_s {
     long long coef_rows_active;  /* nonzero rows of every layer's and level's coefficient square:
                                     the K extent of the second contraction                    */
     long long coef_rows_total;

@@ -64,6 +64,7 @@ SIGNATURES = {
     "cgh_plan_execute": (_c_int, [_vp, _vp]),
     "cgh_plan_destroy": (_c_int, [_vp]),
     "cgh_plan_get_info": (_c_int, [_vp, _vp]),
+    "cgh_plan_get_stats": (_c_int, [_vp, _vp, _vp]),
 }
 
 
@@ -374,6 +375,12 @@ class Plan:
                 "second_tile": tuple(inf.second_tile), "from_cache": bool(inf.from_cache),
                 "persistent_grid": inf.persistent_grid, "tune_ms_first": inf.tune_ms_first,
                 "tune_ms_second": inf.tune_ms_second, "device_bytes": inf.device_bytes}
+
+    def stats(self):
+        st = Stats()
+        _check(lib().cgh_plan_get_stats(self._handle, ctypes.byref(st), _stream()),
+               "cgh_plan_get_stats")
+        return st.as_dict()
 
     def close(self):
         if getattr(self, "_handle", None):

@@ -11,6 +11,10 @@
 
 namespace cgh {
 namespace host {
+Profiler& profiler() {
+    static Profiler p;
+    return p;
+}
 thread_local int g_last_hip_error = 0;
 int hip_status(hipError_t e) {
     if (e == hipSuccess) return CGH_SUCCESS;
@@ -23,71 +27,6 @@ int hip_status(hipError_t e) {
 namespace {
 
 using namespace cgh::host;
-
-// Per-stage HIP event timing of the forward call (diagnostics).
-struct Profiler {
-    std::mutex mu;
-    bool on = false;
-    std::vector<hipEvent_t> pool;
-    struct Pair { int stage; hipEvent_t a, b; };
-    std::vector<Pair> pending;
-    double ms[CGH_STAGE_COUNT] = {};
-    long long launches[CGH_STAGE_COUNT] = {};
-
-    hipEvent_t take() {
-        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-};
-
-Profiler& profiler() {
-    static Profiler p;
-    return p;
-}
-
-// Records an event pair around one stage when profiling is on.
-struct StageTimer {
-    hipStream_t s;
-    int stage;
-    hipEvent_t a = nullptr, b = nullptr;
-    StageTimer(hipStream_t st, int stg) : s(st), stage(stg) {
-        Profiler& p = profiler();
-        std::lock_guard<std::mutex> g(p.mu);
-        if (!p.on) return;
-        a = p.take();
-        b = p.take();
-        if (a && b && hipEventRecord(a, s) == hipSuccess) return;
-        if (a) p.pool.push_back(a);
-        if (b) p.pool.push_back(b);
-        a = b = nullptr;
-    }
-    void done() {
-        if (!a || !b) return;
-        if (hipEventRecord(b, s) != hipSuccess) return;  // destructor returns both to the pool
-        Profiler& p = profiler();
-        std::lock_guard<std::mutex> g(p.mu);
-        p.pending.push_back({stage, a, b});
-        a = b = nullptr;
-    }
-    ~StageTimer() {
-        if (a || b) {  // stage failed before done(): give the events back unrecorded
-            Profiler& p = profiler();
-            std::lock_guard<std::mutex> g(p.mu);
-            if (a) p.pool.push_back(a);
-            if (b) p.pool.push_back(b);
-        }
-    }
-};
-
-template <class F>
-hipError_t timed(hipStream_t s, int stage, F&& f) {
-    StageTimer t(s, stage);
-    hipError_t e = f();
-    if (e == hipSuccess) t.done();
-    return e;
-}
 
 }  // namespace
 

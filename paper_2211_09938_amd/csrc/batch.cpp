@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -56,9 +57,9 @@ struct Events {
     hipEvent_t a = nullptr, b = nullptr, c = nullptr;
 };
 
-// Enqueues the whole batch on `s` with the given tile shapes; records ev (if
-// given) before the first contraction, between the two, and after the second.
-hipError_t enqueue(const cgh_plan& p, hipStream_t s, const int* tiles, const Events* ev) {
+// Per-scene stages of the whole batch (coefficients, fringe tables, active
+// lists, plans, panels), then the merge of the problem tables.
+hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s, const int* tiles) {
     Optics op;
     for (size_t i = 0; i < p.scenes.size(); ++i) {
         const cgh_plan::Scene& sc = p.scenes[i];
@@ -93,17 +94,28 @@ hipError_t enqueue(const cgh_plan& p, hipStream_t s, const int* tiles, const Eve
                                            nl, p.levels, p.precision, nb, s);
         if (e != hipSuccess) return e;
     }
-    const int n = (int)p.scenes.size();
-    hipError_t e = cgh::launch_batch_prefix(p.hdrs, n, p.first_off, p.first, p.second, p.counts,
-                                            p.queues, s);
+    return cgh::launch_batch_prefix(p.hdrs, (int)p.scenes.size(), p.first_off, p.first, p.second,
+                                    p.counts, p.queues, s);
+}
+
+hipError_t enqueue_first(const cgh_plan& p, hipStream_t s, const int* tiles) {
+    return cgh::launch_nt_persistent(false, p.precision, tiles[0], tiles[1], p.first, p.n_first,
+                                     p.counts, p.queues, p.grid, s);
+}
+
+hipError_t enqueue_second(const cgh_plan& p, hipStream_t s, const int* tiles) {
+    return cgh::launch_nt_persistent(true, p.precision, tiles[2], tiles[3], p.second,
+                                     (int)p.scenes.size(), p.counts + 1, p.queues + 1, p.grid, s);
+}
+
+// Enqueues the whole batch on `s` with the given tile shapes; records ev (if
+// given) before the first contraction, between the two, and after the second.
+hipError_t enqueue(const cgh_plan& p, hipStream_t s, const int* tiles, const Events* ev) {
+    hipError_t e = enqueue_prep(p, s, tiles);
     if (e == hipSuccess && ev) e = hipEventRecord(ev->a, s);
-    if (e == hipSuccess)
-        e = cgh::launch_nt_persistent(false, p.precision, tiles[0], tiles[1], p.first, p.n_first,
-                                      p.counts, p.queues, p.grid, s);
+    if (e == hipSuccess) e = enqueue_first(p, s, tiles);
     if (e == hipSuccess && ev) e = hipEventRecord(ev->b, s);
-    if (e == hipSuccess)
-        e = cgh::launch_nt_persistent(true, p.precision, tiles[2], tiles[3], p.second, n,
-                                      p.counts + 1, p.queues + 1, p.grid, s);
+    if (e == hipSuccess) e = enqueue_second(p, s, tiles);
     if (e == hipSuccess && ev) e = hipEventRecord(ev->c, s);
     return e;
 }
@@ -340,7 +352,66 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
 
 int cgh_plan_execute(cgh_plan* plan, void* stream) {
     if (!plan || !plan->exec) return CGH_ERROR_INVALID_VALUE;
-    return hip_status(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    bool profiling;
+    {
+        Profiler& pr = profiler();
+        std::lock_guard<std::mutex> g(pr.mu);
+        profiling = pr.on;
+    }
+    if (!profiling) return hip_status(hipGraphLaunch(plan->exec, s));
+    // diagnostics: the same kernels launched eagerly, each stage timed on `s`
+    const cgh_plan& p = *plan;
+    hipError_t e = timed(s, CGH_STAGE_PLAN, [&] { return enqueue_prep(p, s, p.tiles); });
+    if (e == hipSuccess) e = timed(s, CGH_STAGE_FIRST, [&] { return enqueue_first(p, s, p.tiles); });
+    if (e == hipSuccess) e = timed(s, CGH_STAGE_SECOND, [&] { return enqueue_second(p, s, p.tiles); });
+    return hip_status(e);
+}
+
+int cgh_plan_get_stats(const cgh_plan* plan, cgh_stats* stats, void* stream) {
+    if (!plan || !stats) return CGH_ERROR_INVALID_VALUE;
+    try {
+        std::memset(stats, 0, sizeof(*stats));
+        hipStream_t s = (hipStream_t)stream;
+        const int n = (int)plan->scenes.size();
+        std::vector<cgh::PlanHeader> hdrs(n);
+        hipError_t e = hipMemcpyAsync(hdrs.data(), plan->hdrs, n * sizeof(cgh::PlanHeader),
+                                      hipMemcpyDeviceToHost, s);
+        std::vector<std::vector<int>> cr(n), cc(n);
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+            const auto& sc = plan->scenes[i];
+            const int n_dl = sc.s.n_layers * plan->levels;
+            cr[i].resize(n_dl);
+            cc[i].resize(n_dl);
+            const char* ws = plan->mem + sc.ws_off;
+            e = hipMemcpyAsync(cr[i].data(), ws + sc.lo.cnt_row, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(cc[i].data(), ws + sc.lo.cnt_col, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_status(e);
+        for (int i = 0; i < n; ++i) {
+            const auto& sc = plan->scenes[i];
+            const double ny = sc.s.ny, nx = sc.s.nx;
+            double rc = 0.0;
+            for (size_t k = 0; k < cr[i].size(); ++k) rc += (double)cr[i][k] * cc[i][k];
+            long long total = 0;
+            for (int l = 1; l <= plan->levels; ++l) total += cgh::band_side(sc.s.ny, l);
+            total *= sc.s.n_layers;
+            stats->coef_rows_active += hdrs[i].rows_active;
+            stats->coef_rows_total += total;
+            stats->k_padded += hdrs[i].kpad;
+            stats->k_total += total;
+            stats->flops_first += 4.0 * nx * rc;
+            stats->flops_second += 8.0 * ny * nx * hdrs[i].rows_active;
+            stats->flops_second_issued += 8.0 * ny * nx * hdrs[i].kpad;
+        }
+        stats->k_tile = cgh::kKT;
+        stats->split_k = 1;
+        return CGH_SUCCESS;
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
 }
 
 int cgh_plan_destroy(cgh_plan* plan) {
