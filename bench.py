@@ -45,6 +45,10 @@ WORKLOADS = {
                   "3 Haar levels, lambda 532 nm, pitch 8 um"),
     "tiny128": (scenes.tiny,
                 "128x128 object, one plane z=0.2 m, ~25% saliency, 3 Haar levels"),
+    "grad1024": (scenes.differentiable,
+                 "1024x1024 float32 amplitudes, one plane z=0.2 m, ~30% saliency, 3 Haar levels; "
+                 "loss = sum (|Fresnel back-propagation of H| - T)^2 with a blob target; one "
+                 "step = forward + back-propagation + loss + gradient through the adjoints"),
     "batch64": (scenes.batched,
                 "64 scenes, sides uniform in {256,512,768,1024,1536,2048}, 1-4 depth planes, "
                 "saliency 5-60% from 1-3 ellipses, 3 Haar levels; one batched plan "
@@ -179,6 +183,53 @@ def run_single(scene, prec, steps, warmup):
     }
 
 
+def run_grad(scene, prec, steps, warmup):
+    import torch
+
+    from paper_2211_09938_amd import cgh
+
+    dev = torch.device("cuda:0")
+    ny, nx = scene.shape
+    obj = torch.from_numpy(scene.obj).to(dev).requires_grad_(True)
+    sal = torch.from_numpy(scene.saliency).to(dev)
+    target = torch.from_numpy(scene.extra["target"]).to(dev)
+    z = scene.z[0]
+
+    def step():
+        obj.grad = None
+        h = cgh.hologram_fn(obj, [z], scene.lam, scene.pitch, scene.levels, sal, None, None, prec)
+        u = cgh.backprop_fn(h, scene.lam, scene.pitch, z, prec)
+        loss = ((u.abs() - target) ** 2).sum()
+        loss.backward()
+        return loss
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    cgh.profile_enable(True)
+    cgh.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = cgh.profile_read(reset=True)
+    cgh.profile_enable(False)
+    ws = torch.empty(cgh.workspace_size(ny, nx, 1, scene.levels, prec), dtype=torch.uint8, device=dev)
+    cgh.progressive_hologram(obj.detach(), [z], scene.lam, scene.pitch, scene.levels, sal,
+                             precision=prec, workspace=ws)
+    stats = cgh.workspace_stats(ws, ny, nx, 1, scene.levels, prec)
+    sec_ms, sec_n = prof["second"]
+    return {
+        "value": steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "stages_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
+        "work": stats,
+        "roofline": roofline(stats, prec, sec_ms / max(1, sec_n),
+                             f"forward second contraction inside the step (nt_direct_kernel<{prec}>)"),
+    }
+
+
 def run_batch(batch, prec, steps, warmup, tune_cache):
     import torch
 
@@ -244,7 +295,8 @@ def main():
     batch = isinstance(work, list)
     scene = work[0] if batch else work
 
-    base = None if (args.no_cpu_baseline or batch) else cpu_baseline(scene, args.cpu_pixels)
+    grad = args.workload.startswith("grad")
+    base = None if (args.no_cpu_baseline or batch or grad) else cpu_baseline(scene, args.cpu_pixels)
 
     import torch
 
@@ -257,6 +309,8 @@ def main():
     for prec in precs:
         if batch:
             forms[prec] = run_batch(work, prec, args.steps, args.warmup, args.tune_cache)
+        elif grad:
+            forms[prec] = run_grad(scene, prec, args.steps, args.warmup)
         else:
             forms[prec] = run_single(scene, prec, args.steps, args.warmup)
         out = forms[prec].pop("_out", None)
@@ -278,7 +332,7 @@ def main():
     line = {
         "metric": METRIC,
         "value": head["value"],
-        "unit": "holograms/s",
+        "unit": "loss+grad/s" if grad else "holograms/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,

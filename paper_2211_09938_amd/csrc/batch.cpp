@@ -51,6 +51,7 @@ struct cgh_plan {
 namespace {
 
 constexpr int kMaxScenes = 4096;
+constexpr int kPrepBranches = 8;  // parallel graph branches for the per-scene stages
 constexpr int kCandidates[4][2] = {{128, 128}, {64, 128}, {128, 64}, {64, 64}};
 
 struct Events {
@@ -58,10 +59,21 @@ struct Events {
 };
 
 // Per-scene stages of the whole batch (coefficients, fringe tables, active
-// lists, plans, panels), then the merge of the problem tables.
-hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s, const int* tiles) {
+// lists, plans, panels), then the merge of the problem tables.  With side
+// streams, scene i's stages go to side[i % n_side] (parallel graph branches
+// forked from and joined back into `s`).
+hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s, const int* tiles,
+                        const hipStream_t* side = nullptr, const hipEvent_t* ev = nullptr,
+                        int n_side = 0) {
     Optics op;
+    hipError_t fe = hipSuccess;
+    if (n_side > 0) {
+        fe = hipEventRecord(ev[0], s);
+        for (int k = 0; k < n_side && fe == hipSuccess; ++k) fe = hipStreamWaitEvent(side[k], ev[0], 0);
+        if (fe != hipSuccess) return fe;
+    }
     for (size_t i = 0; i < p.scenes.size(); ++i) {
+        hipStream_t st = n_side > 0 ? side[i % n_side] : s;
         const cgh_plan::Scene& sc = p.scenes[i];
         const cgh::Layout& lo = sc.lo;
         char* ws = p.mem + sc.ws_off;
@@ -73,25 +85,30 @@ hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s, const int* tiles) {
         nb.second = p.second + i;
         nb.hdr = p.hdrs + i;
         const cgh::NtOutput o{reinterpret_cast<float2*>(sc.s.hologram), nullptr, 0};
-        hipError_t e = cgh::launch_fill_u8(fl, (size_t)nl * lo.flags_layer, s);
+        hipError_t e = cgh::launch_fill_u8(fl, (size_t)nl * lo.flags_layer, st);
         if (e == hipSuccess)
             e = cgh::launch_dwt_mask(sc.s.object, sc.s.layer_index, sc.s.saliency, ny, nx, nl,
                                      p.levels, p.thr, cgh::P_FP32, ws + lo.coef, nullptr, fl,
-                                     lo.flags_layer, s);
+                                     lo.flags_layer, st);
         if (e == hipSuccess)
             e = cgh::launch_luts(nx, nl, p.levels, 1, op.c, op.one_re, op.one_im, cgh::P_FP32,
-                                 ws + lo.lut_x, nullptr, s);
+                                 ws + lo.lut_x, nullptr, st);
         if (e == hipSuccess)
             e = cgh::launch_luts(ny, nl, p.levels, 1, op.c, op.pre_re, op.pre_im, cgh::P_FP32,
-                                 ws + lo.lut_y, nullptr, s);
+                                 ws + lo.lut_y, nullptr, st);
         if (e == hipSuccess)
             e = cgh::launch_nt_plan(fl, ny, nx, nl, p.levels, lo.flags_layer, p.precision, tiles, nb,
-                                    o, s);
+                                    o, st);
         if (e == hipSuccess)
             e = cgh::launch_nt_materialize(reinterpret_cast<const float*>(ws + lo.coef),
                                            reinterpret_cast<const float*>(ws + lo.lut_x),
                                            reinterpret_cast<const float*>(ws + lo.lut_y), ny, nx,
-                                           nl, p.levels, p.precision, nb, s);
+                                           nl, p.levels, p.precision, nb, st);
+        if (e != hipSuccess) return e;
+    }
+    for (int k = 0; k < n_side; ++k) {
+        hipError_t e = hipEventRecord(ev[1 + k], side[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ev[1 + k], 0);
         if (e != hipSuccess) return e;
     }
     return cgh::launch_batch_prefix(p.hdrs, (int)p.scenes.size(), p.first_off, p.first, p.second,
@@ -327,16 +344,29 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
                 if (e == hipSuccess) cache_store(tune_cache_path, key, p->tiles, p->ms_first, p->ms_second);
             }
         }
-        // capture the batch on a private stream and instantiate it
+        // capture the batch on a private stream, the per-scene stages as
+        // kPrepBranches parallel branches, and instantiate it
         hipStream_t cs = nullptr;
+        hipStream_t side[kPrepBranches] = {};
+        hipEvent_t fj[kPrepBranches + 1] = {};
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        for (int k = 0; k < kPrepBranches && e == hipSuccess; ++k)
+            e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
+        for (int k = 0; k <= kPrepBranches && e == hipSuccess; ++k)
+            e = hipEventCreateWithFlags(&fj[k], hipEventDisableTiming);
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
         if (e == hipSuccess) {
-            hipError_t ee = enqueue(*p, cs, p->tiles, nullptr);
+            hipError_t ee = enqueue_prep(*p, cs, p->tiles, side, fj, kPrepBranches);
+            if (ee == hipSuccess) ee = enqueue_first(*p, cs, p->tiles);
+            if (ee == hipSuccess) ee = enqueue_second(*p, cs, p->tiles);
             e = hipStreamEndCapture(cs, &p->graph);
             if (ee != hipSuccess) e = ee;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        for (int k = 0; k <= kPrepBranches; ++k)
+            if (fj[k]) (void)hipEventDestroy(fj[k]);
+        for (int k = 0; k < kPrepBranches; ++k)
+            if (side[k]) (void)hipStreamDestroy(side[k]);
         if (cs) (void)hipStreamDestroy(cs);
         if (e != hipSuccess) {
             const int st = hip_status(e);
