@@ -32,14 +32,23 @@ typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
-template <int P>
+// Operand format of precision P with KS rows of K per staged tile (the FP32
+// path always stages 16).  Measured on MI355X: the direct split kernels run
+// best at K 16 with two workgroups per CU, the persistent split kernels at
+// K 32 with one (more MFMA work per load batch and per barrier pair).
+template <int P, int KS = kKT>
 struct Fmt {
     static constexpr int ES = (P == P_FP32) ? 4 : 2;        // bytes per element
     static constexpr int PC = (P == P_FP32) ? 2 : 4;        // planes of a complex operand
     static constexpr int PR = (P == P_FP32) ? 1 : 2;        // planes of a real operand
-    static constexpr int CPR = kKT * ES / 16;               // 16-byte chunks per row and plane
-    static constexpr int PITCH = kKT * ES + 16;             // LDS bytes per row (with padding)
+    static constexpr int KB = (P == P_FP32) ? kKT : KS;     // K per staged tile
+    static constexpr int CPR = KB * ES / 16;                // 16-byte chunks per row and plane
+    static constexpr int PITCH = KB * ES + 16;              // LDS bytes per row (with padding)
 };
+
+constexpr int kDirectKS = 16, kPersistKS = 32;
+template <int P> constexpr int direct_occ() { return 2; }
+template <int P> constexpr int persist_occ() { return P == P_FP32 ? 2 : 1; }
 
 __device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
@@ -137,10 +146,10 @@ struct SecondEpi {
 };
 
 // One output tile (m0, n0) of problem e over K tiles [kb, ke).
-template <int P, bool A_CPLX, class Epi, int TM, int TN>
+template <int P, bool A_CPLX, class Epi, int TM, int TN, int KS>
 __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb, int ke, int s,
                                         int split, unsigned char* As, unsigned char* Bs) {
-    using F = Fmt<P>;
+    using F = Fmt<P, KS>;
     constexpr int NPA = A_CPLX ? F::PC : F::PR;
     constexpr int NPB = F::PC;
     constexpr int BI = TM / 64, BJ = TN / 64;  // 32 x 32 blocks per wave
@@ -149,7 +158,7 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
     constexpr int QB = NPB * TN * F::CPR / 256;
     static_assert(QA >= 1 && QB >= 1, "tile too small for the staging layout");
 
-    const int nk = ke > kb ? (ke - kb) / kKT : 0;
+    const int nk = ke > kb ? (ke - kb + F::KB - 1) / F::KB : 0;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TN / 2);
@@ -169,14 +178,17 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
     u32x4 ra[QA], rb[QB];
     const unsigned char* Ab = static_cast<const unsigned char*>(e.a);
     const unsigned char* Bb = static_cast<const unsigned char*>(e.b);
+    // a staged tile may run past the K range (ke is a multiple of 16 only):
+    // chunks starting at or beyond ke read as zero
+    constexpr int KPC = 16 / F::ES;  // k per 16-byte chunk
     auto load = [&](int kt) {
-        const int k0 = kb + kt * kKT;
+        const int k0 = kb + kt * F::KB;
 #pragma unroll
         for (int u = 0; u < QA; ++u) {
             const int q = tid + 256 * u;
             const int c = q % F::CPR, row = (q / F::CPR) % TM, plane = q / (F::CPR * TM);
             const int m = m0 + row;
-            if (m < e.M) {
+            if (m < e.M && (F::KB == kKT || k0 + c * KPC < ke)) {
                 const size_t el = (size_t)plane * e.a_ps + (size_t)m * e.lda + k0;
                 ra[u] = *reinterpret_cast<const u32x4*>(Ab + el * F::ES + c * 16);
             } else {
@@ -188,7 +200,7 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
             const int q = tid + 256 * u;
             const int c = q % F::CPR, row = (q / F::CPR) % TN, plane = q / (F::CPR * TN);
             const int n = n0 + row;
-            if (n < e.N) {
+            if (n < e.N && (F::KB == kKT || k0 + c * KPC < ke)) {
                 const size_t el = (size_t)plane * e.b_ps + (size_t)n * e.ldb + k0;
                 rb[u] = *reinterpret_cast<const u32x4*>(Bb + el * F::ES + c * 16);
             } else {
@@ -255,19 +267,21 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
                 }
             }
         } else {
+#pragma unroll
+          for (int kc = 0; kc < F::KB / 16; ++kc) {
             u32x4 a[BI][NPA], b[BJ][NPB];
 #pragma unroll
             for (int i = 0; i < BI; ++i)
 #pragma unroll
                 for (int c = 0; c < NPA; ++c)
                     a[i][c] = *reinterpret_cast<const u32x4*>(
-                        As + c * APLANE + (wm + 32 * i + l32) * F::PITCH + g * 16);
+                        As + c * APLANE + (wm + 32 * i + l32) * F::PITCH + kc * 32 + g * 16);
 #pragma unroll
             for (int j = 0; j < BJ; ++j)
 #pragma unroll
                 for (int c = 0; c < NPB; ++c)
                     b[j][c] = *reinterpret_cast<const u32x4*>(
-                        Bs + c * BPLANE + (wn + 32 * j + l32) * F::PITCH + g * 16);
+                        Bs + c * BPLANE + (wn + 32 * j + l32) * F::PITCH + kc * 32 + g * 16);
 #pragma unroll
             for (int i = 0; i < BI; ++i)
 #pragma unroll
@@ -287,6 +301,7 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
                     }
                 }
             }
+          }
         }
         __syncthreads();
         if (kt + 1 < nk) stash();
@@ -310,15 +325,16 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
             }
 }
 
-template <int P, bool A_CPLX, int TM, int TN>
+template <int P, bool A_CPLX, int TM, int TN, int KS>
 struct Smem {
-    static constexpr int NPA = A_CPLX ? Fmt<P>::PC : Fmt<P>::PR;
-    static constexpr int A = NPA * TM * Fmt<P>::PITCH;
-    static constexpr int B = Fmt<P>::PC * TN * Fmt<P>::PITCH;
+    using F = Fmt<P, KS>;
+    static constexpr int NPA = A_CPLX ? F::PC : F::PR;
+    static constexpr int A = NPA * TM * F::PITCH;
+    static constexpr int B = F::PC * TN * F::PITCH;
 };
 
 // Resolves tile t of the table and runs it (K range of split s).
-template <int P, bool A_CPLX, class Epi, int TM, int TN>
+template <int P, bool A_CPLX, class Epi, int TM, int TN, int KS>
 __device__ __forceinline__ void run_tile(const NtEntry* __restrict__ entries, int n_entries,
                                          int t, int s, int split, unsigned char* As,
                                          unsigned char* Bs) {
@@ -329,32 +345,31 @@ __device__ __forceinline__ void run_tile(const NtEntry* __restrict__ entries, in
     const int chunk = pad_kt((e.K + split - 1) / split);
     const int kb = s * chunk;
     const int ke = min(e.K, kb + chunk);
-    nt_tile<P, A_CPLX, Epi, TM, TN>(e, m0, n0, kb, ke, s, split, As, Bs);
+    nt_tile<P, A_CPLX, Epi, TM, TN, KS>(e, m0, n0, kb, ke, s, split, As, Bs);
 }
 
 // Direct schedule: block id = s * count + t.
 template <int P, bool A_CPLX, class Epi, int TM, int TN>
-__global__ __launch_bounds__(256, 2) void nt_direct_kernel(const NtEntry* __restrict__ entries,
-                                                           int n_entries,
-                                                           const int* __restrict__ tile_count,
-                                                           int split) {
-    using S = Smem<P, A_CPLX, TM, TN>;
+__global__ __launch_bounds__(256, direct_occ<P>()) void nt_direct_kernel(
+    const NtEntry* __restrict__ entries, int n_entries, const int* __restrict__ tile_count,
+    int split) {
+    using S = Smem<P, A_CPLX, TM, TN, kDirectKS>;
     __shared__ __attribute__((aligned(16))) unsigned char As[S::A];
     __shared__ __attribute__((aligned(16))) unsigned char Bs[S::B];
     const int count = *tile_count;
     const int bid = blockIdx.x;
     if (bid >= count * split) return;
     const int s = bid / count;
-    run_tile<P, A_CPLX, Epi, TM, TN>(entries, n_entries, bid - s * count, s, split, As, Bs);
+    run_tile<P, A_CPLX, Epi, TM, TN, kDirectKS>(entries, n_entries, bid - s * count, s, split, As, Bs);
 }
 
 // Persistent schedule: pull tiles from *queue until *tile_count is reached;
 // every workgroup exits once the counter passes the end of the table.
 template <int P, bool A_CPLX, class Epi, int TM, int TN>
-__global__ __launch_bounds__(256, 2) void nt_persistent_kernel(
+__global__ __launch_bounds__(256, persist_occ<P>()) void nt_persistent_kernel(
     const NtEntry* __restrict__ entries, int n_entries, const int* __restrict__ tile_count,
     int* __restrict__ queue) {
-    using S = Smem<P, A_CPLX, TM, TN>;
+    using S = Smem<P, A_CPLX, TM, TN, kPersistKS>;
     __shared__ __attribute__((aligned(16))) unsigned char As[S::A];
     __shared__ __attribute__((aligned(16))) unsigned char Bs[S::B];
     __shared__ int s_next;
@@ -365,7 +380,7 @@ __global__ __launch_bounds__(256, 2) void nt_persistent_kernel(
         const int t = s_next;
         __syncthreads();
         if (t >= count) break;
-        run_tile<P, A_CPLX, Epi, TM, TN>(entries, n_entries, t, 0, 1, As, Bs);
+        run_tile<P, A_CPLX, Epi, TM, TN, kPersistKS>(entries, n_entries, t, 0, 1, As, Bs);
     }
 }
 
