@@ -119,7 +119,35 @@ def cpu_baseline(scene, n_pixels, seed=12345):
     }
 
 
-def roofline(stats, prec, avg_ms, kernel):
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# valid only while the kernel and plan sources hash to what they were when counted
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+TRAFFIC_SOURCES = ("paper_2211_09938_amd/csrc/ntgemm.hip", "paper_2211_09938_amd/csrc/nt.h",
+                   "paper_2211_09938_amd/csrc/plan.hip")
+
+
+def sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, prec):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha1") != sources_sha1():
+        return None
+    entry = rec.get("entries", {}).get(f"{workload}/{prec}")
+    return None if entry is None else entry["bytes"]
+
+
+def roofline(stats, prec, avg_ms, kernel, traffic=None):
     """Second contraction: algorithmic flops per launch / average launch time."""
     achieved = stats["flops_second"] / (avg_ms * 1e-3) / 1e12
     peak = PEAKS_TFLOPS[prec]
@@ -131,14 +159,14 @@ def roofline(stats, prec, avg_ms, kernel):
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": achieved / peak,
-        "traffic": None,
+        "traffic": traffic,
         "flops_per_launch": stats["flops_second"],
         "avg_launch_ms": avg_ms,
         "issued_mfma_frac": issued / peak,
     }
 
 
-def run_single(scene, prec, steps, warmup):
+def run_single(scene, prec, steps, warmup, workload):
     import torch
 
     from paper_2211_09938_amd import cgh
@@ -178,7 +206,8 @@ def run_single(scene, prec, steps, warmup):
         "ms_per_step": 1e3 * elapsed / steps,
         "stages_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
         "work": stats,
-        "roofline": roofline(stats, prec, sec_ms / max(1, sec_n), kernel),
+        "roofline": roofline(stats, prec, sec_ms / max(1, sec_n), kernel,
+                             measured_traffic(workload, prec)),
         "_out": out.cpu().numpy(),
     }
 
@@ -288,7 +317,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the hologram would shard by column bands, see DESIGN.md)", file=sys.stderr)
+              "(the hologram would shard by bands of hologram columns)", file=sys.stderr)
         sys.exit(2)
     make, desc = WORKLOADS[args.workload]
     work = make()
@@ -312,7 +341,7 @@ def main():
         elif grad:
             forms[prec] = run_grad(scene, prec, args.steps, args.warmup)
         else:
-            forms[prec] = run_single(scene, prec, args.steps, args.warmup)
+            forms[prec] = run_single(scene, prec, args.steps, args.warmup, args.workload)
         out = forms[prec].pop("_out", None)
         if base is not None and out is not None:
             ys, xs, vals = base["_pixels"]
