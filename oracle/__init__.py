@@ -19,6 +19,8 @@ saliency", arXiv 2211.09938):
 * ``literal``     -- the same hologram computed the way steps 2-5 describe it
                      (image-domain residual maps times shifted block fringes)
                      plus the paper's operator accounting (Sec. 3).
+* ``separable``   -- the same hologram over a window as three matrix products
+                     (the paraxial kernel factors per axis), for large sizes.
 * ``gradient``    -- the adjoint (gradient of a real loss with respect to the
                      object amplitudes) and the Fresnel back-propagation used
                      for the differentiable form.
@@ -27,4 +29,4 @@ All arithmetic is float64 / complex128.  Nothing here is blocked, fused or
 reordered beyond the definitions it states.
 """
 
-from . import haar, saliency, fresnel, progressive, literal, gradient  # noqa: F401
+from . import haar, saliency, fresnel, progressive, literal, gradient, separable  # noqa: F401

@@ -1,0 +1,57 @@
+"""The same progressive hologram over a rectangular window, evaluated separably (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+The Fresnel kernel of Eq. 1 in its paraxial form depends on the lateral offset
+only through (dy^2 + dx^2), so it is the product of a y factor and an x factor:
+
+    exp(i pi p^2 (dy^2 + dx^2) / (lambda z)) = k_z(dy) * k_z(dx),
+    k_z(m) = exp(i pi p^2 m^2 / (lambda z)).
+
+For one layer the direct 2D sum over points is therefore a product of three
+matrices, H[Y, X] = K_y[Y, :] . Ahat . K_x[X, :]^T with K[m, q] = k_z(m - q),
+and a window of the hologram needs only the window's rows of K_y and columns
+of K_x.  Ahat is the masked reconstruction of the layer (Eq. 3, steps 2-5),
+from ``progressive.masked_reconstruction``.  The matrix products are NumPy's
+FP64 BLAS; everything else is float64 / complex128.
+
+It computes nothing that ``progressive.hologram`` does not; it is pinned to it
+(the direct sum) in the test suite and serves where the direct sum would take
+minutes: windows of 2048 x 2048 objects and full 1024 x 1024 holograms.
+"""
+
+import numpy as np
+
+from . import fresnel, progressive
+
+
+def kernel_rows(rows, n, lam, pitch, z):
+    """K[r, q] = k_z(rows[r] - q) for q in [0, n), complex128 (len(rows), n)."""
+    d = np.asarray(rows, dtype=np.float64)[:, None] - np.arange(n, dtype=np.float64)[None, :]
+    th = np.pi * pitch * pitch * (d * d) / (lam * z)
+    return np.cos(th) + 1j * np.sin(th)
+
+
+def window(obj, z, lam, pitch, levels=3, saliency_map=None, layer_index=None,
+           thresholds=None, y0=0, x0=0, h=None, w=None, eq1_prefactor=False):
+    """Hologram window [y0:y0+h, x0:x0+w] of the progressive hologram, complex128 (h, w)."""
+    obj = np.asarray(obj, dtype=np.float64)
+    ny, nx = obj.shape
+    h = ny - y0 if h is None else h
+    w = nx - x0 if w is None else w
+    z = list(np.atleast_1d(np.asarray(z, dtype=np.float64)))
+    out = np.zeros((h, w), dtype=np.complex128)
+    for d, a_d in enumerate(progressive.layer_split(obj, layer_index, len(z))):
+        if not np.any(a_d):
+            continue
+        a_hat = progressive.masked_reconstruction(a_d, saliency_map, levels, thresholds)
+        ky = kernel_rows(np.arange(y0, y0 + h), ny, lam, pitch, z[d])
+        kx = kernel_rows(np.arange(x0, x0 + w), nx, lam, pitch, z[d])
+        # (K_y Ahat) with a real Ahat: two real products (contiguous operands,
+        # so that NumPy hands them to BLAS)
+        left = np.ascontiguousarray(ky.real) @ a_hat + 1j * (np.ascontiguousarray(ky.imag) @ a_hat)
+        part = left @ np.ascontiguousarray(kx.T)
+        if eq1_prefactor:
+            part = part * fresnel.prefactor(lam, z[d])
+        out += part
+    return out

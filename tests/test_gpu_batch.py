@@ -8,6 +8,7 @@ rel-L2 <= 1e-6) and the FP64 oracle on sampled pixels (rel-L2 <= 1e-5 for FP32,
 with unrelated eager work and synchronisations between the replays.
 """
 
+import functools
 import os
 
 import numpy as np
@@ -138,4 +139,42 @@ def test_empty_and_single_scene_batches():
     torch.cuda.synchronize()
     assert rel_l2(plan.holograms[1].cpu().numpy(), single(s, "fp32")) <= 1e-6
     assert plan.info()["n_scenes"] == 1
+    plan.close()
+
+
+@functools.lru_cache(maxsize=1)
+def batch64():
+    return scenes.batched()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16_split"])
+def test_batch64_workload_matches_single_calls_and_oracle_windows(precision, tmp_path):
+    # the 64-scene workload at its real sizes (256..2048, 1-4 planes)
+    import torch
+
+    from oracle import separable
+
+    batch = batch64()
+    plan = cgh().Plan([dev_scene(s) for s in batch], scenes.WAVELENGTH, scenes.PITCH,
+                      precision=precision, tune_cache=str(tmp_path / "tune.jsonl"))
+    plan.execute()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k, s in enumerate(batch):
+        err = rel_l2(plan.holograms[k].cpu().numpy(), single(s, precision))
+        worst = max(worst, err)
+        assert err <= 1e-6, (k, s.name, err)
+    print(f"batch64 {precision}: worst rel-L2 vs single-scene calls {worst:.2e}")
+    tol = 1e-5 if precision == "fp32" else 1e-3
+    rng = np.random.default_rng(64)
+    for k in rng.choice(len(batch), 4, replace=False):
+        s = batch[int(k)]
+        n = s.shape[0]
+        y0, x0 = (int(v) for v in rng.integers(0, n - 64 + 1, 2))
+        ref = separable.window(s.obj.astype(np.float64), s.z, s.lam, s.pitch, s.levels,
+                               s.saliency.astype(np.float64), s.layer, y0=y0, x0=x0, h=64, w=64)
+        got = plan.holograms[int(k)][y0:y0 + 64, x0:x0 + 64].cpu().numpy()
+        err = rel_l2(got, ref)
+        print(f"batch64 {precision} scene {s.name} window ({y0}, {x0}): rel-L2 {err:.2e}")
+        assert err <= tol
     plan.close()

@@ -213,3 +213,35 @@ def test_split_precision_edge_cases(precision):
     z = scenes.random_scene(17, 64, 64)
     z.obj[:] = 0
     assert np.all(gpu_hologram(z, precision=precision) == 0)
+
+
+# ------------------------------------------------ full-size windows, separable FP64 oracle
+def separable_window(s, y0, x0, h, w):
+    from oracle import separable
+
+    sal = None if s.saliency is None else s.saliency.astype(np.float64)
+    return separable.window(s.obj.astype(np.float64), s.z, s.lam, s.pitch, s.levels, sal,
+                            s.layer, y0=y0, x0=x0, h=h, w=w)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", FP32_TOL), ("bf16_split", SPLIT_TOL),
+                                           ("fp16_split", SPLIT_TOL)])
+def test_plane_1024_full_hologram(precision, tol):
+    s = scenes.plane_1024()
+    h = gpu_hologram(s, precision=precision)
+    err = rel_l2(h, separable_window(s, 0, 0, 1024, 1024))
+    print(f"plane1024 full {precision}: rel-L2 {err:.3e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", FP32_TOL), ("bf16_split", SPLIT_TOL),
+                                           ("fp16_split", SPLIT_TOL)])
+def test_depth_2048_crop_256(precision, tol):
+    # a 256 x 256 window at a seeded offset of the 2048 x 2048, 8-plane hologram
+    s = scenes.depth_2048()
+    rng = np.random.default_rng(2048)
+    y0, x0 = (int(v) for v in rng.integers(0, 2048 - 256 + 1, 2))
+    h = gpu_hologram(s, precision=precision)
+    err = rel_l2(h[y0:y0 + 256, x0:x0 + 256], separable_window(s, y0, x0, 256, 256))
+    print(f"depth2048 crop 256 at ({y0}, {x0}) {precision}: rel-L2 {err:.3e}")
+    assert err <= tol

@@ -1,0 +1,59 @@
+"""Pins of the separable window evaluation (oracle/separable.py).
+
+It must equal the direct 2D point sum (oracle/progressive.py, itself pinned to
+closed forms in test_oracle_hologram.py) on small scenes, for windows that do
+not start at the origin, non-square objects, several layers, graded saliency
+and the Eq. 1 prefactor; and it must reproduce the analytic zone plate of a
+single point far from the window.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import progressive, separable
+from paper_2211_09938_amd import scenes
+
+
+def direct_window(s, y0, x0, h, w, **kw):
+    ys, xs = np.meshgrid(np.arange(y0, y0 + h), np.arange(x0, x0 + w), indexing="ij")
+    sal = None if s.saliency is None else s.saliency.astype(np.float64)
+    v = progressive.hologram(s.obj.astype(np.float64), s.z, s.lam, s.pitch, s.levels, sal,
+                             s.layer, pixels=(ys.ravel(), xs.ravel()), workers=1, **kw)
+    return v.reshape(h, w)
+
+
+@pytest.mark.parametrize("shape,planes,win", [
+    ((40, 48), 1, (0, 0, 40, 48)),
+    ((40, 48), 2, (8, 5, 17, 30)),
+    ((64, 32), 3, (31, 0, 33, 32)),
+])
+def test_window_equals_direct_sum(shape, planes, win):
+    s = scenes.random_scene(71 + planes, *shape, planes=planes, fraction=0.3)
+    y0, x0, h, w = win
+    got = separable.window(s.obj, s.z, s.lam, s.pitch, s.levels, s.saliency.astype(np.float64),
+                           s.layer, y0=y0, x0=x0, h=h, w=w)
+    ref = direct_window(s, y0, x0, h, w)
+    assert progressive.rel_l2(got, ref) <= 1e-12
+
+
+def test_window_with_thresholds_and_prefactor_equals_direct_sum():
+    rng = np.random.default_rng(5)
+    s = scenes.random_scene(90, 48, 40, planes=2, fraction=None)
+    s.saliency = rng.uniform(0.0, 1.0, s.obj.shape).astype(np.float32)
+    th = (0.8, 0.4, 0.2)
+    got = separable.window(s.obj, s.z, s.lam, s.pitch, 3, s.saliency.astype(np.float64), s.layer,
+                           thresholds=th, y0=3, x0=7, h=20, w=11, eq1_prefactor=True)
+    ref = direct_window(s, 3, 7, 20, 11, thresholds=th, eq1_prefactor=True)
+    assert progressive.rel_l2(got, ref) <= 1e-12
+
+
+def test_single_point_far_window_is_the_zone_plate():
+    # all-salient single point: the hologram is the sampled chirp itself (|H| = 1)
+    ny, nx, q0, p0, z = 96, 80, 70, 9, 0.15
+    obj = np.zeros((ny, nx))
+    obj[q0, p0] = 1.0
+    got = separable.window(obj, (z,), scenes.WAVELENGTH, scenes.PITCH, 3, None, None,
+                           y0=0, x0=40, h=24, w=40)
+    yy, xx = np.meshgrid(np.arange(0, 24), np.arange(40, 80), indexing="ij")
+    th = np.pi * scenes.PITCH ** 2 * ((yy - q0) ** 2 + (xx - p0) ** 2) / (scenes.WAVELENGTH * z)
+    assert np.max(np.abs(got - np.exp(1j * th))) <= 1e-12
