@@ -130,6 +130,25 @@ int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, in
                              size_t workspace_bytes, float* hologram, void* stream);
 
 /*
+ * Progressive stage holograms (Sec. 2, steps 2-5; the progressive display of
+ * Sec. 3): levels+1 cumulative holograms written one after the other,
+ *   stages[0]      the level-L approximation alone (every block, step 2),
+ *   stages[j]      stages[j-1] + the salient details of level L-j+1 (steps 3-5),
+ *   stages[levels] the full progressive hologram of cgh_progressive_hologram
+ *                  (equal up to FP32 summation order).
+ * stages: (levels+1)*2*ny*nx floats, complex64 interleaved, overwritten; must
+ * not alias the inputs.  The workspace is the one cgh_workspace_size() gives
+ * for the same arguments; the stages run one after the other in stream order
+ * and reuse it.  CGH_FLAG_ACCUMULATE is rejected; other arguments, errors and
+ * ownership as for cgh_progressive_hologram.
+ */
+int cgh_progressive_stages(const float* object, const uint8_t* layer_index, int n_layers,
+                           const double* z, const float* saliency, const float* thresholds,
+                           double lambda, double pitch, int ny, int nx, int levels, int precision,
+                           unsigned flags, void* workspace, size_t workspace_bytes, float* stages,
+                           void* stream);
+
+/*
  * Adjoint of cgh_progressive_hologram with respect to the object amplitudes.
  * grad_hologram: 2*ny*nx floats, G = dL/dRe(H) + i dL/dIm(H) (the cotangent
  * torch hands to a complex output).  Writes grad_object (ny*nx floats):
@@ -261,6 +280,13 @@ typedef struct cgh_stats_s {
     double flops_second;         /* algorithmic real flops, second contraction:
                                     8 * ny * nx * coef_rows_active                             */
     double flops_second_issued;  /* 8 * ny * nx * k_padded                                     */
+    long long operators[4];      /* operator count of Sec. 3 per progressive step, for one image
+                                    plane (the saliency masks are shared by the layers):
+                                    [0] the approximation, one per point of the (ny/2^L) x
+                                    (nx/2^L) image; [j] the residual-map points of level L-j+1
+                                    whose block is salient (4 per salient detail position);
+                                    entries beyond `levels` are 0                             */
+    long long operators_pointwise; /* ny * nx: one operator per object point                   */
 } cgh_stats;
 
 /* Reads the plan back from `workspace` (same problem arguments as the forward

@@ -33,6 +33,27 @@ def masked_reconstruction(amp, sal, levels, thresholds=None):
     return haar.synthesis(c, levels)
 
 
+def stage_reconstruction(amp, sal, levels, stage, thresholds=None):
+    """Object of progressive stage ``stage`` (0..levels) of one layer.
+
+    Sec. 2, steps 2-5, and the progressive display of Sec. 3: stage 0 shows the
+    coarsest approximation alone (every block, step 2); stage j adds the salient
+    details of levels levels, levels-1, ..., levels-j+1 (steps 3-5 in order), so
+    stage ``levels`` is ``masked_reconstruction``.
+    """
+    amp = np.asarray(amp, dtype=np.float64)
+    c = haar.analysis(amp, levels)
+    if sal is not None:
+        masks = saliency.detail_masks(sal, levels, thresholds)
+    else:
+        masks = [np.ones((amp.shape[0] >> l, amp.shape[1] >> l), dtype=bool)
+                 for l in range(1, levels + 1)]
+    masks = [m if l > levels - stage else np.zeros_like(m)
+             for l, m in zip(range(1, levels + 1), masks)]
+    c = saliency.apply_masks(c, masks, levels)
+    return haar.synthesis(c, levels)
+
+
 def layer_split(obj, layer_index, n_layers):
     obj = np.asarray(obj, dtype=np.float64)
     if layer_index is None:
@@ -66,6 +87,33 @@ def hologram(obj, z, lam, pitch, levels=3, saliency_map=None, layer_index=None,
         out += part
     if pixels is None:
         return out.reshape(ny, nx)
+    return out
+
+
+def stage_holograms(obj, z, lam, pitch, levels=3, saliency_map=None, layer_index=None,
+                    thresholds=None, pixels=None, eq1_prefactor=False, workers=None):
+    """The levels + 1 cumulative stage holograms (see ``stage_reconstruction``).
+
+    Returns complex128 of shape (levels + 1, ny, nx), or (levels + 1, len(ys))
+    when ``pixels`` is given.
+    """
+    obj = np.asarray(obj, dtype=np.float64)
+    ny, nx = obj.shape
+    z = list(np.atleast_1d(np.asarray(z, dtype=np.float64)))
+    if pixels is None:
+        ys, xs = fresnel.grid_pixels(ny, nx)
+    else:
+        ys, xs = (np.asarray(v).ravel() for v in pixels)
+    out = np.zeros((levels + 1, ys.shape[0]), dtype=np.complex128)
+    for d, a_d in enumerate(layer_split(obj, layer_index, len(z))):
+        for j in range(levels + 1):
+            a_hat = stage_reconstruction(a_d, saliency_map, levels, j, thresholds)
+            part = fresnel.direct_sum(a_hat, lam, pitch, z[d], ys, xs, workers=workers)
+            if eq1_prefactor:
+                part = part * fresnel.prefactor(lam, z[d])
+            out[j] += part
+    if pixels is None:
+        return out.reshape(levels + 1, ny, nx)
     return out
 
 

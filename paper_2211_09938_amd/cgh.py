@@ -51,6 +51,9 @@ SIGNATURES = {
     "cgh_progressive_hologram": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double,
                                           _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp,
                                           _vp]),
+    "cgh_progressive_stages": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double,
+                                        _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp,
+                                        _vp]),
     "cgh_hologram_backward": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double,
                                        _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp, _vp]),
     "cgh_fresnel_backpropagate": (_c_int, [_vp, _c_int, _c_int, _c_double, _c_double, _c_double,
@@ -113,10 +116,14 @@ class Stats(ctypes.Structure):
         ("flops_first", ctypes.c_double),
         ("flops_second", ctypes.c_double),
         ("flops_second_issued", ctypes.c_double),
+        ("operators", ctypes.c_longlong * 4),
+        ("operators_pointwise", ctypes.c_longlong),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {name: getattr(self, name) for name, _ in self._fields_}
+        out["operators"] = list(out["operators"])
+        return out
 
 
 class CghError(RuntimeError):
@@ -260,6 +267,30 @@ def progressive_hologram(obj, z, lam, pitch, levels=3, saliency=None, layer_inde
         p_obj, p_lay, len(zs), _host_doubles(zs), p_sal, _host_floats(thresholds), float(lam),
         float(pitch), ny, nx, levels, prec, flags, ctypes.c_void_p(ws.data_ptr()),
         ws.numel(), p_out, _stream()), "cgh_progressive_hologram")
+    return out
+
+
+def progressive_stages(obj, z, lam, pitch, levels=3, saliency=None, layer_index=None,
+                       thresholds=None, precision="fp32", eq1_prefactor=False, out=None,
+                       workspace=None):
+    """Complex64 (levels + 1, ny, nx) cumulative stage holograms; see cgh_progressive_stages."""
+    torch = _torch()
+    ny, nx = obj.shape
+    zs = list(np.atleast_1d(np.asarray(z, dtype=np.float64)))
+    p_obj = _dev_tensor(obj, torch.float32, "object")
+    p_sal = None if saliency is None else _dev_tensor(saliency, torch.float32, "saliency", (ny, nx))
+    p_lay = None if layer_index is None else _dev_tensor(layer_index, torch.uint8, "layer_index", (ny, nx))
+    prec = _precision(precision)
+    nbytes = workspace_size(ny, nx, len(zs), levels, prec)
+    ws = _workspace(nbytes, obj.device, workspace)
+    if out is None:
+        out = torch.empty((levels + 1, ny, nx), dtype=torch.complex64, device=obj.device)
+    p_out = _dev_tensor(out, torch.complex64, "out", (levels + 1, ny, nx))
+    flags = FLAG_EQ1_PREFACTOR if eq1_prefactor else 0
+    _check(lib().cgh_progressive_stages(
+        p_obj, p_lay, len(zs), _host_doubles(zs), p_sal, _host_floats(thresholds), float(lam),
+        float(pitch), ny, nx, levels, prec, flags, ctypes.c_void_p(ws.data_ptr()),
+        ws.numel(), p_out, _stream()), "cgh_progressive_stages")
     return out
 
 

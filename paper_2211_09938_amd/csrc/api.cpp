@@ -28,6 +28,61 @@ namespace {
 
 using namespace cgh::host;
 
+// One forward pass of the hot path into `out` (validated arguments).  parts
+// selects the approximation / detail levels (progressive stages); with_luts
+// false reuses the fringe tables already in the workspace.
+hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers,
+                   const float* saliency, const float* thr, const Optics& op, int ny, int nx,
+                   int levels, int precision, const cgh::Layout& lo, char* ws, unsigned parts,
+                   bool with_luts, int acc, float2* out, hipStream_t s) {
+    uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
+    const cgh::GemmShape sh{ny, nx, n_layers, levels, lo.split_k, precision, lo.t_layer,
+                            lo.flags_layer};
+    const cgh::NtBuffers nb = nt_buffers(ws, lo);
+    const float* coef = reinterpret_cast<const float*>(ws + lo.coef);
+    const float* lut_x = reinterpret_cast<const float*>(ws + lo.lut_x);
+    const float* lut_y = reinterpret_cast<const float*>(ws + lo.lut_y);
+    float2* partial = reinterpret_cast<float2*>(ws + lo.partial);
+
+    hipError_t e = timed(s, CGH_STAGE_COEF, [&] {
+        hipError_t r = cgh::launch_fill_u8(fl, lo.flags_fill, s);
+        if (r != hipSuccess) return r;
+        return cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels, thr,
+                                    parts, reinterpret_cast<float*>(ws + lo.coef), fl,
+                                    lo.flags_layer,
+                                    reinterpret_cast<unsigned long long*>(ws + lo.ops), s);
+    });
+    if (e == hipSuccess && with_luts)
+        e = timed(s, CGH_STAGE_LUT, [&] {
+            hipError_t r = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
+                                            cgh::P_FP32, ws + lo.lut_x, nullptr, s);
+            if (r != hipSuccess) return r;
+            return cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im,
+                                    cgh::P_FP32, ws + lo.lut_y, nullptr, s);
+        });
+    if (e == hipSuccess)
+        e = timed(s, CGH_STAGE_PLAN, [&] {
+            const int tiles[4] = {cgh::kNtTile, cgh::kNtTile, cgh::kNtTile, cgh::kNtTile};
+            const cgh::NtOutput o{out, lo.split_k > 1 ? partial : nullptr, acc};
+            hipError_t r = cgh::launch_nt_plan(fl, ny, nx, n_layers, levels, lo.flags_layer,
+                                               precision, tiles, nb, o, s);
+            if (r != hipSuccess) return r;
+            return cgh::launch_nt_materialize(coef, lut_x, lut_y, ny, nx, n_layers, levels,
+                                              precision, nb, s);
+        });
+    if (e == hipSuccess)
+        e = timed(s, CGH_STAGE_FIRST, [&] {
+            return cgh::launch_nt_first(n_layers, levels, precision, nb, lo.first_tiles_max, s);
+        });
+    if (e == hipSuccess)
+        e = timed(s, CGH_STAGE_SECOND,
+                  [&] { return cgh::launch_nt_second(ny, nx, precision, lo.split_k, nb, s); });
+    if (e == hipSuccess && lo.split_k > 1)
+        e = timed(s, CGH_STAGE_REDUCE,
+                  [&] { return cgh::launch_reduce_partial(sh, partial, out, acc, s); });
+    return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -57,7 +112,7 @@ int cgh_haar_dwt(const float* x, int ny, int nx, int levels, float* coeffs, void
         if (!x || !coeffs || (const void*)x == (const void*)coeffs) return CGH_ERROR_INVALID_VALUE;
         const float thr[3] = {0.f, 0.f, 0.f};
         return hip_status(cgh::launch_dwt_mask(x, nullptr, nullptr, ny, nx, 1, levels, thr,
-                                               cgh::P_FP32, coeffs, nullptr, nullptr, 0,
+                                               cgh::kAllParts, coeffs, nullptr, 0, nullptr,
                                                (hipStream_t)stream));
     } catch (...) {
         return CGH_ERROR_HIP;
@@ -100,59 +155,49 @@ int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, in
         if (!object || !hologram) return CGH_ERROR_INVALID_VALUE;
         const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
         if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
-
-        hipStream_t s = (hipStream_t)stream;
-        char* ws = static_cast<char*>(workspace);
         Optics op;
         make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
-        uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
+        return hip_status(forward(object, layer_index, n_layers, saliency, thr, op, ny, nx, levels,
+                                  precision, lo, static_cast<char*>(workspace), cgh::kAllParts,
+                                  true, (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0,
+                                  reinterpret_cast<float2*>(hologram), (hipStream_t)stream));
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
 
-        const int acc = (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0;
-        const cgh::GemmShape sh{ny, nx, n_layers, levels, lo.split_k, precision, lo.t_layer,
-                                lo.flags_layer};
-        const cgh::NtBuffers nb = nt_buffers(ws, lo);
-        const float* coef = reinterpret_cast<const float*>(ws + lo.coef);
-        const float* lut_x = reinterpret_cast<const float*>(ws + lo.lut_x);
-        const float* lut_y = reinterpret_cast<const float*>(ws + lo.lut_y);
-        float2* partial = reinterpret_cast<float2*>(ws + lo.partial);
-        float2* out = reinterpret_cast<float2*>(hologram);
-
-        hipError_t e = timed(s, CGH_STAGE_COEF, [&] {
-            hipError_t r = cgh::launch_fill_u8(fl, (size_t)n_layers * lo.flags_layer, s);
-            if (r != hipSuccess) return r;
-            return cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels,
-                                        thr, cgh::P_FP32, ws + lo.coef, nullptr, fl,
-                                        lo.flags_layer, s);
-        });
-        if (e == hipSuccess)
-            e = timed(s, CGH_STAGE_LUT, [&] {
-                hipError_t r = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
-                                                cgh::P_FP32, ws + lo.lut_x, nullptr, s);
-                if (r != hipSuccess) return r;
-                return cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im,
-                                        cgh::P_FP32, ws + lo.lut_y, nullptr, s);
-            });
-        if (e == hipSuccess)
-            e = timed(s, CGH_STAGE_PLAN, [&] {
-                const int tiles[4] = {cgh::kNtTile, cgh::kNtTile, cgh::kNtTile, cgh::kNtTile};
-                const cgh::NtOutput o{out, lo.split_k > 1 ? partial : nullptr, acc};
-                hipError_t r = cgh::launch_nt_plan(fl, ny, nx, n_layers, levels, lo.flags_layer,
-                                                   precision, tiles, nb, o, s);
-                if (r != hipSuccess) return r;
-                return cgh::launch_nt_materialize(coef, lut_x, lut_y, ny, nx, n_layers, levels,
-                                                  precision, nb, s);
-            });
-        if (e == hipSuccess)
-            e = timed(s, CGH_STAGE_FIRST, [&] {
-                return cgh::launch_nt_first(n_layers, levels, precision, nb, lo.first_tiles_max, s);
-            });
-        if (e == hipSuccess)
-            e = timed(s, CGH_STAGE_SECOND, [&] {
-                return cgh::launch_nt_second(ny, nx, precision, lo.split_k, nb, s);
-            });
-        if (e == hipSuccess && lo.split_k > 1)
-            e = timed(s, CGH_STAGE_REDUCE,
-                      [&] { return cgh::launch_reduce_partial(sh, partial, out, acc, s); });
+int cgh_progressive_stages(const float* object, const uint8_t* layer_index, int n_layers,
+                           const double* z, const float* saliency, const float* thresholds,
+                           double lambda, double pitch, int ny, int nx, int levels, int precision,
+                           unsigned flags, void* workspace, size_t workspace_bytes, float* stages,
+                           void* stream) {
+    try {
+        float thr[CGH_MAX_LEVELS];
+        int st = check_common(n_layers, layer_index, z, thresholds, lambda, pitch, ny, nx, levels,
+                              precision, flags, thr);
+        if (st) return st;
+        if (flags & CGH_FLAG_ACCUMULATE) return CGH_ERROR_INVALID_VALUE;
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        if (!object || !stages) return CGH_ERROR_INVALID_VALUE;
+        const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
+        if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        Optics op;
+        make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
+        hipStream_t s = (hipStream_t)stream;
+        char* ws = static_cast<char*>(workspace);
+        float2* out = reinterpret_cast<float2*>(stages);
+        const size_t plane = (size_t)ny * nx;
+        // stage 0: the approximation alone
+        hipError_t e = forward(object, layer_index, n_layers, saliency, thr, op, ny, nx, levels,
+                               precision, lo, ws, 1u << levels, true, 0, out, s);
+        // stage j = stage j-1 + the salient details of level levels-j+1
+        for (int j = 1; j <= levels && e == hipSuccess; ++j) {
+            e = hipMemcpyAsync(out + j * plane, out + (j - 1) * plane, plane * sizeof(float2),
+                               hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess)
+                e = forward(object, layer_index, n_layers, saliency, thr, op, ny, nx, levels,
+                            precision, lo, ws, 1u << (levels - j), false, 1, out + j * plane, s);
+        }
         return hip_status(e);
     } catch (...) {
         return CGH_ERROR_HIP;
@@ -285,7 +330,9 @@ int cgh_workspace_stats(const void* workspace, int ny, int nx, int n_layers, int
         const int n_dl = n_layers * levels;
         std::vector<int> cr(n_dl), cc(n_dl);
         cgh::PlanHeader hdr{};
+        unsigned long long ops[4] = {0, 0, 0, 0};
         hipError_t e = hipMemcpyAsync(cr.data(), ws + lo.cnt_row, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(ops, ws + lo.ops, sizeof(ops), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipMemcpyAsync(cc.data(), ws + lo.cnt_col, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipMemcpyAsync(&hdr, ws + lo.hdr, sizeof(hdr), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -304,6 +351,9 @@ int cgh_workspace_stats(const void* workspace, int ny, int nx, int n_layers, int
         stats->flops_first = 4.0 * (double)nx * rc;
         stats->flops_second = 8.0 * (double)ny * (double)nx * (double)hdr.rows_active;
         stats->flops_second_issued = 8.0 * (double)ny * (double)nx * (double)hdr.kpad;
+        stats->operators[0] = (long long)(ny >> levels) * (nx >> levels);
+        for (int j = 1; j <= levels; ++j) stats->operators[j] = (long long)ops[levels - j];
+        stats->operators_pointwise = (long long)ny * nx;
         return CGH_SUCCESS;
     } catch (...) {
         return CGH_ERROR_HIP;

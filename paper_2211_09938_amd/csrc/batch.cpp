@@ -85,11 +85,12 @@ hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s, const int* tiles,
         nb.second = p.second + i;
         nb.hdr = p.hdrs + i;
         const cgh::NtOutput o{reinterpret_cast<float2*>(sc.s.hologram), nullptr, 0};
-        hipError_t e = cgh::launch_fill_u8(fl, (size_t)nl * lo.flags_layer, st);
+        hipError_t e = cgh::launch_fill_u8(fl, lo.flags_fill, st);
         if (e == hipSuccess)
             e = cgh::launch_dwt_mask(sc.s.object, sc.s.layer_index, sc.s.saliency, ny, nx, nl,
-                                     p.levels, p.thr, cgh::P_FP32, ws + lo.coef, nullptr, fl,
-                                     lo.flags_layer, st);
+                                     p.levels, p.thr, cgh::kAllParts,
+                                     reinterpret_cast<float*>(ws + lo.coef), fl, lo.flags_layer,
+                                     reinterpret_cast<unsigned long long*>(ws + lo.ops), st);
         if (e == hipSuccess)
             e = cgh::launch_luts(nx, nl, p.levels, 1, op.c, op.one_re, op.one_im, cgh::P_FP32,
                                  ws + lo.lut_x, nullptr, st);
@@ -408,6 +409,7 @@ int cgh_plan_get_stats(const cgh_plan* plan, cgh_stats* stats, void* stream) {
         hipError_t e = hipMemcpyAsync(hdrs.data(), plan->hdrs, n * sizeof(cgh::PlanHeader),
                                       hipMemcpyDeviceToHost, s);
         std::vector<std::vector<int>> cr(n), cc(n);
+        std::vector<unsigned long long> ops(4 * (size_t)n, 0ull);
         for (int i = 0; i < n && e == hipSuccess; ++i) {
             const auto& sc = plan->scenes[i];
             const int n_dl = sc.s.n_layers * plan->levels;
@@ -417,6 +419,9 @@ int cgh_plan_get_stats(const cgh_plan* plan, cgh_stats* stats, void* stream) {
             e = hipMemcpyAsync(cr[i].data(), ws + sc.lo.cnt_row, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(cc[i].data(), ws + sc.lo.cnt_col, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ops.data() + 4 * i, ws + sc.lo.ops, 4 * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, s);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_status(e);
@@ -435,6 +440,10 @@ int cgh_plan_get_stats(const cgh_plan* plan, cgh_stats* stats, void* stream) {
             stats->flops_first += 4.0 * nx * rc;
             stats->flops_second += 8.0 * ny * nx * hdrs[i].rows_active;
             stats->flops_second_issued += 8.0 * ny * nx * hdrs[i].kpad;
+            const int L = plan->levels;
+            stats->operators[0] += (long long)(sc.s.ny >> L) * (sc.s.nx >> L);
+            for (int j = 1; j <= L; ++j) stats->operators[j] += (long long)ops[4 * i + L - j];
+            stats->operators_pointwise += (long long)sc.s.ny * sc.s.nx;
         }
         stats->k_tile = cgh::kKT;
         stats->split_k = 1;

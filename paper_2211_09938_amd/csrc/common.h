@@ -60,6 +60,8 @@ struct Layout {
     size_t total;
     size_t t_layer;              // complex elements of T per layer
     size_t flags_layer;          // flag bytes per layer
+    size_t ops;                  // 4 x u64 operator counters, right after the flags
+    size_t flags_fill;           // bytes to clear from `flags` (flags and counters)
     int entries_n;               // problems in the table: one per (layer, level), then one
     int first_tiles_max;
     int split_k;
@@ -69,9 +71,12 @@ struct Launch;  // forward declaration for the host dispatcher
 
 // ------------------------------------------------------------ launchers (host)
 hipError_t launch_fill_u8(uint8_t* p, size_t n, hipStream_t s);
+// parts: bit l-1 keeps the level-l details, bit `levels` the approximation.
+constexpr unsigned kAllParts = 0xFu;
 hipError_t launch_dwt_mask(const float* obj, const uint8_t* layer, const float* sal, int ny, int nx,
-                           int layers, int levels, const float* thr, int precision, void* coef,
-                           void* coef_lo, uint8_t* flags, size_t flags_layer, hipStream_t s);
+                           int layers, int levels, const float* thr, unsigned parts, float* coef,
+                           uint8_t* flags, size_t flags_layer, unsigned long long* ops,
+                           hipStream_t s);
 hipError_t launch_idwt(const float* coef, int ny, int nx, int levels, float* out, hipStream_t s);
 hipError_t launch_grad_synthesis(const float* gcoef, const uint8_t* layer, const float* sal, int ny,
                                  int nx, int layers, int levels, const float* thr, float* grad,

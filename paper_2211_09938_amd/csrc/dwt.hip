@@ -8,7 +8,6 @@
 // The averaging Haar transform of 2^L levels never mixes pixels of different
 // aligned 2^L blocks, so every block is independent: no halo, one pass over HBM.
 #include "common.h"
-#include "split.h"
 
 namespace cgh {
 
@@ -57,11 +56,19 @@ __device__ __forceinline__ float pooled(const Pool<B>& p, int lev, int j, int i)
 }
 
 // One thread per 2^L x 2^L block; threads along x are adjacent blocks.
-template <int L, int P>
+//
+// parts: bit l-1 enables the level-l details (l = 1..L), bit L the level-L
+// approximation; a disabled part is written as zero (progressive stages).
+// ops (optional, zeroed by the caller): ops[l-1] += 4 x the level-l detail
+// positions whose block is salient, the operator count of Sec. 3 (one
+// operator per point of the level's residual map that is processed).  The
+// masks are the same for every layer, so they are counted once.
+template <int L>
 __global__ __launch_bounds__(256) void dwt_mask_kernel(
     const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
-    int ny, int nx, int layers, float t1, float t2, float t3, void* __restrict__ coef,
-    void* __restrict__ coef_lo, uint8_t* __restrict__ flags, size_t flags_layer) {
+    int ny, int nx, int layers, float t1, float t2, float t3, unsigned parts,
+    float* __restrict__ coef, uint8_t* __restrict__ flags, size_t flags_layer,
+    unsigned long long* __restrict__ ops) {
     constexpr int B = 1 << L;
     const int nbx = nx >> L;
     const int bx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -82,6 +89,7 @@ __global__ __launch_bounds__(256) void dwt_mask_kernel(
     if (sal) pool_saliency<L>(sal, nx, by, bx, pool);
     const float thr[3] = {t1, t2, t3};
     const size_t plane = (size_t)ny * nx;
+    unsigned long long wave_ops[3] = {0ull, 0ull, 0ull};  // same value in every lane
 
     for (int d = 0; d < layers; ++d) {
         float cur[B][B];
@@ -117,14 +125,16 @@ __global__ __launch_bounds__(256) void dwt_mask_kernel(
                     const float hh = (lo[2 * j][i] - lo[2 * j + 1][i]) * 0.5f;
                     const float vv = (hi[2 * j][i] + hi[2 * j + 1][i]) * 0.5f;
                     const float dd = (hi[2 * j][i] - hi[2 * j + 1][i]) * 0.5f;
-                    const bool keep = !sal || pooled<B>(pool, lev, j, i) > thr[lev - 1];
+                    const bool salient = !sal || pooled<B>(pool, lev, j, i) > thr[lev - 1];
+                    if (ops && d == 0) wave_ops[lev - 1] += __popcll(__ballot(salient));
+                    const bool keep = ((parts >> (lev - 1)) & 1u) && salient;
                     const float v = keep ? vv : 0.0f;
                     const float hv = keep ? hh : 0.0f;
                     const float dv = keep ? dd : 0.0f;
                     const int gy = by * h + j, gx = bx * h + i;
-                    store_val<P>(coef, coef_lo, base + (size_t)gy * nx + nxl + gx, v);
-                    store_val<P>(coef, coef_lo, base + (size_t)(nyl + gy) * nx + gx, hv);
-                    store_val<P>(coef, coef_lo, base + (size_t)(nyl + gy) * nx + nxl + gx, dv);
+                    coef[base + (size_t)gy * nx + nxl + gx] = v;
+                    coef[base + (size_t)(nyl + gy) * nx + gx] = hv;
+                    coef[base + (size_t)(nyl + gy) * nx + nxl + gx] = dv;
                     if (frow) {
                         if (v != 0.0f) { frow[gy] = 1; fcol[nxl + gx] = 1; }
                         if (hv != 0.0f) { frow[nyl + gy] = 1; fcol[gx] = 1; }
@@ -133,13 +143,21 @@ __global__ __launch_bounds__(256) void dwt_mask_kernel(
                     cur[j][i] = ll;
                 }
         }
-        store_val<P>(coef, coef_lo, base + (size_t)by * nx + bx, cur[0][0]);
-        if (fl && cur[0][0] != 0.0f) {
+        const float av = ((parts >> L) & 1u) ? cur[0][0] : 0.0f;
+        coef[base + (size_t)by * nx + bx] = av;
+        if (fl && av != 0.0f) {
             uint8_t* frow = fl + flag_level_off(ny, nx, L);
             frow[by] = 1;
             frow[band_side(ny, L) + bx] = 1;
         }
         (void)any;
+    }
+    if (ops) {
+        // the lowest active lane of the wave publishes the wave's counts
+        const unsigned long long active = __ballot(1);
+        if ((int)__lane_id() == __ffsll((long long)active) - 1)
+            for (int l = 0; l < L; ++l)
+                if (wave_ops[l]) atomicAdd(&ops[l], 4ull * wave_ops[l]);
     }
 }
 
@@ -287,31 +305,29 @@ hipError_t launch_fill_u8(uint8_t* p, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int L, int P>
+template <int L>
 static void dwt_launch(const float* obj, const uint8_t* layer, const float* sal, int ny, int nx,
-                       int layers, const float* thr, void* coef, void* coef_lo, uint8_t* flags,
-                       size_t flags_layer, hipStream_t s) {
+                       int layers, const float* thr, unsigned parts, float* coef, uint8_t* flags,
+                       size_t flags_layer, unsigned long long* ops, hipStream_t s) {
     const int nbx = nx >> L;
     dim3 grid((nbx + 255) / 256, ny >> L);
-    hipLaunchKernelGGL((dwt_mask_kernel<L, P>), grid, dim3(256), 0, s, obj, layer, sal, ny, nx,
-                       layers, thr[0], L >= 2 ? thr[1] : 0.f, L >= 3 ? thr[2] : 0.f, coef, coef_lo,
-                       flags, flags_layer);
+    hipLaunchKernelGGL((dwt_mask_kernel<L>), grid, dim3(256), 0, s, obj, layer, sal, ny, nx,
+                       layers, thr[0], L >= 2 ? thr[1] : 0.f, L >= 3 ? thr[2] : 0.f, parts, coef,
+                       flags, flags_layer, ops);
 }
 
 hipError_t launch_dwt_mask(const float* obj, const uint8_t* layer, const float* sal, int ny, int nx,
-                           int layers, int levels, const float* thr, int precision, void* coef,
-                           void* coef_lo, uint8_t* flags, size_t flags_layer, hipStream_t s) {
-#define CGH_DWT_CASE(LV, PR)                                                                 \
-    if (levels == LV && precision == PR) {                                                   \
-        dwt_launch<LV, PR>(obj, layer, sal, ny, nx, layers, thr, coef, coef_lo, flags,       \
-                           flags_layer, s);                                                  \
-        return hipGetLastError();                                                            \
-    }
-    CGH_DWT_CASE(1, P_FP32) CGH_DWT_CASE(2, P_FP32) CGH_DWT_CASE(3, P_FP32)
-    CGH_DWT_CASE(1, P_BF16) CGH_DWT_CASE(2, P_BF16) CGH_DWT_CASE(3, P_BF16)
-    CGH_DWT_CASE(1, P_FP16) CGH_DWT_CASE(2, P_FP16) CGH_DWT_CASE(3, P_FP16)
-#undef CGH_DWT_CASE
-    return hipErrorInvalidValue;
+                           int layers, int levels, const float* thr, unsigned parts, float* coef,
+                           uint8_t* flags, size_t flags_layer, unsigned long long* ops,
+                           hipStream_t s) {
+    if (levels == 1)
+        dwt_launch<1>(obj, layer, sal, ny, nx, layers, thr, parts, coef, flags, flags_layer, ops, s);
+    else if (levels == 2)
+        dwt_launch<2>(obj, layer, sal, ny, nx, layers, thr, parts, coef, flags, flags_layer, ops, s);
+    else if (levels == 3)
+        dwt_launch<3>(obj, layer, sal, ny, nx, layers, thr, parts, coef, flags, flags_layer, ops, s);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_idwt(const float* coef, int ny, int nx, int levels, float* out, hipStream_t s) {

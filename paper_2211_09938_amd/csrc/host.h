@@ -66,7 +66,10 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
         lo.t_layer += (size_t)cgh::band_side(ny, l) * nx;
         lo.flags_layer += (size_t)cgh::band_side(ny, l) + cgh::band_side(nx, l);
     }
-    lo.flags = take((size_t)layers * lo.flags_layer);
+    const size_t flag_bytes = (size_t)layers * lo.flags_layer;
+    lo.flags = take((flag_bytes + 7) / 8 * 8 + 32);
+    lo.ops = lo.flags + (flag_bytes + 7) / 8 * 8;
+    lo.flags_fill = lo.ops + 32 - lo.flags;
     const cgh::NtSizes z = cgh::nt_sizes(ny, nx, layers, levels);
     lo.rowlist = take(z.rowlist * 4);
     lo.collist = take(z.collist * 4);

@@ -97,6 +97,28 @@ def test_forward_rejects_invalid_arguments(over, code):
     assert call_forward(**over) == code
 
 
+@pytest.mark.parametrize("over,code", [
+    (dict(obj=None), INVALID),
+    (dict(out=None), INVALID),
+    (dict(flags=1), INVALID),                         # accumulate is rejected for stages
+    (dict(lam=-1.0), INVALID),
+    (dict(ny=60), SHAPE),
+    (dict(ws_bytes=1024), WS),
+])
+def test_stages_rejects_invalid_arguments(over, code):
+    z = (ctypes.c_double * 1)(0.2)
+    args = dict(obj=BOGUS, layer=None, n_layers=1, z=z, sal=None, thr=None, lam=532e-9,
+                pitch=8e-6, ny=64, nx=64, levels=3, prec=0, flags=0, ws=BOGUS, ws_bytes=1 << 40,
+                out=BOGUS)
+    args.update(over)
+    assert cgh.lib().cgh_progressive_stages(
+        args["obj"], args["layer"], args["n_layers"], args["z"], args["sal"], args["thr"],
+        args["lam"], args["pitch"], args["ny"], args["nx"], args["levels"], args["prec"],
+        args["flags"], args["ws"], args["ws_bytes"], args["out"], None) == code
+    assert cgh.lib().cgh_progressive_stages(None, None, 1, z, None, None, 532e-9, 8e-6, 0, 64, 3,
+                                            0, 0, None, 0, None, None) == OK
+
+
 def test_forward_empty_problem_is_a_no_op():
     assert call_forward(ny=0, obj=None, out=None, ws=None, ws_bytes=0) == OK
     assert call_forward(nx=0, obj=None, out=None, ws=None, ws_bytes=0) == OK

@@ -2,8 +2,9 @@
 launch per contraction over scenes of uneven size.
 
 Each scene of a batch must match its own single-scene call (same method; only
-the tile schedule and the K split differ, so agreement is to FP32 rounding,
-rel-L2 <= 1e-6) and the FP64 oracle on sampled pixels (rel-L2 <= 1e-5 for FP32,
+the tile schedule and the K split differ, so agreement is to FP32 rounding:
+rel-L2 <= 1e-6 on the small batches, and within twice the summation-order bound
+sqrt(K) * 2^-24 on the 64-scene workload, whose scenes reach K ~ 3000 rows) and the FP64 oracle on sampled pixels (rel-L2 <= 1e-5 for FP32,
 1e-3 for the split forms).  Graph replays are checked against the eager result
 with unrelated eager work and synchronisations between the replays.
 """
@@ -77,6 +78,15 @@ def test_batch_matches_single_scene_calls_and_oracle(precision, tmp_path):
         assert rel_l2(hs[k][ys, xs], oracle_hologram(s, pixels=(ys, xs))) <= tol
     info = plan.info()
     assert info["n_scenes"] == len(batch) and not info["from_cache"]
+    # operator accounting of Sec. 3, summed over the scenes, exact
+    from oracle import literal
+
+    want = np.zeros(4, dtype=np.int64)
+    for s in batch:
+        want += np.array(literal.operator_counts(*s.shape, 3, s.saliency.astype(np.float64))[0])
+    st = plan.stats()
+    assert st["operators"] == [int(v) for v in want]
+    assert st["operators_pointwise"] == sum(s.obj.size for s in batch)
     plan.close()
 
 
@@ -142,6 +152,21 @@ def test_empty_and_single_scene_batches():
     plan.close()
 
 
+def single_with_rows(s, precision):
+    import torch
+
+    m = cgh()
+    d = dev_scene(s)
+    ny, nx = s.shape
+    ws = torch.empty(m.workspace_size(ny, nx, len(s.z), 3, precision), dtype=torch.uint8,
+                     device="cuda")
+    h = m.progressive_hologram(d["obj"], s.z, s.lam, s.pitch, 3, d["saliency"],
+                               d.get("layer_index"), precision=precision, workspace=ws)
+    rows = m.workspace_stats(ws, ny, nx, len(s.z), 3, precision)["coef_rows_active"]
+    torch.cuda.synchronize()
+    return h.cpu().numpy(), rows
+
+
 @functools.lru_cache(maxsize=1)
 def batch64():
     return scenes.batched()
@@ -161,10 +186,16 @@ def test_batch64_workload_matches_single_calls_and_oracle_windows(precision, tmp
     torch.cuda.synchronize()
     worst = 0.0
     for k, s in enumerate(batch):
-        err = rel_l2(plan.holograms[k].cpu().numpy(), single(s, precision))
-        worst = max(worst, err)
-        assert err <= 1e-6, (k, s.name, err)
-    print(f"batch64 {precision}: worst rel-L2 vs single-scene calls {worst:.2e}")
+        # the single-scene call splits K in two and sums the halves; the batched
+        # call runs K in one pass.  Each ordering of an FP32 sum over K active
+        # rows is off the exact sum by about sqrt(K) * 2^-24 relative, so the two
+        # may differ by up to twice that.
+        h1, rows = single_with_rows(s, precision)
+        tol = 2.0 * np.sqrt(rows) * 2.0 ** -24
+        err = rel_l2(plan.holograms[k].cpu().numpy(), h1)
+        worst = max(worst, err / tol)
+        assert err <= tol, (k, s.name, err, tol)
+    print(f"batch64 {precision}: worst rel-L2 vs single-scene calls {worst:.2f} of its bound")
     tol = 1e-5 if precision == "fp32" else 1e-3
     rng = np.random.default_rng(64)
     for k in rng.choice(len(batch), 4, replace=False):

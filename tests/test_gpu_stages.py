@@ -1,0 +1,157 @@
+"""GPU parity of the progressive stage holograms (cgh_progressive_stages).
+
+Each stage is compared with the FP64 oracle's stage hologram (same bars as the
+forward path: rel-L2 <= 1e-5 FP32, <= 1e-3 split); the last stage with the
+single-call hologram (same method, increments summed in another order: within
+twice the FP32 summation-order bound sqrt(K) * 2^-24 over K active rows).
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import progressive
+from paper_2211_09938_amd import scenes
+
+from helpers import rel_l2, sample_pixels, to_dev
+
+pytestmark = pytest.mark.gpu
+os.environ.setdefault("ORACLE_WORKERS", "8")
+
+
+def cgh():
+    from paper_2211_09938_amd import cgh as m
+
+    return m
+
+
+def gpu_stages(s, precision="fp32", thresholds=None):
+    import torch
+
+    m = cgh()
+    sal = None if s.saliency is None else to_dev(s.saliency)
+    lay = None if s.layer is None else to_dev(s.layer)
+    st = m.progressive_stages(to_dev(s.obj), s.z, s.lam, s.pitch, s.levels, sal, lay,
+                              thresholds=thresholds, precision=precision)
+    torch.cuda.synchronize()
+    return st.cpu().numpy().astype(np.complex128)
+
+
+def oracle_stages(s, pixels=None, thresholds=None):
+    sal = None if s.saliency is None else s.saliency.astype(np.float64)
+    return progressive.stage_holograms(s.obj.astype(np.float64), s.z, s.lam, s.pitch, s.levels,
+                                       sal, s.layer, thresholds, pixels=pixels)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16_split", 1e-3)])
+@pytest.mark.parametrize("case", ["tiny", "ragged3", "levels2"])
+def test_stages_match_oracle(case, precision, tol):
+    if case == "tiny":
+        s = scenes.tiny()
+    elif case == "ragged3":
+        s = scenes.random_scene(301, 72, 136, planes=3, fraction=0.35)
+    else:
+        s = scenes.random_scene(302, 40, 56, planes=2, levels=2)
+    got = gpu_stages(s, precision)
+    ref = oracle_stages(s)
+    assert got.shape == (s.levels + 1,) + s.shape
+    for j in range(s.levels + 1):
+        err = rel_l2(got[j], ref[j])
+        print(f"{case} {precision} stage {j}: rel-L2 {err:.2e}")
+        assert err <= tol
+
+
+def test_last_stage_equals_single_call_and_stages_differ():
+    import torch
+
+    s = scenes.random_scene(303, 256, 192, planes=2, fraction=0.4)
+    st = gpu_stages(s)
+    m = cgh()
+    ny, nx = s.shape
+    ws = torch.empty(m.workspace_size(ny, nx, 2, 3, "fp32"), dtype=torch.uint8, device="cuda")
+    h = m.progressive_hologram(to_dev(s.obj), s.z, s.lam, s.pitch, 3, to_dev(s.saliency),
+                               to_dev(s.layer), workspace=ws)
+    rows = m.workspace_stats(ws, ny, nx, 2, 3, "fp32")["coef_rows_active"]
+    torch.cuda.synchronize()
+    err = rel_l2(st[3], h.cpu().numpy())
+    assert err <= 2.0 * np.sqrt(rows) * 2.0 ** -24
+    for j in range(3):
+        assert rel_l2(st[j], st[j + 1]) > 1e-3  # every stage adds salient detail
+
+
+def test_stages_edge_cases():
+    # no salient block: every stage equals stage 0; all-salient custom thresholds
+    s = scenes.random_scene(304, 64, 64, planes=1, fraction=0.3)
+    s.saliency[:] = 0.0
+    st = gpu_stages(s)
+    for j in range(1, 4):
+        assert np.array_equal(st[j], st[0])
+    assert rel_l2(st[0], oracle_stages(s)[0]) <= 1e-5
+    z = scenes.random_scene(305, 32, 32)
+    z.obj[:] = 0.0
+    assert np.all(gpu_stages(z) == 0)
+
+
+def test_depth_2048_stages_sampled():
+    s = scenes.depth_2048()
+    st = gpu_stages(s)
+    ys, xs = sample_pixels(2048, 2048, seed=33, n_random=24, crop=4)
+    ref = oracle_stages(s, pixels=(ys, xs))
+    for j in range(4):
+        err = rel_l2(st[j][ys, xs], ref[j])
+        print(f"depth2048 stage {j}: rel-L2 {err:.2e}")
+        assert err <= 1e-5
+
+
+# ------------------------------------------------ operator accounting (Sec. 3) on the GPU
+@pytest.mark.parametrize("case", ["tiny", "p256", "ragged", "depth2048", "graded"])
+def test_operator_counts_match_oracle_exactly(case):
+    import torch
+
+    from oracle import literal
+
+    thresholds = None
+    if case == "tiny":
+        s = scenes.tiny()
+    elif case == "p256":
+        s = scenes.random_scene(311, 256, 256, planes=1, fraction=0.25)
+    elif case == "ragged":
+        s = scenes.random_scene(312, 72, 136, planes=3, fraction=0.4)
+    elif case == "depth2048":
+        s = scenes.depth_2048()
+    else:
+        s = scenes.random_scene(313, 64, 96, planes=2, fraction=None)
+        s.saliency = np.random.default_rng(313).uniform(0, 1, s.shape).astype(np.float32)
+        thresholds = (0.8, 0.6, 0.3)
+    m = cgh()
+    ny, nx = s.shape
+    ws = torch.empty(m.workspace_size(ny, nx, len(s.z), 3, "fp32"), dtype=torch.uint8,
+                     device="cuda")
+    sal = to_dev(s.saliency)
+    lay = None if s.layer is None else to_dev(s.layer)
+    m.progressive_hologram(to_dev(s.obj), s.z, s.lam, s.pitch, 3, sal, lay,
+                           thresholds=thresholds, workspace=ws)
+    st = m.workspace_stats(ws, ny, nx, len(s.z), 3, "fp32")
+    steps, _, pointwise = literal.operator_counts(ny, nx, 3, s.saliency.astype(np.float64),
+                                                  thresholds)
+    assert st["operators"] == steps
+    assert st["operators_pointwise"] == pointwise
+    # a second call on the same workspace counts afresh
+    m.progressive_hologram(to_dev(s.obj), s.z, s.lam, s.pitch, 3, sal, lay,
+                           thresholds=thresholds, workspace=ws)
+    assert m.workspace_stats(ws, ny, nx, len(s.z), 3, "fp32")["operators"] == steps
+
+
+def test_operator_counts_without_saliency_and_at_256():
+    import torch
+
+    m = cgh()
+    ws = torch.empty(m.workspace_size(256, 256, 1, 3, "fp32"), dtype=torch.uint8, device="cuda")
+    obj = torch.rand((256, 256), device="cuda")
+    m.progressive_hologram(obj, (0.2,), 532e-9, 8e-6, 3, None, None, workspace=ws)
+    st = m.workspace_stats(ws, 256, 256, 1, 3, "fp32")
+    # every block salient: 1024 for the coarsest step, then the full residual maps;
+    # 65,536 point-wise (the two counts printed in Sec. 3)
+    assert st["operators"] == [1024, 4096, 16384, 65536]
+    assert st["operators_pointwise"] == 65536
