@@ -266,12 +266,17 @@ int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lamb
         hipError_t e = cgh::launch_luts(nx, 1, 1, 0, &c, &one, &zero, cgh::P_FP32, lut0_x, nullptr, s);
         if (e == hipSuccess)
             e = cgh::launch_luts(ny, 1, 1, 0, &c, &one, &zero, cgh::P_FP32, lut0_y, nullptr, s);
-        if (e == hipSuccess)
-            e = cgh::launch_backprop(ny, nx, lut0_x, lut0_y,
-                                         reinterpret_cast<const float2*>(field_in),
-                                         reinterpret_cast<float2*>(ws + lo.t),
-                                         reinterpret_cast<float2*>(field_out), adjoint ? 1 : 0,
-                                         (float)(1.0 / ((double)ny * (double)nx)), precision, s);
+        if (e == hipSuccess) {
+            const cgh::DenseBuffers b = cgh::dense_buffers(
+                ws + lo.big, ny, nx, lo.split_k, reinterpret_cast<float2*>(ws + lo.partial),
+                reinterpret_cast<cgh::NtEntry*>(ws + lo.entries), reinterpret_cast<int*>(ws + lo.hdr));
+            e = cgh::launch_dense_backprop(b, lut0_x, lut0_y,
+                                           reinterpret_cast<const float2*>(field_in),
+                                           reinterpret_cast<float2*>(field_out), ny, nx,
+                                           adjoint ? 1 : 0,
+                                           (float)(1.0 / ((double)ny * (double)nx)), precision,
+                                           lo.split_k, s);
+        }
         return hip_status(e);
     } catch (...) {
         return CGH_ERROR_HIP;

@@ -1,0 +1,200 @@
+// Dense complex products with Toeplitz fringe panels on the MFMA kernel of the
+// forward pass: the Fresnel back-propagation used by the differentiable form
+// (numerical reconstruction, Sec. 2 last paragraph, with the Fresnel kernel)
+// and its adjoint.
+//
+// With K[m][q] = k(m - q) (symmetric, k from the level-0 fringe table) and
+// K' = conj(K) for the back-propagation, K' = K for its adjoint:
+//     U = s * K'_y . H . K'_x
+// as two NT products (operands K-contiguous, padded with zeros to 16):
+//     step 1:  T[p][y] = sum_x K'_x[p][x] * H[y][x]       A = K'_x panel, B = H panel
+//     step 2:  U[q][p] = sum_y s K'_y[q][y] * T[p][y]     A = s K'_y panel, B = T panel
+// Both run split-K into FP32 partials; step 1's partials are summed straight
+// into the operand planes of T.
+#include "gemm.h"
+#include "nt.h"
+#include "split.h"
+
+namespace cgh {
+
+namespace {
+
+inline int grid_1d(size_t n) {
+    const size_t b = (n + 255) / 256;
+    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+// out[r][c] = scale * k'(r - c) for c < cols, zero for cols <= c < ld.
+// table: re part then im part, each lut_len(n_tab) floats, entry m + n_tab.
+template <int P>
+__global__ __launch_bounds__(256) void toeplitz_panel_kernel(const float* __restrict__ table,
+                                                             int n_tab, int rows, int cols, int ld,
+                                                             float scale, float im_sign,
+                                                             void* __restrict__ out, size_t ps) {
+    const size_t total = (size_t)rows * ld;
+    const int len = lut_len(n_tab);
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / ld), c = (int)(e - (size_t)r * ld);
+        float re = 0.f, im = 0.f;
+        if (c < cols) {
+            const int idx = r - c + n_tab;
+            re = scale * table[idx];
+            im = im_sign * scale * table[len + idx];
+        }
+        put_c<P>(out, ps, e, re, im);
+    }
+}
+
+// Interleaved complex64 [rows][cols] -> operand planes [rows][ld], zero pad.
+template <int P>
+__global__ __launch_bounds__(256) void complex_panel_kernel(const float2* __restrict__ in,
+                                                            int rows, int cols, int ld,
+                                                            void* __restrict__ out, size_t ps) {
+    const size_t total = (size_t)rows * ld;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / ld), c = (int)(e - (size_t)r * ld);
+        const float2 v = c < cols ? in[(size_t)r * cols + c] : make_float2(0.f, 0.f);
+        put_c<P>(out, ps, e, v.x, v.y);
+    }
+}
+
+// Sum of `split` FP32 partials [split][rows][cols] -> operand planes [rows][ld].
+template <int P>
+__global__ __launch_bounds__(256) void reduce_panel_kernel(const float2* __restrict__ partial,
+                                                           int split, int rows, int cols, int ld,
+                                                           void* __restrict__ out, size_t ps) {
+    const size_t total = (size_t)rows * ld, plane = (size_t)rows * cols;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / ld), c = (int)(e - (size_t)r * ld);
+        float re = 0.f, im = 0.f;
+        if (c < cols) {
+            const size_t i = (size_t)r * cols + c;
+            for (int s = 0; s < split; ++s) {
+                const float2 v = partial[(size_t)s * plane + i];
+                re += v.x;
+                im += v.y;
+            }
+        }
+        put_c<P>(out, ps, e, re, im);
+    }
+}
+
+// Writes one problem and its tile count where the contraction kernel reads them.
+__global__ void dense_entry_kernel(NtEntry e, int tiles, NtEntry* __restrict__ dst,
+                                   int* __restrict__ count) {
+    if (threadIdx.x == 0) {
+        *dst = e;
+        *count = tiles;
+    }
+}
+
+template <int P>
+hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const float* lut0_y,
+                          const float2* in, float2* out, int ny, int nx, int adjoint, float scale,
+                          int split, hipStream_t s) {
+    const int ldx = pad_kt(nx), ldy = pad_kt(ny);
+    const float im_sign = adjoint ? 1.f : -1.f;
+    const size_t kx_ps = (size_t)nx * ldx, ky_ps = (size_t)ny * ldy;
+    const size_t h_ps = (size_t)ny * ldx, t_ps = (size_t)nx * ldy;
+    hipLaunchKernelGGL(toeplitz_panel_kernel<P>, dim3(grid_1d(kx_ps)), dim3(256), 0, s, lut0_x,
+                       nx, nx, nx, ldx, 1.f, im_sign, b.kx, kx_ps);
+    hipLaunchKernelGGL(toeplitz_panel_kernel<P>, dim3(grid_1d(ky_ps)), dim3(256), 0, s, lut0_y,
+                       ny, ny, ny, ldy, scale, im_sign, b.ky, ky_ps);
+    hipLaunchKernelGGL(complex_panel_kernel<P>, dim3(grid_1d(h_ps)), dim3(256), 0, s, in, ny, nx,
+                       ldx, b.h, h_ps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+
+    const int tiles = nt_tiles(nx, ny, kNtTile, kNtTile);  // same count for both steps
+    NtEntry e1{};
+    e1.a = b.kx;
+    e1.b = b.h;
+    e1.out = split > 1 ? b.partial : b.c1;
+    e1.partial = b.partial;
+    e1.a_ps = (long long)kx_ps;
+    e1.b_ps = (long long)h_ps;
+    e1.M = nx;
+    e1.N = ny;
+    e1.K = ldx;
+    e1.lda = ldx;
+    e1.ldb = ldx;
+    e1.out_ld = ny;
+    e1.tiles_n = (ny + kNtTile - 1) / kNtTile;
+    e1.tile_m = e1.tile_n = kNtTile;
+    hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e1, tiles, b.entries,
+                       b.counts);
+    if ((e = launch_nt_complex(P, b.entries, b.counts, tiles, split, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_panel_kernel<P>, dim3(grid_1d(t_ps)), dim3(256), 0, s,
+                       split > 1 ? b.partial : b.c1, split, nx, ny, ldy, b.t, t_ps);
+
+    NtEntry e2{};
+    e2.a = b.ky;
+    e2.b = b.t;
+    e2.out = out;
+    e2.partial = b.partial;
+    e2.a_ps = (long long)ky_ps;
+    e2.b_ps = (long long)t_ps;
+    e2.M = ny;
+    e2.N = nx;
+    e2.K = ldy;
+    e2.lda = ldy;
+    e2.ldb = ldy;
+    e2.out_ld = nx;
+    e2.tiles_n = (nx + kNtTile - 1) / kNtTile;
+    e2.tile_m = e2.tile_n = kNtTile;
+    hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e2, tiles, b.entries + 1,
+                       b.counts + 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_nt_complex(P, b.entries + 1, b.counts + 1, tiles, split, s)) != hipSuccess)
+        return e;
+    if (split > 1) {
+        const GemmShape sh{ny, nx, 1, 1, split, P, 0, 0};
+        return launch_reduce_partial(sh, b.partial, out, 0, s);
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+size_t dense_bytes(int ny, int nx, int split) {
+    const size_t ldx = pad_kt(nx), ldy = pad_kt(ny);
+    const size_t panels = 8 * ((size_t)nx * ldx + (size_t)ny * ldy + (size_t)ny * ldx +
+                               (size_t)nx * ldy);
+    return panels + 4 * 256 + (split > 1 ? 0 : 8 * (size_t)ny * nx);
+}
+
+DenseBuffers dense_buffers(char* base, int ny, int nx, int split, float2* partial,
+                           NtEntry* entries, int* counts) {
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t ldx = pad_kt(nx), ldy = pad_kt(ny);
+    DenseBuffers b{};
+    size_t off = 0;
+    b.kx = base + off;
+    off += al(8 * (size_t)nx * ldx);
+    b.ky = base + off;
+    off += al(8 * (size_t)ny * ldy);
+    b.h = base + off;
+    off += al(8 * (size_t)ny * ldx);
+    b.t = base + off;
+    off += al(8 * (size_t)nx * ldy);
+    b.c1 = split > 1 ? nullptr : reinterpret_cast<float2*>(base + off);
+    b.partial = partial;
+    b.entries = entries;
+    b.counts = counts;
+    return b;
+}
+
+hipError_t launch_dense_backprop(const DenseBuffers& b, const float* lut0_x, const float* lut0_y,
+                                 const float2* in, float2* out, int ny, int nx, int adjoint,
+                                 float scale, int precision, int split, hipStream_t s) {
+    if (precision == P_BF16)
+        return dense_backprop<P_BF16>(b, lut0_x, lut0_y, in, out, ny, nx, adjoint, scale, split, s);
+    if (precision == P_FP16)
+        return dense_backprop<P_FP16>(b, lut0_x, lut0_y, in, out, ny, nx, adjoint, scale, split, s);
+    return dense_backprop<P_FP32>(b, lut0_x, lut0_y, in, out, ny, nx, adjoint, scale, split, s);
+}
+
+}  // namespace cgh

@@ -22,8 +22,4 @@ hipError_t launch_reduce_partial(const GemmShape& sh, const float2* partial, flo
 hipError_t launch_backward(const GemmShape& sh, const float2* grad_h, const float* lut_x,
                                const float* lut_y, float2* q, float* gcoef, hipStream_t s);
 
-hipError_t launch_backprop(int ny, int nx, const float* lut0_x, const float* lut0_y,
-                           const float2* in, float2* tmp, float2* out, int adjoint, float scale,
-                           int precision, hipStream_t s);
-
 }  // namespace cgh

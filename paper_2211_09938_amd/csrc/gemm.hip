@@ -1,13 +1,12 @@
-// Complex contractions of the adjoint and of the Fresnel back-propagation on
-// CDNA4 matrix cores (the forward pass uses the compacted kernels of ntgemm.hip).
+// Complex contractions of the adjoint on CDNA4 matrix cores (the forward pass
+// uses the compacted kernels of ntgemm.hip, the back-propagation dense.hip).
 //
 // Per depth layer d and Haar level l the hologram contribution factors as
 //     H_{d,l} = Fy_{d,l} * Cb_{d,l} * Fx_{d,l}^T                        (Eq. 3, separable Eq. 1)
 // where Cb is the level-l square of Mallat coefficients (its LL quadrant empty
 // for l < L) and F[pix, j] = g_band(j)[pix - (j mod n_l) * 2^l] is the
 // strided-Toeplitz matrix of the 1D block fringes (lut.hip).  The adjoint is
-//     Q_{d,l}  = Fy_{d,l}^H * G,   gC_{d,l} = Re(Q_{d,l} * conj(Fx_{d,l}))
-// and the back-propagation uses the level-0 fringe (the kernel itself).
+//     Q_{d,l}  = Fy_{d,l}^H * G,   gC_{d,l} = Re(Q_{d,l} * conj(Fx_{d,l})).
 // Fringe operands are never materialised: each K tile gathers its elements of
 // the 1D table (a few KB, cache resident) straight into LDS.
 //
@@ -477,80 +476,6 @@ struct BwdS2 {
     }
 };
 
-// ------------------------------------------------- Fresnel back-propagation
-// stage 1: V[q, x] = sum_y k*(y - q) H[y, x]      (k* = conj(k), or k for the adjoint)
-// stage 2: U[q, p] = s * sum_x V[q, x] k*(x - p)
-struct PropS1 {
-    static constexpr bool A_CPLX = true, B_CPLX = true, OUT_REAL = false;
-    static constexpr bool A_KFAST = true, B_KFAST = false;
-    const float* lut_y;  // level-0 table of the y axis (re then im)
-    const float2* in;
-    float2* v;
-    int ny, nx, conj, ctiles;
-    struct Ctx { int m0, n0; };
-    struct KT { int y0; };
-    __device__ bool setup(Ctx& cx) const {
-        cx.m0 = (blockIdx.x / ctiles) * BM;
-        cx.n0 = (blockIdx.x % ctiles) * BN;
-        return true;
-    }
-    __device__ int nk(const Ctx&) const { return (ny + BK - 1) / BK; }
-    __device__ KT kt(const Ctx&, int i) const { return KT{i * BK}; }
-    __device__ float2 a(const Ctx& cx, const KT& kd, int m, int k) const {
-        const int qq = cx.m0 + m, y = kd.y0 + k;
-        if (qq < ny && y < ny) {
-            const int len = lut_len(ny), idx = y - qq + ny;
-            return make_float2(lut_y[idx], conj ? -lut_y[len + idx] : lut_y[len + idx]);
-        }
-        return cz();
-    }
-    __device__ float2 b(const Ctx& cx, const KT& kd, int k, int n) const {
-        const int y = kd.y0 + k, x = cx.n0 + n;
-        if (y < ny && x < nx) return in[(size_t)y * nx + x];
-        return cz();
-    }
-    __device__ void store(const Ctx& cx, int m, int n, float re, float im) const {
-        const int qq = cx.m0 + m, x = cx.n0 + n;
-        if (qq < ny && x < nx) v[(size_t)qq * nx + x] = make_float2(re, im);
-    }
-};
-
-struct PropS2 {
-    static constexpr bool A_CPLX = true, B_CPLX = true, OUT_REAL = false;
-    static constexpr bool A_KFAST = true, B_KFAST = true;
-    const float* lut_x;
-    const float2* v;
-    float2* out;
-    int ny, nx, conj, ctiles;
-    float scale;
-    struct Ctx { int m0, n0; };
-    struct KT { int x0; };
-    __device__ bool setup(Ctx& cx) const {
-        cx.m0 = (blockIdx.x / ctiles) * BM;
-        cx.n0 = (blockIdx.x % ctiles) * BN;
-        return true;
-    }
-    __device__ int nk(const Ctx&) const { return (nx + BK - 1) / BK; }
-    __device__ KT kt(const Ctx&, int i) const { return KT{i * BK}; }
-    __device__ float2 a(const Ctx& cx, const KT& kd, int m, int k) const {
-        const int qq = cx.m0 + m, x = kd.x0 + k;
-        if (qq < ny && x < nx) return v[(size_t)qq * nx + x];
-        return cz();
-    }
-    __device__ float2 b(const Ctx& cx, const KT& kd, int k, int n) const {
-        const int x = kd.x0 + k, p = cx.n0 + n;
-        if (x < nx && p < nx) {
-            const int len = lut_len(nx), idx = x - p + nx;
-            return make_float2(lut_x[idx], conj ? -lut_x[len + idx] : lut_x[len + idx]);
-        }
-        return cz();
-    }
-    __device__ void store(const Ctx& cx, int m, int n, float re, float im) const {
-        const int qq = cx.m0 + m, p = cx.n0 + n;
-        if (qq < ny && p < nx) out[(size_t)qq * nx + p] = make_float2(re * scale, im * scale);
-    }
-};
-
 __global__ __launch_bounds__(256) void reduce_partial_kernel(const float2* __restrict__ partial,
                                                              int split, size_t n, int accumulate,
                                                              float2* __restrict__ out) {
@@ -631,31 +556,6 @@ hipError_t launch_backward(const GemmShape& sh, const float2* grad_h, const floa
     p2.t_layer = sh.t_layer;
     p2.g = make_grid(sh.ny, sh.levels, cols);
     return run(p2, dim3(p2.g.cum[sh.levels] * sh.layers), s, sh.precision);
-}
-
-hipError_t launch_backprop(int ny, int nx, const float* lut0_x, const float* lut0_y,
-                           const float2* in, float2* tmp, float2* out, int adjoint, float scale,
-                           int precision, hipStream_t s) {
-    PropS1 p1{};
-    p1.lut_y = lut0_y;
-    p1.in = in;
-    p1.v = tmp;
-    p1.ny = ny;
-    p1.nx = nx;
-    p1.conj = adjoint ? 0 : 1;
-    p1.ctiles = (nx + BN - 1) / BN;
-    hipError_t e = run(p1, dim3(((ny + BM - 1) / BM) * p1.ctiles), s, precision);
-    if (e != hipSuccess) return e;
-    PropS2 p2{};
-    p2.lut_x = lut0_x;
-    p2.v = tmp;
-    p2.out = out;
-    p2.ny = ny;
-    p2.nx = nx;
-    p2.conj = adjoint ? 0 : 1;
-    p2.ctiles = (nx + BN - 1) / BN;
-    p2.scale = scale;
-    return run(p2, dim3(((ny + BM - 1) / BM) * p2.ctiles), s, precision);
 }
 
 }  // namespace cgh

@@ -87,7 +87,11 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
     if (t_bytes < plane * 8) t_bytes = plane * 8;
     const size_t fx_b = align_up(z.fx_plane * 8), cb_b = align_up(z.cb_plane * 4);
     const size_t fy_b = align_up(z.fy_plane * 8), tc_b = align_up(z.tc_plane * 8);
-    const size_t panels = fx_b + cb_b + fy_b + tc_b;
+    size_t panels = fx_b + cb_b + fy_b + tc_b;
+    // the dense back-propagation panels share the region (one layer, one level)
+    lo.split_k = with_partial ? choose_split(ny, nx, levels, layers) : 1;
+    const size_t dense = cgh::dense_bytes(ny, nx, lo.split_k);
+    if (dense > panels) panels = dense;
     lo.big = take(t_bytes > panels ? t_bytes : panels);
     lo.t = lo.big;
     lo.fx = lo.big;
@@ -98,7 +102,6 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
     lo.cb_ps = z.cb_plane;
     lo.fy_ps = z.fy_plane;
     lo.tc_ps = z.tc_plane;
-    lo.split_k = with_partial ? choose_split(ny, nx, levels, layers) : 1;
     lo.partial = take(lo.split_k > 1 ? (size_t)lo.split_k * plane * 8 : 0);
     lo.total = off;
     return lo;

@@ -159,6 +159,31 @@ hipError_t launch_nt_persistent(bool second, int precision, int tile_m, int tile
 hipError_t launch_batch_prefix(const PlanHeader* hdrs, int n_scenes, const int* first_off,
                                NtEntry* first, NtEntry* second, int* counts, int* queues,
                                hipStream_t s);
+// Direct launch of one complex x complex problem (tile 128 x 128, split-K when
+// split > 1: the problem's partial buffer holds `split` FP32 planes).
+hipError_t launch_nt_complex(int precision, const NtEntry* entry, const int* tile_count, int tiles,
+                             int split, hipStream_t s);
+
+// Dense products with Toeplitz fringe panels (Fresnel back-propagation).
+struct DenseBuffers {
+    void* kx;           // K'_x panel [p][x], nx x pad16(nx)
+    void* ky;           // s K'_y panel [q][y], ny x pad16(ny)
+    void* h;            // input field panel [y][x], ny x pad16(nx)
+    void* t;            // step-1 product panel [p][y], nx x pad16(ny)
+    float2* c1;         // step-1 FP32 product when the K range is not split
+    float2* partial;    // split-K partials (split x ny x nx)
+    NtEntry* entries;   // 2 problem slots
+    int* counts;        // 2 tile counts
+};
+// Bytes of the panel region (plus the unsplit step-1 product) for a split.
+size_t dense_bytes(int ny, int nx, int split);
+DenseBuffers dense_buffers(char* base, int ny, int nx, int split, float2* partial,
+                           NtEntry* entries, int* counts);
+// out = scale * K'_y in K'_x, K' = conj(K) (adjoint == 0) or K (adjoint != 0).
+hipError_t launch_dense_backprop(const DenseBuffers& b, const float* lut0_x, const float* lut0_y,
+                                 const float2* in, float2* out, int ny, int nx, int adjoint,
+                                 float scale, int precision, int split, hipStream_t s);
+
 // Tiles of a problem with M rows and N columns under a tile shape.
 __host__ __device__ inline int nt_tiles(int M, int N, int tm, int tn) {
     return ((M + tm - 1) / tm) * ((N + tn - 1) / tn);

@@ -438,6 +438,21 @@ hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBu
     return second_direct<P_FP32>(ny, nx, split, b, s);
 }
 
+hipError_t launch_nt_complex(int precision, const NtEntry* entry, const int* tile_count, int tiles,
+                             int split, hipStream_t s) {
+    const dim3 grid(tiles * split);
+    if (precision == P_BF16)
+        hipLaunchKernelGGL((nt_direct_kernel<P_BF16, true, SecondEpi, 128, 128>), grid, dim3(256),
+                           0, s, entry, 1, tile_count, split);
+    else if (precision == P_FP16)
+        hipLaunchKernelGGL((nt_direct_kernel<P_FP16, true, SecondEpi, 128, 128>), grid, dim3(256),
+                           0, s, entry, 1, tile_count, split);
+    else
+        hipLaunchKernelGGL((nt_direct_kernel<P_FP32, true, SecondEpi, 128, 128>), grid, dim3(256),
+                           0, s, entry, 1, tile_count, split);
+    return hipGetLastError();
+}
+
 hipError_t launch_nt_persistent(bool second, int precision, int tile_m, int tile_n,
                                 const NtEntry* entries, int n_entries, const int* tile_count,
                                 int* queue, int grid, hipStream_t s) {

@@ -222,39 +222,6 @@ __global__ __launch_bounds__(1024) void batch_prefix_kernel(const PlanHeader* __
     }
 }
 
-// Complex value -> planes (FP32: re, im; split: re_hi, re_lo, im_hi, im_lo).
-template <int P>
-__device__ __forceinline__ void put_c(void* base, size_t ps, size_t off, float re, float im) {
-    if constexpr (P == P_FP32) {
-        float* b = static_cast<float*>(base);
-        b[off] = re;
-        b[ps + off] = im;
-    } else {
-        uint16_t* b = static_cast<uint16_t*>(base);
-        uint16_t h, l;
-        split16<P>(re, h, l);
-        b[off] = h;
-        b[ps + off] = l;
-        split16<P>(im, h, l);
-        b[2 * ps + off] = h;
-        b[3 * ps + off] = l;
-    }
-}
-
-// Real value -> planes (FP32: one plane; split: hi, lo).
-template <int P>
-__device__ __forceinline__ void put_r(void* base, size_t ps, size_t off, float v) {
-    if constexpr (P == P_FP32) {
-        static_cast<float*>(base)[off] = v;
-    } else {
-        uint16_t* b = static_cast<uint16_t*>(base);
-        uint16_t h, l;
-        split16<P>(v, h, l);
-        b[off] = h;
-        b[ps + off] = l;
-    }
-}
-
 template <int P>
 __global__ __launch_bounds__(256) void fy_kernel(const float* __restrict__ lut_y,
                                                  const int* __restrict__ rowlist,

@@ -49,4 +49,39 @@ __device__ __forceinline__ void store_val(void* hi, void* lo, size_t i, float v)
     }
 }
 
+// Store one complex / real operand element into planar operand storage:
+// FP32 planes (re, im) or split planes (re_hi, re_lo, im_hi, im_lo) / (hi, lo),
+// plane stride ps elements.
+template <int P>
+__device__ __forceinline__ void put_c(void* base, size_t ps, size_t off, float re, float im) {
+    if constexpr (P == P_FP32) {
+        float* b = static_cast<float*>(base);
+        b[off] = re;
+        b[ps + off] = im;
+    } else {
+        uint16_t* b = static_cast<uint16_t*>(base);
+        uint16_t h, l;
+        split16<P>(re, h, l);
+        b[off] = h;
+        b[ps + off] = l;
+        split16<P>(im, h, l);
+        b[2 * ps + off] = h;
+        b[3 * ps + off] = l;
+    }
+}
+
+// Real value -> planes (FP32: one plane; split: hi, lo).
+template <int P>
+__device__ __forceinline__ void put_r(void* base, size_t ps, size_t off, float v) {
+    if constexpr (P == P_FP32) {
+        static_cast<float*>(base)[off] = v;
+    } else {
+        uint16_t* b = static_cast<uint16_t*>(base);
+        uint16_t h, l;
+        split16<P>(v, h, l);
+        b[off] = h;
+        b[ps + off] = l;
+    }
+}
+
 }  // namespace cgh

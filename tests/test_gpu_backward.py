@@ -83,7 +83,7 @@ def test_forward_backward_dot_product_identity(n, planes):
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
-@pytest.mark.parametrize("shape", [(32, 48), (136, 128)])
+@pytest.mark.parametrize("shape", [(32, 48), (136, 128), (200, 264)])
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_backpropagation_matches_oracle(shape, adjoint):
     import torch
@@ -95,6 +95,26 @@ def test_backpropagation_matches_oracle(shape, adjoint):
     ref = (gradient.fresnel_backpropagate_adjoint if adjoint else gradient.fresnel_backpropagate)(
         fd, 532e-9, 8e-6, 0.2)
     assert rel_l2(u.cpu().numpy(), ref) <= LIN_TOL
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", LIN_TOL), ("bf16_split", 1e-3)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_backpropagation_at_1024_sampled(precision, tol, adjoint):
+    # the reconstruction of the differentiable workload at its size, sampled pixels
+    import torch
+
+    from helpers import sample_pixels
+
+    f = _cot(6, 1024, 1024)
+    u = cgh().fresnel_backpropagate(to_dev(f), 532e-9, 8e-6, 0.2, adjoint=adjoint,
+                                    precision=precision)
+    torch.cuda.synchronize()
+    ys, xs = sample_pixels(1024, 1024, seed=6, n_random=96, crop=8)
+    fn = gradient.fresnel_backpropagate_adjoint if adjoint else gradient.fresnel_backpropagate
+    ref = fn(f.astype(np.complex128), 532e-9, 8e-6, 0.2, pixels=(ys, xs))
+    err = rel_l2(u.cpu().numpy()[ys, xs], ref)
+    print(f"backprop 1024 {precision} adjoint={adjoint}: rel-L2 {err:.2e}")
+    assert err <= tol
 
 
 def test_autograd_loss_gradient_matches_oracle_chain():
