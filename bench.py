@@ -49,6 +49,9 @@ WORKLOADS = {
                  "1024x1024 float32 amplitudes, one plane z=0.2 m, ~30% saliency, 3 Haar levels; "
                  "loss = sum (|Fresnel back-propagation of H| - T)^2 with a blob target; one "
                  "step = forward + back-propagation + loss + gradient through the adjoints"),
+    "exact256": (lambda: scenes.tiny(n=256),
+                 "256x256 object, one plane z=0.2 m, ~25% saliency, 3 Haar levels; Eq. 1 with the "
+                 "exact distance and 1/r amplitude as a direct sum (evaluation of the Fresnel form)"),
     "batch64": (scenes.batched,
                 "64 scenes, sides uniform in {256,512,768,1024,1536,2048}, 1-4 depth planes, "
                 "saliency 5-60% from 1-3 ellipses, 3 Haar levels; one batched plan "
@@ -145,6 +148,78 @@ def measured_traffic(workload, prec):
         return None
     entry = rec.get("entries", {}).get(f"{workload}/{prec}")
     return None if entry is None else entry["bytes"]
+
+
+# exact-distance kernel: VALU instructions per (point, pixel) term, counted in the
+# gfx950 ISA of its inner loop; VALU issue peak = 256 CUs x 64 lanes per clock x 2.4 GHz
+EXACT_VALU_PER_TERM = 79
+VALU_LANE_OPS_PER_S = 256 * 64 * 2.4e9
+
+
+def run_exact(scene, steps, warmup):
+    import torch
+
+    from paper_2211_09938_amd import cgh
+
+    dev = torch.device("cuda:0")
+    ny, nx = scene.shape
+    obj = torch.from_numpy(scene.obj).to(dev)
+    sal = torch.from_numpy(scene.saliency).to(dev)
+    ws = torch.empty(cgh.workspace_size(ny, nx, 1, scene.levels, "fp32"), dtype=torch.uint8,
+                     device=dev)
+    out = torch.empty((ny, nx), dtype=torch.complex64, device=dev)
+
+    def step():
+        cgh.exact_hologram(obj, scene.z, scene.lam, scene.pitch, scene.levels, sal, out=out,
+                           workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = a.elapsed_time(b) / steps
+    # every point of the blob object's masked reconstruction is nonzero: dense count
+    terms = float(ny * nx) ** 2
+    achieved = terms / (ms * 1e-3) / 1e9
+    peak = VALU_LANE_OPS_PER_S / EXACT_VALU_PER_TERM / 1e9
+    return {
+        "value": steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "roofline": {"bound": "alu", "kernel": "exact_kernel", "achieved": achieved,
+                     "peak": peak, "unit": "Gterm/s", "frac": achieved / peak, "traffic": None,
+                     "valu_per_term": EXACT_VALU_PER_TERM, "avg_launch_ms": ms},
+        "_out": out.cpu().numpy(),
+    }
+
+
+def exact_cpu_baseline(scene, n_pixels=256):
+    from oracle import exact, fresnel
+
+    ny, nx = scene.shape
+    rng = np.random.default_rng(12345)
+    ys = rng.integers(0, ny, n_pixels)
+    xs = rng.integers(0, nx, n_pixels)
+    t0 = time.perf_counter()
+    vals = exact.hologram_exact(scene.obj.astype(np.float64), scene.z, scene.lam, scene.pitch,
+                                scene.levels, scene.saliency.astype(np.float64), None,
+                                pixels=(ys, xs))
+    t = time.perf_counter() - t0
+    return {
+        "value": 1.0 / (t * ny * nx / n_pixels),
+        "unit": "holograms/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"FP64 exact-distance sum at {n_pixels} seeded pixels ({t:.1f} s), "
+                  f"extrapolated linearly to all {ny * nx} pixels",
+        "_pixels": (ys, xs, vals),
+    }
 
 
 def roofline(stats, prec, avg_ms, kernel, traffic=None):
@@ -321,6 +396,29 @@ def main():
         sys.exit(2)
     make, desc = WORKLOADS[args.workload]
     work = make()
+    if args.workload.startswith("exact"):
+        base = None if args.no_cpu_baseline else exact_cpu_baseline(work)
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("bench.py needs a GPU")
+        res = run_exact(work, args.steps, args.warmup)
+        out = res.pop("_out")
+        line = {"metric": "exact-distance Eq. 1 holograms/s (evaluation kernel)",
+                "value": res["value"], "unit": "holograms/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f32 (f64 phase reduction and tile sums)", "data": "synthetic",
+                "config": {"workload": args.workload, "description": desc,
+                           "ny": work.shape[0], "nx": work.shape[1]},
+                "roofline": res["roofline"]}
+        if base is not None:
+            ys, xs, vals = base.pop("_pixels")
+            got = out[ys, xs].astype(np.complex128)
+            line["rel_l2_vs_oracle"] = float(np.linalg.norm(got - vals) / np.linalg.norm(vals))
+            line["cpu_baseline"] = base
+        print(json.dumps(line), flush=True)
+        return
     batch = isinstance(work, list)
     scene = work[0] if batch else work
 

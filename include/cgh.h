@@ -149,6 +149,26 @@ int cgh_progressive_stages(const float* object, const uint8_t* layer_index, int 
                            void* stream);
 
 /*
+ * Eq. 1 with the exact distance (no Fresnel approximation), for measuring
+ * the error of the Fresnel form of the hot path:
+ *   hologram[y][x] = sum_d sum_{q,p} Ahat_d[q][p] / r * exp(i 2 pi r / lambda),
+ *   r = sqrt(pitch^2 ((x-p)^2 + (y-q)^2) + z_d^2),
+ * with Ahat_d the same masked reconstruction of layer d as in
+ * cgh_progressive_hologram (whose result with CGH_FLAG_EQ1_PREFACTOR is the
+ * Fresnel approximation of this sum).  Direct sum: ny*nx*ny*nx*n_layers
+ * terms (at most; zero points are skipped), FP64 reduction of the large phase
+ * term, FP32 elsewhere, FP64 summation of 64-point partial sums.
+ * flags: CGH_FLAG_ACCUMULATE only (CGH_FLAG_EQ1_PREFACTOR is rejected: the
+ * exact sum already carries the phase and 1/r of Eq. 1).  Workspace as
+ * cgh_workspace_size(ny, nx, n_layers, levels, any precision).  Other
+ * arguments, errors and ownership as for cgh_progressive_hologram.
+ */
+int cgh_exact_hologram(const float* object, const uint8_t* layer_index, int n_layers,
+                       const double* z, const float* saliency, const float* thresholds,
+                       double lambda, double pitch, int ny, int nx, int levels, unsigned flags,
+                       void* workspace, size_t workspace_bytes, float* hologram, void* stream);
+
+/*
  * Adjoint of cgh_progressive_hologram with respect to the object amplitudes.
  * grad_hologram: 2*ny*nx floats, G = dL/dRe(H) + i dL/dIm(H) (the cotangent
  * torch hands to a complex output).  Writes grad_object (ny*nx floats):

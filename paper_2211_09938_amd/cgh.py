@@ -54,6 +54,8 @@ SIGNATURES = {
     "cgh_progressive_stages": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double,
                                         _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp,
                                         _vp]),
+    "cgh_exact_hologram": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double, _c_int,
+                                    _c_int, _c_int, _c_uint, _vp, _sz, _vp, _vp]),
     "cgh_hologram_backward": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double,
                                        _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp, _vp]),
     "cgh_fresnel_backpropagate": (_c_int, [_vp, _c_int, _c_int, _c_double, _c_double, _c_double,
@@ -291,6 +293,29 @@ def progressive_stages(obj, z, lam, pitch, levels=3, saliency=None, layer_index=
         p_obj, p_lay, len(zs), _host_doubles(zs), p_sal, _host_floats(thresholds), float(lam),
         float(pitch), ny, nx, levels, prec, flags, ctypes.c_void_p(ws.data_ptr()),
         ws.numel(), p_out, _stream()), "cgh_progressive_stages")
+    return out
+
+
+def exact_hologram(obj, z, lam, pitch, levels=3, saliency=None, layer_index=None,
+                   thresholds=None, out=None, accumulate=False, workspace=None):
+    """Complex64 exact-distance Eq. 1 hologram of the masked reconstruction; see cgh_exact_hologram."""
+    torch = _torch()
+    ny, nx = obj.shape
+    zs = list(np.atleast_1d(np.asarray(z, dtype=np.float64)))
+    p_obj = _dev_tensor(obj, torch.float32, "object")
+    p_sal = None if saliency is None else _dev_tensor(saliency, torch.float32, "saliency", (ny, nx))
+    p_lay = None if layer_index is None else _dev_tensor(layer_index, torch.uint8, "layer_index", (ny, nx))
+    nbytes = workspace_size(ny, nx, len(zs), levels, 0)
+    ws = _workspace(nbytes, obj.device, workspace)
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs an existing `out`")
+        out = torch.empty((ny, nx), dtype=torch.complex64, device=obj.device)
+    p_out = _dev_tensor(out, torch.complex64, "out", (ny, nx))
+    _check(lib().cgh_exact_hologram(
+        p_obj, p_lay, len(zs), _host_doubles(zs), p_sal, _host_floats(thresholds), float(lam),
+        float(pitch), ny, nx, levels, FLAG_ACCUMULATE if accumulate else 0,
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), p_out, _stream()), "cgh_exact_hologram")
     return out
 
 

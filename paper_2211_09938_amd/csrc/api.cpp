@@ -204,6 +204,44 @@ int cgh_progressive_stages(const float* object, const uint8_t* layer_index, int 
     }
 }
 
+int cgh_exact_hologram(const float* object, const uint8_t* layer_index, int n_layers,
+                       const double* z, const float* saliency, const float* thresholds,
+                       double lambda, double pitch, int ny, int nx, int levels, unsigned flags,
+                       void* workspace, size_t workspace_bytes, float* hologram, void* stream) {
+    try {
+        float thr[CGH_MAX_LEVELS];
+        int st = check_common(n_layers, layer_index, z, thresholds, lambda, pitch, ny, nx, levels,
+                              CGH_FP32, flags, thr);
+        if (st) return st;
+        if (flags & CGH_FLAG_EQ1_PREFACTOR) return CGH_ERROR_INVALID_VALUE;  // inherent here
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        if (!object || !hologram) return CGH_ERROR_INVALID_VALUE;
+        const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
+        if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        hipStream_t s = (hipStream_t)stream;
+        char* ws = static_cast<char*>(workspace);
+        uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
+        float* coef = reinterpret_cast<float*>(ws + lo.coef);
+        float* amp = reinterpret_cast<float*>(ws + lo.big);
+        const size_t plane = (size_t)ny * nx;
+        hipError_t e = cgh::launch_fill_u8(fl, lo.flags_fill, s);
+        if (e == hipSuccess)
+            e = cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels, thr,
+                                     cgh::kAllParts, coef, fl, lo.flags_layer,
+                                     reinterpret_cast<unsigned long long*>(ws + lo.ops), s);
+        const int acc = (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0;
+        for (int d = 0; d < n_layers && e == hipSuccess; ++d) {
+            e = cgh::launch_idwt(coef + d * plane, ny, nx, levels, amp, s);
+            if (e == hipSuccess)
+                e = cgh::launch_exact(amp, ny, nx, lambda, pitch, z[d], (d > 0 || acc) ? 1 : 0,
+                                      reinterpret_cast<float2*>(hologram), s);
+        }
+        return hip_status(e);
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
 int cgh_hologram_backward(const float* grad_hologram, const uint8_t* layer_index, int n_layers,
                           const double* z, const float* saliency, const float* thresholds,
                           double lambda, double pitch, int ny, int nx, int levels, int precision,

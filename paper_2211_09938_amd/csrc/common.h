@@ -77,6 +77,9 @@ hipError_t launch_dwt_mask(const float* obj, const uint8_t* layer, const float* 
                            int layers, int levels, const float* thr, unsigned parts, float* coef,
                            uint8_t* flags, size_t flags_layer, unsigned long long* ops,
                            hipStream_t s);
+// Exact-distance Eq. 1 sum of one layer's points `amp` into `out` (exact.hip).
+hipError_t launch_exact(const float* amp, int ny, int nx, double lambda, double pitch, double z,
+                        int accumulate, float2* out, hipStream_t s);
 hipError_t launch_idwt(const float* coef, int ny, int nx, int levels, float* out, hipStream_t s);
 hipError_t launch_grad_synthesis(const float* gcoef, const uint8_t* layer, const float* sal, int ny,
                                  int nx, int layers, int levels, const float* thr, float* grad,

@@ -119,6 +119,22 @@ def test_stages_rejects_invalid_arguments(over, code):
                                             0, 0, None, 0, None, None) == OK
 
 
+def test_exact_validation():
+    lib = cgh.lib()
+    z = (ctypes.c_double * 1)(0.2)
+    base = [BOGUS, None, 1, z, None, None, 532e-9, 8e-6, 64, 64, 3, 0, BOGUS, 1 << 40, BOGUS, None]
+    for idx, val, code in [(11, 2, INVALID),      # the Eq. 1 prefactor is inherent
+                           (11, 8, INVALID),      # unknown flag
+                           (0, None, INVALID), (14, None, INVALID), (8, 60, SHAPE),
+                           (13, 16, WS), (6, 0.0, INVALID)]:
+        a = list(base)
+        a[idx] = val
+        assert lib.cgh_exact_hologram(*a) == code, (idx, val)
+    a = list(base)
+    a[8], a[0], a[14], a[12], a[13] = 0, None, None, None, 0
+    assert lib.cgh_exact_hologram(*a) == OK
+
+
 def test_forward_empty_problem_is_a_no_op():
     assert call_forward(ny=0, obj=None, out=None, ws=None, ws_bytes=0) == OK
     assert call_forward(nx=0, obj=None, out=None, ws=None, ws_bytes=0) == OK
