@@ -36,8 +36,6 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
                    int levels, int precision, const cgh::Layout& lo, char* ws, unsigned parts,
                    bool with_luts, int acc, float2* out, hipStream_t s) {
     uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
-    const cgh::GemmShape sh{ny, nx, n_layers, levels, lo.split_k, precision, lo.t_layer,
-                            lo.flags_layer};
     const cgh::NtBuffers nb = nt_buffers(ws, lo);
     const float* coef = reinterpret_cast<const float*>(ws + lo.coef);
     const float* lut_x = reinterpret_cast<const float*>(ws + lo.lut_x);
@@ -79,7 +77,7 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
                   [&] { return cgh::launch_nt_second(ny, nx, precision, lo.split_k, nb, s); });
     if (e == hipSuccess && lo.split_k > 1)
         e = timed(s, CGH_STAGE_REDUCE,
-                  [&] { return cgh::launch_reduce_partial(sh, partial, out, acc, s); });
+                  [&] { return cgh::launch_reduce_partial(ny, nx, lo.split_k, partial, out, acc, s); });
     return e;
 }
 
@@ -267,14 +265,12 @@ int cgh_hologram_backward(const float* grad_hologram, const uint8_t* layer_index
         if (e == hipSuccess)
             e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im, cgh::P_FP32,
                                  ws + lo.lut_y, nullptr, s);
-        if (e == hipSuccess) {
-            cgh::GemmShape sh{ny, nx, n_layers, levels, 1, precision, lo.t_layer, lo.flags_layer};
-            e = cgh::launch_backward(sh, reinterpret_cast<const float2*>(grad_hologram),
-                                         reinterpret_cast<const float*>(ws + lo.lut_x),
-                                         reinterpret_cast<const float*>(ws + lo.lut_y),
-                                         reinterpret_cast<float2*>(ws + lo.t),
-                                         reinterpret_cast<float*>(ws + lo.coef), s);
-        }
+        if (e == hipSuccess)
+            e = cgh::launch_backward_nt(reinterpret_cast<const float2*>(grad_hologram),
+                                        reinterpret_cast<const float*>(ws + lo.lut_x),
+                                        reinterpret_cast<const float*>(ws + lo.lut_y), ny, nx,
+                                        n_layers, levels, precision,
+                                        reinterpret_cast<float*>(ws + lo.coef), ws + lo.big, s);
         if (e == hipSuccess)
             e = cgh::launch_grad_synthesis(reinterpret_cast<const float*>(ws + lo.coef), layer_index,
                                            saliency, ny, nx, n_layers, levels, thr, grad_object, s);

@@ -77,6 +77,9 @@ hipError_t launch_dwt_mask(const float* obj, const uint8_t* layer, const float* 
                            int layers, int levels, const float* thr, unsigned parts, float* coef,
                            uint8_t* flags, size_t flags_layer, unsigned long long* ops,
                            hipStream_t s);
+// out (+)= sum of `split` partial holograms of ny x nx (split <= 1: nothing).
+hipError_t launch_reduce_partial(int ny, int nx, int split, const float2* partial, float2* out,
+                                 int accumulate, hipStream_t s);
 // Exact-distance Eq. 1 sum of one layer's points `amp` into `out` (exact.hip).
 hipError_t launch_exact(const float* amp, int ny, int nx, double lambda, double pitch, double z,
                         int accumulate, float2* out, hipStream_t s);

@@ -11,7 +11,6 @@
 //     step 2:  U[q][p] = sum_y s K'_y[q][y] * T[p][y]     A = s K'_y panel, B = T panel
 // Both run split-K into FP32 partials; step 1's partials are summed straight
 // into the operand planes of T.
-#include "gemm.h"
 #include "nt.h"
 #include "split.h"
 
@@ -126,7 +125,7 @@ hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const floa
     e1.tile_m = e1.tile_n = kNtTile;
     hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e1, tiles, b.entries,
                        b.counts);
-    if ((e = launch_nt_complex(P, b.entries, b.counts, tiles, split, s)) != hipSuccess) return e;
+    if ((e = launch_nt_table(kEpiComplex, P, b.entries, 1, b.counts, tiles, split, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_panel_kernel<P>, dim3(grid_1d(t_ps)), dim3(256), 0, s,
                        split > 1 ? b.partial : b.c1, split, nx, ny, ldy, b.t, t_ps);
 
@@ -148,13 +147,9 @@ hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const floa
     hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e2, tiles, b.entries + 1,
                        b.counts + 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_nt_complex(P, b.entries + 1, b.counts + 1, tiles, split, s)) != hipSuccess)
+    if ((e = launch_nt_table(kEpiComplex, P, b.entries + 1, 1, b.counts + 1, tiles, split, s)) != hipSuccess)
         return e;
-    if (split > 1) {
-        const GemmShape sh{ny, nx, 1, 1, split, P, 0, 0};
-        return launch_reduce_partial(sh, b.partial, out, 0, s);
-    }
-    return hipSuccess;
+    return launch_reduce_partial(ny, nx, split, b.partial, out, 0, s);
 }
 
 }  // namespace

@@ -9,7 +9,6 @@
 
 #include "../../include/cgh.h"
 #include "common.h"
-#include "gemm.h"
 #include "nt.h"
 
 namespace cgh {
@@ -92,6 +91,8 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
     lo.split_k = with_partial ? choose_split(ny, nx, levels, layers) : 1;
     const size_t dense = cgh::dense_bytes(ny, nx, lo.split_k);
     if (dense > panels) panels = dense;
+    const size_t bw = cgh::backward_bytes(ny, nx, layers, levels);
+    if (bw > panels) panels = bw;
     lo.big = take(t_bytes > panels ? t_bytes : panels);
     lo.t = lo.big;
     lo.fx = lo.big;

@@ -159,10 +159,16 @@ hipError_t launch_nt_persistent(bool second, int precision, int tile_m, int tile
 hipError_t launch_batch_prefix(const PlanHeader* hdrs, int n_scenes, const int* first_off,
                                NtEntry* first, NtEntry* second, int* counts, int* queues,
                                hipStream_t s);
-// Direct launch of one complex x complex problem (tile 128 x 128, split-K when
-// split > 1: the problem's partial buffer holds `split` FP32 planes).
-hipError_t launch_nt_complex(int precision, const NtEntry* entry, const int* tile_count, int tiles,
-                             int split, hipStream_t s);
+// Direct launch over a table of complex x complex problems (A and B complex,
+// tile 128 x 128; `tiles` bounds the device tile count, split-K when split > 1
+// into each problem's partial buffer).  Epilogues:
+//   kEpiComplex  complex64 rows of `out` (row stride out_ld), partials [s][M][out_ld]
+//   kEpiPanel    operand planes of `out` (row stride out_ld, plane stride out_ps),
+//                columns up to pad16(N); partials [s][M][N]
+//   kEpiReal     real part only into floats of `out`; partials [s][M][N] floats
+enum { kEpiComplex = 0, kEpiPanel = 1, kEpiReal = 2 };
+hipError_t launch_nt_table(int epi, int precision, const NtEntry* entries, int n_entries,
+                           const int* tile_count, int tiles, int split, hipStream_t s);
 
 // Dense products with Toeplitz fringe panels (Fresnel back-propagation).
 struct DenseBuffers {
@@ -183,6 +189,14 @@ DenseBuffers dense_buffers(char* base, int ny, int nx, int split, float2* partia
 hipError_t launch_dense_backprop(const DenseBuffers& b, const float* lut0_x, const float* lut0_y,
                                  const float2* in, float2* out, int ny, int nx, int adjoint,
                                  float scale, int precision, int split, hipStream_t s);
+
+// Coefficient gradient of every layer and level (adjoint of the forward
+// contractions) into gcoef (per layer an ny x nx plane at Mallat positions);
+// `region` holds backward_bytes() of panels, partials and problem tables.
+size_t backward_bytes(int ny, int nx, int layers, int levels);
+hipError_t launch_backward_nt(const float2* grad_h, const float* lut_x, const float* lut_y, int ny,
+                              int nx, int layers, int levels, int precision, float* gcoef,
+                              void* region, hipStream_t s);
 
 // Tiles of a problem with M rows and N columns under a tile shape.
 __host__ __device__ inline int nt_tiles(int M, int N, int tm, int tn) {

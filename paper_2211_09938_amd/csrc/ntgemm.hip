@@ -17,7 +17,6 @@
 //         operands of 4 consecutive MFMAs (lane half g supplies k = 4g + t).
 //  split: v_mfma_f32_32x32x16_{bf16,f16}; operands stored as hi and lo planes,
 //         each real product as hi*hi + hi*lo + lo*hi, FP32 accumulation.
-#include "gemm.h"
 #include "nt.h"
 #include "split.h"
 
@@ -88,6 +87,7 @@ __device__ __forceinline__ int find_entry(const NtEntry* __restrict__ en, int n,
 // m is the first of 4 consecutive rows k', n the column x.
 template <int P>
 struct FirstEpi {
+    static constexpr bool kImag = true;
     __device__ static void store4(const NtEntry& e, int, int, int m, int n, const float* re,
                                   const float* im) {
         if (m >= pad_kt(e.M) || n >= e.N) return;
@@ -121,6 +121,7 @@ struct FirstEpi {
 // Second contraction output: complex64 hologram rows m..m+3, column n (or a
 // split-K partial).
 struct SecondEpi {
+    static constexpr bool kImag = true;
     __device__ static void store4(const NtEntry& e, int s, int split, int m, int n,
                                   const float* re, const float* im) {
         if (n >= e.N) return;
@@ -141,6 +142,48 @@ struct SecondEpi {
             } else {
                 e.partial[(size_t)s * e.M * e.N + i] = v;
             }
+        }
+    }
+};
+
+// Complex product stored row-major into operand planes (the B panel of a
+// following contraction): rows m..m+3, column n < pad16(N) (columns past N
+// hold the zeros the K padding needs); split-K partials [s][M][N] otherwise.
+template <int P>
+struct PanelEpi {
+    static constexpr bool kImag = true;
+    __device__ static void store4(const NtEntry& e, int s, int split, int m, int n,
+                                  const float* re, const float* im) {
+        if (split > 1) {
+            if (n >= e.N) return;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (m + q < e.M)
+                    e.partial[((size_t)s * e.M + m + q) * e.N + n] = make_float2(re[q], im[q]);
+            return;
+        }
+        if (n >= pad_kt(e.N)) return;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (m + q < e.M)
+                put_c<P>(e.out, (size_t)e.out_ps, (size_t)(m + q) * e.out_ld + n, re[q], im[q]);
+    }
+};
+
+// Real part only (the imaginary products are skipped): out[m][n] floats with
+// row stride out_ld, or split-K partials [s][M][N] floats.
+struct RealEpi {
+    static constexpr bool kImag = false;
+    __device__ static void store4(const NtEntry& e, int s, int split, int m, int n,
+                                  const float* re, const float*) {
+        if (n >= e.N) return;
+        float* part = reinterpret_cast<float*>(e.partial);
+        float* out = static_cast<float*>(e.out);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (m + q >= e.M) continue;
+            if (split > 1) part[((size_t)s * e.M + m + q) * e.N + n] = re[q];
+            else out[(size_t)(m + q) * e.out_ld + n] = re[q];
         }
     }
 };
@@ -253,7 +296,8 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
 #pragma unroll
                         for (int j = 0; j < BJ; ++j) {
                             cr[i][j] = mfma32(fa[i][0][tt], fb[j][0][tt], cr[i][j]);
-                            ci[i][j] = mfma32(fa[i][0][tt], fb[j][1][tt], ci[i][j]);
+                            if constexpr (Epi::kImag)
+                                ci[i][j] = mfma32(fa[i][0][tt], fb[j][1][tt], ci[i][j]);
                         }
                     if constexpr (A_CPLX) {
 #pragma unroll
@@ -261,7 +305,8 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
 #pragma unroll
                             for (int j = 0; j < BJ; ++j) {
                                 cr[i][j] = mfma32(-fa[i][1][tt], fb[j][1][tt], cr[i][j]);
-                                ci[i][j] = mfma32(fa[i][1][tt], fb[j][0][tt], ci[i][j]);
+                                if constexpr (Epi::kImag)
+                                    ci[i][j] = mfma32(fa[i][1][tt], fb[j][0][tt], ci[i][j]);
                             }
                     }
                 }
@@ -287,7 +332,8 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
 #pragma unroll
                 for (int j = 0; j < BJ; ++j) {
                     cr[i][j] = prod3<P>(cr[i][j], a[i][0], a[i][1], b[j][0], b[j][1]);
-                    ci[i][j] = prod3<P>(ci[i][j], a[i][0], a[i][1], b[j][2], b[j][3]);
+                    if constexpr (Epi::kImag)
+                        ci[i][j] = prod3<P>(ci[i][j], a[i][0], a[i][1], b[j][2], b[j][3]);
                 }
             if constexpr (A_CPLX) {
 #pragma unroll
@@ -297,7 +343,8 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
 #pragma unroll
                     for (int j = 0; j < BJ; ++j) {
                         cr[i][j] = prod3<P>(cr[i][j], nah, nal, b[j][2], b[j][3]);
-                        ci[i][j] = prod3<P>(ci[i][j], a[i][2], a[i][3], b[j][0], b[j][1]);
+                        if constexpr (Epi::kImag)
+                            ci[i][j] = prod3<P>(ci[i][j], a[i][2], a[i][3], b[j][0], b[j][1]);
                     }
                 }
             }
@@ -438,18 +485,28 @@ hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBu
     return second_direct<P_FP32>(ny, nx, split, b, s);
 }
 
-hipError_t launch_nt_complex(int precision, const NtEntry* entry, const int* tile_count, int tiles,
-                             int split, hipStream_t s) {
-    const dim3 grid(tiles * split);
-    if (precision == P_BF16)
-        hipLaunchKernelGGL((nt_direct_kernel<P_BF16, true, SecondEpi, 128, 128>), grid, dim3(256),
-                           0, s, entry, 1, tile_count, split);
-    else if (precision == P_FP16)
-        hipLaunchKernelGGL((nt_direct_kernel<P_FP16, true, SecondEpi, 128, 128>), grid, dim3(256),
-                           0, s, entry, 1, tile_count, split);
-    else
-        hipLaunchKernelGGL((nt_direct_kernel<P_FP32, true, SecondEpi, 128, 128>), grid, dim3(256),
-                           0, s, entry, 1, tile_count, split);
+namespace {
+template <int P, class Epi>
+void table_launch(const NtEntry* entries, int n_entries, const int* tile_count, int tiles,
+                  int split, hipStream_t s) {
+    hipLaunchKernelGGL((nt_direct_kernel<P, true, Epi, 128, 128>), dim3(tiles * split),
+                       dim3(256), 0, s, entries, n_entries, tile_count, split);
+}
+template <int P>
+void table_epi(int epi, const NtEntry* entries, int n_entries, const int* tile_count, int tiles,
+               int split, hipStream_t s) {
+    if (epi == kEpiPanel) table_launch<P, PanelEpi<P>>(entries, n_entries, tile_count, tiles, split, s);
+    else if (epi == kEpiReal) table_launch<P, RealEpi>(entries, n_entries, tile_count, tiles, split, s);
+    else table_launch<P, SecondEpi>(entries, n_entries, tile_count, tiles, split, s);
+}
+}  // namespace
+
+hipError_t launch_nt_table(int epi, int precision, const NtEntry* entries, int n_entries,
+                           const int* tile_count, int tiles, int split, hipStream_t s) {
+    if (tiles <= 0 || n_entries <= 0) return hipSuccess;
+    if (precision == P_BF16) table_epi<P_BF16>(epi, entries, n_entries, tile_count, tiles, split, s);
+    else if (precision == P_FP16) table_epi<P_FP16>(epi, entries, n_entries, tile_count, tiles, split, s);
+    else table_epi<P_FP32>(epi, entries, n_entries, tile_count, tiles, split, s);
     return hipGetLastError();
 }
 
