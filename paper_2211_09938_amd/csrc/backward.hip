@@ -29,7 +29,7 @@ inline int grid_1d(size_t n) {
 
 // Conjugated block-fringe panel of every (layer, level) of one axis:
 //   out_{d,l}[j][pix] = conj(F_{d,l}[pix][j]) = conj(g_{band(j)}[pix - (j mod n_l) 2^l])
-// rows j of the level square (s_l = n >> (l-1)), columns pix < ld (zero past n).
+// rows j of the level square (s_l = n >> (l-1)), K = pix < ld (zero past n), K-blocked.
 template <int P>
 __global__ __launch_bounds__(256) void fringe_h_kernel(const float* __restrict__ lut, int n,
                                                        int levels, int ld, void* __restrict__ out,
@@ -46,7 +46,8 @@ __global__ __launch_bounds__(256) void fringe_h_kernel(const float* __restrict__
     const size_t total = (size_t)s * ld;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
-        const int j = (int)(e / ld), pix = (int)(e - (size_t)j * ld);
+        int j, pix;
+        kblk_pos(e, s, j, pix);
         float re = 0.f, im = 0.f;
         if (pix < n) {
             const int band = j >= nl, jj = j - band * nl;
@@ -67,7 +68,8 @@ __global__ __launch_bounds__(256) void cotangent_panel_kernel(const float2* __re
     const size_t total = (size_t)rows * ld;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
-        const int r = (int)(e / ld), c = (int)(e - (size_t)r * ld);
+        int r, c;
+        kblk_pos(e, rows, r, c);
         const float2 v = c < cols ? in[(size_t)r * cols + c] : make_float2(0.f, 0.f);
         put_c<P>(out, ps, e, v.x, v.y);
     }
@@ -129,9 +131,9 @@ __global__ void bw_entries_kernel(BwArgs a) {
         e.M = sx;
         e.N = a.ny;
         e.K = a.ldx;
-        e.lda = a.ldx;
-        e.ldb = a.ldx;
-        e.out_ld = a.ldy;
+        e.lda = sx * 16;     // FxH_{d,l}: sx rows
+        e.ldb = a.ny * 16;   // G: ny rows
+        e.out_ld = sx * 16;  // P_{d,l}: sx rows
         e.tiles_n = (a.ny + kNtTile - 1) / kNtTile;
         e.tile_begin = d * a.tiles_a_layer + ta;
         e.tile_m = e.tile_n = kNtTile;
@@ -153,8 +155,8 @@ __global__ void bw_entries_kernel(BwArgs a) {
         for (int b = 0; b < nblk; ++b) {
             const int r0 = blk[b][0], M = blk[b][1], c0 = blk[b][2], N = blk[b][3];
             NtEntry f{};
-            f.a = a.fyh + (fy_off + (size_t)r0 * a.ldy) * a.es;
-            f.b = a.pt + (pt_off + (size_t)c0 * a.ldy) * a.es;
+            f.a = a.fyh + (fy_off + (size_t)r0 * 16) * a.es;  // row r0 of FyH_{d,l}
+            f.b = a.pt + (pt_off + (size_t)c0 * 16) * a.es;   // row c0 of P_{d,l}
             f.out = a.gcoef + (size_t)d * a.ny * a.nx + (size_t)r0 * a.nx + c0;
             f.partial = reinterpret_cast<float2*>(
                 reinterpret_cast<float*>(a.partial) +
@@ -164,8 +166,8 @@ __global__ void bw_entries_kernel(BwArgs a) {
             f.M = M;
             f.N = N;
             f.K = a.ldy;
-            f.lda = a.ldy;
-            f.ldb = a.ldy;
+            f.lda = sy * 16;
+            f.ldb = sx * 16;
             f.out_ld = a.nx;
             f.tiles_n = (N + kNtTile - 1) / kNtTile;
             f.tile_begin = d * a.tiles_b_layer + tb;
@@ -189,7 +191,8 @@ __global__ __launch_bounds__(256) void reduce_panel_entries_kernel(const NtEntry
     const size_t total = (size_t)e.M * ldp, mn = (size_t)e.M * e.N;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (size_t)gridDim.x * blockDim.x) {
-        const int r = (int)(i / ldp), c = (int)(i - (size_t)r * ldp);
+        int r, c;
+        kblk_pos(i, e.M, r, c);
         float re = 0.f, im = 0.f;
         if (c < e.N) {
             for (int s = 0; s < split; ++s) {
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(256) void reduce_panel_entries_kernel(const NtEntry
                 im += v.y;
             }
         }
-        put_c<P>(e.out, (size_t)e.out_ps, (size_t)r * e.out_ld + c, re, im);
+        put_c<P>(e.out, (size_t)e.out_ps, i, re, im);  // e.out_ld == M * 16
     }
 }
 

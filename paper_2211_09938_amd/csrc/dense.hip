@@ -23,7 +23,7 @@ inline int grid_1d(size_t n) {
     return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
 }
 
-// out[r][c] = scale * k'(r - c) for c < cols, zero for cols <= c < ld.
+// out[r][c] = scale * k'(r - c) for c < cols, zero for cols <= c < ld (K-blocked panel).
 // table: re part then im part, each lut_len(n_tab) floats, entry m + n_tab.
 template <int P>
 __global__ __launch_bounds__(256) void toeplitz_panel_kernel(const float* __restrict__ table,
@@ -34,7 +34,8 @@ __global__ __launch_bounds__(256) void toeplitz_panel_kernel(const float* __rest
     const int len = lut_len(n_tab);
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
-        const int r = (int)(e / ld), c = (int)(e - (size_t)r * ld);
+        int r, c;
+        kblk_pos(e, rows, r, c);
         float re = 0.f, im = 0.f;
         if (c < cols) {
             const int idx = r - c + n_tab;
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(256) void toeplitz_panel_kernel(const float* __rest
     }
 }
 
-// Interleaved complex64 [rows][cols] -> operand planes [rows][ld], zero pad.
+// Interleaved complex64 [rows][cols] -> K-blocked operand planes [rows][ld], zero pad.
 template <int P>
 __global__ __launch_bounds__(256) void complex_panel_kernel(const float2* __restrict__ in,
                                                             int rows, int cols, int ld,
@@ -53,13 +54,14 @@ __global__ __launch_bounds__(256) void complex_panel_kernel(const float2* __rest
     const size_t total = (size_t)rows * ld;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
-        const int r = (int)(e / ld), c = (int)(e - (size_t)r * ld);
+        int r, c;
+        kblk_pos(e, rows, r, c);
         const float2 v = c < cols ? in[(size_t)r * cols + c] : make_float2(0.f, 0.f);
         put_c<P>(out, ps, e, v.x, v.y);
     }
 }
 
-// Sum of `split` FP32 partials [split][rows][cols] -> operand planes [rows][ld].
+// Sum of `split` FP32 partials [split][rows][cols] -> K-blocked operand planes [rows][ld].
 template <int P>
 __global__ __launch_bounds__(256) void reduce_panel_kernel(const float2* __restrict__ partial,
                                                            int split, int rows, int cols, int ld,
@@ -67,7 +69,8 @@ __global__ __launch_bounds__(256) void reduce_panel_kernel(const float2* __restr
     const size_t total = (size_t)rows * ld, plane = (size_t)rows * cols;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
-        const int r = (int)(e / ld), c = (int)(e - (size_t)r * ld);
+        int r, c;
+        kblk_pos(e, rows, r, c);
         float re = 0.f, im = 0.f;
         if (c < cols) {
             const size_t i = (size_t)r * cols + c;
@@ -118,8 +121,8 @@ hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const floa
     e1.M = nx;
     e1.N = ny;
     e1.K = ldx;
-    e1.lda = ldx;
-    e1.ldb = ldx;
+    e1.lda = nx * 16;  // K'_x panel: nx rows
+    e1.ldb = ny * 16;  // H panel: ny rows
     e1.out_ld = ny;
     e1.tiles_n = (ny + kNtTile - 1) / kNtTile;
     e1.tile_m = e1.tile_n = kNtTile;
@@ -139,8 +142,8 @@ hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const floa
     e2.M = ny;
     e2.N = nx;
     e2.K = ldy;
-    e2.lda = ldy;
-    e2.ldb = ldy;
+    e2.lda = ny * 16;  // s K'_y panel: ny rows
+    e2.ldb = nx * 16;  // T panel: nx rows
     e2.out_ld = nx;
     e2.tiles_n = (nx + kNtTile - 1) / kNtTile;
     e2.tile_m = e2.tile_n = kNtTile;

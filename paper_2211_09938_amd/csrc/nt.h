@@ -7,9 +7,11 @@
 // r' / c' index the active rows / columns of a level's coefficient square; k'
 // runs over the active rows of every (layer, level) in order, each segment
 // padded with zero rows to a multiple of kKT.  Every operand panel is stored
-// K-contiguous ("row-major M x K" and "row-major N x K"), in the operand
-// precision: FP32 planes (re[, im]) or 16-bit split planes
-// (re_hi, re_lo[, im_hi, im_lo]).
+// K-blocked: element (row r, k) of a panel of R rows sits at
+//     (k / 16) * (R * 16) + r * 16 + k % 16
+// so the 16-wide K slice of a tile of rows is one contiguous run (whole cache
+// lines per load), in the operand precision: FP32 planes (re[, im]) or 16-bit
+// split planes (re_hi, re_lo[, im_hi, im_lo]).
 #pragma once
 
 #include "common.h"
@@ -21,6 +23,18 @@ constexpr int kNtTile = 128;  // output tile rows and columns
 
 __host__ __device__ inline int pad_kt(int v) { return (v + kKT - 1) / kKT * kKT; }
 
+// Element (row r, k) of a K-blocked panel whose K-block stride is blk (rows x 16).
+__host__ __device__ inline size_t kblk_off(int r, int k, size_t blk) {
+    return (size_t)(k >> 4) * blk + (size_t)r * 16 + (k & 15);
+}
+// Inverse for writers that walk a panel of `rows` rows in storage order.
+__host__ __device__ inline void kblk_pos(size_t e, int rows, int& r, int& k) {
+    const size_t blk = (size_t)rows * 16;
+    const size_t b = e / blk, rem = e - b * blk;
+    r = (int)(rem >> 4);
+    k = (int)(b * 16 + (rem & 15));
+}
+
 // One GEMM problem of the batched NT kernel (self-contained, so problems of
 // different scenes can share one launch).
 struct NtEntry {
@@ -29,10 +43,11 @@ struct NtEntry {
     void* out;              // first: T_c plane 0 at this problem's k' segment; second: hologram
     float2* partial;        // second: split-K partial holograms (single-scene calls), else null
     long long a_ps, b_ps;   // plane strides of A and B (elements)
-    long long out_ps;       // first: plane stride of T_c (elements)
+    long long out_ps;       // panel outputs: plane stride (elements)
     int M, N, K;            // output rows, output columns (complex), reduction length
-    int lda, ldb;           // row strides of the A and B panels (elements)
-    int out_ld;             // first: row stride of T_c (the scene's kpad); second: nx
+    int lda, ldb;           // K-block strides of the A and B panels (rows x 16 elements)
+    int out_ld;             // complex / real outputs: row stride; panel outputs
+                            // (T_c, P): K-block stride (rows x 16 elements)
     int tiles_n;            // column tiles
     int tile_begin;         // exclusive prefix of tiles over the table
     int accumulate;         // second: hologram += result

@@ -91,7 +91,7 @@ struct FirstEpi {
     __device__ static void store4(const NtEntry& e, int, int, int m, int n, const float* re,
                                   const float* im) {
         if (m >= pad_kt(e.M) || n >= e.N) return;
-        const size_t off = (size_t)n * e.out_ld + m;
+        const size_t off = kblk_off(n, m, (size_t)e.out_ld);  // 4 consecutive k' of row n
         const size_t ps = (size_t)e.out_ps;
         if constexpr (P == P_FP32) {
             float* b = static_cast<float*>(e.out);
@@ -166,7 +166,8 @@ struct PanelEpi {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (m + q < e.M)
-                put_c<P>(e.out, (size_t)e.out_ps, (size_t)(m + q) * e.out_ld + n, re[q], im[q]);
+                put_c<P>(e.out, (size_t)e.out_ps, kblk_off(m + q, n, (size_t)e.out_ld), re[q],
+                         im[q]);
     }
 };
 
@@ -232,8 +233,8 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
             const int c = q % F::CPR, row = (q / F::CPR) % TM, plane = q / (F::CPR * TM);
             const int m = m0 + row;
             if (m < e.M && (F::KB == kKT || k0 + c * KPC < ke)) {
-                const size_t el = (size_t)plane * e.a_ps + (size_t)m * e.lda + k0;
-                ra[u] = *reinterpret_cast<const u32x4*>(Ab + el * F::ES + c * 16);
+                const size_t el = (size_t)plane * e.a_ps + kblk_off(m, k0 + c * KPC, e.lda);
+                ra[u] = *reinterpret_cast<const u32x4*>(Ab + el * F::ES);
             } else {
                 ra[u] = u32x4{0u, 0u, 0u, 0u};
             }
@@ -244,8 +245,8 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
             const int c = q % F::CPR, row = (q / F::CPR) % TN, plane = q / (F::CPR * TN);
             const int n = n0 + row;
             if (n < e.N && (F::KB == kKT || k0 + c * KPC < ke)) {
-                const size_t el = (size_t)plane * e.b_ps + (size_t)n * e.ldb + k0;
-                rb[u] = *reinterpret_cast<const u32x4*>(Bb + el * F::ES + c * 16);
+                const size_t el = (size_t)plane * e.b_ps + kblk_off(n, k0 + c * KPC, e.ldb);
+                rb[u] = *reinterpret_cast<const u32x4*>(Bb + el * F::ES);
             } else {
                 rb[u] = u32x4{0u, 0u, 0u, 0u};
             }

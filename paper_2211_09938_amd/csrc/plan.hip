@@ -134,7 +134,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(PlanArgs a) {
         NtEntry e;
         e.a = cb + dl_cb_off(a.ny, a.nx, a.levels, d, l) * a.esize;
         e.b = fx + dl_fx_off(a.nx, a.levels, d, l) * a.esize;
-        e.out = tc + (size_t)a.seg_row[t] * a.esize;
+        e.out = tc + (size_t)a.seg_row[t] * a.nx * a.esize;  // K block seg/16 of T_c
         e.partial = nullptr;
         e.a_ps = a.cb_ps;
         e.b_ps = a.fx_ps;
@@ -142,9 +142,9 @@ __global__ __launch_bounds__(1024) void plan_kernel(PlanArgs a) {
         e.M = a.cnt_row[t];
         e.N = a.nx;
         e.K = pad_kt(a.cnt_col[t]);
-        e.lda = e.K;
-        e.ldb = e.K;
-        e.out_ld = kpad;
+        e.lda = e.M * 16;
+        e.ldb = a.nx * 16;
+        e.out_ld = a.nx * 16;
         e.tiles_n = tn1;
         e.tile_begin = a.tbeg[t];
         e.accumulate = 0;
@@ -168,8 +168,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(PlanArgs a) {
         e.M = a.ny;
         e.N = a.nx;
         e.K = kpad;
-        e.lda = kpad;
-        e.ldb = kpad;
+        e.lda = a.ny * 16;
+        e.ldb = a.nx * 16;
         e.out_ld = a.nx;
         e.tiles_n = (a.nx + a.tn2 - 1) / a.tn2;
         e.tile_begin = 0;
@@ -233,14 +233,15 @@ __global__ __launch_bounds__(256) void fy_kernel(const float* __restrict__ lut_y
     const int d = dl / levels, l = dl % levels + 1;
     const int cr = cnt_row[dl], pr = pad_kt(cr);
     if (pr == 0) return;
-    const int seg = seg_row[dl], kpad = hdr->kpad;
+    const int seg = seg_row[dl];
     const int nyl = ny >> l, len = lut_len(ny);
     const int* rl = rowlist + dl_rows_off(ny, levels, d, l);
     const float* lutl = lut_y + lut_table(d, l, 0, 0, levels) * len;
     const long long total = (long long)ny * pr;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
-        const int y = (int)(e / pr), i = (int)(e - (long long)y * pr);
+        int y, i;
+        kblk_pos((size_t)e, ny, y, i);
         float re = 0.f, im = 0.f;
         if (i < cr) {
             const int r = rl[i];
@@ -250,7 +251,8 @@ __global__ __launch_bounds__(256) void fy_kernel(const float* __restrict__ lut_y
             re = tb[idx];
             im = tb[len + idx];
         }
-        put_c<P>(fy, ps, (size_t)y * kpad + seg + i, re, im);
+        // the segment starts on a K-block boundary: its blocks follow in storage order
+        put_c<P>(fy, ps, (size_t)seg * ny + (size_t)e, re, im);
     }
 }
 
@@ -271,7 +273,8 @@ __global__ __launch_bounds__(256) void fx_kernel(const float* __restrict__ lut_x
     const long long total = (long long)nx * pc;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
-        const int x = (int)(e / pc), c = (int)(e - (long long)x * pc);
+        int x, c;
+        kblk_pos((size_t)e, nx, x, c);
         float re = 0.f, im = 0.f;
         if (c < cc) {
             const int j = cl[c];
@@ -281,7 +284,7 @@ __global__ __launch_bounds__(256) void fx_kernel(const float* __restrict__ lut_x
             re = tb[idx];
             im = tb[len + idx];
         }
-        put_c<P>(fx, ps, base + (size_t)x * pc + c, re, im);
+        put_c<P>(fx, ps, base + (size_t)e, re, im);
     }
 }
 
@@ -304,14 +307,15 @@ __global__ __launch_bounds__(256) void cb_kernel(const float* __restrict__ coef,
     const long long total = (long long)cr * pc;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (long long)gridDim.x * blockDim.x) {
-        const int rr = (int)(e / pc), c = (int)(e - (long long)rr * pc);
+        int rr, c;
+        kblk_pos((size_t)e, cr, rr, c);
         float v = 0.f;
         if (c < cc) {
             const int r = rl[rr], j = cl[c];
             // the LL quadrant of a level below the top belongs to the coarser levels
             if (!(l < levels && r < nyl && j < nxl)) v = cd[(size_t)r * nx + j];
         }
-        put_r<P>(cb, ps, base + (size_t)rr * pc + c, v);
+        put_r<P>(cb, ps, base + (size_t)e, v);
     }
 }
 
