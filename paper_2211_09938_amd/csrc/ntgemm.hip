@@ -216,9 +216,11 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
 #pragma unroll
             for (int r = 0; r < 16; ++r) { cr[i][j][r] = 0.f; ci[i][j][r] = 0.f; }
 
-    // chunk q of an operand tile -> (plane, row, 16-byte chunk c of the row);
-    // neighbouring threads read neighbouring chunks of a row (a row-fastest
-    // assignment avoids LDS store conflicts but was measured 20% slower)
+    // chunk q of an operand tile -> (plane, row, 16-byte chunk c of the row):
+    // 8 consecutive threads take 8 consecutive rows at one chunk (with the
+    // padded row pitch those 8 stores hit 8 different LDS bank groups), the
+    // next 8 the next chunk of the same rows; with K-blocked panels the 64
+    // threads of a wave still read one contiguous run of global memory
     u32x4 ra[QA], rb[QB];
     const unsigned char* Ab = static_cast<const unsigned char*>(e.a);
     const unsigned char* Bb = static_cast<const unsigned char*>(e.b);
@@ -230,7 +232,8 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
 #pragma unroll
         for (int u = 0; u < QA; ++u) {
             const int q = tid + 256 * u;
-            const int c = q % F::CPR, row = (q / F::CPR) % TM, plane = q / (F::CPR * TM);
+            const int c = (q >> 3) % F::CPR, rl = (q & 7) + 8 * (q / (8 * F::CPR));
+            const int row = rl % TM, plane = rl / TM;
             const int m = m0 + row;
             if (m < e.M && (F::KB == kKT || k0 + c * KPC < ke)) {
                 const size_t el = (size_t)plane * e.a_ps + kblk_off(m, k0 + c * KPC, e.lda);
@@ -242,7 +245,8 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
 #pragma unroll
         for (int u = 0; u < QB; ++u) {
             const int q = tid + 256 * u;
-            const int c = q % F::CPR, row = (q / F::CPR) % TN, plane = q / (F::CPR * TN);
+            const int c = (q >> 3) % F::CPR, rl = (q & 7) + 8 * (q / (8 * F::CPR));
+            const int row = rl % TN, plane = rl / TN;
             const int n = n0 + row;
             if (n < e.N && (F::KB == kKT || k0 + c * KPC < ke)) {
                 const size_t el = (size_t)plane * e.b_ps + kblk_off(n, k0 + c * KPC, e.ldb);
@@ -256,13 +260,15 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
 #pragma unroll
         for (int u = 0; u < QA; ++u) {
             const int q = tid + 256 * u;
-            const int c = q % F::CPR, row = (q / F::CPR) % TM, plane = q / (F::CPR * TM);
+            const int c = (q >> 3) % F::CPR, rl = (q & 7) + 8 * (q / (8 * F::CPR));
+            const int row = rl % TM, plane = rl / TM;
             *reinterpret_cast<u32x4*>(As + plane * APLANE + row * F::PITCH + c * 16) = ra[u];
         }
 #pragma unroll
         for (int u = 0; u < QB; ++u) {
             const int q = tid + 256 * u;
-            const int c = q % F::CPR, row = (q / F::CPR) % TN, plane = q / (F::CPR * TN);
+            const int c = (q >> 3) % F::CPR, rl = (q & 7) + 8 * (q / (8 * F::CPR));
+            const int row = rl % TN, plane = rl / TN;
             *reinterpret_cast<u32x4*>(Bs + plane * BPLANE + row * F::PITCH + c * 16) = rb[u];
         }
     };
