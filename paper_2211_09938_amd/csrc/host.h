@@ -48,7 +48,8 @@ inline int choose_split(int ny, int nx, int levels, int layers) {
     return split;
 }
 
-// with_partial: reserve split-K partial holograms (single-scene calls only).
+// with_partial: reserve split-K partials and the adjoint / back-propagation
+// scratch (single-scene calls); batched plans run the forward pass only.
 inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with_partial = true) {
     cgh::Layout lo{};
     const size_t plane = (size_t)ny * nx;
@@ -89,10 +90,12 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
     size_t panels = fx_b + cb_b + fy_b + tc_b;
     // the dense back-propagation panels share the region (one layer, one level)
     lo.split_k = with_partial ? choose_split(ny, nx, levels, layers) : 1;
-    const size_t dense = cgh::dense_bytes(ny, nx, lo.split_k);
-    if (dense > panels) panels = dense;
-    const size_t bw = cgh::backward_bytes(ny, nx, layers, levels);
-    if (bw > panels) panels = bw;
+    if (with_partial) {
+        const size_t dense = cgh::dense_bytes(ny, nx, lo.split_k);
+        if (dense > panels) panels = dense;
+        const size_t bw = cgh::backward_bytes(ny, nx, layers, levels);
+        if (bw > panels) panels = bw;
+    }
     lo.big = take(t_bytes > panels ? t_bytes : panels);
     lo.t = lo.big;
     lo.fx = lo.big;

@@ -27,12 +27,13 @@ __host__ __device__ inline int pad_kt(int v) { return (v + kKT - 1) / kKT * kKT;
 __host__ __device__ inline size_t kblk_off(int r, int k, size_t blk) {
     return (size_t)(k >> 4) * blk + (size_t)r * 16 + (k & 15);
 }
-// Inverse for writers that walk a panel of `rows` rows in storage order.
+// Inverse for writers that walk a panel of `rows` rows in storage order.  One
+// panel holds at most 16384 x 16384 elements, so 32-bit arithmetic is exact.
 __host__ __device__ inline void kblk_pos(size_t e, int rows, int& r, int& k) {
-    const size_t blk = (size_t)rows * 16;
-    const size_t b = e / blk, rem = e - b * blk;
+    const unsigned u = (unsigned)e, blk = (unsigned)rows * 16u;
+    const unsigned b = u / blk, rem = u - b * blk;
     r = (int)(rem >> 4);
-    k = (int)(b * 16 + (rem & 15));
+    k = (int)(b * 16u + (rem & 15u));
 }
 
 // One GEMM problem of the batched NT kernel (self-contained, so problems of

@@ -32,9 +32,9 @@ typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 namespace {
 
 // Operand format of precision P with KS rows of K per staged tile (the FP32
-// path always stages 16).  Measured on MI355X: the direct split kernels run
-// best at K 16 with two workgroups per CU, the persistent split kernels at
-// K 32 with one (more MFMA work per load batch and per barrier pair).
+// path always stages 16).  Measured on MI355X with K-blocked panels: both
+// schedules run best at K 16 per staged tile with two workgroups per CU (K 32
+// at one workgroup per CU was 15% slower in the persistent split kernels).
 template <int P, int KS = kKT>
 struct Fmt {
     static constexpr int ES = (P == P_FP32) ? 4 : 2;        // bytes per element
@@ -45,9 +45,9 @@ struct Fmt {
     static constexpr int PITCH = KB * ES + 16;              // LDS bytes per row (with padding)
 };
 
-constexpr int kDirectKS = 16, kPersistKS = 32;
+constexpr int kDirectKS = 16, kPersistKS = 16;
 template <int P> constexpr int direct_occ() { return 2; }
-template <int P> constexpr int persist_occ() { return P == P_FP32 ? 2 : 1; }
+template <int P> constexpr int persist_occ() { return 2; }
 
 __device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
