@@ -237,22 +237,30 @@ __global__ __launch_bounds__(256) void fy_kernel(const float* __restrict__ lut_y
     const int nyl = ny >> l, len = lut_len(ny);
     const int* rl = rowlist + dl_rows_off(ny, levels, d, l);
     const float* lutl = lut_y + lut_table(d, l, 0, 0, levels) * len;
-    const long long total = (long long)ny * pr;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
-        int y, i;
-        kblk_pos((size_t)e, ny, y, i);
-        float re = 0.f, im = 0.f;
-        if (i < cr) {
-            const int r = rl[i];
-            const int band = r >= nyl, j = r - band * nyl;
-            const float* tb = lutl + (size_t)band * 2 * len;
-            const int idx = y - (j << l) + ny;
-            re = tb[idx];
-            im = tb[len + idx];
+    // four consecutive storage elements per thread: one row y, four k'
+    const long long total4 = (long long)ny * pr / 4;
+    for (long long e4 = (long long)blockIdx.x * blockDim.x + threadIdx.x; e4 < total4;
+         e4 += (long long)gridDim.x * blockDim.x) {
+        const size_t e = (size_t)e4 * 4;
+        int y, i0;
+        kblk_pos(e, ny, y, i0);
+        float re[4], im[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + q;
+            re[q] = 0.f;
+            im[q] = 0.f;
+            if (i < cr) {
+                const int r = rl[i];
+                const int band = r >= nyl, j = r - band * nyl;
+                const float* tb = lutl + (size_t)band * 2 * len;
+                const int idx = y - (j << l) + ny;
+                re[q] = tb[idx];
+                im[q] = tb[len + idx];
+            }
         }
         // the segment starts on a K-block boundary: its blocks follow in storage order
-        put_c<P>(fy, ps, (size_t)seg * ny + (size_t)e, re, im);
+        put_c4<P>(fy, ps, (size_t)seg * ny + e, re, im);
     }
 }
 
@@ -270,21 +278,28 @@ __global__ __launch_bounds__(256) void fx_kernel(const float* __restrict__ lut_x
     const int* cl = collist + dl_cols_off(nx, levels, d, l);
     const float* lutl = lut_x + lut_table(d, l, 0, 0, levels) * len;
     const size_t base = dl_fx_off(nx, levels, d, l);
-    const long long total = (long long)nx * pc;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
-        int x, c;
-        kblk_pos((size_t)e, nx, x, c);
-        float re = 0.f, im = 0.f;
-        if (c < cc) {
-            const int j = cl[c];
-            const int band = j >= nxl, jj = j - band * nxl;
-            const float* tb = lutl + (size_t)band * 2 * len;
-            const int idx = x - (jj << l) + nx;
-            re = tb[idx];
-            im = tb[len + idx];
+    const long long total4 = (long long)nx * pc / 4;
+    for (long long e4 = (long long)blockIdx.x * blockDim.x + threadIdx.x; e4 < total4;
+         e4 += (long long)gridDim.x * blockDim.x) {
+        const size_t e = (size_t)e4 * 4;
+        int x, c0;
+        kblk_pos(e, nx, x, c0);
+        float re[4], im[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = c0 + q;
+            re[q] = 0.f;
+            im[q] = 0.f;
+            if (c < cc) {
+                const int j = cl[c];
+                const int band = j >= nxl, jj = j - band * nxl;
+                const float* tb = lutl + (size_t)band * 2 * len;
+                const int idx = x - (jj << l) + nx;
+                re[q] = tb[idx];
+                im[q] = tb[len + idx];
+            }
         }
-        put_c<P>(fx, ps, base + (size_t)e, re, im);
+        put_c4<P>(fx, ps, base + e, re, im);
     }
 }
 
@@ -304,18 +319,25 @@ __global__ __launch_bounds__(256) void cb_kernel(const float* __restrict__ coef,
     const int* cl = collist + dl_cols_off(nx, levels, d, l);
     const float* cd = coef + (size_t)d * ny * nx;
     const size_t base = dl_cb_off(ny, nx, levels, d, l);
-    const long long total = (long long)cr * pc;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (long long)gridDim.x * blockDim.x) {
-        int rr, c;
-        kblk_pos((size_t)e, cr, rr, c);
-        float v = 0.f;
-        if (c < cc) {
-            const int r = rl[rr], j = cl[c];
-            // the LL quadrant of a level below the top belongs to the coarser levels
-            if (!(l < levels && r < nyl && j < nxl)) v = cd[(size_t)r * nx + j];
+    const long long total4 = (long long)cr * pc / 4;
+    for (long long e4 = (long long)blockIdx.x * blockDim.x + threadIdx.x; e4 < total4;
+         e4 += (long long)gridDim.x * blockDim.x) {
+        const size_t e = (size_t)e4 * 4;
+        int rr, c0;
+        kblk_pos(e, cr, rr, c0);
+        const int r = rl[rr];
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = c0 + q;
+            v[q] = 0.f;
+            if (c < cc) {
+                const int j = cl[c];
+                // the LL quadrant of a level below the top belongs to the coarser levels
+                if (!(l < levels && r < nyl && j < nxl)) v[q] = cd[(size_t)r * nx + j];
+            }
         }
-        put_r<P>(cb, ps, base + (size_t)e, v);
+        put_r4<P>(cb, ps, base + e, v);
     }
 }
 
