@@ -49,6 +49,9 @@ WORKLOADS = {
                  "1024x1024 float32 amplitudes, one plane z=0.2 m, ~30% saliency, 3 Haar levels; "
                  "loss = sum (|Fresnel back-propagation of H| - T)^2 with a blob target; one "
                  "step = forward + back-propagation + loss + gradient through the adjoints"),
+    "literal2048x8": (scenes.depth_2048,
+                      "the 2048x2048, 8-plane scene of depth2048x8 by the paper-literal form: "
+                      "approximation image and residual maps times uniform-block fringes, dense"),
     "exact256": (lambda: scenes.tiny(n=256),
                  "256x256 object, one plane z=0.2 m, ~25% saliency, 3 Haar levels; Eq. 1 with the "
                  "exact distance and 1/r amplitude as a direct sum (evaluation of the Fresnel form)"),
@@ -195,6 +198,54 @@ def run_exact(scene, steps, warmup):
         "roofline": {"bound": "alu", "kernel": "exact_kernel", "achieved": achieved,
                      "peak": peak, "unit": "Gterm/s", "frac": achieved / peak, "traffic": None,
                      "valu_per_term": EXACT_VALU_PER_TERM, "avg_launch_ms": ms},
+        "_out": out.cpu().numpy(),
+    }
+
+
+def run_literal(scene, prec, steps, warmup):
+    import torch
+
+    from paper_2211_09938_amd import cgh
+
+    dev = torch.device("cuda:0")
+    ny, nx = scene.shape
+    obj = torch.from_numpy(scene.obj).to(dev)
+    sal = torch.from_numpy(scene.saliency).to(dev)
+    lay = None if scene.layer is None else torch.from_numpy(scene.layer).to(dev)
+    layers = len(scene.z)
+    ws = torch.empty(cgh.workspace_size(ny, nx, layers, scene.levels, prec), dtype=torch.uint8,
+                     device=dev)
+    out = torch.empty((ny, nx), dtype=torch.complex64, device=dev)
+
+    def step():
+        cgh.literal_hologram(obj, scene.z, scene.lam, scene.pitch, scene.levels, sal, lay,
+                             precision=prec, out=out, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # dense work: per layer and image b (block 2^b) a (ny>>b x nx>>b) x (nx>>b x nx) real x complex
+    # product and a (ny x ny>>b) x (ny>>b x nx) complex product
+    fl = 0.0
+    for b in range(scene.levels, -1, -1):
+        r, c = ny >> b, nx >> b
+        fl += layers * (4.0 * r * c * nx + 8.0 * ny * r * nx)
+    ms = 1e3 * elapsed / steps
+    achieved = fl / (ms * 1e-3) / 1e12
+    return {
+        "value": steps / elapsed,
+        "ms_per_step": ms,
+        "stages_ms_per_step": {},
+        "work": {"flops_dense": fl},
+        "roofline": {"bound": "mfma", "kernel": "whole literal step (both contractions dominate)",
+                     "achieved": achieved, "peak": PEAKS_TFLOPS[prec], "unit": "TFLOP/s",
+                     "frac": achieved / PEAKS_TFLOPS[prec], "traffic": None,
+                     "issued_mfma_frac": achieved * ISSUE_FACTOR[prec] / PEAKS_TFLOPS[prec]},
         "_out": out.cpu().numpy(),
     }
 
@@ -438,6 +489,8 @@ def main():
             forms[prec] = run_batch(work, prec, args.steps, args.warmup, args.tune_cache)
         elif grad:
             forms[prec] = run_grad(scene, prec, args.steps, args.warmup)
+        elif args.workload.startswith("literal"):
+            forms[prec] = run_literal(scene, prec, args.steps, args.warmup)
         else:
             forms[prec] = run_single(scene, prec, args.steps, args.warmup, args.workload)
         out = forms[prec].pop("_out", None)

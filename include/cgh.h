@@ -149,6 +149,25 @@ int cgh_progressive_stages(const float* object, const uint8_t* layer_index, int 
                            void* stream);
 
 /*
+ * Paper-literal form of the progressive hologram (Sec. 2, steps 2-5 in the
+ * image domain): the coarsest approximation image (2^L x 2^L block means) and
+ * the residual map of every level (finer approximation image minus the coarser
+ * one replicated 2 x 2, kept where the level's quantised saliency is above its
+ * threshold), each point multiplied onto the Fresnel fringe of a uniform block
+ * of its size and added at its position.  The result equals
+ * cgh_progressive_hologram up to rounding order (a cross-check of the
+ * coefficient form); the work is dense, one contraction per image and level
+ * with inner dimension N/2^L, ..., N/2, N (no saliency skipping).  Arguments,
+ * flags, workspace (cgh_workspace_size), errors and ownership as for
+ * cgh_progressive_hologram.
+ */
+int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_layers,
+                         const double* z, const float* saliency, const float* thresholds,
+                         double lambda, double pitch, int ny, int nx, int levels, int precision,
+                         unsigned flags, void* workspace, size_t workspace_bytes, float* hologram,
+                         void* stream);
+
+/*
  * Eq. 1 with the exact distance (no Fresnel approximation), for measuring
  * the error of the Fresnel form of the hot path:
  *   hologram[y][x] = sum_d sum_{q,p} Ahat_d[q][p] / r * exp(i 2 pi r / lambda),

@@ -202,6 +202,53 @@ int cgh_progressive_stages(const float* object, const uint8_t* layer_index, int 
     }
 }
 
+int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_layers,
+                         const double* z, const float* saliency, const float* thresholds,
+                         double lambda, double pitch, int ny, int nx, int levels, int precision,
+                         unsigned flags, void* workspace, size_t workspace_bytes, float* hologram,
+                         void* stream) {
+    try {
+        float thr[CGH_MAX_LEVELS];
+        int st = check_common(n_layers, layer_index, z, thresholds, lambda, pitch, ny, nx, levels,
+                              precision, flags, thr);
+        if (st) return st;
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        if (!object || !hologram) return CGH_ERROR_INVALID_VALUE;
+        const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
+        if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        hipStream_t s = (hipStream_t)stream;
+        char* ws = static_cast<char*>(workspace);
+        Optics op;
+        make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
+        uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
+        hipError_t e = cgh::launch_fill_u8(fl, lo.flags_fill, s);
+        if (e == hipSuccess)
+            e = cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels, thr,
+                                     cgh::kAllParts, reinterpret_cast<float*>(ws + lo.coef), fl,
+                                     lo.flags_layer,
+                                     reinterpret_cast<unsigned long long*>(ws + lo.ops), s);
+        if (e == hipSuccess)
+            e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im, cgh::P_FP32,
+                                 ws + lo.lut_x, nullptr, s);
+        if (e == hipSuccess)
+            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im, cgh::P_FP32,
+                                 ws + lo.lut_y, nullptr, s);
+        if (e == hipSuccess) {
+            const cgh::LitTables tb{op.c, op.one_re, op.one_im, op.pre_re, op.pre_im};
+            e = cgh::launch_literal(reinterpret_cast<const float*>(ws + lo.coef),
+                                    reinterpret_cast<const float*>(ws + lo.lut_x),
+                                    reinterpret_cast<const float*>(ws + lo.lut_y), tb, ny, nx,
+                                    n_layers, levels, precision, lo.split_k,
+                                    reinterpret_cast<float2*>(ws + lo.partial),
+                                    reinterpret_cast<float2*>(hologram),
+                                    (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0, ws + lo.big, s);
+        }
+        return hip_status(e);
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
 int cgh_exact_hologram(const float* object, const uint8_t* layer_index, int n_layers,
                        const double* z, const float* saliency, const float* thresholds,
                        double lambda, double pitch, int ny, int nx, int levels, unsigned flags,

@@ -95,6 +95,8 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
         if (dense > panels) panels = dense;
         const size_t bw = cgh::backward_bytes(ny, nx, layers, levels);
         if (bw > panels) panels = bw;
+        const size_t lit = cgh::literal_bytes(ny, nx, layers, levels);
+        if (lit > panels) panels = lit;
     }
     lo.big = take(t_bytes > panels ? t_bytes : panels);
     lo.t = lo.big;

@@ -214,6 +214,23 @@ hipError_t launch_backward_nt(const float2* grad_h, const float* lut_x, const fl
                               int nx, int layers, int levels, int precision, float* gcoef,
                               void* region, hipStream_t s);
 
+// Direct launch of first-contraction problems (A real, B complex, transposed
+// K-blocked panel output) over a table; `tiles` bounds the device tile count.
+hipError_t launch_nt_first_table(int precision, const NtEntry* entries, int n_entries,
+                                 const int* tile_count, int tiles, hipStream_t s);
+
+// Paper-literal form (image-domain residual maps times uniform-block fringes).
+// Per-layer optical constants ([host] arrays of the layer count): c = p^2 / (2 lambda z)
+// and the prefactors of the x (unit) and y (optional Eq. 1 constant) tables.
+struct LitTables {
+    const double *c, *one_re, *one_im, *pre_re, *pre_im;
+};
+size_t literal_bytes(int ny, int nx, int layers, int levels);
+hipError_t launch_literal(const float* coef, const float* lut_x, const float* lut_y,
+                          const LitTables& tb, int ny, int nx, int layers, int levels,
+                          int precision, int split, float2* partial, float2* hologram,
+                          int accumulate, void* region, hipStream_t s);
+
 // Tiles of a problem with M rows and N columns under a tile shape.
 __host__ __device__ inline int nt_tiles(int M, int N, int tm, int tn) {
     return ((M + tm - 1) / tm) * ((N + tn - 1) / tn);

@@ -508,6 +508,21 @@ void table_epi(int epi, const NtEntry* entries, int n_entries, const int* tile_c
 }
 }  // namespace
 
+hipError_t launch_nt_first_table(int precision, const NtEntry* entries, int n_entries,
+                                 const int* tile_count, int tiles, hipStream_t s) {
+    if (tiles <= 0 || n_entries <= 0) return hipSuccess;
+    if (precision == P_BF16)
+        hipLaunchKernelGGL((nt_direct_kernel<P_BF16, false, FirstEpi<P_BF16>, 128, 128>),
+                           dim3(tiles), dim3(256), 0, s, entries, n_entries, tile_count, 1);
+    else if (precision == P_FP16)
+        hipLaunchKernelGGL((nt_direct_kernel<P_FP16, false, FirstEpi<P_FP16>, 128, 128>),
+                           dim3(tiles), dim3(256), 0, s, entries, n_entries, tile_count, 1);
+    else
+        hipLaunchKernelGGL((nt_direct_kernel<P_FP32, false, FirstEpi<P_FP32>, 128, 128>),
+                           dim3(tiles), dim3(256), 0, s, entries, n_entries, tile_count, 1);
+    return hipGetLastError();
+}
+
 hipError_t launch_nt_table(int epi, int precision, const NtEntry* entries, int n_entries,
                            const int* tile_count, int tiles, int split, hipStream_t s) {
     if (tiles <= 0 || n_entries <= 0) return hipSuccess;

@@ -119,6 +119,18 @@ def test_stages_rejects_invalid_arguments(over, code):
                                             0, 0, None, 0, None, None) == OK
 
 
+def test_literal_validation():
+    lib = cgh.lib()
+    z = (ctypes.c_double * 1)(0.2)
+    base = [BOGUS, None, 1, z, None, None, 532e-9, 8e-6, 64, 64, 3, 0, 0, BOGUS, 1 << 40, BOGUS,
+            None]
+    for idx, val, code in [(0, None, INVALID), (15, None, INVALID), (8, 60, SHAPE),
+                           (14, 16, WS), (11, 9, INVALID), (12, 8, INVALID), (2, 2, INVALID)]:
+        a = list(base)
+        a[idx] = val
+        assert lib.cgh_literal_hologram(*a) == code, (idx, val)
+
+
 def test_exact_validation():
     lib = cgh.lib()
     z = (ctypes.c_double * 1)(0.2)
