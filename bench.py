@@ -52,6 +52,11 @@ WORKLOADS = {
     "literal2048x8": (scenes.depth_2048,
                       "the 2048x2048, 8-plane scene of depth2048x8 by the paper-literal form: "
                       "approximation image and residual maps times uniform-block fringes, dense"),
+    "stages256": (lambda: scenes.tiny(n=256),
+                  "256x256 object (the paper's image size), one plane z=0.2 m, ~25% saliency, "
+                  "3 levels: the four progressive stage holograms, their Fresnel "
+                  "back-propagated amplitudes and the SSIM of each against the point-wise "
+                  "hologram's, with the operator counts of every step"),
     "exact256": (lambda: scenes.tiny(n=256),
                  "256x256 object, one plane z=0.2 m, ~25% saliency, 3 Haar levels; Eq. 1 with the "
                  "exact distance and 1/r amplitude as a direct sum (evaluation of the Fresnel form)"),
@@ -247,6 +252,57 @@ def run_literal(scene, prec, steps, warmup):
                      "frac": achieved / PEAKS_TFLOPS[prec], "traffic": None,
                      "issued_mfma_frac": achieved * ISSUE_FACTOR[prec] / PEAKS_TFLOPS[prec]},
         "_out": out.cpu().numpy(),
+    }
+
+
+def run_stages(scene, prec, steps, warmup):
+    import torch
+
+    from paper_2211_09938_amd import cgh, quality
+
+    dev = torch.device("cuda:0")
+    ny, nx = scene.shape
+    obj = torch.from_numpy(scene.obj).to(dev)
+    sal = torch.from_numpy(scene.saliency).to(dev)
+    ws = torch.empty(cgh.workspace_size(ny, nx, 1, scene.levels, prec), dtype=torch.uint8,
+                     device=dev)
+    st = torch.empty((scene.levels + 1, ny, nx), dtype=torch.complex64, device=dev)
+
+    def step():
+        cgh.progressive_stages(obj, scene.z, scene.lam, scene.pitch, scene.levels, sal,
+                               precision=prec, out=st, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = cgh.workspace_stats(ws, ny, nx, 1, scene.levels, prec)
+    # every block salient = the point-wise hologram (each point its own fringe)
+    full = cgh.progressive_hologram(obj, scene.z, scene.lam, scene.pitch, scene.levels, None,
+                                    precision=prec)
+    z = scene.z[0]
+    ref = cgh.fresnel_backpropagate(full, scene.lam, scene.pitch, z, precision=prec).abs()
+    ref = ref.cpu().numpy().astype(np.float64)
+    rng = float(ref.max() - ref.min())
+    rows = []
+    cum = 0
+    for j in range(scene.levels + 1):
+        amp = cgh.fresnel_backpropagate(st[j].contiguous(), scene.lam, scene.pitch, z,
+                                        precision=prec).abs().cpu().numpy().astype(np.float64)
+        cum += stats["operators"][j]
+        rows.append({"stage": ["LLL", "LL", "L", "object"][j] if scene.levels == 3 else j,
+                     "ssim_vs_pointwise": quality.ssim(amp, ref, rng),
+                     "operators_cumulative": cum,
+                     "operators_frac_of_pointwise": cum / stats["operators_pointwise"]})
+    return {
+        "value": steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "stages": rows,
+        "operators_pointwise": stats["operators_pointwise"],
     }
 
 
@@ -447,6 +503,23 @@ def main():
         sys.exit(2)
     make, desc = WORKLOADS[args.workload]
     work = make()
+    if args.workload.startswith("stages"):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("bench.py needs a GPU")
+        res = run_stages(work, args.precision, args.steps, args.warmup)
+        line = {"metric": "progressive stage sets/s (all levels+1 stage holograms) with SSIM "
+                          "of each stage vs the point-wise hologram and operator counts",
+                "value": res["value"], "unit": "stage sets/s", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": DTYPES[args.precision], "data": "synthetic",
+                "config": {"workload": args.workload, "description": desc,
+                           "ny": work.shape[0], "nx": work.shape[1]},
+                "stages": res["stages"], "operators_pointwise": res["operators_pointwise"]}
+        print(json.dumps(line), flush=True)
+        return
     if args.workload.startswith("exact"):
         base = None if args.no_cpu_baseline else exact_cpu_baseline(work)
         import torch

@@ -32,26 +32,42 @@ def kernel_rows(rows, n, lam, pitch, z):
     return np.cos(th) + 1j * np.sin(th)
 
 
-def window(obj, z, lam, pitch, levels=3, saliency_map=None, layer_index=None,
-           thresholds=None, y0=0, x0=0, h=None, w=None, eq1_prefactor=False):
-    """Hologram window [y0:y0+h, x0:x0+w] of the progressive hologram, complex128 (h, w)."""
+def windows(obj, z, lam, pitch, levels=3, saliency_map=None, layer_index=None,
+            thresholds=None, corners=((0, 0),), h=None, w=None, eq1_prefactor=False):
+    """Hologram windows [y0:y0+h, x0:x0+w] for every (y0, x0) in ``corners``.
+
+    Each layer's masked reconstruction is formed once and shared by the windows.
+    Returns a list of complex128 (h, w) arrays.
+    """
     obj = np.asarray(obj, dtype=np.float64)
     ny, nx = obj.shape
-    h = ny - y0 if h is None else h
-    w = nx - x0 if w is None else w
     z = list(np.atleast_1d(np.asarray(z, dtype=np.float64)))
-    out = np.zeros((h, w), dtype=np.complex128)
+    outs = []
+    for (y0, x0) in corners:
+        hh = ny - y0 if h is None else h
+        ww = nx - x0 if w is None else w
+        outs.append(np.zeros((hh, ww), dtype=np.complex128))
     for d, a_d in enumerate(progressive.layer_split(obj, layer_index, len(z))):
         if not np.any(a_d):
             continue
         a_hat = progressive.masked_reconstruction(a_d, saliency_map, levels, thresholds)
-        ky = kernel_rows(np.arange(y0, y0 + h), ny, lam, pitch, z[d])
-        kx = kernel_rows(np.arange(x0, x0 + w), nx, lam, pitch, z[d])
-        # (K_y Ahat) with a real Ahat: two real products (contiguous operands,
-        # so that NumPy hands them to BLAS)
-        left = np.ascontiguousarray(ky.real) @ a_hat + 1j * (np.ascontiguousarray(ky.imag) @ a_hat)
-        part = left @ np.ascontiguousarray(kx.T)
-        if eq1_prefactor:
-            part = part * fresnel.prefactor(lam, z[d])
-        out += part
-    return out
+        for (y0, x0), out in zip(corners, outs):
+            hh, ww = out.shape
+            ky = kernel_rows(np.arange(y0, y0 + hh), ny, lam, pitch, z[d])
+            kx = kernel_rows(np.arange(x0, x0 + ww), nx, lam, pitch, z[d])
+            # (K_y Ahat) with a real Ahat: two real products (contiguous operands,
+            # so that NumPy hands them to BLAS)
+            left = (np.ascontiguousarray(ky.real) @ a_hat
+                    + 1j * (np.ascontiguousarray(ky.imag) @ a_hat))
+            part = left @ np.ascontiguousarray(kx.T)
+            if eq1_prefactor:
+                part = part * fresnel.prefactor(lam, z[d])
+            out += part
+    return outs
+
+
+def window(obj, z, lam, pitch, levels=3, saliency_map=None, layer_index=None,
+           thresholds=None, y0=0, x0=0, h=None, w=None, eq1_prefactor=False):
+    """Hologram window [y0:y0+h, x0:x0+w] of the progressive hologram, complex128 (h, w)."""
+    return windows(obj, z, lam, pitch, levels, saliency_map, layer_index, thresholds,
+                   corners=((y0, x0),), h=h, w=w, eq1_prefactor=eq1_prefactor)[0]

@@ -155,3 +155,33 @@ def test_operator_counts_without_saliency_and_at_256():
     # 65,536 point-wise (the two counts printed in Sec. 3)
     assert st["operators"] == [1024, 4096, 16384, 65536]
     assert st["operators_pointwise"] == 65536
+
+
+def test_stage_quality_rises_towards_the_pointwise_hologram():
+    # the measure of Sec. 3: SSIM of each stage's reconstruction against the
+    # point-wise hologram's; the coarsest stage scores lowest, every block salient
+    # reproduces the point-wise hologram
+    import torch
+
+    from oracle import quality
+    from paper_2211_09938_amd import quality as pq
+
+    m = cgh()
+    s = scenes.tiny()
+    z = s.z[0]
+    st = torch.from_numpy(gpu_stages(s).astype(np.complex64)).cuda()
+    full = m.progressive_hologram(to_dev(s.obj), s.z, s.lam, s.pitch, 3, None)
+    ref = m.fresnel_backpropagate(full, s.lam, s.pitch, z).abs().cpu().numpy().astype(np.float64)
+    rng = ref.max() - ref.min()
+    scores = []
+    for j in range(4):
+        amp = m.fresnel_backpropagate(st[j].contiguous(), s.lam, s.pitch, z).abs()
+        amp = amp.cpu().numpy().astype(np.float64)
+        scores.append(quality.ssim(amp, ref, rng))
+        assert abs(pq.ssim(amp, ref, rng) - scores[-1]) <= 1e-9
+    print("SSIM per stage vs point-wise:", ["%.4f" % v for v in scores])
+    assert scores[0] < scores[-1] < 1.0
+    s.saliency = None
+    all_sal = torch.from_numpy(gpu_stages(s)[3].astype(np.complex64)).cuda()
+    amp = m.fresnel_backpropagate(all_sal, s.lam, s.pitch, z).abs().cpu().numpy().astype(np.float64)
+    assert quality.ssim(amp, ref, rng) >= 0.9999

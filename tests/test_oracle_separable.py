@@ -57,3 +57,12 @@ def test_single_point_far_window_is_the_zone_plate():
     yy, xx = np.meshgrid(np.arange(0, 24), np.arange(40, 80), indexing="ij")
     th = np.pi * scenes.PITCH ** 2 * ((yy - q0) ** 2 + (xx - p0) ** 2) / (scenes.WAVELENGTH * z)
     assert np.max(np.abs(got - np.exp(1j * th))) <= 1e-12
+
+
+def test_several_windows_share_one_reconstruction():
+    s = scenes.random_scene(77, 48, 64, planes=2, fraction=0.3)
+    sal = s.saliency.astype(np.float64)
+    corners = [(0, 0), (10, 33), (32, 48)]
+    ws = separable.windows(s.obj, s.z, s.lam, s.pitch, 3, sal, s.layer, corners=corners, h=16, w=16)
+    for (y0, x0), got in zip(corners, ws):
+        assert progressive.rel_l2(got, direct_window(s, y0, x0, 16, 16)) <= 1e-12
