@@ -461,10 +461,15 @@ hipError_t persistent_shape(int tm, int tn, const NtEntry* entries, int n_entrie
 }
 
 template <int P>
-hipError_t first_direct(int layers, int levels, const NtBuffers& b, int max_tiles, hipStream_t s) {
+hipError_t first_direct(int layers, int levels, const NtBuffers& b, int max_tiles, int tile_m,
+                        hipStream_t s) {
     if (max_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((nt_direct_kernel<P, false, FirstEpi<P>, 128, 128>), dim3(max_tiles),
-                       dim3(256), 0, s, b.first, layers * levels, &b.hdr->first_tiles, 1);
+    if (tile_m == 64)
+        hipLaunchKernelGGL((nt_direct_kernel<P, false, FirstEpi<P>, 64, 128>), dim3(max_tiles),
+                           dim3(256), 0, s, b.first, layers * levels, &b.hdr->first_tiles, 1);
+    else
+        hipLaunchKernelGGL((nt_direct_kernel<P, false, FirstEpi<P>, 128, 128>), dim3(max_tiles),
+                           dim3(256), 0, s, b.first, layers * levels, &b.hdr->first_tiles, 1);
     return hipGetLastError();
 }
 
@@ -478,11 +483,14 @@ hipError_t second_direct(int ny, int nx, int split, const NtBuffers& b, hipStrea
 
 }  // namespace
 
+int nt_first_tile_m(int precision) { return precision == P_FP32 ? 64 : 128; }
+
 hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffers& b,
                            int max_tiles, hipStream_t s) {
-    if (precision == P_BF16) return first_direct<P_BF16>(layers, levels, b, max_tiles, s);
-    if (precision == P_FP16) return first_direct<P_FP16>(layers, levels, b, max_tiles, s);
-    return first_direct<P_FP32>(layers, levels, b, max_tiles, s);
+    const int tm = nt_first_tile_m(precision);
+    if (precision == P_BF16) return first_direct<P_BF16>(layers, levels, b, max_tiles, tm, s);
+    if (precision == P_FP16) return first_direct<P_FP16>(layers, levels, b, max_tiles, tm, s);
+    return first_direct<P_FP32>(layers, levels, b, max_tiles, tm, s);
 }
 
 hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBuffers& b,
