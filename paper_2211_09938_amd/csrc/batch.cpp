@@ -1,9 +1,10 @@
 // Batched plans: many scenes of uneven size planned, tuned and captured as one
-// unit.  Every scene runs the same per-scene stages as cgh_progressive_hologram
-// (coefficients, fringe tables, active lists and panels); the contraction
-// problems of all scenes are then merged into one table per contraction and
-// each contraction runs as a single persistent launch over that table.  Tile
-// shapes come from an autotuner (timed on this batch, cached as JSON lines).
+// unit.  Every stage of cgh_progressive_hologram (coefficients, fringe tables,
+// active lists, plans, panels) runs as one launch over every scene, driven by
+// device-resident per-scene tables written at plan creation; the contraction
+// problems of all scenes are merged into one table per contraction and each
+// contraction runs as a single persistent launch over that table.  Tile shapes
+// come from an autotuner (timed on this batch, cached as JSON lines).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,74 +47,59 @@ struct cgh_plan {
     double ms_first = 0, ms_second = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // batched preparation: device tables and the extents of the largest scene
+    cgh::DwtScene* d_dwt = nullptr;
+    cgh::PrepScene* d_prep = nullptr;
+    cgh::LutJob* d_luts = nullptr;
+    cgh::PlanArgs* d_args = nullptr;
+    std::vector<cgh::PrepScene> h_prep;
+    std::vector<cgh::PlanArgs> h_args;
+    int n_luts = 0, max_nbx = 0, max_nby = 0, max_ndl = 0, max_len = 0;
+    size_t max_fill = 0;
+    long long big_y = 0, big_x = 0, big_c = 0;
 };
 
 namespace {
 
 constexpr int kMaxScenes = 4096;
-constexpr int kPrepBranches = 8;  // parallel graph branches for the per-scene stages
 constexpr int kCandidates[4][2] = {{128, 128}, {64, 128}, {128, 64}, {64, 64}};
 
 struct Events {
     hipEvent_t a = nullptr, b = nullptr, c = nullptr;
 };
 
-// Per-scene stages of the whole batch (coefficients, fringe tables, active
-// lists, plans, panels), then the merge of the problem tables.  With side
-// streams, scene i's stages go to side[i % n_side] (parallel graph branches
-// forked from and joined back into `s`).
-hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s, const int* tiles,
-                        const hipStream_t* side = nullptr, const hipEvent_t* ev = nullptr,
-                        int n_side = 0) {
-    Optics op;
-    hipError_t fe = hipSuccess;
-    if (n_side > 0) {
-        fe = hipEventRecord(ev[0], s);
-        for (int k = 0; k < n_side && fe == hipSuccess; ++k) fe = hipStreamWaitEvent(side[k], ev[0], 0);
-        if (fe != hipSuccess) return fe;
-    }
+// Every per-scene stage of the batch as one launch over all scenes, then the
+// merge of the problem tables.  The planning arguments (tile shapes included)
+// are the ones last uploaded by upload_args.
+hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s) {
+    const int n = (int)p.scenes.size();
+    hipError_t e = cgh::launch_prep_fill(p.d_dwt, n, p.max_fill, s);
+    if (e == hipSuccess)
+        e = cgh::launch_dwt_mask_batch(p.d_dwt, n, p.levels, p.thr, p.max_nbx, p.max_nby, s);
+    if (e == hipSuccess) e = cgh::launch_luts_batch(p.d_luts, p.n_luts, p.max_len, p.levels, s);
+    if (e == hipSuccess) e = cgh::launch_lists_batch(p.d_prep, n, p.levels, p.max_ndl, s);
+    if (e == hipSuccess) e = cgh::launch_plan_batch(p.d_args, n, s);
+    if (e == hipSuccess)
+        e = cgh::launch_materialize_batch(p.d_prep, n, p.levels, p.precision, p.max_ndl, p.big_y,
+                                          p.big_x, p.big_c, s);
+    if (e != hipSuccess) return e;
+    return cgh::launch_batch_prefix(p.hdrs, n, p.first_off, p.first, p.second, p.counts,
+                                    p.queues, s);
+}
+
+// Planning arguments of every scene for the given tile shapes (synchronous).
+hipError_t upload_args(cgh_plan& p, const int* tiles, hipStream_t s) {
+    p.h_args.resize(p.scenes.size());
     for (size_t i = 0; i < p.scenes.size(); ++i) {
-        hipStream_t st = n_side > 0 ? side[i % n_side] : s;
         const cgh_plan::Scene& sc = p.scenes[i];
-        const cgh::Layout& lo = sc.lo;
-        char* ws = p.mem + sc.ws_off;
-        const int ny = sc.s.ny, nx = sc.s.nx, nl = sc.s.n_layers;
-        make_optics(op, nl, sc.z.data(), p.lambda, p.pitch, (p.flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
-        uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
-        cgh::NtBuffers nb = nt_buffers(ws, lo);
-        nb.first = p.first + sc.first_off;
-        nb.second = p.second + i;
-        nb.hdr = p.hdrs + i;
         const cgh::NtOutput o{reinterpret_cast<float2*>(sc.s.hologram), nullptr, 0};
-        hipError_t e = cgh::launch_fill_u8(fl, lo.flags_fill, st);
-        if (e == hipSuccess)
-            e = cgh::launch_dwt_mask(sc.s.object, sc.s.layer_index, sc.s.saliency, ny, nx, nl,
-                                     p.levels, p.thr, cgh::kAllParts,
-                                     reinterpret_cast<float*>(ws + lo.coef), fl, lo.flags_layer,
-                                     reinterpret_cast<unsigned long long*>(ws + lo.ops), st);
-        if (e == hipSuccess)
-            e = cgh::launch_luts(nx, nl, p.levels, 1, op.c, op.one_re, op.one_im, cgh::P_FP32,
-                                 ws + lo.lut_x, nullptr, st);
-        if (e == hipSuccess)
-            e = cgh::launch_luts(ny, nl, p.levels, 1, op.c, op.pre_re, op.pre_im, cgh::P_FP32,
-                                 ws + lo.lut_y, nullptr, st);
-        if (e == hipSuccess)
-            e = cgh::launch_nt_plan(fl, ny, nx, nl, p.levels, lo.flags_layer, p.precision, tiles, nb,
-                                    o, st);
-        if (e == hipSuccess)
-            e = cgh::launch_nt_materialize(reinterpret_cast<const float*>(ws + lo.coef),
-                                           reinterpret_cast<const float*>(ws + lo.lut_x),
-                                           reinterpret_cast<const float*>(ws + lo.lut_y), ny, nx,
-                                           nl, p.levels, p.precision, nb, st);
-        if (e != hipSuccess) return e;
+        p.h_args[i] = cgh::make_plan_args(sc.s.ny, sc.s.nx, sc.s.n_layers, p.levels, p.precision,
+                                          tiles, p.h_prep[i].b, o);
     }
-    for (int k = 0; k < n_side; ++k) {
-        hipError_t e = hipEventRecord(ev[1 + k], side[k]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, ev[1 + k], 0);
-        if (e != hipSuccess) return e;
-    }
-    return cgh::launch_batch_prefix(p.hdrs, (int)p.scenes.size(), p.first_off, p.first, p.second,
-                                    p.counts, p.queues, s);
+    hipError_t e = hipMemcpyAsync(p.d_args, p.h_args.data(), p.h_args.size() * sizeof(cgh::PlanArgs),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
 }
 
 hipError_t enqueue_first(const cgh_plan& p, hipStream_t s, const int* tiles) {
@@ -126,10 +112,11 @@ hipError_t enqueue_second(const cgh_plan& p, hipStream_t s, const int* tiles) {
                                      (int)p.scenes.size(), p.counts + 1, p.queues + 1, p.grid, s);
 }
 
-// Enqueues the whole batch on `s` with the given tile shapes; records ev (if
-// given) before the first contraction, between the two, and after the second.
+// Enqueues the whole batch on `s` with the given tile shapes (the planning
+// arguments must have been uploaded for them); records ev (if given) before the
+// first contraction, between the two, and after the second.
 hipError_t enqueue(const cgh_plan& p, hipStream_t s, const int* tiles, const Events* ev) {
-    hipError_t e = enqueue_prep(p, s, tiles);
+    hipError_t e = enqueue_prep(p, s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev->a, s);
     if (e == hipSuccess) e = enqueue_first(p, s, tiles);
     if (e == hipSuccess && ev) e = hipEventRecord(ev->b, s);
@@ -208,6 +195,7 @@ hipError_t autotune(cgh_plan& p, hipStream_t s) {
     for (const auto& c : kCandidates) {
         if (e != hipSuccess) break;
         const int tiles[4] = {c[0], c[1], c[0], c[1]};
+        e = upload_args(p, tiles, s);
         double t1 = 1e30, t2 = 1e30;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // first run warms up
             e = enqueue(p, s, tiles, &ev);
@@ -298,7 +286,15 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
         const size_t second_b = align_up((size_t)n * sizeof(cgh::NtEntry));
         const size_t hdr_b = align_up((size_t)n * sizeof(cgh::PlanHeader));
         const size_t off_b = align_up((size_t)(n + 1) * sizeof(int));
-        p->bytes = off + first_b + second_b + hdr_b + off_b + align_up(4 * sizeof(int));
+        int n_luts = 0;
+        for (const auto& sc : p->scenes) n_luts += 2 * sc.s.n_layers;
+        p->n_luts = n_luts;
+        const size_t dwt_b = align_up((size_t)n * sizeof(cgh::DwtScene));
+        const size_t prep_b = align_up((size_t)n * sizeof(cgh::PrepScene));
+        const size_t luts_b = align_up((size_t)n_luts * sizeof(cgh::LutJob));
+        const size_t args_b = align_up((size_t)n * sizeof(cgh::PlanArgs));
+        p->bytes = off + first_b + second_b + hdr_b + off_b + align_up(4 * sizeof(int)) + dwt_b +
+                   prep_b + luts_b + args_b;
 
         const char* fail = std::getenv("CGH_TEST_FAIL_ALLOC");  // host-forced failure for tests
         if (fail && fail[0] == '1') {
@@ -322,6 +318,57 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
         m += off_b;
         p->counts = reinterpret_cast<int*>(m);
         p->queues = p->counts + 2;
+        m += align_up(4 * sizeof(int));
+        p->d_dwt = reinterpret_cast<cgh::DwtScene*>(m);
+        m += dwt_b;
+        p->d_prep = reinterpret_cast<cgh::PrepScene*>(m);
+        m += prep_b;
+        p->d_luts = reinterpret_cast<cgh::LutJob*>(m);
+        m += luts_b;
+        p->d_args = reinterpret_cast<cgh::PlanArgs*>(m);
+
+        // per-scene tables of the batched preparation
+        std::vector<cgh::DwtScene> h_dwt(n);
+        std::vector<cgh::LutJob> h_luts;
+        h_luts.reserve(n_luts);
+        p->h_prep.resize(n);
+        Optics op;
+        for (int i = 0; i < n; ++i) {
+            const cgh_plan::Scene& sc = p->scenes[i];
+            const cgh::Layout& lo = sc.lo;
+            char* ws = p->mem + sc.ws_off;
+            const int ny = sc.s.ny, nx = sc.s.nx, nl = sc.s.n_layers;
+            cgh::NtBuffers nb = nt_buffers(ws, lo);
+            nb.first = p->first + sc.first_off;
+            nb.second = p->second + i;
+            nb.hdr = p->hdrs + i;
+            h_dwt[i] = cgh::DwtScene{sc.s.object, sc.s.layer_index, sc.s.saliency, ny, nx, nl,
+                                     reinterpret_cast<float*>(ws + lo.coef),
+                                     reinterpret_cast<uint8_t*>(ws + lo.flags), lo.flags_layer,
+                                     lo.flags_fill,
+                                     reinterpret_cast<unsigned long long*>(ws + lo.ops)};
+            p->h_prep[i] = cgh::PrepScene{reinterpret_cast<const uint8_t*>(ws + lo.flags),
+                                          reinterpret_cast<const float*>(ws + lo.coef),
+                                          reinterpret_cast<const float*>(ws + lo.lut_x),
+                                          reinterpret_cast<const float*>(ws + lo.lut_y), ny, nx,
+                                          nl, lo.flags_layer, nb};
+            make_optics(op, nl, sc.z.data(), lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
+            for (int d = 0; d < nl; ++d) {
+                h_luts.push_back(cgh::LutJob{nx, d, levels, op.c[d], op.one_re[d], op.one_im[d],
+                                             reinterpret_cast<float*>(ws + lo.lut_x)});
+                h_luts.push_back(cgh::LutJob{ny, d, levels, op.c[d], op.pre_re[d], op.pre_im[d],
+                                             reinterpret_cast<float*>(ws + lo.lut_y)});
+            }
+            p->max_nbx = std::max(p->max_nbx, nx >> levels);
+            p->max_nby = std::max(p->max_nby, ny >> levels);
+            p->max_ndl = std::max(p->max_ndl, nl * levels);
+            p->max_len = std::max(p->max_len, cgh::lut_len(std::max(nx, ny)));
+            p->max_fill = std::max(p->max_fill, lo.flags_fill);
+            p->big_y = std::max(p->big_y, (long long)ny * cgh::pad_kt(cgh::band_side(ny, 1)));
+            p->big_x = std::max(p->big_x, (long long)nx * cgh::pad_kt(cgh::band_side(nx, 1)));
+            p->big_c = std::max(p->big_c, (long long)cgh::band_side(ny, 1) *
+                                              cgh::pad_kt(cgh::band_side(nx, 1)));
+        }
 
         hipStream_t s = (hipStream_t)stream;
         std::vector<int> fo(n + 1);
@@ -329,6 +376,15 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
         fo[n] = n_first;
         hipError_t e = hipMemcpyAsync(p->first_off, fo.data(), (n + 1) * sizeof(int),
                                       hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p->d_dwt, h_dwt.data(), n * sizeof(cgh::DwtScene),
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p->d_prep, p->h_prep.data(), n * sizeof(cgh::PrepScene),
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p->d_luts, h_luts.data(), h_luts.size() * sizeof(cgh::LutJob),
+                               hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         int dev = 0;
         hipDeviceProp_t prop;
@@ -345,29 +401,19 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
                 if (e == hipSuccess) cache_store(tune_cache_path, key, p->tiles, p->ms_first, p->ms_second);
             }
         }
-        // capture the batch on a private stream, the per-scene stages as
-        // kPrepBranches parallel branches, and instantiate it
+        // the final tile shapes, then capture the batch on a private stream
+        if (e == hipSuccess) e = upload_args(*p, p->tiles, s);
         hipStream_t cs = nullptr;
-        hipStream_t side[kPrepBranches] = {};
-        hipEvent_t fj[kPrepBranches + 1] = {};
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-        for (int k = 0; k < kPrepBranches && e == hipSuccess; ++k)
-            e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
-        for (int k = 0; k <= kPrepBranches && e == hipSuccess; ++k)
-            e = hipEventCreateWithFlags(&fj[k], hipEventDisableTiming);
         if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
         if (e == hipSuccess) {
-            hipError_t ee = enqueue_prep(*p, cs, p->tiles, side, fj, kPrepBranches);
+            hipError_t ee = enqueue_prep(*p, cs);
             if (ee == hipSuccess) ee = enqueue_first(*p, cs, p->tiles);
             if (ee == hipSuccess) ee = enqueue_second(*p, cs, p->tiles);
             e = hipStreamEndCapture(cs, &p->graph);
             if (ee != hipSuccess) e = ee;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-        for (int k = 0; k <= kPrepBranches; ++k)
-            if (fj[k]) (void)hipEventDestroy(fj[k]);
-        for (int k = 0; k < kPrepBranches; ++k)
-            if (side[k]) (void)hipStreamDestroy(side[k]);
         if (cs) (void)hipStreamDestroy(cs);
         if (e != hipSuccess) {
             const int st = hip_status(e);
@@ -393,7 +439,7 @@ int cgh_plan_execute(cgh_plan* plan, void* stream) {
     if (!profiling) return hip_status(hipGraphLaunch(plan->exec, s));
     // diagnostics: the same kernels launched eagerly, each stage timed on `s`
     const cgh_plan& p = *plan;
-    hipError_t e = timed(s, CGH_STAGE_PLAN, [&] { return enqueue_prep(p, s, p.tiles); });
+    hipError_t e = timed(s, CGH_STAGE_PLAN, [&] { return enqueue_prep(p, s); });
     if (e == hipSuccess) e = timed(s, CGH_STAGE_FIRST, [&] { return enqueue_first(p, s, p.tiles); });
     if (e == hipSuccess) e = timed(s, CGH_STAGE_SECOND, [&] { return enqueue_second(p, s, p.tiles); });
     return hip_status(e);

@@ -77,6 +77,30 @@ hipError_t launch_dwt_mask(const float* obj, const uint8_t* layer, const float* 
                            int layers, int levels, const float* thr, unsigned parts, float* coef,
                            uint8_t* flags, size_t flags_layer, unsigned long long* ops,
                            hipStream_t s);
+// One scene of a batched preparation (device-resident tables, batched plans).
+struct DwtScene {
+    const float* obj;
+    const uint8_t* layer;
+    const float* sal;
+    int ny, nx, layers;
+    float* coef;
+    uint8_t* flags;
+    size_t flags_layer;
+    size_t flags_fill;  // bytes of flags and operator counters to clear
+    unsigned long long* ops;
+};
+// One fringe table set (one axis of one layer of one scene), FP32.
+struct LutJob {
+    int n_pix, d, levels;
+    double c, pre_re, pre_im;
+    float* table;  // the scene's table region of that axis
+};
+hipError_t launch_prep_fill(const DwtScene* scenes, int n, size_t max_fill, hipStream_t s);
+hipError_t launch_dwt_mask_batch(const DwtScene* scenes, int n, int levels, const float* thr,
+                                 int max_nbx, int max_nby, hipStream_t s);
+hipError_t launch_luts_batch(const LutJob* jobs, int n_jobs, int max_len, int levels,
+                             hipStream_t s);
+
 // out (+)= sum of `split` partial holograms of ny x nx (split <= 1: nothing).
 hipError_t launch_reduce_partial(int ny, int nx, int split, const float2* partial, float2* out,
                                  int accumulate, hipStream_t s);

@@ -64,15 +64,13 @@ __device__ __forceinline__ float pooled(const Pool<B>& p, int lev, int j, int i)
 // operator per point of the level's residual map that is processed).  The
 // masks are the same for every layer, so they are counted once.
 template <int L>
-__global__ __launch_bounds__(256) void dwt_mask_kernel(
+__device__ __forceinline__ void dwt_mask_block(
     const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
     int ny, int nx, int layers, float t1, float t2, float t3, unsigned parts,
     float* __restrict__ coef, uint8_t* __restrict__ flags, size_t flags_layer,
-    unsigned long long* __restrict__ ops) {
+    unsigned long long* __restrict__ ops, int bx, int by) {
     constexpr int B = 1 << L;
     const int nbx = nx >> L;
-    const int bx = blockIdx.x * blockDim.x + threadIdx.x;
-    const int by = blockIdx.y;
     if (bx >= nbx) return;
 
     float a[B][B];
@@ -159,6 +157,27 @@ __global__ __launch_bounds__(256) void dwt_mask_kernel(
             for (int l = 0; l < L; ++l)
                 if (wave_ops[l]) atomicAdd(&ops[l], 4ull * wave_ops[l]);
     }
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void dwt_mask_kernel(
+    const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
+    int ny, int nx, int layers, float t1, float t2, float t3, unsigned parts,
+    float* __restrict__ coef, uint8_t* __restrict__ flags, size_t flags_layer,
+    unsigned long long* __restrict__ ops) {
+    dwt_mask_block<L>(obj, layer, sal, ny, nx, layers, t1, t2, t3, parts, coef, flags,
+                      flags_layer, ops, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+}
+
+// Every scene of a batch in one launch: grid.z = scene, x / y sized for the largest.
+template <int L>
+__global__ __launch_bounds__(256) void dwt_mask_batch_kernel(const DwtScene* __restrict__ scenes,
+                                                             float t1, float t2, float t3) {
+    const DwtScene sc = scenes[blockIdx.z];
+    if ((int)blockIdx.y >= (sc.ny >> L)) return;
+    dwt_mask_block<L>(sc.obj, sc.layer, sc.sal, sc.ny, sc.nx, sc.layers, t1, t2, t3, kAllParts,
+                      sc.coef, sc.flags, sc.flags_layer, sc.ops,
+                      blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
 }
 
 // Synthesis of one block from Mallat coefficients (inverse of the analysis above).
@@ -294,7 +313,33 @@ __global__ void fill_u8_kernel(uint8_t* p, size_t n) {
     for (; i < n; i += stride) p[i] = 0;
 }
 
+__global__ void prep_fill_kernel(const DwtScene* __restrict__ scenes) {
+    const DwtScene sc = scenes[blockIdx.y];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < sc.flags_fill;
+         i += (size_t)gridDim.x * blockDim.x)
+        sc.flags[i] = 0;
+}
+
 }  // namespace
+
+hipError_t launch_prep_fill(const DwtScene* scenes, int n, size_t max_fill, hipStream_t s) {
+    size_t blocks = (max_fill + 255) / 256;
+    if (blocks > 256) blocks = 256;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(prep_fill_kernel, dim3((unsigned)blocks, n), dim3(256), 0, s, scenes);
+    return hipGetLastError();
+}
+
+hipError_t launch_dwt_mask_batch(const DwtScene* scenes, int n, int levels, const float* thr,
+                                 int max_nbx, int max_nby, hipStream_t s) {
+    const dim3 grid((max_nbx + 255) / 256, max_nby, n);
+    const float t1 = thr[0], t2 = levels >= 2 ? thr[1] : 0.f, t3 = levels >= 3 ? thr[2] : 0.f;
+    if (levels == 1) hipLaunchKernelGGL(dwt_mask_batch_kernel<1>, grid, dim3(256), 0, s, scenes, t1, t2, t3);
+    else if (levels == 2) hipLaunchKernelGGL(dwt_mask_batch_kernel<2>, grid, dim3(256), 0, s, scenes, t1, t2, t3);
+    else if (levels == 3) hipLaunchKernelGGL(dwt_mask_batch_kernel<3>, grid, dim3(256), 0, s, scenes, t1, t2, t3);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_u8(uint8_t* p, size_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;

@@ -20,23 +20,18 @@ namespace cgh {
 
 namespace {
 
+// Entry idx of table (level lev(combo), band(combo)) of layer d.
 template <int P>
-__global__ __launch_bounds__(256) void lut_kernel(int n_pix, int d0, int levels, int lmin,
-                                                  LayerConsts lc, void* __restrict__ hi,
-                                                  void* __restrict__ lo) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void lut_entry(int n_pix, int d, int levels, int lmin, double c,
+                                          double pre_re, double pre_im, int idx, int combo,
+                                          void* __restrict__ hi, void* __restrict__ lo) {
     const int len = lut_len(n_pix);
-    if (idx >= len) return;
-    const int combo = blockIdx.y;
     const int lev = (lmin == 0) ? 0 : 1 + combo / 2;
     const int band = (lmin == 0) ? 0 : combo % 2;
-    const int dl = blockIdx.z;
-    const int d = d0 + dl;
     const int m = idx - n_pix;
     const int bsz = 1 << lev;
     double re = 0.0, im = 0.0;
     if (m >= -(n_pix - bsz) && m <= n_pix - 1) {
-        const double c = lc.c[dl];
         for (int u = 0; u < bsz; ++u) {
             const long long mm = (long long)(m - u);
             const double cyc_full = (double)(mm * mm) * c;
@@ -47,9 +42,8 @@ __global__ __launch_bounds__(256) void lut_kernel(int n_pix, int d0, int levels,
             re += sign * co;
             im += sign * s;
         }
-        const double pr = lc.pre_re[dl], pi = lc.pre_im[dl];
-        const double r2 = re * pr - im * pi;
-        const double i2 = re * pi + im * pr;
+        const double r2 = re * pre_re - im * pre_im;
+        const double i2 = re * pre_im + im * pre_re;
         re = r2;
         im = i2;
     }
@@ -59,7 +53,40 @@ __global__ __launch_bounds__(256) void lut_kernel(int n_pix, int d0, int levels,
     store_val<P>(hi, lo, t_im * len + idx, (float)im);
 }
 
+template <int P>
+__global__ __launch_bounds__(256) void lut_kernel(int n_pix, int d0, int levels, int lmin,
+                                                  LayerConsts lc, void* __restrict__ hi,
+                                                  void* __restrict__ lo) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= lut_len(n_pix)) return;
+    const int dl = blockIdx.z;
+    lut_entry<P>(n_pix, d0 + dl, levels, lmin, lc.c[dl], lc.pre_re[dl], lc.pre_im[dl], idx,
+                 blockIdx.y, hi, lo);
+}
+
+// Every (scene, layer, axis) table set of a batch: grid.z = job.
+__global__ __launch_bounds__(256) void lut_batch_kernel(const LutJob* __restrict__ jobs,
+                                                        int job0) {
+    const LutJob j = jobs[job0 + blockIdx.z];
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= lut_len(j.n_pix)) return;
+    lut_entry<P_FP32>(j.n_pix, j.d, j.levels, 1, j.c, j.pre_re, j.pre_im, idx, blockIdx.y,
+                      j.table, nullptr);
+}
+
 }  // namespace
+
+hipError_t launch_luts_batch(const LutJob* jobs, int n_jobs, int max_len, int levels,
+                             hipStream_t s) {
+    for (int j0 = 0; j0 < n_jobs; j0 += 65535) {
+        const int nj = n_jobs - j0 < 65535 ? n_jobs - j0 : 65535;
+        hipLaunchKernelGGL(lut_batch_kernel, dim3((max_len + 255) / 256, 2 * levels, nj),
+                           dim3(256), 0, s, jobs, j0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double* c,
                        const double* pre_re, const double* pre_im, int precision, void* hi,

@@ -153,6 +153,49 @@ struct NtOutput {
     int accumulate;
 };
 
+// Arguments of the planning kernel of one scene (device-side tables).
+struct PlanArgs {
+    int ny, nx, layers, levels, esize;
+    int tm1, tn1, tm2, tn2;  // tile shapes of the first and second contraction
+    const int* cnt_row;
+    const int* cnt_col;
+    int* seg_row;
+    int* tbeg;
+    PlanHeader* hdr;
+    NtEntry* first;
+    NtEntry* second;
+    const void* cb;
+    const void* fx;
+    const void* fy;
+    void* tc;
+    long long cb_ps, fx_ps, fy_ps, tc_ps;
+    float2* hologram;
+    float2* partial;
+    int accumulate;
+};
+
+// tiles: {rows, cols} of the first contraction's tile, then of the second's.
+PlanArgs make_plan_args(int ny, int nx, int layers, int levels, int precision, const int* tiles,
+                        const NtBuffers& b, const NtOutput& o);
+
+// One scene of a batched preparation: its flags, coefficients, tables and buffers.
+struct PrepScene {
+    const uint8_t* flags;
+    const float* coef;
+    const float* lut_x;
+    const float* lut_y;
+    int ny, nx, layers;
+    size_t flags_layer;
+    NtBuffers b;
+};
+// Batched launches over device tables of n scenes (grid sized for the largest).
+hipError_t launch_lists_batch(const PrepScene* scenes, int n, int levels, int max_ndl,
+                              hipStream_t s);
+hipError_t launch_plan_batch(const PlanArgs* args, int n, hipStream_t s);
+hipError_t launch_materialize_batch(const PrepScene* scenes, int n, int levels, int precision,
+                                    int max_ndl, long long big_y, long long big_x,
+                                    long long big_c, hipStream_t s);
+
 // tiles: {rows, cols} of the first contraction's tile, then of the second's.
 hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int levels,
                           size_t flags_layer, int precision, const int* tiles,

@@ -37,14 +37,11 @@ __device__ int block_compact(const uint8_t* __restrict__ f, int n, int* __restri
     return running;
 }
 
-__global__ __launch_bounds__(1024) void lists_kernel(const uint8_t* __restrict__ flags, int ny,
-                                                     int nx, int levels, size_t flags_layer,
-                                                     int* __restrict__ rowlist,
-                                                     int* __restrict__ collist,
-                                                     int* __restrict__ cnt_row,
-                                                     int* __restrict__ cnt_col) {
-    __shared__ int s_wave[16];
-    const int dl = blockIdx.x;
+__device__ __forceinline__ void lists_block(const uint8_t* __restrict__ flags, int ny, int nx,
+                                            int levels, size_t flags_layer,
+                                            int* __restrict__ rowlist, int* __restrict__ collist,
+                                            int* __restrict__ cnt_row, int* __restrict__ cnt_col,
+                                            int dl, int* s_wave) {
     const int d = dl / levels, l = dl % levels + 1;
     const uint8_t* fr = flags + (size_t)d * flags_layer + flag_level_off(ny, nx, l);
     const int sy = band_side(ny, l), sx = band_side(nx, l);
@@ -54,6 +51,27 @@ __global__ __launch_bounds__(1024) void lists_kernel(const uint8_t* __restrict__
         cnt_row[dl] = nr;
         cnt_col[dl] = nc;
     }
+}
+
+__global__ __launch_bounds__(1024) void lists_kernel(const uint8_t* __restrict__ flags, int ny,
+                                                     int nx, int levels, size_t flags_layer,
+                                                     int* __restrict__ rowlist,
+                                                     int* __restrict__ collist,
+                                                     int* __restrict__ cnt_row,
+                                                     int* __restrict__ cnt_col) {
+    __shared__ int s_wave[16];
+    lists_block(flags, ny, nx, levels, flags_layer, rowlist, collist, cnt_row, cnt_col,
+                blockIdx.x, s_wave);
+}
+
+// Batched: grid.y = scene, grid.x sized for the scene with the most (layer, level) pairs.
+__global__ __launch_bounds__(1024) void lists_batch_kernel(const PrepScene* __restrict__ scenes,
+                                                           int levels) {
+    __shared__ int s_wave[16];
+    const PrepScene& sc = scenes[blockIdx.y];
+    if ((int)blockIdx.x >= sc.layers * levels) return;
+    lists_block(sc.flags, sc.ny, sc.nx, levels, sc.flags_layer, sc.b.rowlist, sc.b.collist,
+                sc.b.cnt_row, sc.b.cnt_col, blockIdx.x, s_wave);
 }
 
 // Inclusive Hillis-Steele scan over the block (blockDim.x == 1024).
@@ -71,29 +89,8 @@ __device__ int block_scan_incl(int v, int* sh) {
     return r;
 }
 
-struct PlanArgs {
-    int ny, nx, layers, levels, esize;
-    int tm1, tn1, tm2, tn2;  // tile shapes of the first and second contraction
-    const int* cnt_row;
-    const int* cnt_col;
-    int* seg_row;
-    int* tbeg;
-    PlanHeader* hdr;
-    NtEntry* first;
-    NtEntry* second;
-    const void* cb;
-    const void* fx;
-    const void* fy;
-    void* tc;
-    long long cb_ps, fx_ps, fy_ps, tc_ps;
-    float2* hologram;
-    float2* partial;
-    int accumulate;
-};
 
-__global__ __launch_bounds__(1024) void plan_kernel(PlanArgs a) {
-    __shared__ int sh[1024];
-    __shared__ int last[3];
+__device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last) {
     const int n_dl = a.layers * a.levels;
     const int tn1 = (a.nx + a.tn1 - 1) / a.tn1;
     int total_k = 0, total_t = 0, total_r = 0;
@@ -180,6 +177,20 @@ __global__ __launch_bounds__(1024) void plan_kernel(PlanArgs a) {
     }
 }
 
+__global__ __launch_bounds__(1024) void plan_kernel(PlanArgs a) {
+    __shared__ int sh[1024];
+    __shared__ int last[3];
+    plan_block(a, sh, last);
+}
+
+// Batched: one workgroup per scene.
+__global__ __launch_bounds__(1024) void plan_batch_kernel(const PlanArgs* __restrict__ args) {
+    __shared__ int sh[1024];
+    __shared__ int last[3];
+    const PlanArgs a = args[blockIdx.x];
+    plan_block(a, sh, last);
+}
+
 // Merges the per-scene problem tables of a batch: scene i's first-contraction
 // entries (first_off[i] .. first_off[i+1]) and its second-contraction entry get
 // the tile offset of every scene before it; writes the batch tile totals and
@@ -223,13 +234,11 @@ __global__ __launch_bounds__(1024) void batch_prefix_kernel(const PlanHeader* __
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void fy_kernel(const float* __restrict__ lut_y,
-                                                 const int* __restrict__ rowlist,
-                                                 const int* __restrict__ cnt_row,
-                                                 const int* __restrict__ seg_row,
-                                                 const PlanHeader* __restrict__ hdr, int ny,
-                                                 int levels, void* fy, size_t ps) {
-    const int dl = blockIdx.y;
+__device__ __forceinline__ void fy_block(const float* __restrict__ lut_y,
+                                         const int* __restrict__ rowlist,
+                                         const int* __restrict__ cnt_row,
+                                         const int* __restrict__ seg_row, int ny, int levels,
+                                         void* fy, size_t ps, int dl) {
     const int d = dl / levels, l = dl % levels + 1;
     const int cr = cnt_row[dl], pr = pad_kt(cr);
     if (pr == 0) return;
@@ -265,12 +274,11 @@ __global__ __launch_bounds__(256) void fy_kernel(const float* __restrict__ lut_y
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void fx_kernel(const float* __restrict__ lut_x,
-                                                 const int* __restrict__ collist,
-                                                 const int* __restrict__ cnt_row,
-                                                 const int* __restrict__ cnt_col, int nx,
-                                                 int levels, void* fx, size_t ps) {
-    const int dl = blockIdx.y;
+__device__ __forceinline__ void fx_block(const float* __restrict__ lut_x,
+                                         const int* __restrict__ collist,
+                                         const int* __restrict__ cnt_row,
+                                         const int* __restrict__ cnt_col, int nx, int levels,
+                                         void* fx, size_t ps, int dl) {
     const int d = dl / levels, l = dl % levels + 1;
     const int cc = cnt_col[dl], pc = pad_kt(cc);
     if (pc == 0 || cnt_row[dl] == 0) return;
@@ -304,13 +312,12 @@ __global__ __launch_bounds__(256) void fx_kernel(const float* __restrict__ lut_x
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void cb_kernel(const float* __restrict__ coef,
-                                                 const int* __restrict__ rowlist,
-                                                 const int* __restrict__ collist,
-                                                 const int* __restrict__ cnt_row,
-                                                 const int* __restrict__ cnt_col, int ny, int nx,
-                                                 int levels, void* cb, size_t ps) {
-    const int dl = blockIdx.y;
+__device__ __forceinline__ void cb_block(const float* __restrict__ coef,
+                                         const int* __restrict__ rowlist,
+                                         const int* __restrict__ collist,
+                                         const int* __restrict__ cnt_row,
+                                         const int* __restrict__ cnt_col, int ny, int nx,
+                                         int levels, void* cb, size_t ps, int dl) {
     const int d = dl / levels, l = dl % levels + 1;
     const int cr = cnt_row[dl], cc = cnt_col[dl], pc = pad_kt(cc);
     if (cr == 0 || pc == 0) return;
@@ -341,6 +348,63 @@ __global__ __launch_bounds__(256) void cb_kernel(const float* __restrict__ coef,
     }
 }
 
+template <int P>
+__global__ __launch_bounds__(256) void fy_kernel(const float* __restrict__ lut_y,
+                                                 const int* __restrict__ rowlist,
+                                                 const int* __restrict__ cnt_row,
+                                                 const int* __restrict__ seg_row, int ny,
+                                                 int levels, void* fy, size_t ps) {
+    fy_block<P>(lut_y, rowlist, cnt_row, seg_row, ny, levels, fy, ps, blockIdx.y);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void fx_kernel(const float* __restrict__ lut_x,
+                                                 const int* __restrict__ collist,
+                                                 const int* __restrict__ cnt_row,
+                                                 const int* __restrict__ cnt_col, int nx,
+                                                 int levels, void* fx, size_t ps) {
+    fx_block<P>(lut_x, collist, cnt_row, cnt_col, nx, levels, fx, ps, blockIdx.y);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void cb_kernel(const float* __restrict__ coef,
+                                                 const int* __restrict__ rowlist,
+                                                 const int* __restrict__ collist,
+                                                 const int* __restrict__ cnt_row,
+                                                 const int* __restrict__ cnt_col, int ny, int nx,
+                                                 int levels, void* cb, size_t ps) {
+    cb_block<P>(coef, rowlist, collist, cnt_row, cnt_col, ny, nx, levels, cb, ps, blockIdx.y);
+}
+
+// Batched panels: grid.z = scene, grid.y = (layer, level), grid.x = chunks; the
+// three panels of a scene are gathered by one launch each over every scene.
+template <int P>
+__global__ __launch_bounds__(256) void fy_batch_kernel(const PrepScene* __restrict__ scenes,
+                                                       int levels) {
+    const PrepScene& sc = scenes[blockIdx.z];
+    if ((int)blockIdx.y >= sc.layers * levels) return;
+    fy_block<P>(sc.lut_y, sc.b.rowlist, sc.b.cnt_row, sc.b.seg_row, sc.ny, levels, sc.b.fy,
+                sc.b.fy_ps, blockIdx.y);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void fx_batch_kernel(const PrepScene* __restrict__ scenes,
+                                                       int levels) {
+    const PrepScene& sc = scenes[blockIdx.z];
+    if ((int)blockIdx.y >= sc.layers * levels) return;
+    fx_block<P>(sc.lut_x, sc.b.collist, sc.b.cnt_row, sc.b.cnt_col, sc.nx, levels, sc.b.fx,
+                sc.b.fx_ps, blockIdx.y);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void cb_batch_kernel(const PrepScene* __restrict__ scenes,
+                                                       int levels) {
+    const PrepScene& sc = scenes[blockIdx.z];
+    if ((int)blockIdx.y >= sc.layers * levels) return;
+    cb_block<P>(sc.coef, sc.b.rowlist, sc.b.collist, sc.b.cnt_row, sc.b.cnt_col, sc.ny, sc.nx,
+                levels, sc.b.cb, sc.b.cb_ps, blockIdx.y);
+}
+
 int grid_for(long long elems) {
     long long g = (elems + 256 * 8 - 1) / (256 * 8);
     if (g < 1) g = 1;
@@ -350,14 +414,8 @@ int grid_for(long long elems) {
 
 }  // namespace
 
-hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int levels,
-                          size_t flags_layer, int precision, const int* tiles,
-                          const NtBuffers& b, const NtOutput& o, hipStream_t s) {
-    const int n_dl = layers * levels;
-    hipLaunchKernelGGL(lists_kernel, dim3(n_dl), dim3(1024), 0, s, flags, ny, nx, levels,
-                       flags_layer, b.rowlist, b.collist, b.cnt_row, b.cnt_col);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+PlanArgs make_plan_args(int ny, int nx, int layers, int levels, int precision, const int* tiles,
+                        const NtBuffers& b, const NtOutput& o) {
     PlanArgs a{};
     a.ny = ny;
     a.nx = nx;
@@ -386,6 +444,18 @@ hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int 
     a.hologram = o.hologram;
     a.partial = o.partial;
     a.accumulate = o.accumulate;
+    return a;
+}
+
+hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int levels,
+                          size_t flags_layer, int precision, const int* tiles,
+                          const NtBuffers& b, const NtOutput& o, hipStream_t s) {
+    const int n_dl = layers * levels;
+    hipLaunchKernelGGL(lists_kernel, dim3(n_dl), dim3(1024), 0, s, flags, ny, nx, levels,
+                       flags_layer, b.rowlist, b.collist, b.cnt_row, b.cnt_col);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const PlanArgs a = make_plan_args(ny, nx, layers, levels, precision, tiles, b, o);
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
@@ -398,7 +468,7 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
     const long long big_x = (long long)nx * pad_kt(band_side(nx, 1));
     const long long big_c = (long long)band_side(ny, 1) * pad_kt(band_side(nx, 1));
     hipLaunchKernelGGL(fy_kernel<P>, dim3(grid_for(big_y), n_dl), dim3(256), 0, s, lut_y,
-                       b.rowlist, b.cnt_row, b.seg_row, b.hdr, ny, levels, b.fy, b.fy_ps);
+                       b.rowlist, b.cnt_row, b.seg_row, ny, levels, b.fy, b.fy_ps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fx_kernel<P>, dim3(grid_for(big_x), n_dl), dim3(256), 0, s, lut_x,
@@ -406,6 +476,37 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(cb_kernel<P>, dim3(grid_for(big_c), n_dl), dim3(256), 0, s, coef,
                        b.rowlist, b.collist, b.cnt_row, b.cnt_col, ny, nx, levels, b.cb, b.cb_ps);
+    return hipGetLastError();
+}
+
+template <int P>
+static void materialize_batch(const PrepScene* scenes, int n, int levels, int max_ndl,
+                              long long big_y, long long big_x, long long big_c, hipStream_t s) {
+    hipLaunchKernelGGL(fy_batch_kernel<P>, dim3(grid_for(big_y), max_ndl, n), dim3(256), 0, s,
+                       scenes, levels);
+    hipLaunchKernelGGL(fx_batch_kernel<P>, dim3(grid_for(big_x), max_ndl, n), dim3(256), 0, s,
+                       scenes, levels);
+    hipLaunchKernelGGL(cb_batch_kernel<P>, dim3(grid_for(big_c), max_ndl, n), dim3(256), 0, s,
+                       scenes, levels);
+}
+
+hipError_t launch_lists_batch(const PrepScene* scenes, int n, int levels, int max_ndl,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(lists_batch_kernel, dim3(max_ndl, n), dim3(1024), 0, s, scenes, levels);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_batch(const PlanArgs* args, int n, hipStream_t s) {
+    hipLaunchKernelGGL(plan_batch_kernel, dim3(n), dim3(1024), 0, s, args);
+    return hipGetLastError();
+}
+
+hipError_t launch_materialize_batch(const PrepScene* scenes, int n, int levels, int precision,
+                                    int max_ndl, long long big_y, long long big_x,
+                                    long long big_c, hipStream_t s) {
+    if (precision == P_BF16) materialize_batch<P_BF16>(scenes, n, levels, max_ndl, big_y, big_x, big_c, s);
+    else if (precision == P_FP16) materialize_batch<P_FP16>(scenes, n, levels, max_ndl, big_y, big_x, big_c, s);
+    else materialize_batch<P_FP32>(scenes, n, levels, max_ndl, big_y, big_x, big_c, s);
     return hipGetLastError();
 }
 
