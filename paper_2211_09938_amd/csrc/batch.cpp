@@ -56,7 +56,6 @@ struct cgh_plan {
     std::vector<cgh::PlanArgs> h_args;
     int n_luts = 0, max_nbx = 0, max_nby = 0, max_ndl = 0, max_len = 0;
     size_t max_fill = 0;
-    long long big_y = 0, big_x = 0, big_c = 0;
 };
 
 namespace {
@@ -80,8 +79,7 @@ hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s) {
     if (e == hipSuccess) e = cgh::launch_lists_batch(p.d_prep, n, p.levels, p.max_ndl, s);
     if (e == hipSuccess) e = cgh::launch_plan_batch(p.d_args, n, s);
     if (e == hipSuccess)
-        e = cgh::launch_materialize_batch(p.d_prep, n, p.levels, p.precision, p.max_ndl, p.big_y,
-                                          p.big_x, p.big_c, s);
+        e = cgh::launch_materialize_batch(p.d_prep, n, p.levels, p.precision, p.max_ndl, s);
     if (e != hipSuccess) return e;
     return cgh::launch_batch_prefix(p.hdrs, n, p.first_off, p.first, p.second, p.counts,
                                     p.queues, s);
@@ -364,10 +362,6 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
             p->max_ndl = std::max(p->max_ndl, nl * levels);
             p->max_len = std::max(p->max_len, cgh::lut_len(std::max(nx, ny)));
             p->max_fill = std::max(p->max_fill, lo.flags_fill);
-            p->big_y = std::max(p->big_y, (long long)ny * cgh::pad_kt(cgh::band_side(ny, 1)));
-            p->big_x = std::max(p->big_x, (long long)nx * cgh::pad_kt(cgh::band_side(nx, 1)));
-            p->big_c = std::max(p->big_c, (long long)cgh::band_side(ny, 1) *
-                                              cgh::pad_kt(cgh::band_side(nx, 1)));
         }
 
         hipStream_t s = (hipStream_t)stream;

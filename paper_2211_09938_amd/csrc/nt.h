@@ -193,8 +193,7 @@ hipError_t launch_lists_batch(const PrepScene* scenes, int n, int levels, int ma
                               hipStream_t s);
 hipError_t launch_plan_batch(const PlanArgs* args, int n, hipStream_t s);
 hipError_t launch_materialize_batch(const PrepScene* scenes, int n, int levels, int precision,
-                                    int max_ndl, long long big_y, long long big_x,
-                                    long long big_c, hipStream_t s);
+                                    int max_ndl, hipStream_t s);
 
 // tiles: {rows, cols} of the first contraction's tile, then of the second's.
 hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int levels,

@@ -479,15 +479,18 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
     return hipGetLastError();
 }
 
+// Workgroups per (scene, layer, level) of the batched panel kernels: the scenes
+// already give the launch its parallelism (a grid sized for the largest scene
+// left most workgroups idle: measured 30% slower preparation on the 64-scene batch).
+constexpr int kBatchPanelBlocks = 64;
+
 template <int P>
 static void materialize_batch(const PrepScene* scenes, int n, int levels, int max_ndl,
-                              long long big_y, long long big_x, long long big_c, hipStream_t s) {
-    hipLaunchKernelGGL(fy_batch_kernel<P>, dim3(grid_for(big_y), max_ndl, n), dim3(256), 0, s,
-                       scenes, levels);
-    hipLaunchKernelGGL(fx_batch_kernel<P>, dim3(grid_for(big_x), max_ndl, n), dim3(256), 0, s,
-                       scenes, levels);
-    hipLaunchKernelGGL(cb_batch_kernel<P>, dim3(grid_for(big_c), max_ndl, n), dim3(256), 0, s,
-                       scenes, levels);
+                              hipStream_t s) {
+    const dim3 grid(kBatchPanelBlocks, max_ndl, n);
+    hipLaunchKernelGGL(fy_batch_kernel<P>, grid, dim3(256), 0, s, scenes, levels);
+    hipLaunchKernelGGL(fx_batch_kernel<P>, grid, dim3(256), 0, s, scenes, levels);
+    hipLaunchKernelGGL(cb_batch_kernel<P>, grid, dim3(256), 0, s, scenes, levels);
 }
 
 hipError_t launch_lists_batch(const PrepScene* scenes, int n, int levels, int max_ndl,
@@ -502,11 +505,10 @@ hipError_t launch_plan_batch(const PlanArgs* args, int n, hipStream_t s) {
 }
 
 hipError_t launch_materialize_batch(const PrepScene* scenes, int n, int levels, int precision,
-                                    int max_ndl, long long big_y, long long big_x,
-                                    long long big_c, hipStream_t s) {
-    if (precision == P_BF16) materialize_batch<P_BF16>(scenes, n, levels, max_ndl, big_y, big_x, big_c, s);
-    else if (precision == P_FP16) materialize_batch<P_FP16>(scenes, n, levels, max_ndl, big_y, big_x, big_c, s);
-    else materialize_batch<P_FP32>(scenes, n, levels, max_ndl, big_y, big_x, big_c, s);
+                                    int max_ndl, hipStream_t s) {
+    if (precision == P_BF16) materialize_batch<P_BF16>(scenes, n, levels, max_ndl, s);
+    else if (precision == P_FP16) materialize_batch<P_FP16>(scenes, n, levels, max_ndl, s);
+    else materialize_batch<P_FP32>(scenes, n, levels, max_ndl, s);
     return hipGetLastError();
 }
 
