@@ -72,33 +72,67 @@ __device__ __forceinline__ void dwt_mask_block(
     constexpr int B = 1 << L;
     const int nbx = nx >> L;
     if (bx >= nbx) return;
+    // lowest active lane: writes the row flags once per wave (all lanes share by)
+    const bool leader = (int)__lane_id() == __ffsll((long long)__ballot(1)) - 1;
 
     float a[B][B];
     uint8_t li[B][B];
+    // rows of B >= 4 floats start on 16-byte boundaries (nx is a multiple of B):
+    // vector loads when the base pointers allow them
+    const bool vec = B >= 4 && ((reinterpret_cast<uintptr_t>(obj) & 15) == 0) &&
+                     (!layer || (reinterpret_cast<uintptr_t>(layer) & (B - 1)) == 0);
 #pragma unroll
-    for (int r = 0; r < B; ++r)
+    for (int r = 0; r < B; ++r) {
+        const size_t g = (size_t)(by * B + r) * nx + (size_t)bx * B;
+        if (vec) {
+            if constexpr (B >= 4) {
 #pragma unroll
-        for (int c = 0; c < B; ++c) {
-            const size_t g = (size_t)(by * B + r) * nx + bx * B + c;
-            a[r][c] = obj[g];
-            li[r][c] = layer ? layer[g] : 0;
+                for (int c = 0; c < B; c += 4) {
+                    const float4 v = *reinterpret_cast<const float4*>(obj + g + c);
+                    a[r][c] = v.x;
+                    a[r][c + 1] = v.y;
+                    a[r][c + 2] = v.z;
+                    a[r][c + 3] = v.w;
+                }
+                if (layer) {
+                    if constexpr (B == 8) {
+                        const uint2 u = *reinterpret_cast<const uint2*>(layer + g);
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            li[r][c] = (u.x >> (8 * c)) & 0xffu;
+                            li[r][c + 4] = (u.y >> (8 * c)) & 0xffu;
+                        }
+                    } else {
+                        const unsigned u = *reinterpret_cast<const unsigned*>(layer + g);
+#pragma unroll
+                        for (int c = 0; c < B; ++c) li[r][c] = (u >> (8 * c)) & 0xffu;
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < B; ++c) li[r][c] = 0;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+                a[r][c] = obj[g + c];
+                li[r][c] = layer ? layer[g + c] : 0;
+            }
         }
+    }
     Pool<B> pool;
     if (sal) pool_saliency<L>(sal, nx, by, bx, pool);
+    const bool vst = (reinterpret_cast<uintptr_t>(coef) & 15) == 0;  // vector stores
     const float thr[3] = {t1, t2, t3};
     const size_t plane = (size_t)ny * nx;
     unsigned long long wave_ops[3] = {0ull, 0ull, 0ull};  // same value in every lane
 
     for (int d = 0; d < layers; ++d) {
         float cur[B][B];
-        bool any = false;
 #pragma unroll
         for (int r = 0; r < B; ++r)
 #pragma unroll
-            for (int c = 0; c < B; ++c) {
-                cur[r][c] = (li[r][c] == d) ? a[r][c] : 0.0f;
-                any |= (li[r][c] == d);
-            }
+            for (int c = 0; c < B; ++c) cur[r][c] = (li[r][c] == d) ? a[r][c] : 0.0f;
         const size_t base = (size_t)d * plane;
         uint8_t* fl = flags ? flags + (size_t)d * flags_layer : nullptr;
 #pragma unroll
@@ -115,8 +149,13 @@ __device__ __forceinline__ void dwt_mask_block(
                     lo[r][i] = (cur[r][2 * i] + cur[r][2 * i + 1]) * 0.5f;
                     hi[r][i] = (cur[r][2 * i] - cur[r][2 * i + 1]) * 0.5f;
                 }
+            bool col_lo[B / 2], col_hi[B / 2];  // column flags of this thread's h columns
 #pragma unroll
-            for (int j = 0; j < h; ++j)
+            for (int i = 0; i < h; ++i) col_lo[i] = col_hi[i] = false;
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                float v[B / 2], hv[B / 2], dv[B / 2];
+                bool row_top = false, row_bot = false;
 #pragma unroll
                 for (int i = 0; i < h; ++i) {
                     const float ll = (lo[2 * j][i] + lo[2 * j + 1][i]) * 0.5f;
@@ -126,34 +165,69 @@ __device__ __forceinline__ void dwt_mask_block(
                     const bool salient = !sal || pooled<B>(pool, lev, j, i) > thr[lev - 1];
                     if (ops && d == 0) wave_ops[lev - 1] += __popcll(__ballot(salient));
                     const bool keep = ((parts >> (lev - 1)) & 1u) && salient;
-                    const float v = keep ? vv : 0.0f;
-                    const float hv = keep ? hh : 0.0f;
-                    const float dv = keep ? dd : 0.0f;
-                    const int gy = by * h + j, gx = bx * h + i;
-                    coef[base + (size_t)gy * nx + nxl + gx] = v;
-                    coef[base + (size_t)(nyl + gy) * nx + gx] = hv;
-                    coef[base + (size_t)(nyl + gy) * nx + nxl + gx] = dv;
-                    if (frow) {
-                        if (v != 0.0f) { frow[gy] = 1; fcol[nxl + gx] = 1; }
-                        if (hv != 0.0f) { frow[nyl + gy] = 1; fcol[gx] = 1; }
-                        if (dv != 0.0f) { frow[nyl + gy] = 1; fcol[nxl + gx] = 1; }
-                    }
+                    v[i] = keep ? vv : 0.0f;
+                    hv[i] = keep ? hh : 0.0f;
+                    dv[i] = keep ? dd : 0.0f;
+                    row_top |= v[i] != 0.0f;
+                    row_bot |= (hv[i] != 0.0f) || (dv[i] != 0.0f);
+                    col_hi[i] |= (v[i] != 0.0f) || (dv[i] != 0.0f);
+                    col_lo[i] |= hv[i] != 0.0f;
                     cur[j][i] = ll;
                 }
+                const int gy = by * h + j, gx0 = bx * h;
+                float* pv = coef + base + (size_t)gy * nx + nxl + gx0;
+                float* ph = coef + base + (size_t)(nyl + gy) * nx + gx0;
+                float* pd = coef + base + (size_t)(nyl + gy) * nx + nxl + gx0;
+                // h consecutive floats on an h*4-byte boundary (nx is a multiple of 2^L)
+                if constexpr (B / 2 >= 4) {
+                    if (h == 4 && vst) {
+                        *reinterpret_cast<float4*>(pv) = make_float4(v[0], v[1], v[2], v[3]);
+                        *reinterpret_cast<float4*>(ph) = make_float4(hv[0], hv[1], hv[2], hv[3]);
+                        *reinterpret_cast<float4*>(pd) = make_float4(dv[0], dv[1], dv[2], dv[3]);
+                    }
+                }
+                if constexpr (B / 2 >= 2) {
+                    if (h == 2 && vst) {
+                        *reinterpret_cast<float2*>(pv) = make_float2(v[0], v[1]);
+                        *reinterpret_cast<float2*>(ph) = make_float2(hv[0], hv[1]);
+                        *reinterpret_cast<float2*>(pd) = make_float2(dv[0], dv[1]);
+                    }
+                }
+                if (h == 1 || !vst) {
+#pragma unroll
+                    for (int i = 0; i < h; ++i) {
+                        pv[i] = v[i];
+                        ph[i] = hv[i];
+                        pd[i] = dv[i];
+                    }
+                }
+                if (frow) {
+                    const bool any_top = __ballot(row_top) != 0ull;
+                    const bool any_bot = __ballot(row_bot) != 0ull;
+                    if (leader && any_top) frow[gy] = 1;
+                    if (leader && any_bot) frow[nyl + gy] = 1;
+                }
+            }
+            if (fcol) {
+#pragma unroll
+                for (int i = 0; i < h; ++i) {
+                    if (col_lo[i]) fcol[bx * h + i] = 1;
+                    if (col_hi[i]) fcol[nxl + bx * h + i] = 1;
+                }
+            }
         }
         const float av = ((parts >> L) & 1u) ? cur[0][0] : 0.0f;
         coef[base + (size_t)by * nx + bx] = av;
-        if (fl && av != 0.0f) {
+        if (fl) {
             uint8_t* frow = fl + flag_level_off(ny, nx, L);
-            frow[by] = 1;
-            frow[band_side(ny, L) + bx] = 1;
+            const bool any_av = __ballot(av != 0.0f) != 0ull;  // every lane takes part
+            if (leader && any_av) frow[by] = 1;
+            if (av != 0.0f) frow[band_side(ny, L) + bx] = 1;
         }
-        (void)any;
     }
     if (ops) {
         // the lowest active lane of the wave publishes the wave's counts
-        const unsigned long long active = __ballot(1);
-        if ((int)__lane_id() == __ffsll((long long)active) - 1)
+        if (leader)
             for (int l = 0; l < L; ++l)
                 if (wave_ops[l]) atomicAdd(&ops[l], 4ull * wave_ops[l]);
     }
