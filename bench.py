@@ -383,6 +383,17 @@ def run_single(scene, prec, steps, warmup, workload):
     stats = cgh.workspace_stats(ws, ny, nx, n_layers, scene.levels, prec)
     sec_ms, sec_n = prof["second"]
     kernel = f"second contraction (nt_direct_kernel<{prec}, complex A, 128x128>)"
+    # the HBM-bound coefficient stage: flag clear + fused layer split / Haar / masks;
+    # algorithmic bytes = object 4 B + layer id 1 B + saliency 4 B read per pixel,
+    # 4 B written per pixel and layer
+    coef_ms = prof["coef"][0] / max(1, prof["coef"][1])
+    px = float(ny * nx)
+    coef_bytes = px * (4 + (1 if lay is not None else 0) + (4 if sal is not None else 0)) \
+        + px * 4 * n_layers
+    hbm = {"kernel": "dwt_mask_kernel (coefficient stage)", "bound": "hbm",
+           "achieved": coef_bytes / (coef_ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+           "bytes_per_launch": coef_bytes, "avg_launch_ms": coef_ms}
+    hbm["frac"] = hbm["achieved"] / hbm["peak"]
     return {
         "value": steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
@@ -390,6 +401,7 @@ def run_single(scene, prec, steps, warmup, workload):
         "work": stats,
         "roofline": roofline(stats, prec, sec_ms / max(1, sec_n), kernel,
                              measured_traffic(workload, prec)),
+        "hbm_roofline": hbm,
         "_out": out.cpu().numpy(),
     }
 
@@ -599,6 +611,7 @@ def main():
         "gpoint_pixel_per_s": head["value"] * points_pixels / 1e9,
         "roofline": head["roofline"],
         "stages_ms_per_step": head["stages_ms_per_step"],
+        "hbm_roofline": head.get("hbm_roofline"),
         "work": head["work"],
     }
     if "rel_l2_vs_oracle" in head:
