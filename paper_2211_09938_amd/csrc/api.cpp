@@ -41,6 +41,8 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
     const float* lut_x = reinterpret_cast<const float*>(ws + lo.lut_x);
     const float* lut_y = reinterpret_cast<const float*>(ws + lo.lut_y);
     float2* partial = reinterpret_cast<float2*>(ws + lo.partial);
+    const int tn2 = cgh::nt_second_tile_n(precision);
+    const int split = second_split(lo, ny, nx, levels, n_layers, precision);
 
     hipError_t e = timed(s, CGH_STAGE_COEF, [&] {
         hipError_t r = cgh::launch_fill_u8(fl, lo.flags_fill, s);
@@ -61,8 +63,8 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_PLAN, [&] {
             const int tiles[4] = {cgh::nt_first_tile_m(precision), cgh::kNtTile, cgh::kNtTile,
-                                  cgh::kNtTile};
-            const cgh::NtOutput o{out, lo.split_k > 1 ? partial : nullptr, acc};
+                                  tn2};
+            const cgh::NtOutput o{out, split > 1 ? partial : nullptr, acc};
             hipError_t r = cgh::launch_nt_plan(fl, ny, nx, n_layers, levels, lo.flags_layer,
                                                precision, tiles, nb, o, s);
             if (r != hipSuccess) return r;
@@ -75,10 +77,10 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_SECOND,
-                  [&] { return cgh::launch_nt_second(ny, nx, precision, lo.split_k, nb, s); });
-    if (e == hipSuccess && lo.split_k > 1)
+                  [&] { return cgh::launch_nt_second(ny, nx, precision, split, nb, s); });
+    if (e == hipSuccess && split > 1)
         e = timed(s, CGH_STAGE_REDUCE,
-                  [&] { return cgh::launch_reduce_partial(ny, nx, lo.split_k, partial, out, acc, s); });
+                  [&] { return cgh::launch_reduce_partial(ny, nx, split, partial, out, acc, s); });
     return e;
 }
 
@@ -434,7 +436,7 @@ int cgh_workspace_stats(const void* workspace, int ny, int nx, int n_layers, int
         stats->k_padded = hdr.kpad;
         stats->k_total = total;
         stats->k_tile = cgh::kKT;
-        stats->split_k = lo.split_k;
+        stats->split_k = second_split(lo, ny, nx, levels, n_layers, precision);
         stats->flops_first = 4.0 * (double)nx * rc;
         stats->flops_second = 8.0 * (double)ny * (double)nx * (double)hdr.rows_active;
         stats->flops_second_issued = 8.0 * (double)ny * (double)nx * (double)hdr.kpad;

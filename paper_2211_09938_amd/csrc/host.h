@@ -36,8 +36,9 @@ inline int check_precision(int precision) {
     return CGH_SUCCESS;
 }
 
-inline int choose_split(int ny, int nx, int levels, int layers) {
-    const int tiles = ((ny + cgh::kNtTile - 1) / cgh::kNtTile) * ((nx + cgh::kNtTile - 1) / cgh::kNtTile);
+inline int choose_split(int ny, int nx, int levels, int layers, int tm = cgh::kNtTile,
+                        int tn = cgh::kNtTile) {
+    const int tiles = ((ny + tm - 1) / tm) * ((nx + tn - 1) / tn);
     const int target = 512;  // two resident workgroups on each of 256 CUs
     int split = (target + tiles - 1) / tiles;
     // keep at least four K tiles per split of the dense K range
@@ -111,6 +112,16 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
     lo.partial = take(lo.split_k > 1 ? (size_t)lo.split_k * plane * 8 : 0);
     lo.total = off;
     return lo;
+}
+
+// Split of the single-scene second contraction: about 512 workgroups with the
+// precision's tile shape, at most the layout's split (128 x 128 tiles), which
+// sized the partial buffer.
+inline int second_split(const cgh::Layout& lo, int ny, int nx, int levels, int layers,
+                        int precision) {
+    const int split = choose_split(ny, nx, levels, layers, cgh::kNtTile,
+                                   cgh::nt_second_tile_n(precision));
+    return split < lo.split_k ? split : lo.split_k;
 }
 
 inline cgh::NtBuffers nt_buffers(char* ws, const cgh::Layout& lo) {

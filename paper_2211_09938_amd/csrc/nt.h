@@ -202,11 +202,13 @@ hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int 
 hipError_t launch_nt_materialize(const float* coef, const float* lut_x, const float* lut_y, int ny,
                                  int nx, int layers, int levels, int precision,
                                  const NtBuffers& b, hipStream_t s);
-// Direct launches over one scene's table (tile 128 x 128; split-K for the second).
+// Direct launches over one scene's table (split-K for the second).
 // Row tile of the single-scene first contraction: 64 for FP32 (measured 10%
 // faster there: the active row counts of a level are often far below 128), 128
-// for the split forms.
+// for the split forms.  Column tile of the second: 64 for FP32 (128 x 64 tiles
+// take the three-product complex form), 128 for the split forms.
 int nt_first_tile_m(int precision);
+int nt_second_tile_n(int precision);
 hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffers& b,
                            int max_tiles, hipStream_t s);
 hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBuffers& b,

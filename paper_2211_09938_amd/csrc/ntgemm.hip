@@ -208,13 +208,24 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
     const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TN / 2);
     const int l32 = lane & 31, g = lane >> 5;
 
-    floatx16 cr[BI][BJ], ci[BI][BJ];
+    // FP32 complex x complex: three real products per complex product (Gauss):
+    // X = Ar Br, Y = Ai Bi, Z = (Ar + Ai)(Br + Bi); re = X - Y, im = Z - X - Y.
+    // cr, ci, cz hold X, Y, Z there; cr, ci hold re, im otherwise.
+    // (64 x 32 wave tiles and smaller: the third accumulator set of a 64 x 64
+    // wave tile does not fit in the registers of two workgroups per CU)
+    constexpr bool G3 = P == P_FP32 && A_CPLX && Epi::kImag && BI * BJ <= 2;
+    constexpr int BZ = G3 ? BJ : 1;
+    floatx16 cr[BI][BJ], ci[BI][BJ], cz[BI][BZ];
 #pragma unroll
     for (int i = 0; i < BI; ++i)
 #pragma unroll
         for (int j = 0; j < BJ; ++j)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) { cr[i][j][r] = 0.f; ci[i][j][r] = 0.f; }
+            for (int r = 0; r < 16; ++r) {
+                cr[i][j][r] = 0.f;
+                ci[i][j][r] = 0.f;
+                if constexpr (G3) cz[i][j][r] = 0.f;
+            }
 
     // chunk q of an operand tile -> (plane, row, 16-byte chunk c of the row):
     // 8 consecutive threads take 8 consecutive rows at one chunk (with the
@@ -296,6 +307,24 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
                     for (int c = 0; c < NPB; ++c)
                         fb[j][c] = *reinterpret_cast<const floatx4*>(
                             Bs + c * BPLANE + (wn + 32 * j + l32) * F::PITCH + (8 * h + 4 * g) * 4);
+                if constexpr (G3) {
+                    floatx4 sa[BI], sb[BJ];
+#pragma unroll
+                    for (int i = 0; i < BI; ++i) sa[i] = fa[i][0] + fa[i][1];
+#pragma unroll
+                    for (int j = 0; j < BJ; ++j) sb[j] = fb[j][0] + fb[j][1];
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                        for (int i = 0; i < BI; ++i)
+#pragma unroll
+                            for (int j = 0; j < BJ; ++j) {
+                                cr[i][j] = mfma32(fa[i][0][tt], fb[j][0][tt], cr[i][j]);
+                                ci[i][j] = mfma32(fa[i][1][tt], fb[j][1][tt], ci[i][j]);
+                                cz[i][j] = mfma32(sa[i][tt], sb[j][tt], cz[i][j]);
+                            }
+                    continue;
+                }
 #pragma unroll
                 for (int tt = 0; tt < 4; ++tt) {
 #pragma unroll
@@ -371,8 +400,14 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
                 float re[4], im[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    re[q] = cr[i][j][4 * qd + q];
-                    im[q] = ci[i][j][4 * qd + q];
+                    if constexpr (G3) {
+                        const float x = cr[i][j][4 * qd + q], y = ci[i][j][4 * qd + q];
+                        re[q] = x - y;
+                        im[q] = cz[i][j][4 * qd + q] - x - y;
+                    } else {
+                        re[q] = cr[i][j][4 * qd + q];
+                        im[q] = ci[i][j][4 * qd + q];
+                    }
                 }
                 Epi::store4(e, s, split, m0 + wm + 32 * i + 8 * qd + 4 * g,
                             n0 + wn + 32 * j + l32, re, im);
@@ -473,10 +508,10 @@ hipError_t first_direct(int layers, int levels, const NtBuffers& b, int max_tile
     return hipGetLastError();
 }
 
-template <int P>
+template <int P, int TN>
 hipError_t second_direct(int ny, int nx, int split, const NtBuffers& b, hipStream_t s) {
-    const int tiles = nt_tiles(ny, nx, 128, 128);
-    hipLaunchKernelGGL((nt_direct_kernel<P, true, SecondEpi, 128, 128>), dim3(tiles * split),
+    const int tiles = nt_tiles(ny, nx, 128, TN);
+    hipLaunchKernelGGL((nt_direct_kernel<P, true, SecondEpi, 128, TN>), dim3(tiles * split),
                        dim3(256), 0, s, b.second, 1, &b.hdr->second_tiles, split);
     return hipGetLastError();
 }
@@ -484,6 +519,7 @@ hipError_t second_direct(int ny, int nx, int split, const NtBuffers& b, hipStrea
 }  // namespace
 
 int nt_first_tile_m(int precision) { return precision == P_FP32 ? 64 : 128; }
+int nt_second_tile_n(int precision) { return precision == P_FP32 ? 64 : 128; }
 
 hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffers& b,
                            int max_tiles, hipStream_t s) {
@@ -495,9 +531,9 @@ hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffer
 
 hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBuffers& b,
                             hipStream_t s) {
-    if (precision == P_BF16) return second_direct<P_BF16>(ny, nx, split, b, s);
-    if (precision == P_FP16) return second_direct<P_FP16>(ny, nx, split, b, s);
-    return second_direct<P_FP32>(ny, nx, split, b, s);
+    if (precision == P_BF16) return second_direct<P_BF16, 128>(ny, nx, split, b, s);
+    if (precision == P_FP16) return second_direct<P_FP16, 128>(ny, nx, split, b, s);
+    return second_direct<P_FP32, 64>(ny, nx, split, b, s);
 }
 
 namespace {
