@@ -24,6 +24,8 @@ saliency", arXiv 2211.09938):
 * ``exact``       -- Eq. 1 with the exact distance and 1/r amplitude, to measure
                      the error of the Fresnel form.
 * ``quality``     -- SSIM of the stage evaluation (Sec. 3).
+* ``angular``     -- angular-spectrum propagation; with z -> -z the inverse
+                     method the paper reconstructs its holograms with (Sec. 2).
 * ``gradient``    -- the adjoint (gradient of a real loss with respect to the
                      object amplitudes) and the Fresnel back-propagation used
                      for the differentiable form.
@@ -32,4 +34,5 @@ All arithmetic is float64 / complex128.  Nothing here is blocked, fused or
 reordered beyond the definitions it states.
 """
 
-from . import haar, saliency, fresnel, progressive, literal, gradient, separable, exact, quality  # noqa: F401
+from . import (haar, saliency, fresnel, progressive, literal, gradient, separable, exact,  # noqa: F401
+               quality, angular)
