@@ -216,6 +216,28 @@ int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lamb
                               double z, int precision, int adjoint, void* workspace,
                               size_t workspace_bytes, float* field_out, void* stream);
 
+/*
+ * Angular-spectrum propagation of a complex field over distance z (metres,
+ * any sign).  The paper reconstructs its holograms with the inverse
+ * angular-spectrum method at the scene parameters (Sec. 2, end of the method):
+ * that is this operator with z -> -z, the hologram as `field` and the object
+ * plane in `out`.
+ *   out = IDFT2( DFT2(field) * T ),
+ *   T(fx, fy) = exp(i 2 pi z sqrt(1/lambda^2 - fx^2 - fy^2)), 0 where the root is
+ *   imaginary (evanescent),  fx = kx / (nx pitch), kx in [-nx/2, nx/2) in DFT order,
+ * DFT2 unnormalised, IDFT2 scaled by 1/(ny nx); the grid is the field's own (no
+ * padding: the DFT's periodic wrap-around is part of the operator).
+ *  field, out   [device] 2*ny*nx floats, complex64 interleaved, row-major; may be
+ *               the same array (in place).
+ *  ny, nx       2^a or 3*2^a in [2, 4096] (CGH_ERROR_SHAPE otherwise; 0: no-op).
+ *  lambda, pitch  finite, > 0; z finite.
+ *  workspace    [device] at least cgh_angular_spectrum_workspace_size(ny, nx) bytes.
+ * FP32 FFTs with FP64 twiddle tables and an FP64 transfer phase.
+ */
+size_t cgh_angular_spectrum_workspace_size(int ny, int nx);  /* 0 for unsupported sides */
+int cgh_angular_spectrum(const float* field, int ny, int nx, double lambda, double pitch, double z,
+                         void* workspace, size_t workspace_bytes, float* out, void* stream);
+
 /* ---------------------------------------------------------- batched plans */
 
 /*

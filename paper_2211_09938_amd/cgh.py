@@ -63,6 +63,9 @@ SIGNATURES = {
                                        _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp, _vp]),
     "cgh_fresnel_backpropagate": (_c_int, [_vp, _c_int, _c_int, _c_double, _c_double, _c_double,
                                            _c_int, _c_int, _vp, _sz, _vp, _vp]),
+    "cgh_angular_spectrum_workspace_size": (_sz, [_c_int, _c_int]),
+    "cgh_angular_spectrum": (_c_int, [_vp, _c_int, _c_int, _c_double, _c_double, _c_double, _vp,
+                                      _sz, _vp, _vp]),
     "cgh_profile_enable": (_c_int, [_c_int]),
     "cgh_profile_read": (_c_int, [ctypes.POINTER(_c_double), ctypes.POINTER(ctypes.c_longlong),
                                   _c_int]),
@@ -381,6 +384,29 @@ def fresnel_backpropagate(field, lam, pitch, z, adjoint=False, precision="fp32",
         ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out.data_ptr()), _stream()),
         "cgh_fresnel_backpropagate")
     return out
+
+
+def angular_spectrum(field, lam, pitch, z, out=None, workspace=None):
+    """Angular-spectrum propagation of a complex64 field over z (cgh_angular_spectrum);
+    ``out`` may be ``field`` (in place)."""
+    torch = _torch()
+    ny, nx = field.shape
+    p_in = _dev_tensor(field, torch.complex64, "field")
+    if out is None:
+        out = torch.empty_like(field)
+    p_out = _dev_tensor(out, torch.complex64, "out", (ny, nx))
+    nbytes = lib().cgh_angular_spectrum_workspace_size(ny, nx)
+    ws = _workspace(nbytes, field.device, workspace)
+    _check(lib().cgh_angular_spectrum(p_in, ny, nx, float(lam), float(pitch), float(z),
+                                      ctypes.c_void_p(ws.data_ptr()),
+                                      ws.numel() * ws.element_size(), p_out, _stream()),
+           "cgh_angular_spectrum")
+    return out
+
+
+def reconstruct(hologram, lam, pitch, z, out=None, workspace=None):
+    """Inverse angular-spectrum reconstruction of a hologram recorded at distance z."""
+    return angular_spectrum(hologram, lam, pitch, -float(z), out=out, workspace=workspace)
 
 
 # -------------------------------------------------------------- diagnostics

@@ -367,6 +367,29 @@ int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lamb
     }
 }
 
+size_t cgh_angular_spectrum_workspace_size(int ny, int nx) {
+    if (!cgh::angular_length_ok(ny) || !cgh::angular_length_ok(nx)) return 0;
+    return cgh::angular_bytes(ny, nx);
+}
+
+int cgh_angular_spectrum(const float* field, int ny, int nx, double lambda, double pitch, double z,
+                         void* workspace, size_t workspace_bytes, float* out, void* stream) {
+    try {
+        if (ny < 0 || nx < 0) return CGH_ERROR_SHAPE;
+        if (!finite_pos(lambda) || !finite_pos(pitch) || !std::isfinite(z))
+            return CGH_ERROR_INVALID_VALUE;
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        if (!cgh::angular_length_ok(ny) || !cgh::angular_length_ok(nx)) return CGH_ERROR_SHAPE;
+        if (!field || !out) return CGH_ERROR_INVALID_VALUE;
+        if (!workspace || workspace_bytes < cgh::angular_bytes(ny, nx)) return CGH_ERROR_WORKSPACE;
+        return hip_status(cgh::launch_angular(reinterpret_cast<const float2*>(field), ny, nx,
+                                              lambda, pitch, z, reinterpret_cast<float2*>(out),
+                                              static_cast<char*>(workspace), (hipStream_t)stream));
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
 int cgh_profile_enable(int on) {
     Profiler& p = profiler();
     std::lock_guard<std::mutex> g(p.mu);

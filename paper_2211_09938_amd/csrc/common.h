@@ -104,6 +104,12 @@ hipError_t launch_luts_batch(const LutJob* jobs, int n_jobs, int max_len, int le
 // out (+)= sum of `split` partial holograms of ny x nx (split <= 1: nothing).
 hipError_t launch_reduce_partial(int ny, int nx, int split, const float2* partial, float2* out,
                                  int accumulate, hipStream_t s);
+// Angular-spectrum propagation (angular.hip): sides 2^a or 3 * 2^a in [2, 4096];
+// workspace angular_bytes(ny, nx); field and out may be the same array.
+bool angular_length_ok(int n);
+size_t angular_bytes(int ny, int nx);
+hipError_t launch_angular(const float2* field, int ny, int nx, double lambda, double pitch,
+                          double z, float2* out, char* ws, hipStream_t s);
 // Exact-distance Eq. 1 sum of one layer's points `amp` into `out` (exact.hip).
 hipError_t launch_exact(const float* amp, int ny, int nx, double lambda, double pitch, double z,
                         int accumulate, float2* out, hipStream_t s);

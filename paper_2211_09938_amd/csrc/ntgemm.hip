@@ -31,16 +31,16 @@ typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
-// Operand format of precision P with KS rows of K per staged tile (the FP32
-// path always stages 16).  Measured on MI355X with K-blocked panels: both
-// schedules run best at K 16 per staged tile with two workgroups per CU (K 32
-// at one workgroup per CU was 15% slower in the persistent split kernels).
+// Operand format of precision P with KS rows of K per staged tile.  Measured
+// on MI355X with K-blocked panels: both schedules run best at K 16 per staged
+// tile with two workgroups per CU (K 32 at one workgroup per CU was 15% slower
+// in the persistent split kernels).
 template <int P, int KS = kKT>
 struct Fmt {
     static constexpr int ES = (P == P_FP32) ? 4 : 2;        // bytes per element
     static constexpr int PC = (P == P_FP32) ? 2 : 4;        // planes of a complex operand
     static constexpr int PR = (P == P_FP32) ? 1 : 2;        // planes of a real operand
-    static constexpr int KB = (P == P_FP32) ? kKT : KS;     // K per staged tile
+    static constexpr int KB = KS;                           // K per staged tile
     static constexpr int CPR = KB * ES / 16;                // 16-byte chunks per row and plane
     static constexpr int PITCH = KB * ES + 16;              // LDS bytes per row (with padding)
 };
@@ -293,7 +293,7 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
         if (kt + 1 < nk) load(kt + 1);
         if constexpr (P == P_FP32) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < F::KB / 8; ++h) {
                 floatx4 fa[BI][NPA], fb[BJ][NPB];
 #pragma unroll
                 for (int i = 0; i < BI; ++i)

@@ -230,3 +230,24 @@ def test_plan_validation_and_forced_allocation_failure(monkeypatch):
     assert lib.cgh_plan_execute(None, None) == INVALID
     assert lib.cgh_plan_destroy(None) == INVALID
     assert lib.cgh_plan_get_info(None, None) == INVALID
+
+
+def test_angular_spectrum_validation():
+    lib = cgh.lib()
+    ws_bytes = lib.cgh_angular_spectrum_workspace_size
+    assert ws_bytes(2048, 2048) >= 2048 * 2048 * 8 + 2 * 2048 * 8
+    assert ws_bytes(768, 1536) >= 768 * 1536 * 8
+    for bad in [(5, 8), (8, 10), (8192, 8), (8, 6144), (1, 8), (0, 8)]:
+        assert ws_bytes(*bad) == 0, bad
+
+    def call(ny=64, nx=64, lam=532e-9, pitch=8e-6, z=-0.2, field=BOGUS, ws=BOGUS, nbytes=1 << 30,
+             out=BOGUS):
+        return lib.cgh_angular_spectrum(field, ny, nx, lam, pitch, z, ws, nbytes, out, None)
+
+    assert call(ny=0) == OK and call(nx=0, field=None) == OK
+    assert call(ny=-4) == SHAPE
+    assert call(ny=100) == SHAPE and call(nx=5) == SHAPE and call(nx=8192) == SHAPE
+    assert call(lam=0.0) == INVALID and call(pitch=-1.0) == INVALID
+    assert call(z=float("inf")) == INVALID and call(z=float("nan")) == INVALID
+    assert call(field=None) == INVALID and call(out=None) == INVALID
+    assert call(ws=None) == WS and call(nbytes=ws_bytes(64, 64) - 1) == WS
