@@ -60,12 +60,17 @@ WORKLOADS = {
                       "approximation image and residual maps times uniform-block fringes, dense"),
     "stages256": (lambda: scenes.tiny(n=256),
                   "256x256 object (the paper's image size), one plane z=0.2 m, ~25% saliency, "
-                  "3 levels: the four progressive stage holograms, their Fresnel "
-                  "back-propagated amplitudes and the SSIM of each against the point-wise "
-                  "hologram's, with the operator counts of every step"),
+                  "3 levels: the four progressive stage holograms, their inverse "
+                  "angular-spectrum reconstructions (and Fresnel back-propagations) and the SSIM "
+                  "of each against the point-wise hologram's, with the operator counts of every "
+                  "step"),
     "exact256": (lambda: scenes.tiny(n=256),
                  "256x256 object, one plane z=0.2 m, ~25% saliency, 3 Haar levels; Eq. 1 with the "
                  "exact distance and 1/r amplitude as a direct sum (evaluation of the Fresnel form)"),
+    "recon2048": (lambda: {"n": 2048, "z": 0.2, "seed": 2211},
+                  "inverse angular-spectrum reconstruction (the paper's reconstruction method) of "
+                  "a 2048x2048 unit-modulus random-phase hologram recorded at z=0.2 m, lambda "
+                  "532 nm, pitch 8 um"),
     "batch64": (scenes.batched,
                 "64 scenes, sides uniform in {256,512,768,1024,1536,2048}, 1-4 depth planes, "
                 "saliency 5-60% from 1-3 ellipses, 3 Haar levels; one batched plan "
@@ -243,9 +248,14 @@ def run_literal(scene, prec, steps, warmup):
     # dense work: per layer and image b (block 2^b) a (ny>>b x nx>>b) x (nx>>b x nx) real x complex
     # product and a (ny x ny>>b) x (ny>>b x nx) complex product
     fl = 0.0
+    fl_issued = 0.0
     for b in range(scene.levels, -1, -1):
         r, c = ny >> b, nx >> b
         fl += layers * (4.0 * r * c * nx + 8.0 * ny * r * nx)
+        # matrix-core flops issued: the FP32 second product takes 128 x 64 tiles in
+        # the three-product complex form (3/4 of its real products)
+        fl_issued += layers * (ISSUE_FACTOR[prec] * 4.0 * r * c * nx
+                               + SECOND_ISSUE[prec] * 8.0 * ny * r * nx)
     ms = 1e3 * elapsed / steps
     achieved = fl / (ms * 1e-3) / 1e12
     return {
@@ -256,7 +266,7 @@ def run_literal(scene, prec, steps, warmup):
         "roofline": {"bound": "mfma", "kernel": "whole literal step (both contractions dominate)",
                      "achieved": achieved, "peak": PEAKS_TFLOPS[prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAKS_TFLOPS[prec], "traffic": None,
-                     "issued_mfma_frac": achieved * ISSUE_FACTOR[prec] / PEAKS_TFLOPS[prec]},
+                     "issued_mfma_frac": fl_issued / (ms * 1e-3) / 1e12 / PEAKS_TFLOPS[prec]},
         "_out": out.cpu().numpy(),
     }
 
@@ -291,25 +301,91 @@ def run_stages(scene, prec, steps, warmup):
     full = cgh.progressive_hologram(obj, scene.z, scene.lam, scene.pitch, scene.levels, None,
                                     precision=prec)
     z = scene.z[0]
-    ref = cgh.fresnel_backpropagate(full, scene.lam, scene.pitch, z, precision=prec).abs()
-    ref = ref.cpu().numpy().astype(np.float64)
-    rng = float(ref.max() - ref.min())
+
+    def amp_angular(h):  # the paper's reconstruction: inverse angular spectrum
+        return cgh.reconstruct(h, scene.lam, scene.pitch, z).abs().cpu().numpy().astype(np.float64)
+
+    def amp_fresnel(h):
+        return cgh.fresnel_backpropagate(h, scene.lam, scene.pitch, z, precision=prec).abs() \
+            .cpu().numpy().astype(np.float64)
+
+    refs = {k: f(full) for k, f in (("angular", amp_angular), ("fresnel", amp_fresnel))}
     rows = []
     cum = 0
     for j in range(scene.levels + 1):
-        amp = cgh.fresnel_backpropagate(st[j].contiguous(), scene.lam, scene.pitch, z,
-                                        precision=prec).abs().cpu().numpy().astype(np.float64)
+        h = st[j].contiguous()
         cum += stats["operators"][j]
-        rows.append({"stage": ["LLL", "LL", "L", "object"][j] if scene.levels == 3 else j,
-                     "ssim_vs_pointwise": quality.ssim(amp, ref, rng),
-                     "operators_cumulative": cum,
-                     "operators_frac_of_pointwise": cum / stats["operators_pointwise"]})
+        row = {"stage": ["LLL", "LL", "L", "object"][j] if scene.levels == 3 else j}
+        for k, f in (("angular", amp_angular), ("fresnel", amp_fresnel)):
+            ref = refs[k]
+            key = "ssim_vs_pointwise" if k == "angular" else "ssim_vs_pointwise_fresnel_recon"
+            row[key] = quality.ssim(f(h), ref, float(ref.max() - ref.min()))
+        row.update({"operators_cumulative": cum,
+                    "operators_frac_of_pointwise": cum / stats["operators_pointwise"]})
+        rows.append(row)
     return {
         "value": steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
         "stages": rows,
         "operators_pointwise": stats["operators_pointwise"],
     }
+
+
+def run_recon(spec, steps, warmup):
+    """Inverse angular-spectrum reconstruction of one n x n field per step."""
+    import torch
+
+    from paper_2211_09938_amd import cgh
+
+    n, z = spec["n"], spec["z"]
+    rng = np.random.default_rng(spec["seed"])
+    field_h = np.exp(2j * np.pi * rng.random((n, n))).astype(np.complex64)
+    dev = torch.device("cuda:0")
+    field = torch.from_numpy(field_h).to(dev)
+    out = torch.empty_like(field)
+    ws = torch.empty(cgh.lib().cgh_angular_spectrum_workspace_size(n, n), dtype=torch.uint8,
+                     device=dev)
+
+    def step():
+        cgh.reconstruct(field, scenes.WAVELENGTH, scenes.PITCH, z, out=out, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    # the library launches on torch's current stream: events there bracket its kernels
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = a.elapsed_time(b) / steps
+    alg = 16.0 * n * n  # the field read once, the reconstruction written once
+    achieved = alg / (ms * 1e-3) / 1e9
+    return {
+        "value": steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "roofline": {"bound": "hbm", "kernel": "cgh_angular_spectrum (five launches: row FFT, "
+                     "transpose, column FFT x transfer x inverse FFT, transpose, row inverse FFT)",
+                     "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                     "frac": achieved / 8000.0, "traffic": None, "bytes_per_call": alg,
+                     "pass_bytes_per_call": 5 * alg, "avg_call_ms": ms},
+        "_field": field_h,
+        "_out": out.cpu().numpy(),
+    }
+
+
+def recon_cpu_baseline(field, z):
+    from oracle import angular
+
+    t0 = time.perf_counter()
+    ref = angular.reconstruct(field.astype(np.complex128), scenes.WAVELENGTH, scenes.PITCH, z)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "reconstructions/s", "cores": 1, "kind": "oracle",
+            "sample": f"one whole {field.shape[0]}x{field.shape[1]} reconstruction "
+                      "(numpy FFT, complex128, one thread)", "_ref": ref}
 
 
 def exact_cpu_baseline(scene, n_pixels=256):
@@ -335,11 +411,17 @@ def exact_cpu_baseline(scene, n_pixels=256):
     }
 
 
-def roofline(stats, prec, avg_ms, kernel, traffic=None):
+def gauss_tile(prec, tm, tn):
+    """FP32 complex tiles of 128 x 64 and smaller issue three real products per complex one."""
+    return prec == "fp32" and tm * tn <= 128 * 64
+
+
+def roofline(stats, prec, avg_ms, kernel, traffic=None, issue=None):
     """Second contraction: algorithmic flops per launch / average launch time."""
     achieved = stats["flops_second"] / (avg_ms * 1e-3) / 1e12
     peak = PEAKS_TFLOPS[prec]
-    issued = achieved * SECOND_ISSUE[prec] * stats["flops_second_issued"] / max(1.0, stats["flops_second"])
+    issue = SECOND_ISSUE[prec] if issue is None else issue
+    issued = achieved * issue * stats["flops_second_issued"] / max(1.0, stats["flops_second"])
     return {
         "bound": "mfma",
         "kernel": kernel,
@@ -503,7 +585,11 @@ def run_batch(batch, prec, steps, warmup, tune_cache):
         "work": stats,
         "roofline": roofline(stats, prec, sec_ms / max(1, sec_n),
                              f"second contraction (nt_persistent_kernel<{prec}, "
-                             f"{info['second_tile'][0]}x{info['second_tile'][1]}>)"),
+                             f"{info['second_tile'][0]}x{info['second_tile'][1]}"
+                             + (", 3 real products per complex product>)"
+                                if gauss_tile(prec, *info["second_tile"]) else ">)"),
+                             issue=(0.75 if gauss_tile(prec, *info["second_tile"])
+                                    else ISSUE_FACTOR[prec])),
         "plan": dict(info, create_s=t_plan),
     }
     plan.close()
@@ -536,6 +622,29 @@ def main():
                 "config": {"workload": args.workload, "description": desc,
                            "ny": work.shape[0], "nx": work.shape[1]},
                 "stages": res["stages"], "operators_pointwise": res["operators_pointwise"]}
+        print(json.dumps(line), flush=True)
+        return
+    if args.workload.startswith("recon"):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("bench.py needs a GPU")
+        res = run_recon(work, args.steps, args.warmup)
+        field, out = res.pop("_field"), res.pop("_out")
+        line = {"metric": "inverse angular-spectrum reconstructions/s (the paper's "
+                          "reconstruction method)",
+                "value": res["value"], "unit": "reconstructions/s", "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f32 (f64 twiddles and transfer phase)", "data": "synthetic",
+                "config": {"workload": args.workload, "description": desc, "ny": work["n"],
+                           "nx": work["n"]},
+                "roofline": res["roofline"]}
+        if not args.no_cpu_baseline:
+            base = recon_cpu_baseline(field, work["z"])
+            ref = base.pop("_ref")
+            line["rel_l2_vs_oracle"] = float(np.linalg.norm(out - ref) / np.linalg.norm(ref))
+            line["cpu_baseline"] = base
         print(json.dumps(line), flush=True)
         return
     if args.workload.startswith("exact"):

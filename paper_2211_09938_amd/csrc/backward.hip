@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void cotangent_panel_kernel(const float2* __re
 }
 
 struct BwArgs {
-    int ny, nx, layers, levels, ldx, ldy, es, split_a, split_b;
+    int ny, nx, layers, levels, ldx, ldy, es, split_a, split_b, tn_a;
     int tiles_a_layer, tiles_b_layer;
     const char* g;            // G panel
     const char* fxh;          // FxH panels
@@ -134,11 +134,12 @@ __global__ void bw_entries_kernel(BwArgs a) {
         e.lda = sx * 16;     // FxH_{d,l}: sx rows
         e.ldb = a.ny * 16;   // G: ny rows
         e.out_ld = sx * 16;  // P_{d,l}: sx rows
-        e.tiles_n = (a.ny + kNtTile - 1) / kNtTile;
+        e.tiles_n = (a.ny + a.tn_a - 1) / a.tn_a;
         e.tile_begin = d * a.tiles_a_layer + ta;
-        e.tile_m = e.tile_n = kNtTile;
+        e.tile_m = kNtTile;
+        e.tile_n = a.tn_a;
         a.ea[d * L + l - 1] = e;
-        ta += nt_tiles(sx, a.ny, kNtTile, kNtTile);
+        ta += nt_tiles(sx, a.ny, kNtTile, a.tn_a);
         pa += (size_t)sx * a.ny;
 
         // step B sub-blocks: (r0, M, c0, N)
@@ -234,7 +235,9 @@ struct BwShape {
     size_t g_b, fxh_b, fyh_b, pt_b, part_b, ent_b;  // bytes
 };
 
-BwShape bw_shape(int ny, int nx, int layers, int levels) {
+// tn_a: column tile of step A (the workspace is sized with 128, whose split is
+// the largest).
+BwShape bw_shape(int ny, int nx, int layers, int levels, int tn_a = kNtTile) {
     BwShape z{};
     z.ldx = pad_kt(nx);
     z.ldy = pad_kt(ny);
@@ -242,7 +245,7 @@ BwShape bw_shape(int ny, int nx, int layers, int levels) {
         const int sy = band_side(ny, l), sx = band_side(nx, l);
         z.rows_x += sx;
         z.rows_y += sy;
-        z.tiles_a_layer += nt_tiles(sx, ny, kNtTile, kNtTile);
+        z.tiles_a_layer += nt_tiles(sx, ny, kNtTile, tn_a);
         z.pa_layer += (size_t)sx * ny;
         if (l < levels) {
             z.tiles_b_layer += nt_tiles(sy / 2, sx / 2, kNtTile, kNtTile) +
@@ -270,8 +273,10 @@ BwShape bw_shape(int ny, int nx, int layers, int levels) {
 template <int P>
 hipError_t backward_nt(const float2* grad_h, const float* lut_x, const float* lut_y, int ny,
                        int nx, int layers, int levels, float* gcoef, char* base, hipStream_t s) {
-    const BwShape z = bw_shape(ny, nx, layers, levels);
+    const int tn_a = nt_table_tile_n(kEpiPanel, P);
+    const BwShape z = bw_shape(ny, nx, layers, levels, tn_a);
     BwArgs a{};
+    a.tn_a = tn_a;
     a.ny = ny;
     a.nx = nx;
     a.layers = layers;

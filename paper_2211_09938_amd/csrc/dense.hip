@@ -110,7 +110,8 @@ hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const floa
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 
-    const int tiles = nt_tiles(nx, ny, kNtTile, kNtTile);  // same count for both steps
+    const int tn = nt_table_tile_n(kEpiComplex, P);
+    const int tiles1 = nt_tiles(nx, ny, kNtTile, tn), tiles2 = nt_tiles(ny, nx, kNtTile, tn);
     NtEntry e1{};
     e1.a = b.kx;
     e1.b = b.h;
@@ -124,11 +125,12 @@ hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const floa
     e1.lda = nx * 16;  // K'_x panel: nx rows
     e1.ldb = ny * 16;  // H panel: ny rows
     e1.out_ld = ny;
-    e1.tiles_n = (ny + kNtTile - 1) / kNtTile;
-    e1.tile_m = e1.tile_n = kNtTile;
-    hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e1, tiles, b.entries,
+    e1.tiles_n = (ny + tn - 1) / tn;
+    e1.tile_m = kNtTile;
+    e1.tile_n = tn;
+    hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e1, tiles1, b.entries,
                        b.counts);
-    if ((e = launch_nt_table(kEpiComplex, P, b.entries, 1, b.counts, tiles, split, s)) != hipSuccess) return e;
+    if ((e = launch_nt_table(kEpiComplex, P, b.entries, 1, b.counts, tiles1, split, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_panel_kernel<P>, dim3(grid_1d(t_ps)), dim3(256), 0, s,
                        split > 1 ? b.partial : b.c1, split, nx, ny, ldy, b.t, t_ps);
 
@@ -145,12 +147,13 @@ hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const floa
     e2.lda = ny * 16;  // s K'_y panel: ny rows
     e2.ldb = nx * 16;  // T panel: nx rows
     e2.out_ld = nx;
-    e2.tiles_n = (nx + kNtTile - 1) / kNtTile;
-    e2.tile_m = e2.tile_n = kNtTile;
-    hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e2, tiles, b.entries + 1,
+    e2.tiles_n = (nx + tn - 1) / tn;
+    e2.tile_m = kNtTile;
+    e2.tile_n = tn;
+    hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e2, tiles2, b.entries + 1,
                        b.counts + 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_nt_table(kEpiComplex, P, b.entries + 1, 1, b.counts + 1, tiles, split, s)) != hipSuccess)
+    if ((e = launch_nt_table(kEpiComplex, P, b.entries + 1, 1, b.counts + 1, tiles2, split, s)) != hipSuccess)
         return e;
     return launch_reduce_partial(ny, nx, split, b.partial, out, 0, s);
 }

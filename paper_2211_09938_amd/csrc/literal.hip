@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void block_fringe_panel_kernel(const float* __
 }
 
 struct LitArgs {
-    int ny, nx, layers, L, es, split;
+    int ny, nx, layers, L, es, split, tn2;
     const char* rb;       // residual panels, [d][b] in order b = L .. 0
     const char* fxb;      // x fringe panels, same order
     char* t;              // first-contraction products (K-blocked, rows nx)
@@ -143,12 +143,13 @@ __global__ void literal_entries_kernel(LitArgs a) {
     e.lda = a.ny * 16;
     e.ldb = a.nx * 16;
     e.out_ld = a.nx;
-    e.tiles_n = (a.nx + kNtTile - 1) / kNtTile;
+    e.tiles_n = (a.nx + a.tn2 - 1) / a.tn2;
     e.accumulate = a.accumulate;
-    e.tile_m = e.tile_n = kNtTile;
+    e.tile_m = kNtTile;
+    e.tile_n = a.tn2;
     a.second[0] = e;
     a.counts[0] = tiles;
-    a.counts[1] = nt_tiles(a.ny, a.nx, kNtTile, kNtTile);
+    a.counts[1] = nt_tiles(a.ny, a.nx, kNtTile, a.tn2);
 }
 
 struct LitShape {
@@ -246,6 +247,7 @@ hipError_t literal(const float* coef, const float* lut_x, const float* lut_y,
     a.L = L;
     a.es = es;
     a.split = split;
+    a.tn2 = nt_table_tile_n(kEpiComplex, P);
     a.rb = r.rb;
     a.fxb = r.fxb;
     a.t = r.t;
@@ -265,7 +267,7 @@ hipError_t literal(const float* coef, const float* lut_x, const float* lut_y,
     e = launch_nt_first_table(P, a.first, layers * (L + 1), a.counts, z.first_tiles, s);
     if (e != hipSuccess) return e;
     e = launch_nt_table(kEpiComplex, P, a.second, 1, a.counts + 1,
-                        nt_tiles(ny, nx, kNtTile, kNtTile), split, s);
+                        nt_tiles(ny, nx, kNtTile, a.tn2), split, s);
     if (e != hipSuccess) return e;
     return launch_reduce_partial(ny, nx, split, partial, hologram, accumulate, s);
 }

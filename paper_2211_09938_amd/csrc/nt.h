@@ -224,13 +224,19 @@ hipError_t launch_batch_prefix(const PlanHeader* hdrs, int n_scenes, const int* 
                                NtEntry* first, NtEntry* second, int* counts, int* queues,
                                hipStream_t s);
 // Direct launch over a table of complex x complex problems (A and B complex,
-// tile 128 x 128; `tiles` bounds the device tile count, split-K when split > 1
-// into each problem's partial buffer).  Epilogues:
+// tile 128 x nt_table_tile_n(epi, precision); `tiles` bounds the device tile
+// count, split-K when split > 1 into each problem's partial buffer).  Epilogues:
 //   kEpiComplex  complex64 rows of `out` (row stride out_ld), partials [s][M][out_ld]
 //   kEpiPanel    operand planes of `out` (row stride out_ld, plane stride out_ps),
 //                columns up to pad16(N); partials [s][M][N]
 //   kEpiReal     real part only into floats of `out`; partials [s][M][N] floats
 enum { kEpiComplex = 0, kEpiPanel = 1, kEpiReal = 2 };
+// Column tile of a table launch: 64 where FP32 products keep both parts (128 x 64
+// tiles take the three-product complex form), 128 otherwise; tables built for
+// launch_nt_table must use it for tiles_n and their tile counts.
+__host__ __device__ inline int nt_table_tile_n(int epi, int precision) {
+    return (precision == P_FP32 && epi != kEpiReal) ? 64 : kNtTile;
+}
 hipError_t launch_nt_table(int epi, int precision, const NtEntry* entries, int n_entries,
                            const int* tile_count, int tiles, int split, hipStream_t s);
 

@@ -537,18 +537,19 @@ hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBu
 }
 
 namespace {
-template <int P, class Epi>
+template <int P, class Epi, int TN>
 void table_launch(const NtEntry* entries, int n_entries, const int* tile_count, int tiles,
                   int split, hipStream_t s) {
-    hipLaunchKernelGGL((nt_direct_kernel<P, true, Epi, 128, 128>), dim3(tiles * split),
+    hipLaunchKernelGGL((nt_direct_kernel<P, true, Epi, 128, TN>), dim3(tiles * split),
                        dim3(256), 0, s, entries, n_entries, tile_count, split);
 }
 template <int P>
 void table_epi(int epi, const NtEntry* entries, int n_entries, const int* tile_count, int tiles,
                int split, hipStream_t s) {
-    if (epi == kEpiPanel) table_launch<P, PanelEpi<P>>(entries, n_entries, tile_count, tiles, split, s);
-    else if (epi == kEpiReal) table_launch<P, RealEpi>(entries, n_entries, tile_count, tiles, split, s);
-    else table_launch<P, SecondEpi>(entries, n_entries, tile_count, tiles, split, s);
+    constexpr int TN = P == P_FP32 ? 64 : 128;  // nt_table_tile_n for the complex epilogues
+    if (epi == kEpiPanel) table_launch<P, PanelEpi<P>, TN>(entries, n_entries, tile_count, tiles, split, s);
+    else if (epi == kEpiReal) table_launch<P, RealEpi, 128>(entries, n_entries, tile_count, tiles, split, s);
+    else table_launch<P, SecondEpi, TN>(entries, n_entries, tile_count, tiles, split, s);
 }
 }  // namespace
 
