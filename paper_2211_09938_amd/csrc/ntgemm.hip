@@ -284,43 +284,59 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
         }
     };
 
+    // Per K tile: this tile's operands LDS -> registers; barrier (the LDS tile
+    // is free); stash the next tile and start loading the one after it; the
+    // MFMAs on the registers (they cover the LDS writes and the global loads);
+    // barrier (the next tile is visible).
     if (nk > 0) {
         load(0);
         stash();
     }
     __syncthreads();
+    if (nk > 1) load(1);
+    auto advance = [&](int kt) {
+        __syncthreads();
+        if (kt + 1 < nk) {
+            stash();
+            if (kt + 2 < nk) load(kt + 2);
+        }
+    };
     for (int kt = 0; kt < nk; ++kt) {
-        if (kt + 1 < nk) load(kt + 1);
         if constexpr (P == P_FP32) {
+            constexpr int NH = F::KB / 8;
+            floatx4 fa[NH][BI][NPA], fb[NH][BJ][NPB];
 #pragma unroll
-            for (int h = 0; h < F::KB / 8; ++h) {
-                floatx4 fa[BI][NPA], fb[BJ][NPB];
+            for (int h = 0; h < NH; ++h) {
 #pragma unroll
                 for (int i = 0; i < BI; ++i)
 #pragma unroll
                     for (int c = 0; c < NPA; ++c)
-                        fa[i][c] = *reinterpret_cast<const floatx4*>(
+                        fa[h][i][c] = *reinterpret_cast<const floatx4*>(
                             As + c * APLANE + (wm + 32 * i + l32) * F::PITCH + (8 * h + 4 * g) * 4);
 #pragma unroll
                 for (int j = 0; j < BJ; ++j)
 #pragma unroll
                     for (int c = 0; c < NPB; ++c)
-                        fb[j][c] = *reinterpret_cast<const floatx4*>(
+                        fb[h][j][c] = *reinterpret_cast<const floatx4*>(
                             Bs + c * BPLANE + (wn + 32 * j + l32) * F::PITCH + (8 * h + 4 * g) * 4);
+            }
+            advance(kt);
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
                 if constexpr (G3) {
                     floatx4 sa[BI], sb[BJ];
 #pragma unroll
-                    for (int i = 0; i < BI; ++i) sa[i] = fa[i][0] + fa[i][1];
+                    for (int i = 0; i < BI; ++i) sa[i] = fa[h][i][0] + fa[h][i][1];
 #pragma unroll
-                    for (int j = 0; j < BJ; ++j) sb[j] = fb[j][0] + fb[j][1];
+                    for (int j = 0; j < BJ; ++j) sb[j] = fb[h][j][0] + fb[h][j][1];
 #pragma unroll
                     for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
                         for (int i = 0; i < BI; ++i)
 #pragma unroll
                             for (int j = 0; j < BJ; ++j) {
-                                cr[i][j] = mfma32(fa[i][0][tt], fb[j][0][tt], cr[i][j]);
-                                ci[i][j] = mfma32(fa[i][1][tt], fb[j][1][tt], ci[i][j]);
+                                cr[i][j] = mfma32(fa[h][i][0][tt], fb[h][j][0][tt], cr[i][j]);
+                                ci[i][j] = mfma32(fa[h][i][1][tt], fb[h][j][1][tt], ci[i][j]);
                                 cz[i][j] = mfma32(sa[i][tt], sb[j][tt], cz[i][j]);
                             }
                     continue;
@@ -331,63 +347,66 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
                     for (int i = 0; i < BI; ++i)
 #pragma unroll
                         for (int j = 0; j < BJ; ++j) {
-                            cr[i][j] = mfma32(fa[i][0][tt], fb[j][0][tt], cr[i][j]);
+                            cr[i][j] = mfma32(fa[h][i][0][tt], fb[h][j][0][tt], cr[i][j]);
                             if constexpr (Epi::kImag)
-                                ci[i][j] = mfma32(fa[i][0][tt], fb[j][1][tt], ci[i][j]);
+                                ci[i][j] = mfma32(fa[h][i][0][tt], fb[h][j][1][tt], ci[i][j]);
                         }
                     if constexpr (A_CPLX) {
 #pragma unroll
                         for (int i = 0; i < BI; ++i)
 #pragma unroll
                             for (int j = 0; j < BJ; ++j) {
-                                cr[i][j] = mfma32(-fa[i][1][tt], fb[j][1][tt], cr[i][j]);
+                                cr[i][j] = mfma32(-fa[h][i][1][tt], fb[h][j][1][tt], cr[i][j]);
                                 if constexpr (Epi::kImag)
-                                    ci[i][j] = mfma32(fa[i][1][tt], fb[j][0][tt], ci[i][j]);
+                                    ci[i][j] = mfma32(fa[h][i][1][tt], fb[h][j][0][tt], ci[i][j]);
                             }
                     }
                 }
             }
         } else {
+            constexpr int NC = F::KB / 16;
+            u32x4 a[NC][BI][NPA], b[NC][BJ][NPB];
 #pragma unroll
-          for (int kc = 0; kc < F::KB / 16; ++kc) {
-            u32x4 a[BI][NPA], b[BJ][NPB];
+            for (int kc = 0; kc < NC; ++kc) {
 #pragma unroll
-            for (int i = 0; i < BI; ++i)
+                for (int i = 0; i < BI; ++i)
 #pragma unroll
-                for (int c = 0; c < NPA; ++c)
-                    a[i][c] = *reinterpret_cast<const u32x4*>(
-                        As + c * APLANE + (wm + 32 * i + l32) * F::PITCH + kc * 32 + g * 16);
+                    for (int c = 0; c < NPA; ++c)
+                        a[kc][i][c] = *reinterpret_cast<const u32x4*>(
+                            As + c * APLANE + (wm + 32 * i + l32) * F::PITCH + kc * 32 + g * 16);
 #pragma unroll
-            for (int j = 0; j < BJ; ++j)
+                for (int j = 0; j < BJ; ++j)
 #pragma unroll
-                for (int c = 0; c < NPB; ++c)
-                    b[j][c] = *reinterpret_cast<const u32x4*>(
-                        Bs + c * BPLANE + (wn + 32 * j + l32) * F::PITCH + kc * 32 + g * 16);
+                    for (int c = 0; c < NPB; ++c)
+                        b[kc][j][c] = *reinterpret_cast<const u32x4*>(
+                            Bs + c * BPLANE + (wn + 32 * j + l32) * F::PITCH + kc * 32 + g * 16);
+            }
+            advance(kt);
 #pragma unroll
-            for (int i = 0; i < BI; ++i)
+            for (int kc = 0; kc < NC; ++kc) {
 #pragma unroll
-                for (int j = 0; j < BJ; ++j) {
-                    cr[i][j] = prod3<P>(cr[i][j], a[i][0], a[i][1], b[j][0], b[j][1]);
-                    if constexpr (Epi::kImag)
-                        ci[i][j] = prod3<P>(ci[i][j], a[i][0], a[i][1], b[j][2], b[j][3]);
-                }
-            if constexpr (A_CPLX) {
-#pragma unroll
-                for (int i = 0; i < BI; ++i) {
-                    // -A_im: flip the sign bit of every 16-bit half
-                    const u32x4 nah = a[i][2] ^ 0x80008000u, nal = a[i][3] ^ 0x80008000u;
+                for (int i = 0; i < BI; ++i)
 #pragma unroll
                     for (int j = 0; j < BJ; ++j) {
-                        cr[i][j] = prod3<P>(cr[i][j], nah, nal, b[j][2], b[j][3]);
+                        cr[i][j] = prod3<P>(cr[i][j], a[kc][i][0], a[kc][i][1], b[kc][j][0], b[kc][j][1]);
                         if constexpr (Epi::kImag)
-                            ci[i][j] = prod3<P>(ci[i][j], a[i][2], a[i][3], b[j][0], b[j][1]);
+                            ci[i][j] = prod3<P>(ci[i][j], a[kc][i][0], a[kc][i][1], b[kc][j][2], b[kc][j][3]);
+                    }
+                if constexpr (A_CPLX) {
+#pragma unroll
+                    for (int i = 0; i < BI; ++i) {
+                        // -A_im: flip the sign bit of every 16-bit half
+                        const u32x4 nah = a[kc][i][2] ^ 0x80008000u, nal = a[kc][i][3] ^ 0x80008000u;
+#pragma unroll
+                        for (int j = 0; j < BJ; ++j) {
+                            cr[i][j] = prod3<P>(cr[i][j], nah, nal, b[kc][j][2], b[kc][j][3]);
+                            if constexpr (Epi::kImag)
+                                ci[i][j] = prod3<P>(ci[i][j], a[kc][i][2], a[kc][i][3], b[kc][j][0], b[kc][j][1]);
+                        }
                     }
                 }
             }
-          }
         }
-        __syncthreads();
-        if (kt + 1 < nk) stash();
         __syncthreads();
     }
 
