@@ -12,8 +12,8 @@
 //   4. transpose                                 tmp -> out
 //   5. inverse DFT along x of every row, scaled by 1 / (ny nx)
 // FFT: Stockham autosort (results in natural order, no bit reversal): a
-// radix-3 stage for lengths 3 * 2^a, radix-4 stages, a radix-2 stage when the
-// power of two is odd.  A stage reads the R inputs of each of its butterflies
+// radix-3 stage for lengths 3 * 2^a, radix-8 stages, then one radix-4 or
+// radix-2 stage for the rest of the power of two (2048 = 8^3 * 4: four stages).  A stage reads the R inputs of each of its butterflies
 // into registers, synchronises, and writes the R outputs back in place.
 // Twiddles exp(-2 pi i m / n) come from a table computed with FP64 sincospi of
 // the exact rational 2m/n and rounded to FP32.
@@ -41,7 +41,25 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 // DFT of R points in registers (forward: exp(-2 pi i q q' / R); INV: conjugate).
 template <int R, bool INV>
 __device__ __forceinline__ void butterfly(float2* x) {
-    if constexpr (R == 2) {
+    if constexpr (R == 8) {
+        // two 4-point DFTs (even and odd inputs), odd outputs times w8^k
+        float2 e[4] = {x[0], x[2], x[4], x[6]}, o[4] = {x[1], x[3], x[5], x[7]};
+        butterfly<4, INV>(e);
+        butterfly<4, INV>(o);
+        const float c = 0.70710678118654752440f;  // 1 / sqrt(2)
+        const float2 o1 = o[1], o2 = o[2], o3 = o[3];
+        // forward w8 = (1 - i) / sqrt(2); inverse its conjugate
+        o[1] = INV ? make_float2(c * (o1.x - o1.y), c * (o1.x + o1.y))
+                   : make_float2(c * (o1.x + o1.y), c * (o1.y - o1.x));
+        o[2] = INV ? make_float2(-o2.y, o2.x) : make_float2(o2.y, -o2.x);
+        o[3] = INV ? make_float2(-c * (o3.x + o3.y), c * (o3.x - o3.y))
+                   : make_float2(c * (o3.y - o3.x), -c * (o3.x + o3.y));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[k] = make_float2(e[k].x + o[k].x, e[k].y + o[k].y);
+            x[k + 4] = make_float2(e[k].x - o[k].x, e[k].y - o[k].y);
+        }
+    } else if constexpr (R == 2) {
         const float2 a = x[0], b = x[1];
         x[0] = make_float2(a.x + b.x, a.y + b.y);
         x[1] = make_float2(a.x - b.x, a.y - b.y);
@@ -57,7 +75,7 @@ __device__ __forceinline__ void butterfly(float2* x) {
         x[1] = make_float2(t1.x + r3.x, t1.y + r3.y);
         x[3] = make_float2(t1.x - r3.x, t1.y - r3.y);
     } else {
-        static_assert(R == 3, "radix 2, 3 or 4");
+        static_assert(R == 3, "radix 2, 3, 4 or 8");
         const float h = 0.86602540378443864676f;  // sqrt(3) / 2
         const float2 t = make_float2(x[1].x + x[2].x, x[1].y + x[2].y);
         const float2 u = make_float2(x[1].x - x[2].x, x[1].y - x[2].y);
@@ -75,7 +93,8 @@ __device__ __forceinline__ void butterfly(float2* x) {
 // by w^(q k n/(p R)), and writes output q to buf[(i - k) R + k + q p].
 template <int R, bool INV>
 __device__ __forceinline__ void fft_stage(float2* buf, int n, int p, const float2* __restrict__ tw) {
-    constexpr int MB = kFftMax / (R == 2 ? 2 : 4) / kFftThreads;  // butterflies per thread (3 * 2^a <= 3072)
+    // butterflies per thread: n / R for the longest n of the radix (3 * 2^a <= 3072)
+    constexpr int MB = (R == 3 ? 1024 : kFftMax / R) / kFftThreads;
     const int nb = n / R;
     const int step = n / (p * R);
     float2 v[MB][R];
@@ -116,11 +135,12 @@ __device__ void fft_lds(float2* buf, int n, const float2* __restrict__ tw) {
         fft_stage<3, INV>(buf, n, p, tw);
         p *= 3;
     }
-    while ((n / p) % 4 == 0) {
-        fft_stage<4, INV>(buf, n, p, tw);
-        p *= 4;
+    while ((n / p) % 8 == 0) {
+        fft_stage<8, INV>(buf, n, p, tw);
+        p *= 8;
     }
-    if (n / p == 2) fft_stage<2, INV>(buf, n, p, tw);
+    if (n / p == 4) fft_stage<4, INV>(buf, n, p, tw);
+    else if (n / p == 2) fft_stage<2, INV>(buf, n, p, tw);
 }
 
 __global__ __launch_bounds__(256) void twiddle_kernel(float2* __restrict__ tw_x, int nx,
