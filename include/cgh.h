@@ -340,7 +340,9 @@ typedef struct cgh_stats_s {
                                     4 * nx * sum over (layer, level) of active rows x columns  */
     double flops_second;         /* algorithmic real flops, second contraction:
                                     8 * ny * nx * coef_rows_active                             */
-    double flops_second_issued;  /* 8 * ny * nx * k_padded                                     */
+    double flops_second_issued;  /* 8 * ny * nx * k_padded: the count on the padded K (FP32
+                                    runs three real products per complex product there, i.e.
+                                    3/4 of it on the matrix cores)                          */
     long long operators[4];      /* operator count of Sec. 3 per progressive step, for one image
                                     plane (the saliency masks are shared by the layers):
                                     [0] the approximation, one per point of the (ny/2^L) x

@@ -10,11 +10,14 @@
 // a grid sized to the machine pulls tiles from an atomic counter until the
 // table is exhausted, so problems of very different sizes balance themselves.
 // Per K tile of 16 each thread moves 16-byte chunks of A and B
-// global -> registers -> LDS, the next tile's loads in flight during the
-// current tile's MFMAs.
+// global -> registers -> LDS; a wave takes the tile's operands from LDS into
+// registers, and after one barrier the next tile is stashed and the one after
+// it loaded while the MFMAs run.
 //
 //  FP32:  v_mfma_f32_32x32x2f32; a lane's 16-byte LDS read gives it the
 //         operands of 4 consecutive MFMAs (lane half g supplies k = 4g + t).
+//         Complex x complex tiles of 128 x 64 and smaller use three real
+//         products per complex product (Gauss), four otherwise.
 //  split: v_mfma_f32_32x32x16_{bf16,f16}; operands stored as hi and lo planes,
 //         each real product as hi*hi + hi*lo + lo*hi, FP32 accumulation.
 #include "nt.h"
