@@ -58,6 +58,10 @@ WORKLOADS = {
     "literal2048x8": (scenes.depth_2048,
                       "the 2048x2048, 8-plane scene of depth2048x8 by the paper-literal form: "
                       "approximation image and residual maps times uniform-block fringes, dense"),
+    "fused2048x8": (scenes.depth_2048,
+                    "the 2048x2048, 8-plane scene of depth2048x8 by the dense reconstruct-then-"
+                    "contract form: masked reconstruction per layer, one dense Fresnel "
+                    "contraction pair per layer (12 N^3 flops per layer, no saliency skipping)"),
     "stages256": (lambda: scenes.tiny(n=256),
                   "256x256 object (the paper's image size), one plane z=0.2 m, ~25% saliency, "
                   "3 levels: the four progressive stage holograms, their inverse "
@@ -218,7 +222,9 @@ def run_exact(scene, steps, warmup):
     }
 
 
-def run_literal(scene, prec, steps, warmup):
+def run_dense(scene, prec, steps, warmup, form):
+    """The dense forms: paper-literal residual maps ("literal") or the masked
+    reconstruction contracted once per layer ("fused")."""
     import torch
 
     from paper_2211_09938_amd import cgh
@@ -232,10 +238,11 @@ def run_literal(scene, prec, steps, warmup):
     ws = torch.empty(cgh.workspace_size(ny, nx, layers, scene.levels, prec), dtype=torch.uint8,
                      device=dev)
     out = torch.empty((ny, nx), dtype=torch.complex64, device=dev)
+    fn = cgh.literal_hologram if form == "literal" else cgh.fused_hologram
 
     def step():
-        cgh.literal_hologram(obj, scene.z, scene.lam, scene.pitch, scene.levels, sal, lay,
-                             precision=prec, out=out, workspace=ws)
+        fn(obj, scene.z, scene.lam, scene.pitch, scene.levels, sal, lay, precision=prec, out=out,
+           workspace=ws)
 
     for _ in range(warmup):
         step()
@@ -245,15 +252,16 @@ def run_literal(scene, prec, steps, warmup):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    # dense work: per layer and image b (block 2^b) a (ny>>b x nx>>b) x (nx>>b x nx) real x complex
-    # product and a (ny x ny>>b) x (ny>>b x nx) complex product
+    # dense work: per layer a real x complex product (ny x k) x (k x nx) and a complex product
+    # (ny x k) x (k x nx) with k = nx >> b, ny >> b per image b of the literal form (block 2^b,
+    # b = L..0), k = nx, ny once for the fused form; matrix-core flops issued: the FP32 complex
+    # product takes the three-product form (3/4 of its real products)
+    sizes = [(ny >> b, nx >> b) for b in range(scene.levels, -1, -1)] if form == "literal" \
+        else [(ny, nx)]
     fl = 0.0
     fl_issued = 0.0
-    for b in range(scene.levels, -1, -1):
-        r, c = ny >> b, nx >> b
+    for r, c in sizes:
         fl += layers * (4.0 * r * c * nx + 8.0 * ny * r * nx)
-        # matrix-core flops issued: the FP32 second product takes 128 x 64 tiles in
-        # the three-product complex form (3/4 of its real products)
         fl_issued += layers * (ISSUE_FACTOR[prec] * 4.0 * r * c * nx
                                + SECOND_ISSUE[prec] * 8.0 * ny * r * nx)
     ms = 1e3 * elapsed / steps
@@ -263,7 +271,7 @@ def run_literal(scene, prec, steps, warmup):
         "ms_per_step": ms,
         "stages_ms_per_step": {},
         "work": {"flops_dense": fl},
-        "roofline": {"bound": "mfma", "kernel": "whole literal step (both contractions dominate)",
+        "roofline": {"bound": "mfma", "kernel": f"whole {form} step (both contractions dominate)",
                      "achieved": achieved, "peak": PEAKS_TFLOPS[prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAKS_TFLOPS[prec], "traffic": None,
                      "issued_mfma_frac": fl_issued / (ms * 1e-3) / 1e12 / PEAKS_TFLOPS[prec]},
@@ -690,7 +698,9 @@ def main():
         elif grad:
             forms[prec] = run_grad(scene, prec, args.steps, args.warmup)
         elif args.workload.startswith("literal"):
-            forms[prec] = run_literal(scene, prec, args.steps, args.warmup)
+            forms[prec] = run_dense(scene, prec, args.steps, args.warmup, "literal")
+        elif args.workload.startswith("fused"):
+            forms[prec] = run_dense(scene, prec, args.steps, args.warmup, "fused")
         else:
             forms[prec] = run_single(scene, prec, args.steps, args.warmup, args.workload)
         out = forms[prec].pop("_out", None)

@@ -168,6 +168,26 @@ int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_
                          void* stream);
 
 /*
+ * Dense form of the same hologram (the "reconstruct, then contract" ablation):
+ * by linearity (Eq. 3) the sum over coefficients of coefficient x block
+ * fringe is the Fresnel hologram of each layer's masked reconstruction
+ * A_d = S(M W(object * [layer == d])) (Sec. 2 steps 2-5 summed), so this
+ * computes A_d with the inverse Haar transform and then
+ *   H (+)= sum_d P_d * K_y A_d K_x^T,   K[m][q] = exp(i pi p^2 (m - q)^2 / (lambda z_d)),
+ * two dense products per layer with inner dimensions nx and ny: 12 N^3 real
+ * flops per layer for N x N, against 18 N^3 for the per-level dense form and
+ * the saliency-compacted work of cgh_progressive_hologram.  Equals
+ * cgh_progressive_hologram up to rounding order.  Arguments, flags,
+ * workspace (cgh_workspace_size), errors and ownership as for
+ * cgh_progressive_hologram.
+ */
+int cgh_fused_hologram(const float* object, const uint8_t* layer_index, int n_layers,
+                       const double* z, const float* saliency, const float* thresholds,
+                       double lambda, double pitch, int ny, int nx, int levels, int precision,
+                       unsigned flags, void* workspace, size_t workspace_bytes, float* hologram,
+                       void* stream);
+
+/*
  * Eq. 1 with the exact distance (no Fresnel approximation), for measuring
  * the error of the Fresnel form of the hot path:
  *   hologram[y][x] = sum_d sum_{q,p} Ahat_d[q][p] / r * exp(i 2 pi r / lambda),

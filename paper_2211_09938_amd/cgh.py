@@ -57,6 +57,9 @@ SIGNATURES = {
     "cgh_literal_hologram": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double,
                                       _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp,
                                       _vp]),
+    "cgh_fused_hologram": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double,
+                                      _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp,
+                                      _vp]),
     "cgh_exact_hologram": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double, _c_int,
                                     _c_int, _c_int, _c_uint, _vp, _sz, _vp, _vp]),
     "cgh_hologram_backward": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double,
@@ -324,6 +327,31 @@ def literal_hologram(obj, z, lam, pitch, levels=3, saliency=None, layer_index=No
         p_obj, p_lay, len(zs), _host_doubles(zs), p_sal, _host_floats(thresholds), float(lam),
         float(pitch), ny, nx, levels, prec, flags, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
         p_out, _stream()), "cgh_literal_hologram")
+    return out
+
+
+def fused_hologram(obj, z, lam, pitch, levels=3, saliency=None, layer_index=None,
+                   thresholds=None, precision="fp32", eq1_prefactor=False, out=None,
+                   accumulate=False, workspace=None):
+    """Complex64 hologram by the dense reconstruct-then-contract form; see cgh_fused_hologram."""
+    torch = _torch()
+    ny, nx = obj.shape
+    zs = list(np.atleast_1d(np.asarray(z, dtype=np.float64)))
+    p_obj = _dev_tensor(obj, torch.float32, "object")
+    p_sal = None if saliency is None else _dev_tensor(saliency, torch.float32, "saliency", (ny, nx))
+    p_lay = None if layer_index is None else _dev_tensor(layer_index, torch.uint8, "layer_index", (ny, nx))
+    prec = _precision(precision)
+    ws = _workspace(workspace_size(ny, nx, len(zs), levels, prec), obj.device, workspace)
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs an existing `out`")
+        out = torch.empty((ny, nx), dtype=torch.complex64, device=obj.device)
+    p_out = _dev_tensor(out, torch.complex64, "out", (ny, nx))
+    flags = (FLAG_ACCUMULATE if accumulate else 0) | (FLAG_EQ1_PREFACTOR if eq1_prefactor else 0)
+    _check(lib().cgh_fused_hologram(
+        p_obj, p_lay, len(zs), _host_doubles(zs), p_sal, _host_floats(thresholds), float(lam),
+        float(pitch), ny, nx, levels, prec, flags, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+        p_out, _stream()), "cgh_fused_hologram")
     return out
 
 

@@ -252,6 +252,55 @@ int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_
     }
 }
 
+int cgh_fused_hologram(const float* object, const uint8_t* layer_index, int n_layers,
+                       const double* z, const float* saliency, const float* thresholds,
+                       double lambda, double pitch, int ny, int nx, int levels, int precision,
+                       unsigned flags, void* workspace, size_t workspace_bytes, float* hologram,
+                       void* stream) {
+    try {
+        float thr[CGH_MAX_LEVELS];
+        int st = check_common(n_layers, layer_index, z, thresholds, lambda, pitch, ny, nx, levels,
+                              precision, flags, thr);
+        if (st) return st;
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        if (!object || !hologram) return CGH_ERROR_INVALID_VALUE;
+        const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
+        if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        hipStream_t s = (hipStream_t)stream;
+        char* ws = static_cast<char*>(workspace);
+        Optics op;
+        make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
+        float* coef = reinterpret_cast<float*>(ws + lo.coef);
+        hipError_t e = cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers,
+                                            levels, thr, cgh::kAllParts, coef, nullptr, 0,
+                                            nullptr, s);
+        char* scratch = ws + lo.big;
+        float* recon = reinterpret_cast<float*>(scratch + cgh::fused_recon_offset(ny, nx));
+        float* lut0_x = reinterpret_cast<float*>(ws + lo.lut0);
+        float* lut0_y = lut0_x + 2 * cgh::lut_len(nx);
+        const int acc = (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0;
+        // layer by layer: masked reconstruction, level-0 fringe tables, two dense products
+        for (int d = 0; d < n_layers && e == hipSuccess; ++d) {
+            e = cgh::launch_idwt(coef + (size_t)d * ny * nx, ny, nx, levels, recon, s);
+            if (e == hipSuccess)
+                e = cgh::launch_luts(nx, 1, 1, 0, &op.c[d], &op.one_re[d], &op.one_im[d],
+                                     cgh::P_FP32, lut0_x, nullptr, s);
+            if (e == hipSuccess)
+                e = cgh::launch_luts(ny, 1, 1, 0, &op.c[d], &op.pre_re[d], &op.pre_im[d],
+                                     cgh::P_FP32, lut0_y, nullptr, s);
+            if (e == hipSuccess)
+                e = cgh::launch_fused_layer(recon, lut0_x, lut0_y, ny, nx, precision,
+                                            (d > 0 || acc) ? 1 : 0,
+                                            reinterpret_cast<float2*>(hologram), scratch,
+                                            reinterpret_cast<cgh::NtEntry*>(ws + lo.entries),
+                                            reinterpret_cast<int*>(ws + lo.hdr), s);
+        }
+        return hip_status(e);
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
 int cgh_exact_hologram(const float* object, const uint8_t* layer_index, int n_layers,
                        const double* z, const float* saliency, const float* thresholds,
                        double lambda, double pitch, int ny, int nx, int levels, unsigned flags,

@@ -61,6 +61,21 @@ __global__ __launch_bounds__(256) void complex_panel_kernel(const float2* __rest
     }
 }
 
+// Real image [rows][cols] -> K-blocked operand planes [rows][ld] (zeros for
+// cols <= k < ld).
+template <int P>
+__global__ __launch_bounds__(256) void real_panel_kernel(const float* __restrict__ in, int rows,
+                                                         int cols, int ld,
+                                                         void* __restrict__ out, size_t ps) {
+    const size_t total = (size_t)rows * ld;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        int r, c;
+        kblk_pos(e, rows, r, c);
+        put_r<P>(out, ps, e, c < cols ? in[(size_t)r * cols + c] : 0.f);
+    }
+}
+
 // Sum of `split` FP32 partials [split][rows][cols] -> K-blocked operand planes [rows][ld].
 template <int P>
 __global__ __launch_bounds__(256) void reduce_panel_kernel(const float2* __restrict__ partial,
@@ -158,6 +173,75 @@ hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const floa
     return launch_reduce_partial(ny, nx, split, b.partial, out, 0, s);
 }
 
+// One layer of the dense form: H (+)= K_y A K_x^T for the real image A, with
+// K_x[x][p] = g_x(x - p) and K_y[y][q] = g_y(y - q) from the level-0 tables
+// (the layer's prefactor is in g_y).  Step 1 T[x][q] = sum_p A[q][p] K_x[x][p]
+// (real x complex, written transposed as a K-blocked panel); step 2
+// H[y][x] = sum_q K_y[y][q] T[x][q].
+template <int P>
+hipError_t fused_layer(const float* recon, const float* lut0_x, const float* lut0_y, int ny,
+                       int nx, int accumulate, float2* out, char* scratch, NtEntry* entries,
+                       int* counts, hipStream_t s) {
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const int ldx = pad_kt(nx), ldy = pad_kt(ny);
+    const size_t kx_ps = (size_t)nx * ldx, ky_ps = (size_t)ny * ldy;
+    const size_t a_ps = (size_t)ny * ldx, t_ps = (size_t)nx * ldy;
+    char* kx = scratch;
+    char* ky = kx + al(8 * kx_ps);
+    char* a = ky + al(8 * ky_ps);
+    char* t = a + al(4 * a_ps);
+    hipLaunchKernelGGL(toeplitz_panel_kernel<P>, dim3(grid_1d(kx_ps)), dim3(256), 0, s, lut0_x,
+                       nx, nx, nx, ldx, 1.f, 1.f, kx, kx_ps);
+    hipLaunchKernelGGL(toeplitz_panel_kernel<P>, dim3(grid_1d(ky_ps)), dim3(256), 0, s, lut0_y,
+                       ny, ny, ny, ldy, 1.f, 1.f, ky, ky_ps);
+    hipLaunchKernelGGL(real_panel_kernel<P>, dim3(grid_1d(a_ps)), dim3(256), 0, s, recon, ny, nx,
+                       ldx, a, a_ps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+
+    const int tiles1 = nt_tiles(ny, nx, kNtTile, kNtTile);
+    NtEntry e1{};
+    e1.a = a;
+    e1.b = kx;
+    e1.out = t;
+    e1.a_ps = (long long)a_ps;
+    e1.b_ps = (long long)kx_ps;
+    e1.out_ps = (long long)t_ps;
+    e1.M = ny;
+    e1.N = nx;
+    e1.K = ldx;
+    e1.lda = ny * 16;     // A panel: ny rows
+    e1.ldb = nx * 16;     // K_x panel: nx rows
+    e1.out_ld = nx * 16;  // T panel: nx rows
+    e1.tiles_n = (nx + kNtTile - 1) / kNtTile;
+    e1.tile_m = e1.tile_n = kNtTile;
+    hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e1, tiles1, entries, counts);
+    if ((e = launch_nt_first_table(P, entries, 1, counts, tiles1, s)) != hipSuccess) return e;
+
+    const int tn = nt_table_tile_n(kEpiComplex, P);
+    const int tiles2 = nt_tiles(ny, nx, kNtTile, tn);
+    NtEntry e2{};
+    e2.a = ky;
+    e2.b = t;
+    e2.out = out;
+    e2.a_ps = (long long)ky_ps;
+    e2.b_ps = (long long)t_ps;
+    e2.M = ny;
+    e2.N = nx;
+    e2.K = ldy;
+    e2.lda = ny * 16;  // K_y panel: ny rows
+    e2.ldb = nx * 16;  // T panel: nx rows
+    e2.out_ld = nx;
+    e2.tiles_n = (nx + tn - 1) / tn;
+    e2.tile_m = kNtTile;
+    e2.tile_n = tn;
+    e2.accumulate = accumulate;
+    hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e2, tiles2, entries + 1,
+                       counts + 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_nt_table(kEpiComplex, P, entries + 1, 1, counts + 1, tiles2, 1, s);
+}
+
 }  // namespace
 
 size_t dense_bytes(int ny, int nx, int split) {
@@ -196,6 +280,30 @@ hipError_t launch_dense_backprop(const DenseBuffers& b, const float* lut0_x, con
     if (precision == P_FP16)
         return dense_backprop<P_FP16>(b, lut0_x, lut0_y, in, out, ny, nx, adjoint, scale, split, s);
     return dense_backprop<P_FP32>(b, lut0_x, lut0_y, in, out, ny, nx, adjoint, scale, split, s);
+}
+
+size_t fused_recon_offset(int ny, int nx) {
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t ldx = pad_kt(nx), ldy = pad_kt(ny);
+    return al(8 * (size_t)nx * ldx) + al(8 * (size_t)ny * ldy) + al(4 * (size_t)ny * ldx) +
+           al(8 * (size_t)nx * ldy);
+}
+
+size_t fused_bytes(int ny, int nx) {
+    return fused_recon_offset(ny, nx) + (4 * (size_t)ny * nx + 255) / 256 * 256;
+}
+
+hipError_t launch_fused_layer(const float* recon, const float* lut0_x, const float* lut0_y,
+                              int ny, int nx, int precision, int accumulate, float2* out,
+                              char* scratch, NtEntry* entries, int* counts, hipStream_t s) {
+    if (precision == P_BF16)
+        return fused_layer<P_BF16>(recon, lut0_x, lut0_y, ny, nx, accumulate, out, scratch,
+                                   entries, counts, s);
+    if (precision == P_FP16)
+        return fused_layer<P_FP16>(recon, lut0_x, lut0_y, ny, nx, accumulate, out, scratch,
+                                   entries, counts, s);
+    return fused_layer<P_FP32>(recon, lut0_x, lut0_y, ny, nx, accumulate, out, scratch, entries,
+                               counts, s);
 }
 
 }  // namespace cgh

@@ -98,6 +98,8 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
         if (bw > panels) panels = bw;
         const size_t lit = cgh::literal_bytes(ny, nx, layers, levels);
         if (lit > panels) panels = lit;
+        const size_t fused = cgh::fused_bytes(ny, nx);
+        if (fused > panels) panels = fused;
     }
     lo.big = take(t_bytes > panels ? t_bytes : panels);
     lo.t = lo.big;

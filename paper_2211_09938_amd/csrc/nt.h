@@ -253,6 +253,17 @@ struct DenseBuffers {
 };
 // Bytes of the panel region (plus the unsplit step-1 product) for a split.
 size_t dense_bytes(int ny, int nx, int split);
+// Dense form of one layer (reconstruct the masked object first, then one
+// contraction pair): out (+)= K_y recon K_x^T, K from the level-0 tables
+// lut0_x / lut0_y (float re / im halves of lut_len(n) entries; the layer's
+// prefactor in lut0_y).  scratch: fused_bytes(ny, nx); the ny * nx floats at
+// fused_recon_offset(ny, nx) are not touched (room for the caller's recon);
+// entries / counts: 2 slots.
+size_t fused_bytes(int ny, int nx);
+size_t fused_recon_offset(int ny, int nx);
+hipError_t launch_fused_layer(const float* recon, const float* lut0_x, const float* lut0_y,
+                              int ny, int nx, int precision, int accumulate, float2* out,
+                              char* scratch, NtEntry* entries, int* counts, hipStream_t s);
 DenseBuffers dense_buffers(char* base, int ny, int nx, int split, float2* partial,
                            NtEntry* entries, int* counts);
 // out = scale * K'_y in K'_x, K' = conj(K) (adjoint == 0) or K (adjoint != 0).

@@ -131,6 +131,22 @@ def test_literal_validation():
         assert lib.cgh_literal_hologram(*a) == code, (idx, val)
 
 
+def test_fused_validation():
+    lib = cgh.lib()
+    z = (ctypes.c_double * 1)(0.2)
+    base = [BOGUS, None, 1, z, None, None, 532e-9, 8e-6, 64, 64, 3, 0, 0, BOGUS, 1 << 40, BOGUS,
+            None]
+    for idx, val, code in [(0, None, INVALID), (15, None, INVALID), (8, 60, SHAPE),
+                           (14, 16, WS), (11, 9, INVALID), (12, 8, INVALID), (2, 2, INVALID),
+                           (6, 0.0, INVALID), (10, 0, SHAPE)]:
+        a = list(base)
+        a[idx] = val
+        assert lib.cgh_fused_hologram(*a) == code, (idx, val)
+    a = list(base)
+    a[8] = 0
+    assert lib.cgh_fused_hologram(*a) == OK
+
+
 def test_exact_validation():
     lib = cgh.lib()
     z = (ctypes.c_double * 1)(0.2)
