@@ -13,8 +13,9 @@
 //   5. inverse DFT along x of every row, scaled by 1 / (ny nx)
 // FFT: Stockham autosort (results in natural order, no bit reversal): a
 // radix-3 stage for lengths 3 * 2^a, radix-8 stages, then one radix-4 or
-// radix-2 stage for the rest of the power of two (2048 = 8^3 * 4: four stages).  A stage reads the R inputs of each of its butterflies
-// into registers, synchronises, and writes the R outputs back in place.
+// radix-2 stage for the rest of the power of two (2048 = 8^3 * 4: four
+// stages).  A stage reads the R inputs of each of its butterflies into
+// registers, synchronises, and writes the R outputs back in place.
 // Twiddles exp(-2 pi i m / n) come from a table computed with FP64 sincospi of
 // the exact rational 2m/n and rounded to FP32.
 // The transfer phase reaches 2 pi z / lambda (about 2.4e6 rad at 0.2 m), so in

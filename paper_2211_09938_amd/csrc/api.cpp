@@ -55,10 +55,10 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
     if (e == hipSuccess && with_luts)
         e = timed(s, CGH_STAGE_LUT, [&] {
             hipError_t r = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
-                                            cgh::P_FP32, ws + lo.lut_x, nullptr, s);
+                                            reinterpret_cast<float*>(ws + lo.lut_x), s);
             if (r != hipSuccess) return r;
             return cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im,
-                                    cgh::P_FP32, ws + lo.lut_y, nullptr, s);
+                                    reinterpret_cast<float*>(ws + lo.lut_y), s);
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_PLAN, [&] {
@@ -231,11 +231,11 @@ int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_
                                      lo.flags_layer,
                                      reinterpret_cast<unsigned long long*>(ws + lo.ops), s);
         if (e == hipSuccess)
-            e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im, cgh::P_FP32,
-                                 ws + lo.lut_x, nullptr, s);
+            e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
+                                 reinterpret_cast<float*>(ws + lo.lut_x), s);
         if (e == hipSuccess)
-            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im, cgh::P_FP32,
-                                 ws + lo.lut_y, nullptr, s);
+            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im,
+                                 reinterpret_cast<float*>(ws + lo.lut_y), s);
         if (e == hipSuccess) {
             const cgh::LitTables tb{op.c, op.one_re, op.one_im, op.pre_re, op.pre_im};
             e = cgh::launch_literal(reinterpret_cast<const float*>(ws + lo.coef),
@@ -283,11 +283,11 @@ int cgh_fused_hologram(const float* object, const uint8_t* layer_index, int n_la
         for (int d = 0; d < n_layers && e == hipSuccess; ++d) {
             e = cgh::launch_idwt(coef + (size_t)d * ny * nx, ny, nx, levels, recon, s);
             if (e == hipSuccess)
-                e = cgh::launch_luts(nx, 1, 1, 0, &op.c[d], &op.one_re[d], &op.one_im[d],
-                                     cgh::P_FP32, lut0_x, nullptr, s);
+                e = cgh::launch_luts(nx, 1, 1, 0, &op.c[d], &op.one_re[d], &op.one_im[d], lut0_x,
+                                     s);
             if (e == hipSuccess)
-                e = cgh::launch_luts(ny, 1, 1, 0, &op.c[d], &op.pre_re[d], &op.pre_im[d],
-                                     cgh::P_FP32, lut0_y, nullptr, s);
+                e = cgh::launch_luts(ny, 1, 1, 0, &op.c[d], &op.pre_re[d], &op.pre_im[d], lut0_y,
+                                     s);
             if (e == hipSuccess)
                 e = cgh::launch_fused_layer(recon, lut0_x, lut0_y, ny, nx, precision,
                                             (d > 0 || acc) ? 1 : 0,
@@ -360,10 +360,10 @@ int cgh_hologram_backward(const float* grad_hologram, const uint8_t* layer_index
         Optics op;
         make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
         hipError_t e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
-                                        cgh::P_FP32, ws + lo.lut_x, nullptr, s);
+                                        reinterpret_cast<float*>(ws + lo.lut_x), s);
         if (e == hipSuccess)
-            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im, cgh::P_FP32,
-                                 ws + lo.lut_y, nullptr, s);
+            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im,
+                                 reinterpret_cast<float*>(ws + lo.lut_y), s);
         if (e == hipSuccess)
             e = cgh::launch_backward_nt(reinterpret_cast<const float2*>(grad_hologram),
                                         reinterpret_cast<const float*>(ws + lo.lut_x),
@@ -396,9 +396,9 @@ int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lamb
         const double c = pitch * pitch / (2.0 * lambda * z), one = 1.0, zero = 0.0;
         float* lut0_x = reinterpret_cast<float*>(ws + lo.lut0);
         float* lut0_y = lut0_x + 2 * cgh::lut_len(nx);
-        hipError_t e = cgh::launch_luts(nx, 1, 1, 0, &c, &one, &zero, cgh::P_FP32, lut0_x, nullptr, s);
+        hipError_t e = cgh::launch_luts(nx, 1, 1, 0, &c, &one, &zero, lut0_x, s);
         if (e == hipSuccess)
-            e = cgh::launch_luts(ny, 1, 1, 0, &c, &one, &zero, cgh::P_FP32, lut0_y, nullptr, s);
+            e = cgh::launch_luts(ny, 1, 1, 0, &c, &one, &zero, lut0_y, s);
         if (e == hipSuccess) {
             const cgh::DenseBuffers b = cgh::dense_buffers(
                 ws + lo.big, ny, nx, lo.split_k, reinterpret_cast<float2*>(ws + lo.partial),

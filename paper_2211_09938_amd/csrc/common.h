@@ -118,7 +118,6 @@ hipError_t launch_grad_synthesis(const float* gcoef, const uint8_t* layer, const
                                  int nx, int layers, int levels, const float* thr, float* grad,
                                  hipStream_t s);
 hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double* c,
-                       const double* pre_re, const double* pre_im, int precision, void* hi,
-                       void* lo, hipStream_t s);
+                       const double* pre_re, const double* pre_im, float* table, hipStream_t s);
 
 }  // namespace cgh

@@ -212,9 +212,9 @@ hipError_t literal(const float* coef, const float* lut_x, const float* lut_y,
     // level-0 (point) tables of every layer; y tables carry the per-layer prefactor
     float* l0x = reinterpret_cast<float*>(r.lut0);
     float* l0y = l0x + (size_t)layers * 2 * lut_len(nx);
-    hipError_t e = launch_luts(nx, layers, 1, 0, tb.c, tb.one_re, tb.one_im, P_FP32, l0x, nullptr, s);
+    hipError_t e = launch_luts(nx, layers, 1, 0, tb.c, tb.one_re, tb.one_im, l0x, s);
     if (e == hipSuccess)
-        e = launch_luts(ny, layers, 1, 0, tb.c, tb.pre_re, tb.pre_im, P_FP32, l0y, nullptr, s);
+        e = launch_luts(ny, layers, 1, 0, tb.c, tb.pre_re, tb.pre_im, l0y, s);
     if (e != hipSuccess) return e;
     const int es = P == P_FP32 ? 4 : 2;
     size_t rb_off = 0, fx_off = 0, seg = 0;

@@ -12,19 +12,18 @@
 // Phase evaluation: m^2 is formed exactly as a 64-bit integer, the phase in
 // cycles is m^2 * c with c = pitch^2 / (2 lambda z) in FP64, its fractional
 // part is taken in FP64 and sin/cos come from the HIP device library's FP64
-// sincospi.  Only then is the sum rounded to the operand precision.
+// sincospi.  The sum is rounded once, to FP32 (the panel kernels round to the
+// operand precision).
 #include "common.h"
-#include "split.h"
 
 namespace cgh {
 
 namespace {
 
 // Entry idx of table (level lev(combo), band(combo)) of layer d.
-template <int P>
 __device__ __forceinline__ void lut_entry(int n_pix, int d, int levels, int lmin, double c,
                                           double pre_re, double pre_im, int idx, int combo,
-                                          void* __restrict__ hi, void* __restrict__ lo) {
+                                          float* __restrict__ table) {
     const int len = lut_len(n_pix);
     const int lev = (lmin == 0) ? 0 : 1 + combo / 2;
     const int band = (lmin == 0) ? 0 : combo % 2;
@@ -49,19 +48,17 @@ __device__ __forceinline__ void lut_entry(int n_pix, int d, int levels, int lmin
     }
     const size_t t_re = (lmin == 0) ? (size_t)(d * 2 + 0) : lut_table(d, lev, band, 0, levels);
     const size_t t_im = (lmin == 0) ? (size_t)(d * 2 + 1) : lut_table(d, lev, band, 1, levels);
-    store_val<P>(hi, lo, t_re * len + idx, (float)re);
-    store_val<P>(hi, lo, t_im * len + idx, (float)im);
+    table[t_re * len + idx] = (float)re;
+    table[t_im * len + idx] = (float)im;
 }
 
-template <int P>
 __global__ __launch_bounds__(256) void lut_kernel(int n_pix, int d0, int levels, int lmin,
-                                                  LayerConsts lc, void* __restrict__ hi,
-                                                  void* __restrict__ lo) {
+                                                  LayerConsts lc, float* __restrict__ table) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= lut_len(n_pix)) return;
     const int dl = blockIdx.z;
-    lut_entry<P>(n_pix, d0 + dl, levels, lmin, lc.c[dl], lc.pre_re[dl], lc.pre_im[dl], idx,
-                 blockIdx.y, hi, lo);
+    lut_entry(n_pix, d0 + dl, levels, lmin, lc.c[dl], lc.pre_re[dl], lc.pre_im[dl], idx,
+              blockIdx.y, table);
 }
 
 // Every (scene, layer, axis) table set of a batch: grid.z = job.
@@ -70,8 +67,7 @@ __global__ __launch_bounds__(256) void lut_batch_kernel(const LutJob* __restrict
     const LutJob j = jobs[job0 + blockIdx.z];
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= lut_len(j.n_pix)) return;
-    lut_entry<P_FP32>(j.n_pix, j.d, j.levels, 1, j.c, j.pre_re, j.pre_im, idx, blockIdx.y,
-                      j.table, nullptr);
+    lut_entry(j.n_pix, j.d, j.levels, 1, j.c, j.pre_re, j.pre_im, idx, blockIdx.y, j.table);
 }
 
 }  // namespace
@@ -89,8 +85,7 @@ hipError_t launch_luts_batch(const LutJob* jobs, int n_jobs, int max_len, int le
 }
 
 hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double* c,
-                       const double* pre_re, const double* pre_im, int precision, void* hi,
-                       void* lo, hipStream_t s) {
+                       const double* pre_re, const double* pre_im, float* table, hipStream_t s) {
     const int len = lut_len(n_pix);
     const int combos = (lmin == 0) ? 1 : 2 * levels;
     for (int d0 = 0; d0 < layers; d0 += kLayerChunk) {
@@ -103,15 +98,7 @@ hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double
             lc.pre_im[k] = pre_im[d];
         }
         dim3 grid((len + 255) / 256, combos, nd);
-        if (precision == P_FP32)
-            hipLaunchKernelGGL(lut_kernel<P_FP32>, grid, dim3(256), 0, s, n_pix, d0, levels, lmin,
-                               lc, hi, lo);
-        else if (precision == P_BF16)
-            hipLaunchKernelGGL(lut_kernel<P_BF16>, grid, dim3(256), 0, s, n_pix, d0, levels, lmin,
-                               lc, hi, lo);
-        else
-            hipLaunchKernelGGL(lut_kernel<P_FP16>, grid, dim3(256), 0, s, n_pix, d0, levels, lmin,
-                               lc, hi, lo);
+        hipLaunchKernelGGL(lut_kernel, grid, dim3(256), 0, s, n_pix, d0, levels, lmin, lc, table);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -36,19 +36,6 @@ __device__ __forceinline__ void split16(float v, uint16_t& hi, uint16_t& lo) {
     }
 }
 
-// Store one real value in the representation of precision P.
-template <int P>
-__device__ __forceinline__ void store_val(void* hi, void* lo, size_t i, float v) {
-    if constexpr (P == P_FP32) {
-        static_cast<float*>(hi)[i] = v;
-    } else {
-        uint16_t h, l;
-        split16<P>(v, h, l);
-        static_cast<uint16_t*>(hi)[i] = h;
-        static_cast<uint16_t*>(lo)[i] = l;
-    }
-}
-
 // Store one complex / real operand element into planar operand storage:
 // FP32 planes (re, im) or split planes (re_hi, re_lo, im_hi, im_lo) / (hi, lo),
 // plane stride ps elements.
