@@ -1,0 +1,117 @@
+"""Seeded randomized parity sweep over every forward entry point.
+
+Each case draws: levels 1-3; sides random multiples of 2^levels up to 96; 1-4
+depth planes (with some pixels given a layer id beyond the count, which belong
+to no layer); saliency of a random area fraction or none; the default or random
+thresholds; the Eq. 1 prefactor or not.  Every case runs the coefficient form
+(FP32 and a split form), the stage holograms, the paper-literal form and the
+fused dense form, all against the FP64 oracle's definitions (oracle/progressive.py:
+direct sums of the masked reconstructions and of the stage objects).  A
+batched plan of the 3-level cases (default thresholds) is checked the same way.
+Bars: rel-L2 <= 1e-5 (FP32), <= 1e-3 (split).
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import progressive
+from paper_2211_09938_amd import scenes
+
+from helpers import rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+os.environ.setdefault("ORACLE_WORKERS", "8")
+
+N_CASES = 16
+
+
+def draw(seed):
+    rng = np.random.default_rng(10_000 + seed)
+    levels = int(rng.integers(1, 4))
+    b = 1 << levels
+    ny = b * int(rng.integers(1, 96 // b + 1))
+    nx = b * int(rng.integers(1, 96 // b + 1))
+    planes = int(rng.integers(1, 5))
+    frac = float(rng.uniform(0.05, 0.9))
+    if seed % 5 == 4:
+        frac = None  # no saliency map: every block salient
+    s = scenes.random_scene(20_000 + seed, ny, nx, planes=planes, fraction=frac, levels=levels)
+    if planes > 1 and rng.random() < 0.5:
+        stray = rng.random((ny, nx)) < 0.05
+        s.layer = np.where(stray, planes, s.layer).astype(np.uint8)  # ids beyond the count
+    thr = None if rng.random() < 0.5 else [float(v) for v in rng.uniform(0.0, 1.0, levels)]
+    eq1 = bool(rng.random() < 0.3)
+    return s, thr, eq1
+
+
+def oracle(s, thr, eq1):
+    sal = None if s.saliency is None else s.saliency.astype(np.float64)
+    return progressive.hologram(s.obj.astype(np.float64), s.z, s.lam, s.pitch, s.levels, sal,
+                                s.layer, thr, eq1_prefactor=eq1)
+
+
+def run(fn, s, thr, eq1, **kw):
+    import torch
+
+    sal = None if s.saliency is None else to_dev(s.saliency)
+    lay = None if s.layer is None else to_dev(s.layer)
+    h = fn(to_dev(s.obj), s.z, s.lam, s.pitch, s.levels, sal, lay, thresholds=thr,
+           eq1_prefactor=eq1, **kw)
+    torch.cuda.synchronize()
+    return h.cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("seed", range(N_CASES))
+def test_every_form_matches_the_oracle(seed):
+    from paper_2211_09938_amd import cgh
+
+    s, thr, eq1 = draw(seed)
+    ref = oracle(s, thr, eq1)
+    split = "bf16_split" if seed % 2 else "fp16_split"
+    label = f"case {seed}: {s.obj.shape} x{len(s.z)} L{s.levels} thr={thr} eq1={eq1}"
+    errs = {
+        "coef fp32": rel_l2(run(cgh.progressive_hologram, s, thr, eq1), ref),
+        f"coef {split}": rel_l2(run(cgh.progressive_hologram, s, thr, eq1, precision=split), ref),
+        "literal fp32": rel_l2(run(cgh.literal_hologram, s, thr, eq1), ref),
+        "fused fp32": rel_l2(run(cgh.fused_hologram, s, thr, eq1), ref),
+    }
+    stages = run(cgh.progressive_stages, s, thr, eq1)
+    sal = None if s.saliency is None else s.saliency.astype(np.float64)
+    ref_st = progressive.stage_holograms(s.obj.astype(np.float64), s.z, s.lam, s.pitch,
+                                         s.levels, sal, s.layer, thr, eq1_prefactor=eq1)
+    errs["stages fp32"] = max(rel_l2(stages[j], ref_st[j]) for j in range(s.levels + 1)
+                              if np.any(ref_st[j]))
+    print(label, {k: f"{v:.1e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= (1e-3 if "split" in k else 1e-5), (label, k, v)
+
+
+def test_batched_plan_of_the_sweep_cases():
+    import torch
+
+    from paper_2211_09938_amd import cgh
+
+    # the cases with 3 levels, planned together with the default thresholds and no prefactor
+    cases = [(draw(seed)[0], None, False) for seed in range(N_CASES)]
+    cases = [c for c in cases if c[0].levels == 3]
+    assert len(cases) >= 3
+    descs = []
+    for s, _, _ in cases:
+        d = {"obj": to_dev(s.obj), "z": s.z}
+        if s.saliency is not None:
+            d["saliency"] = to_dev(s.saliency)
+        if s.layer is not None:
+            d["layer_index"] = to_dev(s.layer)
+        descs.append(d)
+    plan = cgh.Plan(descs, scenes.WAVELENGTH, scenes.PITCH, levels=3)
+    try:
+        outs = plan.execute()
+        torch.cuda.synchronize()
+        for (s, thr, eq1), h in zip(cases, outs):
+            err = rel_l2(h.cpu().numpy().astype(np.complex128), oracle(s, thr, eq1))
+            print(f"plan {s.obj.shape} x{len(s.z)}: rel-L2 {err:.1e}")
+            assert err <= 1e-5
+    finally:
+        plan.close()
