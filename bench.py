@@ -38,7 +38,10 @@ ISSUE_FACTOR = {"fp32": 1.0, "bf16_split": 3.0, "fp16_split": 3.0}
 # per complex product (Gauss), so 3/4 of the algorithmic real products are issued
 SECOND_ISSUE = {"fp32": 0.75, "bf16_split": 3.0, "fp16_split": 3.0}
 SECOND_TILE = {"fp32": "128x64, 3 real products per complex product",
-               "bf16_split": "128x128", "fp16_split": "128x128"}
+               "bf16_split": "256x128, one workgroup per CU",
+               "fp16_split": "256x128, one workgroup per CU"}
+SECOND_KERNEL = {"fp32": "nt_direct_kernel", "bf16_split": "nt_pp_kernel",
+                 "fp16_split": "nt_pp_kernel"}
 DTYPES = {"fp32": "f32", "bf16_split": "bf16x3-split/f32-acc", "fp16_split": "f16x3-split/f32-acc"}
 METRIC = "holograms/sec and Gpoint*pixel/s at 2048^2, FP32 vs BF16-split at stated rel-L2"
 
@@ -478,7 +481,7 @@ def run_single(scene, prec, steps, warmup, workload):
     cgh.profile_enable(False)
     stats = cgh.workspace_stats(ws, ny, nx, n_layers, scene.levels, prec)
     sec_ms, sec_n = prof["second"]
-    kernel = f"second contraction (nt_direct_kernel<{prec}, complex A, {SECOND_TILE[prec]}>)"
+    kernel = f"second contraction ({SECOND_KERNEL[prec]}<{prec}, complex A, {SECOND_TILE[prec]}>)"
     # the HBM-bound coefficient stage: flag clear + fused layer split / Haar / masks;
     # algorithmic bytes = object 4 B + layer id 1 B + saliency 4 B read per pixel,
     # 4 B written per pixel and layer
@@ -545,7 +548,7 @@ def run_grad(scene, prec, steps, warmup):
         "stages_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
         "work": stats,
         "roofline": roofline(stats, prec, sec_ms / max(1, sec_n),
-                             f"forward second contraction inside the step (nt_direct_kernel<{prec}>)"),
+                             f"forward second contraction inside the step ({SECOND_KERNEL[prec]}<{prec}>)"),
     }
 
 

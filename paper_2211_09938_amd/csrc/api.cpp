@@ -62,8 +62,8 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_PLAN, [&] {
-            const int tiles[4] = {cgh::nt_first_tile_m(precision), cgh::kNtTile, cgh::kNtTile,
-                                  tn2};
+            const int tiles[4] = {cgh::nt_first_tile_m(precision), cgh::kNtTile,
+                                  cgh::nt_second_tile_m(precision), tn2};
             const cgh::NtOutput o{out, split > 1 ? partial : nullptr, acc};
             hipError_t r = cgh::launch_nt_plan(fl, ny, nx, n_layers, levels, lo.flags_layer,
                                                precision, tiles, nb, o, s);

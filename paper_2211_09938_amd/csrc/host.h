@@ -36,10 +36,10 @@ inline int check_precision(int precision) {
     return CGH_SUCCESS;
 }
 
+// target: resident workgroups of the launch (two on each of 256 CUs by default)
 inline int choose_split(int ny, int nx, int levels, int layers, int tm = cgh::kNtTile,
-                        int tn = cgh::kNtTile) {
+                        int tn = cgh::kNtTile, int target = 512) {
     const int tiles = ((ny + tm - 1) / tm) * ((nx + tn - 1) / tn);
-    const int target = 512;  // two resident workgroups on each of 256 CUs
     int split = (target + tiles - 1) / tiles;
     // keep at least four K tiles per split of the dense K range
     const int kt = (int)(cgh::nt_sizes(ny, nx, layers, levels).kmax / cgh::kKT);
@@ -116,13 +116,14 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
     return lo;
 }
 
-// Split of the single-scene second contraction: about 512 workgroups with the
-// precision's tile shape, at most the layout's split (128 x 128 tiles), which
-// sized the partial buffer.
+// Split of the single-scene second contraction: about 512 resident workgroups
+// with the precision's tile shape (256 for the one-per-CU split kernel), at most
+// the layout's split (128 x 128 tiles), which sized the partial buffer.
 inline int second_split(const cgh::Layout& lo, int ny, int nx, int levels, int layers,
                         int precision) {
-    const int split = choose_split(ny, nx, levels, layers, cgh::kNtTile,
-                                   cgh::nt_second_tile_n(precision));
+    const int tm = cgh::nt_second_tile_m(precision), tn = cgh::nt_second_tile_n(precision);
+    const int target = tm * tn > cgh::kNtTile * cgh::kNtTile ? 256 : 512;
+    const int split = choose_split(ny, nx, levels, layers, tm, tn, target);
     return split < lo.split_k ? split : lo.split_k;
 }
 

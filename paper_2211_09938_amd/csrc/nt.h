@@ -205,9 +205,11 @@ hipError_t launch_nt_materialize(const float* coef, const float* lut_x, const fl
 // Direct launches over one scene's table (split-K for the second).
 // Row tile of the single-scene first contraction: 64 for FP32 (measured 10%
 // faster there: the active row counts of a level are often far below 128), 128
-// for the split forms.  Column tile of the second: 64 for FP32 (128 x 64 tiles
-// take the three-product complex form), 128 for the split forms.
+// for the split forms.  Tile of the second: 128 x 64 for FP32 (the
+// three-product complex form, two workgroups per CU), 256 x 128 for the split
+// forms (one workgroup per CU, two LDS stages).
 int nt_first_tile_m(int precision);
+int nt_second_tile_m(int precision);
 int nt_second_tile_n(int precision);
 hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffers& b,
                            int max_tiles, hipStream_t s);

@@ -20,6 +20,9 @@
 //         products per complex product (Gauss), four otherwise.
 //  split: v_mfma_f32_32x32x16_{bf16,f16}; operands stored as hi and lo planes,
 //         each real product as hi*hi + hi*lo + lo*hi, FP32 accumulation.
+// The single-scene second contraction of the split forms has a kernel of its
+// own (nt_pp_kernel, one workgroup per CU, operands global -> LDS by direct
+// loads into a three-stage ring); see its comment.
 #include "nt.h"
 #include "split.h"
 
@@ -51,6 +54,14 @@ struct Fmt {
 constexpr int kDirectKS = 16, kPersistKS = 16;
 template <int P> constexpr int direct_occ() { return 2; }
 template <int P> constexpr int persist_occ() { return 2; }
+
+// Operand panels are read through global-address-space pointers: generic
+// (flat) loads also count against the LDS wait counter, so the wait before each
+// barrier would stall on the global loads issued for the K tile after next.
+typedef const u32x4 __attribute__((address_space(1)))* gptr_u32x4;
+__device__ __forceinline__ u32x4 gload16(const unsigned char* base, size_t byte_off) {
+    return *(gptr_u32x4)(base + byte_off);
+}
 
 __device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
@@ -251,7 +262,7 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
             const int m = m0 + row;
             if (m < e.M && (F::KB == kKT || k0 + c * KPC < ke)) {
                 const size_t el = (size_t)plane * e.a_ps + kblk_off(m, k0 + c * KPC, e.lda);
-                ra[u] = *reinterpret_cast<const u32x4*>(Ab + el * F::ES);
+                ra[u] = gload16(Ab, el * F::ES);
             } else {
                 ra[u] = u32x4{0u, 0u, 0u, 0u};
             }
@@ -264,7 +275,7 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
             const int n = n0 + row;
             if (n < e.N && (F::KB == kKT || k0 + c * KPC < ke)) {
                 const size_t el = (size_t)plane * e.b_ps + kblk_off(n, k0 + c * KPC, e.ldb);
-                rb[u] = *reinterpret_cast<const u32x4*>(Bb + el * F::ES);
+                rb[u] = gload16(Bb, el * F::ES);
             } else {
                 rb[u] = u32x4{0u, 0u, 0u, 0u};
             }
@@ -459,7 +470,249 @@ __device__ __forceinline__ void run_tile(const NtEntry* __restrict__ entries, in
     nt_tile<P, A_CPLX, Epi, TM, TN, KS>(e, m0, n0, kb, ke, s, split, As, Bs);
 }
 
-// Direct schedule: block id = s * count + t.
+// Workgroups reach the 8 XCDs round-robin (block b on XCD b % 8).  Renumbered
+// so that each XCD takes one contiguous run of (split, tile) indices -- whole
+// rows of tiles of one K split -- and its L2 holds the operand rows they share
+// (the split kernel's single problem has the same K in every tile, so runs stay
+// balanced): block b is the idx-th of XCD x, which owns the run starting at
+// x * (total / 8) + min(x, total % 8).
+__device__ __forceinline__ int xcd_run_index(int total) {
+    const int x = blockIdx.x % 8, idx = blockIdx.x / 8;
+    return x * (total / 8) + min(x, total % 8) + idx;
+}
+
+// Second contraction of the split forms at one workgroup per CU: 256 x 128
+// tiles, each wave 128 x 64 (4 x 2 blocks of 32 x 32, 256 accumulators, which
+// only the AGPR file of a lone wave per SIMD can hold).  With one wave per SIMD
+// nothing hides a stall, so the K loop keeps every wait off the matrix cores:
+//  * operands go global -> LDS by direct loads (global_load_lds_dwordx4: no
+//    staging registers, no LDS stores) into a ring of three LDS stages, issued
+//    two K tiles ahead of their use;
+//  * the next K tile's operands are read LDS -> registers block row by block
+//    row as the current tile's MFMAs release them (B through a second set);
+//  * one barrier per K tile, placed after the first block row's MFMAs.
+// LDS layout of a stage: per plane, blocks of 32 rows x 32 bytes (1 KB, one
+// direct load of a wave); in a block, row r's 16-byte half h sits in slot
+// 2r + (h ^ ((r >> 3) & 1)), so the 16 lanes of each phase of a 16-byte read
+// (16 rows, one half) hit 16 different bank groups.
+// Tile indices past the K range are clamped to its last tile (a harmless
+// reload), and rows past M or N to the last row: the output rows and columns
+// they feed are never stored, so the loop body has no branches.
+struct PpShape {
+    static constexpr int TM = 256, TN = 128;
+    static constexpr int APLANE = TM * 32, BPLANE = TN * 32;      // bytes per K tile
+    static constexpr int STAGE = 4 * APLANE + 4 * BPLANE;        // four 16-bit planes each
+    static constexpr int NSTAGE = 3;
+    static constexpr int LDS = NSTAGE * STAGE;
+    static constexpr int ABLK = 4 * TM / 32, BBLK = 4 * TN / 32;  // 1 KB blocks per K tile
+    static constexpr int DA = ABLK / 4, DB = BBLK / 4;            // direct loads per wave
+};
+
+typedef void __attribute__((address_space(3)))* lptr_t;
+typedef const void __attribute__((address_space(1)))* gvptr_t;
+
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding:
+// vmcnt bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x70 | 0xF00);
+}
+
+template <int P, class Epi>
+__device__ __forceinline__ void pp_tile(const NtEntry& e, int m0, int n0, int kb, int ke, int s,
+                                        int split, unsigned char* smem) {
+    using C = PpShape;
+    const int nk = ke > kb ? (ke - kb) / kKT : 0;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 128, wn = (wave & 1) * 64;
+    const int l32 = lane & 31, g = lane >> 5;
+
+    floatx16 cr[4][2], ci[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                cr[i][j][r] = 0.f;
+                ci[i][j][r] = 0.f;
+            }
+
+    if (nk > 0) {
+        const unsigned char* Ab = static_cast<const unsigned char*>(e.a);
+        const unsigned char* Bb = static_cast<const unsigned char*>(e.b);
+        // direct loads of this wave: A blocks wave + 4u, B blocks wave + 4u
+        // (block = plane * rows / 32 + row block); lane -> (row, 16-byte half).
+        // Address = wave-uniform base (plane, K tile, tile origin) + a 32-bit
+        // lane offset below 8 KB (the row clamp keeps m - m0 in [0, 256)).
+        const int lr = lane >> 1, lh = (lane & 1) ^ ((lr >> 3) & 1);
+        unsigned aoff[C::DA], boff[C::DB];
+#pragma unroll
+        for (int u = 0; u < C::DA; ++u) {
+            const int rb = (wave + 4 * u) % (C::TM / 32);
+            const int m = min(m0 + 32 * rb + lr, e.M - 1);
+            aoff[u] = (unsigned)(((m - m0) * 16 + 8 * lh) * 2);
+        }
+#pragma unroll
+        for (int u = 0; u < C::DB; ++u) {
+            const int rb = (wave + 4 * u) % (C::TN / 32);
+            const int n = min(n0 + 32 * rb + lr, e.N - 1);
+            boff[u] = (unsigned)(((n - n0) * 16 + 8 * lh) * 2);
+        }
+        const unsigned char* abase = Ab + ((size_t)(kb >> 4) * e.lda + (size_t)m0 * 16) * 2;
+        const unsigned char* bbase = Bb + ((size_t)(kb >> 4) * e.ldb + (size_t)n0 * 16) * 2;
+        // one K tile = one K block: lda / ldb elements (rows x 16) of 2 bytes
+        const size_t astep = (size_t)e.lda * 2, bstep = (size_t)e.ldb * 2;
+        const size_t aps = (size_t)e.a_ps * 2, bps = (size_t)e.b_ps * 2;     // bytes per plane
+        auto issue = [&](int kt, int stage_off) {
+            const int t = kt < nk ? kt : nk - 1;
+            unsigned char* st = smem + stage_off;
+#pragma unroll
+            for (int u = 0; u < C::DA; ++u) {
+                const int plane = (wave + 4 * u) / (C::TM / 32);
+                const unsigned char* src = abase + (size_t)t * astep + plane * aps;
+                __builtin_amdgcn_global_load_lds((gvptr_t)(src + aoff[u]),
+                                                 (lptr_t)(st + (wave + 4 * u) * 1024), 16, 0, 0);
+            }
+#pragma unroll
+            for (int u = 0; u < C::DB; ++u) {
+                const int plane = (wave + 4 * u) / (C::TN / 32);
+                const unsigned char* src = bbase + (size_t)t * bstep + plane * bps;
+                __builtin_amdgcn_global_load_lds((gvptr_t)(src + boff[u]),
+                                                 (lptr_t)(st + 4 * C::APLANE + (wave + 4 * u) * 1024),
+                                                 16, 0, 0);
+            }
+        };
+        // a lane's operands: row l32 of a 32-row block, K half g
+        const int slot = (2 * l32 + (g ^ ((l32 >> 3) & 1))) * 16;
+        // stage_off: byte offset of a stage (wave-uniform); the rest folds into
+        // the read's immediate offset
+        const int abyte = (wm >> 5) * 1024 + slot, bbyte = 4 * C::APLANE + (wn >> 5) * 1024 + slot;
+        auto read_a = [&](int stage_off, int i, int c) {
+            return *reinterpret_cast<const u32x4*>(smem + (stage_off + abyte) + c * C::APLANE + i * 1024);
+        };
+        auto read_b = [&](int stage_off, int j, int c) {
+            return *reinterpret_cast<const u32x4*>(smem + (stage_off + bbyte) + c * C::BPLANE + j * 1024);
+        };
+
+        constexpr int NL = C::DA + C::DB;  // direct loads per wave and K tile
+        issue(0, 0);
+        issue(1, C::STAGE);
+        issue(2, 2 * C::STAGE);
+        wait_vmcnt<2 * NL>();
+        __syncthreads();
+        u32x4 a[4][4], b0[2][4], b1[2][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) a[i][c] = read_a(0, i, c);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b0[j][c] = read_b(0, j, c);
+
+        // One K tile: (a, b) hold tile kt.  After the MFMAs of A block row i,
+        // block row i of tile kt + 1 is read into its registers; B of tile
+        // kt + 1 goes to bn.  The barrier sits after block row 0, when every
+        // read of tile kt (issued during the previous K tile) has long landed.
+        // so_cur: stage of tile kt (takes tile kt + 3), so_nxt: stage of tile kt + 1;
+        // rotated through the three stages by the loop
+        int so_cur = 0, so_nxt = C::STAGE, so_far = 2 * C::STAGE;
+        auto step = [&](int kt, u32x4 (&b)[2][4], u32x4 (&bn)[2][4]) {
+            // -B_im: flip the sign bit of every 16-bit half
+            u32x4 nb[2][2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                nb[j][0] = b[j][2] ^ 0x80008000u;
+                nb[j][1] = b[j][3] ^ 0x80008000u;
+            }
+            const int sn = __builtin_amdgcn_readfirstlane(so_nxt);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    cr[i][j] = prod3<P>(cr[i][j], a[i][0], a[i][1], b[j][0], b[j][1]);
+                    ci[i][j] = prod3<P>(ci[i][j], a[i][0], a[i][1], b[j][2], b[j][3]);
+                    cr[i][j] = prod3<P>(cr[i][j], a[i][2], a[i][3], nb[j][0], nb[j][1]);
+                    ci[i][j] = prod3<P>(ci[i][j], a[i][2], a[i][3], b[j][0], b[j][1]);
+                }
+                if (i == 0) {
+                    // own direct loads of tile kt + 1 done (tile kt + 2's may be in
+                    // flight), then everyone's: tile kt + 1 visible, and stage
+                    // kt % 3 (tile kt) read by every wave, so it takes tile kt + 3
+                    wait_vmcnt<NL>();
+                    __syncthreads();
+                    issue(kt + 3, __builtin_amdgcn_readfirstlane(so_cur));
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) bn[j][c] = read_b(sn, j, c);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) a[i][c] = read_a(sn, i, c);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            const int t = so_cur;
+            so_cur = so_nxt;
+            so_nxt = so_far;
+            so_far = t;
+        };
+        for (int kt = 0; kt < nk; ++kt) {
+            step(kt, b0, b1);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) b0[j][c] = b1[j][c];
+        }
+        // no direct load may still write the LDS when the workgroup ends
+        wait_vmcnt<0>();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int qd = 0; qd < 4; ++qd) {
+                float re[4], im[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    re[q] = cr[i][j][4 * qd + q];
+                    im[q] = ci[i][j][4 * qd + q];
+                }
+                Epi::store4(e, s, split, m0 + wm + 32 * i + 8 * qd + 4 * g,
+                            n0 + wn + 32 * j + l32, re, im);
+            }
+}
+
+// Direct schedule of the one-workgroup-per-CU split kernel (block id = s * count + t).
+template <int P, class Epi>
+__global__ __launch_bounds__(256, 1) void nt_pp_kernel(const NtEntry* __restrict__ entries,
+                                                       int n_entries,
+                                                       const int* __restrict__ tile_count,
+                                                       int split) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[PpShape::LDS];
+    const int count = *tile_count;
+    const int total = count * split;
+    if ((int)blockIdx.x >= total) return;
+    const int bid = xcd_run_index(total);
+    const int s = bid / count;
+    const int t = bid - s * count;
+    const NtEntry e = entries[find_entry(entries, n_entries, t)];
+    const int local = t - e.tile_begin;
+    const int m0 = (local / e.tiles_n) * PpShape::TM;
+    const int n0 = (local % e.tiles_n) * PpShape::TN;
+    const int chunk = pad_kt((e.K + split - 1) / split);
+    const int kb = s * chunk;
+    const int ke = min(e.K, kb + chunk);
+    pp_tile<P, Epi>(e, m0, n0, kb, ke, s, split, smem);
+}
+
+// Direct schedule: block id = s * count + t.  (Round-robin over the XCDs: the
+// tables of the first contraction mix problems of very different K, which
+// contiguous runs per XCD would leave unbalanced -- measured 1.8x slower.)
 template <int P, bool A_CPLX, class Epi, int TM, int TN>
 __global__ __launch_bounds__(256, direct_occ<P>()) void nt_direct_kernel(
     const NtEntry* __restrict__ entries, int n_entries, const int* __restrict__ tile_count,
@@ -538,9 +791,18 @@ hipError_t second_direct(int ny, int nx, int split, const NtBuffers& b, hipStrea
     return hipGetLastError();
 }
 
+template <int P>
+hipError_t second_pp(int ny, int nx, int split, const NtBuffers& b, hipStream_t s) {
+    const int tiles = nt_tiles(ny, nx, PpShape::TM, PpShape::TN);
+    hipLaunchKernelGGL((nt_pp_kernel<P, SecondEpi>), dim3(tiles * split), dim3(256), 0, s,
+                       b.second, 1, &b.hdr->second_tiles, split);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int nt_first_tile_m(int precision) { return precision == P_FP32 ? 64 : 128; }
+int nt_second_tile_m(int precision) { return precision == P_FP32 ? 128 : PpShape::TM; }
 int nt_second_tile_n(int precision) { return precision == P_FP32 ? 64 : 128; }
 
 hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffers& b,
@@ -553,8 +815,8 @@ hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffer
 
 hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBuffers& b,
                             hipStream_t s) {
-    if (precision == P_BF16) return second_direct<P_BF16, 128>(ny, nx, split, b, s);
-    if (precision == P_FP16) return second_direct<P_FP16, 128>(ny, nx, split, b, s);
+    if (precision == P_BF16) return second_pp<P_BF16>(ny, nx, split, b, s);
+    if (precision == P_FP16) return second_pp<P_FP16>(ny, nx, split, b, s);
     return second_direct<P_FP32, 64>(ny, nx, split, b, s);
 }
 
