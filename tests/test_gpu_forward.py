@@ -215,6 +215,18 @@ def test_split_precision_edge_cases(precision):
     assert np.all(gpu_hologram(z, precision=precision) == 0)
 
 
+@pytest.mark.parametrize("precision", ["bf16_split", "fp16_split"])
+@pytest.mark.parametrize("shape,planes", [((264, 200), 3), ((520, 136), 2)])
+def test_split_second_contraction_partial_tiles(precision, shape, planes):
+    # sides just past the split second contraction's 256 x 128 output tile: the last row
+    # and column tiles run mostly on clamped rows; whole hologram against the FP64 oracle
+    s = scenes.random_scene(500 + planes, *shape, planes=planes)
+    h = gpu_hologram(s, precision=precision)
+    err = rel_l2(h, separable_window(s, 0, 0, *shape))
+    print(f"{precision} {shape} x{planes}: rel-L2 {err:.3e}")
+    assert err <= SPLIT_TOL
+
+
 # ------------------------------------------------ full-size windows, separable FP64 oracle
 def separable_window(s, y0, x0, h, w):
     from oracle import separable
