@@ -447,6 +447,34 @@ def roofline(stats, prec, avg_ms, kernel, traffic=None, issue=None):
     }
 
 
+def timed_steps(step, steps):
+    """Times `steps` calls of step() with a HIP event pair only around the second
+    contraction (every recorded event idles the stream a few microseconds), then
+    runs a few more steps with a pair at every stage for the per-stage breakdown.
+    Returns (seconds, (second-contraction ms, launches), per-stage profile)."""
+    import torch
+
+    from paper_2211_09938_amd import cgh
+
+    torch.cuda.synchronize()
+    cgh.profile_stages(["second"])
+    cgh.profile_enable(True)
+    cgh.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    second = cgh.profile_read(reset=True)["second"]
+    cgh.profile_stages(None)
+    for _ in range(min(steps, 5)):
+        step()
+    torch.cuda.synchronize()
+    prof = cgh.profile_read(reset=True)
+    cgh.profile_enable(False)
+    return elapsed, second, prof
+
+
 def run_single(scene, prec, steps, warmup, workload):
     import torch
 
@@ -468,19 +496,8 @@ def run_single(scene, prec, steps, warmup, workload):
 
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    cgh.profile_enable(True)
-    cgh.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = cgh.profile_read(reset=True)
-    cgh.profile_enable(False)
+    elapsed, (sec_ms, sec_n), prof = timed_steps(step, steps)
     stats = cgh.workspace_stats(ws, ny, nx, n_layers, scene.levels, prec)
-    sec_ms, sec_n = prof["second"]
     kernel = f"second contraction ({SECOND_KERNEL[prec]}<{prec}, complex A, {SECOND_TILE[prec]}>)"
     # the HBM-bound coefficient stage: flag clear + fused layer split / Haar / masks;
     # algorithmic bytes = object 4 B + layer id 1 B + saliency 4 B read per pixel,
@@ -527,21 +544,11 @@ def run_grad(scene, prec, steps, warmup):
 
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    cgh.profile_enable(True)
-    cgh.profile_read(reset=True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = cgh.profile_read(reset=True)
-    cgh.profile_enable(False)
+    elapsed, (sec_ms, sec_n), prof = timed_steps(step, steps)
     ws = torch.empty(cgh.workspace_size(ny, nx, 1, scene.levels, prec), dtype=torch.uint8, device=dev)
     cgh.progressive_hologram(obj.detach(), [z], scene.lam, scene.pitch, scene.levels, sal,
                              precision=prec, workspace=ws)
     stats = cgh.workspace_stats(ws, ny, nx, 1, scene.levels, prec)
-    sec_ms, sec_n = prof["second"]
     return {
         "value": steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,

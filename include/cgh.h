@@ -341,6 +341,13 @@ enum {
  * (events come from a library-owned pool).  Process-wide, thread-safe. */
 int cgh_profile_enable(int on);
 
+/* Restricts the stages that record event pairs while profiling is on to those
+ * whose bit (1u << CGH_STAGE_*) is set in mask; the default is every stage.
+ * Each recorded event idles the stream for a few microseconds, so a timed loop
+ * that needs one stage's duration brackets only that stage.  Process-wide,
+ * thread-safe; never fails. */
+int cgh_profile_stages(unsigned mask);
+
 /* Waits for every recorded event pair, adds the elapsed times to per-stage
  * totals and returns them: ms[CGH_STAGE_COUNT] milliseconds and
  * launches[CGH_STAGE_COUNT] event pairs, both [host], either may be NULL.

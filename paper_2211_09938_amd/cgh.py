@@ -70,6 +70,7 @@ SIGNATURES = {
     "cgh_angular_spectrum": (_c_int, [_vp, _c_int, _c_int, _c_double, _c_double, _c_double, _vp,
                                       _sz, _vp, _vp]),
     "cgh_profile_enable": (_c_int, [_c_int]),
+    "cgh_profile_stages": (_c_int, [_c_uint]),
     "cgh_profile_read": (_c_int, [ctypes.POINTER(_c_double), ctypes.POINTER(ctypes.c_longlong),
                                   _c_int]),
     "cgh_workspace_stats": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp]),
@@ -441,6 +442,12 @@ def reconstruct(hologram, lam, pitch, z, out=None, workspace=None):
 
 def profile_enable(on=True):
     _check(lib().cgh_profile_enable(1 if on else 0), "cgh_profile_enable")
+
+
+def profile_stages(names=None):
+    """Stages (names from STAGES) that record event pairs while profiling is on; None: all."""
+    mask = 0xFFFFFFFF if names is None else sum(1 << STAGES.index(n) for n in names)
+    _check(lib().cgh_profile_stages(mask), "cgh_profile_stages")
 
 
 def profile_read(reset=True):

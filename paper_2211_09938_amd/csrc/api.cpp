@@ -446,6 +446,13 @@ int cgh_profile_enable(int on) {
     return CGH_SUCCESS;
 }
 
+int cgh_profile_stages(unsigned mask) {
+    Profiler& p = profiler();
+    std::lock_guard<std::mutex> g(p.mu);
+    p.mask = mask;
+    return CGH_SUCCESS;
+}
+
 int cgh_profile_read(double* ms, long long* launches, int reset) {
     try {
         Profiler& p = profiler();

@@ -204,6 +204,7 @@ inline int check_common(int n_layers, const uint8_t* layer_index, const double* 
 struct Profiler {
     std::mutex mu;
     bool on = false;
+    unsigned mask = ~0u;  // stages that record while on (bit 1 << stage)
     std::vector<hipEvent_t> pool;
     struct Pair { int stage; hipEvent_t a, b; };
     std::vector<Pair> pending;
@@ -229,7 +230,7 @@ struct StageTimer {
     StageTimer(hipStream_t st, int stg) : s(st), stage(stg) {
         Profiler& p = profiler();
         std::lock_guard<std::mutex> g(p.mu);
-        if (!p.on) return;
+        if (!p.on || !((p.mask >> stage) & 1u)) return;
         a = p.take();
         b = p.take();
         if (a && b && hipEventRecord(a, s) == hipSuccess) return;
