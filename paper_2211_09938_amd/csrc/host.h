@@ -116,13 +116,14 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
     return lo;
 }
 
-// Split of the single-scene second contraction: about 512 resident workgroups
-// with the precision's tile shape (256 for the one-per-CU split kernel), at most
-// the layout's split (128 x 128 tiles), which sized the partial buffer.
+// Split of the single-scene second contraction: as many workgroups as can be
+// resident with the precision's kernel and tile shape (FP32: two per CU; the split
+// forms' kernel: one per CU, 144 KB of LDS), at most the layout's split (128 x 128
+// tiles, 512 workgroups), which sized the partial buffer.
 inline int second_split(const cgh::Layout& lo, int ny, int nx, int levels, int layers,
                         int precision) {
     const int tm = cgh::nt_second_tile_m(precision), tn = cgh::nt_second_tile_n(precision);
-    const int target = tm * tn > cgh::kNtTile * cgh::kNtTile ? 256 : 512;
+    const int target = precision == CGH_FP32 ? 512 : 256;
     const int split = choose_split(ny, nx, levels, layers, tm, tn, target);
     return split < lo.split_k ? split : lo.split_k;
 }
