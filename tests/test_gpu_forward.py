@@ -161,6 +161,32 @@ def test_repeatable_bit_for_bit():
     assert np.array_equal(gpu_hologram(s), gpu_hologram(s))
 
 
+def test_profile_stage_mask_records_only_selected_stages():
+    from paper_2211_09938_amd import cgh
+
+    s = scenes.tiny()
+    cgh.profile_read(reset=True)
+    cgh.profile_stages(["second"])
+    cgh.profile_enable(True)
+    try:
+        gpu_hologram(s)
+        gpu_hologram(s, precision="bf16_split")
+        prof = cgh.profile_read(reset=True)
+    finally:
+        cgh.profile_enable(False)
+        cgh.profile_stages(None)
+    assert prof["second"][1] == 2 and prof["second"][0] > 0
+    assert all(n == 0 for name, (_, n) in prof.items() if name != "second")
+    # the default mask records every stage again
+    cgh.profile_enable(True)
+    try:
+        gpu_hologram(s)
+        prof = cgh.profile_read(reset=True)
+    finally:
+        cgh.profile_enable(False)
+    assert all(prof[name][1] == 1 for name in ("coef", "lut", "plan", "first", "second"))
+
+
 def test_invalid_workspace_leaves_output_untouched():
     import torch
 
