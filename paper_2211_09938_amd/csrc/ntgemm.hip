@@ -490,7 +490,9 @@ __device__ __forceinline__ int xcd_run_index(int total) {
 //    two K tiles ahead of their use;
 //  * the next K tile's operands are read LDS -> registers block row by block
 //    row as the current tile's MFMAs release them (B through a second set);
-//  * one barrier per K tile, placed after the first block row's MFMAs.
+//  * one barrier per K tile, preceded by the wait for the wave's own direct
+//    loads of the next tile (the compiler schedules the two ahead of the first
+//    block row's MFMAs; fenced after them they measured the same).
 // LDS layout of a stage: per plane, blocks of 32 rows x 32 bytes (1 KB, one
 // direct load of a wave); in a block, row r's 16-byte half h sits in slot
 // 2r + (h ^ ((r >> 3) & 1)), so the 16 lanes of each phase of a 16-byte read
@@ -615,8 +617,8 @@ __device__ __forceinline__ void pp_tile(const NtEntry& e, int m0, int n0, int kb
 
         // One K tile: (a, b) hold tile kt.  After the MFMAs of A block row i,
         // block row i of tile kt + 1 is read into its registers; B of tile
-        // kt + 1 goes to bn.  The barrier sits after block row 0, when every
-        // read of tile kt (issued during the previous K tile) has long landed.
+        // kt + 1 goes to bn.  The wait and the barrier belong to block row 0's
+        // step (the compiler places them ahead of that row's MFMAs).
         // so_cur: stage of tile kt (takes tile kt + 3), so_nxt: stage of tile kt + 1;
         // rotated through the three stages by the loop
         int so_cur = 0, so_nxt = C::STAGE, so_far = 2 * C::STAGE;
