@@ -233,6 +233,62 @@ __global__ __launch_bounds__(1024) void batch_prefix_kernel(const PlanHeader* __
     }
 }
 
+// Fringe panels through LDS.  Column k' of a panel is a contiguous slice of a 1D
+// fringe table (row y reads entry y - j 2^l + n for the k'-th active row j).  A
+// workgroup takes 256 rows x one 16-wide K block: it reads the table with the
+// lanes along the rows (one contiguous run per k'), keeps the tile in LDS (row
+// pitch 17 floats: the 64 lanes of a read or write hit 64 different banks), and
+// writes the tile's K-blocked storage -- 256 rows x 16 elements, contiguous --
+// with consecutive lanes on consecutive 4-element chunks.
+constexpr int kFringeRows = 256, kFringePitch = 17;
+
+template <int P>
+__device__ __forceinline__ void fringe_tiles(const float* __restrict__ lutl, int len,
+                                             const int* __restrict__ list, int count, int half,
+                                             int l, int n, int padded, void* panel, size_t ps,
+                                             size_t base) {
+    __shared__ float lre[kFringeRows * kFringePitch], lim[kFringeRows * kFringePitch];
+    const int tid = threadIdx.x;
+    const int ytiles = (n + kFringeRows - 1) / kFringeRows;
+    const int tasks = ytiles * (padded / 16);
+    for (int task = blockIdx.x; task < tasks; task += gridDim.x) {
+        const int kb = task / ytiles, y0 = (task - kb * ytiles) * kFringeRows;
+        const int y = y0 + tid;
+#pragma unroll 4
+        for (int q = 0; q < 16; ++q) {
+            const int i = 16 * kb + q;
+            float re = 0.f, im = 0.f;
+            if (i < count && y < n) {
+                const int r = list[i];
+                const int band = r >= half, j = r - band * half;
+                const float* tb = lutl + (size_t)band * 2 * len;
+                const int idx = y - (j << l) + n;
+                re = tb[idx];
+                im = tb[len + idx];
+            }
+            lre[tid * kFringePitch + q] = re;
+            lim[tid * kFringePitch + q] = im;
+        }
+        __syncthreads();
+        // chunk c = 4 elements: row c / 4 of the tile, k' 4 (c % 4) .. + 3
+        const size_t tile = base + ((size_t)kb * n + y0) * 16;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int c = s4 * kFringeRows + tid, row = c >> 2, k4 = (c & 3) * 4;
+            if (y0 + row < n) {
+                float re[4], im[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    re[q] = lre[row * kFringePitch + k4 + q];
+                    im[q] = lim[row * kFringePitch + k4 + q];
+                }
+                put_c4<P>(panel, ps, tile + 4 * (size_t)c, re, im);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <int P>
 __device__ __forceinline__ void fy_block(const float* __restrict__ lut_y,
                                          const int* __restrict__ rowlist,
@@ -242,35 +298,11 @@ __device__ __forceinline__ void fy_block(const float* __restrict__ lut_y,
     const int d = dl / levels, l = dl % levels + 1;
     const int cr = cnt_row[dl], pr = pad_kt(cr);
     if (pr == 0) return;
-    const int seg = seg_row[dl];
-    const int nyl = ny >> l, len = lut_len(ny);
-    const int* rl = rowlist + dl_rows_off(ny, levels, d, l);
-    const float* lutl = lut_y + lut_table(d, l, 0, 0, levels) * len;
-    // four consecutive storage elements per thread: one row y, four k'
-    const long long total4 = (long long)ny * pr / 4;
-    for (long long e4 = (long long)blockIdx.x * blockDim.x + threadIdx.x; e4 < total4;
-         e4 += (long long)gridDim.x * blockDim.x) {
-        const size_t e = (size_t)e4 * 4;
-        int y, i0;
-        kblk_pos(e, ny, y, i0);
-        float re[4], im[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = i0 + q;
-            re[q] = 0.f;
-            im[q] = 0.f;
-            if (i < cr) {
-                const int r = rl[i];
-                const int band = r >= nyl, j = r - band * nyl;
-                const float* tb = lutl + (size_t)band * 2 * len;
-                const int idx = y - (j << l) + ny;
-                re[q] = tb[idx];
-                im[q] = tb[len + idx];
-            }
-        }
-        // the segment starts on a K-block boundary: its blocks follow in storage order
-        put_c4<P>(fy, ps, (size_t)seg * ny + e, re, im);
-    }
+    const int len = lut_len(ny);
+    // the segment starts on a K-block boundary: its blocks follow in storage order
+    fringe_tiles<P>(lut_y + lut_table(d, l, 0, 0, levels) * len, len,
+                    rowlist + dl_rows_off(ny, levels, d, l), cr, ny >> l, l, ny, pr, fy, ps,
+                    (size_t)seg_row[dl] * ny);
 }
 
 template <int P>
@@ -282,33 +314,10 @@ __device__ __forceinline__ void fx_block(const float* __restrict__ lut_x,
     const int d = dl / levels, l = dl % levels + 1;
     const int cc = cnt_col[dl], pc = pad_kt(cc);
     if (pc == 0 || cnt_row[dl] == 0) return;
-    const int nxl = nx >> l, len = lut_len(nx);
-    const int* cl = collist + dl_cols_off(nx, levels, d, l);
-    const float* lutl = lut_x + lut_table(d, l, 0, 0, levels) * len;
-    const size_t base = dl_fx_off(nx, levels, d, l);
-    const long long total4 = (long long)nx * pc / 4;
-    for (long long e4 = (long long)blockIdx.x * blockDim.x + threadIdx.x; e4 < total4;
-         e4 += (long long)gridDim.x * blockDim.x) {
-        const size_t e = (size_t)e4 * 4;
-        int x, c0;
-        kblk_pos(e, nx, x, c0);
-        float re[4], im[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = c0 + q;
-            re[q] = 0.f;
-            im[q] = 0.f;
-            if (c < cc) {
-                const int j = cl[c];
-                const int band = j >= nxl, jj = j - band * nxl;
-                const float* tb = lutl + (size_t)band * 2 * len;
-                const int idx = x - (jj << l) + nx;
-                re[q] = tb[idx];
-                im[q] = tb[len + idx];
-            }
-        }
-        put_c4<P>(fx, ps, base + e, re, im);
-    }
+    const int len = lut_len(nx);
+    fringe_tiles<P>(lut_x + lut_table(d, l, 0, 0, levels) * len, len,
+                    collist + dl_cols_off(nx, levels, d, l), cc, nx >> l, l, nx, pc, fx, ps,
+                    dl_fx_off(nx, levels, d, l));
 }
 
 template <int P>
@@ -467,11 +476,12 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
     const long long big_y = (long long)ny * pad_kt(band_side(ny, 1));
     const long long big_x = (long long)nx * pad_kt(band_side(nx, 1));
     const long long big_c = (long long)band_side(ny, 1) * pad_kt(band_side(nx, 1));
-    hipLaunchKernelGGL(fy_kernel<P>, dim3(grid_for(big_y), n_dl), dim3(256), 0, s, lut_y,
+    // fringe panels: one workgroup per 256 rows x 16 K = 4096 elements (grid_for sizes for 2048)
+    hipLaunchKernelGGL(fy_kernel<P>, dim3(grid_for(big_y / 2), n_dl), dim3(256), 0, s, lut_y,
                        b.rowlist, b.cnt_row, b.seg_row, ny, levels, b.fy, b.fy_ps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fx_kernel<P>, dim3(grid_for(big_x), n_dl), dim3(256), 0, s, lut_x,
+    hipLaunchKernelGGL(fx_kernel<P>, dim3(grid_for(big_x / 2), n_dl), dim3(256), 0, s, lut_x,
                        b.collist, b.cnt_row, b.cnt_col, nx, levels, b.fx, b.fx_ps);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(cb_kernel<P>, dim3(grid_for(big_c), n_dl), dim3(256), 0, s, coef,
