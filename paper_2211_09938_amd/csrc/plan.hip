@@ -237,9 +237,10 @@ __global__ __launch_bounds__(1024) void batch_prefix_kernel(const PlanHeader* __
 // fringe table (row y reads entry y - j 2^l + n for the k'-th active row j).  A
 // workgroup takes 256 rows x one 16-wide K block: it reads the table with the
 // lanes along the rows (one contiguous run per k'), keeps the tile in LDS (row
-// pitch 17 floats: the 64 lanes of a read or write hit 64 different banks), and
-// writes the tile's K-blocked storage -- 256 rows x 16 elements, contiguous --
-// with consecutive lanes on consecutive 4-element chunks.
+// pitch 17 floats: the LDS stores of each table read hit 64 different banks; the
+// chunk reads that follow can pair up on a bank), and writes the tile's K-blocked
+// storage -- 256 rows x 16 elements, contiguous -- with consecutive lanes on
+// consecutive 4-element chunks.
 constexpr int kFringeRows = 256, kFringePitch = 17;
 
 template <int P>
