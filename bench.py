@@ -427,6 +427,12 @@ def gauss_tile(prec, tm, tn):
     return prec == "fp32" and tm * tn <= 128 * 64
 
 
+def batch_second_kernel(prec, info):
+    """The batch's second contraction: the ring kernel when the autotuner chose its tile."""
+    return ("nt_pp_kernel" if prec != "fp32" and tuple(info["second_tile"]) == (256, 128)
+            else "nt_persistent_kernel")
+
+
 def roofline(stats, prec, avg_ms, kernel, traffic=None, issue=None):
     """Second contraction: algorithmic flops per launch / average launch time."""
     achieved = stats["flops_second"] / (avg_ms * 1e-3) / 1e12
@@ -602,7 +608,7 @@ def run_batch(batch, prec, steps, warmup, tune_cache):
         "stages_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
         "work": stats,
         "roofline": roofline(stats, prec, sec_ms / max(1, sec_n),
-                             f"second contraction (nt_persistent_kernel<{prec}, "
+                             f"second contraction ({batch_second_kernel(prec, info)}<{prec}, "
                              f"{info['second_tile'][0]}x{info['second_tile'][1]}"
                              + (", 3 real products per complex product>)"
                                 if gauss_tile(prec, *info["second_tile"]) else ">)"),

@@ -285,7 +285,9 @@ typedef struct cgh_plan cgh_plan;
  * problems of all scenes into one table per contraction, runs each contraction
  * as one persistent launch whose workgroups pull tiles from a shared counter,
  * and captures the whole batch into a HIP graph.  Tile shapes come from an
- * autotuner that times the candidates on this batch and caches the winners, as
+ * autotuner that times the candidates on this batch (for the split forms'
+ * second contraction also the one-workgroup-per-CU 256 x 128 kernel, launched
+ * over every scene's tiles) and caches the winners, as
  * JSON lines keyed by GPU architecture, precision and batch signature, in
  * tune_cache_path (NULL: no cache; the file is created if missing).
  * Plan creation synchronises `stream` (it runs the batch while tuning).

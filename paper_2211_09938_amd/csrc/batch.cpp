@@ -105,7 +105,21 @@ hipError_t enqueue_first(const cgh_plan& p, hipStream_t s, const int* tiles) {
                                      p.counts, p.queues, p.grid, s);
 }
 
+// The split forms' second contraction may also take the one-workgroup-per-CU
+// ring kernel (a direct launch over every scene's tiles); the autotuner decides.
+bool ring_second(const cgh_plan& p, const int* tiles) {
+    return p.precision != CGH_FP32 && tiles[2] == cgh::nt_ring_tile_m() &&
+           tiles[3] == cgh::nt_ring_tile_n();
+}
+
 hipError_t enqueue_second(const cgh_plan& p, hipStream_t s, const int* tiles) {
+    if (ring_second(p, tiles)) {
+        int max_tiles = 0;
+        for (const auto& sc : p.scenes)
+            max_tiles += cgh::nt_tiles(sc.s.ny, sc.s.nx, tiles[2], tiles[3]);
+        return cgh::launch_nt_ring_table(p.precision, p.second, (int)p.scenes.size(), p.counts + 1,
+                                         max_tiles, s);
+    }
     return cgh::launch_nt_persistent(true, p.precision, tiles[2], tiles[3], p.second,
                                      (int)p.scenes.size(), p.counts + 1, p.queues + 1, p.grid, s);
 }
@@ -147,7 +161,7 @@ std::string tune_key(const cgh_plan& p) {
 
 // Cache file: one JSON object per line,
 // {"key": "...", "first": [tm, tn], "second": [tm, tn], "ms_first": x, "ms_second": y}
-bool cache_lookup(const char* path, const std::string& key, int* tiles) {
+bool cache_lookup(const char* path, const std::string& key, bool split, int* tiles) {
     if (!path) return false;
     std::ifstream f(path);
     std::string line;
@@ -164,6 +178,8 @@ bool cache_lookup(const char* path, const std::string& key, int* tiles) {
         for (int q = 0; q < 2; ++q) {
             bool found = false;
             for (const auto& c : kCandidates) found |= (c[0] == t[2 * q] && c[1] == t[2 * q + 1]);
+            // the ring shape, second contraction of the split forms only
+            found |= q == 1 && split && t[2] == cgh::nt_ring_tile_m() && t[3] == cgh::nt_ring_tile_n();
             ok &= found;
         }
         if (!ok) continue;
@@ -183,7 +199,8 @@ void cache_store(const char* path, const std::string& key, const int* tiles, dou
     f << "{\"key\": \"" << key << buf;
 }
 
-// Times every candidate shape on this batch and keeps the fastest per contraction.
+// Times every candidate shape on this batch and keeps the fastest per contraction;
+// the split forms also time the ring kernel for the second contraction.
 hipError_t autotune(cgh_plan& p, hipStream_t s) {
     Events ev;
     hipError_t e = hipEventCreate(&ev.a);
@@ -208,6 +225,20 @@ hipError_t autotune(cgh_plan& p, hipStream_t s) {
         }
         if (t1 < best1) { best1 = t1; p.tiles[0] = c[0]; p.tiles[1] = c[1]; }
         if (t2 < best2) { best2 = t2; p.tiles[2] = c[0]; p.tiles[3] = c[1]; }
+    }
+    if (e == hipSuccess && p.precision != CGH_FP32) {
+        // the ring kernel for the second contraction, with the first's best shape
+        const int tiles[4] = {p.tiles[0], p.tiles[1], cgh::nt_ring_tile_m(), cgh::nt_ring_tile_n()};
+        e = upload_args(p, tiles, s);
+        double t2 = 1e30;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = enqueue(p, s, tiles, &ev);
+            if (e == hipSuccess) e = hipEventSynchronize(ev.c);
+            float m2 = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&m2, ev.b, ev.c);
+            if (rep > 0) t2 = std::min(t2, (double)m2);
+        }
+        if (t2 < best2) { best2 = t2; p.tiles[2] = tiles[2]; p.tiles[3] = tiles[3]; }
     }
     if (ev.a) (void)hipEventDestroy(ev.a);
     if (ev.b) (void)hipEventDestroy(ev.b);
@@ -388,7 +419,7 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
 
         const std::string key = tune_key(*p);
         if (e == hipSuccess) {
-            if (cache_lookup(tune_cache_path, key, p->tiles)) {
+            if (cache_lookup(tune_cache_path, key, p->precision != CGH_FP32, p->tiles)) {
                 p->from_cache = 1;
             } else {
                 e = autotune(*p, s);

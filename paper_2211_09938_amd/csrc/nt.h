@@ -211,6 +211,13 @@ hipError_t launch_nt_materialize(const float* coef, const float* lut_x, const fl
 int nt_first_tile_m(int precision);
 int nt_second_tile_m(int precision);
 int nt_second_tile_n(int precision);
+// The split forms' ring kernel over a table of second contractions (a batch of
+// scenes, no split-K): tile shape, and a direct launch of max_tiles workgroups
+// (at least the table's tile count, read from *tile_count on the device).
+int nt_ring_tile_m();
+int nt_ring_tile_n();
+hipError_t launch_nt_ring_table(int precision, const NtEntry* entries, int n_entries,
+                                const int* tile_count, int max_tiles, hipStream_t s);
 hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffers& b,
                            int max_tiles, hipStream_t s);
 hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBuffers& b,

@@ -699,7 +699,8 @@ __global__ __launch_bounds__(256, 1) void nt_pp_kernel(const NtEntry* __restrict
     const int count = *tile_count;
     const int total = count * split;
     if ((int)blockIdx.x >= total) return;
-    const int bid = xcd_run_index(total);
+    // one problem: XCD-contiguous runs; a table of scenes (different K): round-robin
+    const int bid = n_entries == 1 ? xcd_run_index(total) : (int)blockIdx.x;
     const int s = bid / count;
     const int t = bid - s * count;
     const NtEntry e = entries[find_entry(entries, n_entries, t)];
@@ -804,6 +805,23 @@ hipError_t second_pp(int ny, int nx, int split, const NtBuffers& b, hipStream_t 
 }  // namespace
 
 int nt_first_tile_m(int precision) { return precision == P_FP32 ? 64 : 128; }
+int nt_ring_tile_m() { return PpShape::TM; }
+int nt_ring_tile_n() { return PpShape::TN; }
+
+hipError_t launch_nt_ring_table(int precision, const NtEntry* entries, int n_entries,
+                                const int* tile_count, int max_tiles, hipStream_t s) {
+    if (max_tiles <= 0 || n_entries <= 0) return hipSuccess;
+    if (precision == P_BF16)
+        hipLaunchKernelGGL((nt_pp_kernel<P_BF16, SecondEpi>), dim3(max_tiles), dim3(256), 0, s,
+                           entries, n_entries, tile_count, 1);
+    else if (precision == P_FP16)
+        hipLaunchKernelGGL((nt_pp_kernel<P_FP16, SecondEpi>), dim3(max_tiles), dim3(256), 0, s,
+                           entries, n_entries, tile_count, 1);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 int nt_second_tile_m(int precision) { return precision == P_FP32 ? 128 : PpShape::TM; }
 int nt_second_tile_n(int precision) { return precision == P_FP32 ? 64 : 128; }
 

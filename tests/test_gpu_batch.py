@@ -209,3 +209,38 @@ def test_batch64_workload_matches_single_calls_and_oracle_windows(precision, tmp
         print(f"batch64 {precision} scene {s.name} window ({y0}, {x0}): rel-L2 {err:.2e}")
         assert err <= tol
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16_split"])
+def test_cached_ring_tile_for_second_contraction(precision, tmp_path):
+    """A cache entry naming the 256 x 128 ring kernel for the second contraction
+    is taken by the split forms (which then match their single-scene calls) and
+    rejected, with a fresh tuning, by FP32, which has no such kernel."""
+    import re
+
+    import torch
+
+    batch = make_batch(seed=17, n=6)
+    cache = str(tmp_path / "tune.jsonl")
+    devs = [dev_scene(s) for s in batch]
+    cgh().Plan(devs, scenes.WAVELENGTH, scenes.PITCH, precision=precision, tune_cache=cache).close()
+    with open(cache) as f:
+        line = f.read().strip()
+    with open(cache, "w") as f:
+        f.write(re.sub(r'"second": \[\d+, \d+\]', '"second": [256, 128]', line) + "\n")
+    plan = cgh().Plan(devs, scenes.WAVELENGTH, scenes.PITCH, precision=precision, tune_cache=cache)
+    info = plan.info()
+    if precision == "fp32":
+        assert not info["from_cache"] and list(info["second_tile"]) != [256, 128]
+        plan.close()
+        return
+    assert info["from_cache"] and list(info["second_tile"]) == [256, 128]
+    plan.execute()
+    torch.cuda.synchronize()
+    for s, h in zip(batch, plan.holograms):
+        assert rel_l2(h.cpu().numpy(), single(s, precision)) <= 1e-6
+    s = batch[2]
+    ys, xs = sample_pixels(*s.shape, seed=2, n_random=48)
+    h = plan.holograms[2].cpu().numpy()
+    assert rel_l2(h[ys, xs], oracle_hologram(s, pixels=(ys, xs))) <= 1e-3
+    plan.close()
