@@ -211,7 +211,7 @@ def test_batch64_workload_matches_single_calls_and_oracle_windows(precision, tmp
     plan.close()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16_split"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16_split", "fp16_split"])
 def test_cached_ring_tile_for_second_contraction(precision, tmp_path):
     """A cache entry naming the 256 x 128 ring kernel for the second contraction
     is taken by the split forms (which then match their single-scene calls) and
