@@ -161,7 +161,7 @@ std::string tune_key(const cgh_plan& p) {
 
 // Cache file: one JSON object per line,
 // {"key": "...", "first": [tm, tn], "second": [tm, tn], "ms_first": x, "ms_second": y}
-bool cache_lookup(const char* path, const std::string& key, bool split, int* tiles) {
+bool cache_lookup(const char* path, const std::string& key, bool split_form, int* tiles) {
     if (!path) return false;
     std::ifstream f(path);
     std::string line;
@@ -179,7 +179,7 @@ bool cache_lookup(const char* path, const std::string& key, bool split, int* til
             bool found = false;
             for (const auto& c : kCandidates) found |= (c[0] == t[2 * q] && c[1] == t[2 * q + 1]);
             // the ring shape, second contraction of the split forms only
-            found |= q == 1 && split && t[2] == cgh::nt_ring_tile_m() && t[3] == cgh::nt_ring_tile_n();
+            found |= q == 1 && split_form && t[2] == cgh::nt_ring_tile_m() && t[3] == cgh::nt_ring_tile_n();
             ok &= found;
         }
         if (!ok) continue;
