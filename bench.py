@@ -99,6 +99,9 @@ def parse():
                     help="hologram pixels the oracle evaluates for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune-cache", default=None, help="tile-shape cache for batched plans")
+    ap.add_argument("--mfma-peak", action="store_true",
+                    help="only run the matrix-core throughput probe (register-resident MFMA "
+                         "loops, no memory traffic) for FP32, BF16 and FP16 and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference for scaling hardware byte counters) and exit")
@@ -115,6 +118,45 @@ def copy_calibration(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_per_launch": n * 4, "launches": 5}), flush=True)
+
+
+# probe launches: (kind, iterations per wave) sized to about 20 ms at one wave per SIMD
+PEAK_PROBES = {"fp32": ("fp32", 20000), "bf16_split": ("bf16", 40000),
+               "fp16_split": ("fp16", 40000)}
+
+
+def mfma_attainable(prec, blocks=256, zero=False, launches=3):
+    """Sustained matrix-core rate (TFLOP/s) of the probe for the form's MFMA
+    instruction: mean over `launches` timed launches after one warm-up."""
+    import torch
+
+    from paper_2211_09938_amd import cgh
+
+    kind, iters = PEAK_PROBES[prec]
+    sink, flops = cgh.mfma_peak(kind, blocks, iters, zero)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(launches):
+        cgh.mfma_peak(kind, blocks, iters, zero, sink)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / launches
+    return flops / (ms * 1e-3) / 1e12, ms
+
+
+def mfma_peak_lines():
+    """One JSON line per probe configuration (the attainable-peak calibration)."""
+    for prec in ("fp32", "bf16_split", "fp16_split"):
+        for blocks in (256, 512):
+            for zero in (False, True):
+                tf, ms = mfma_attainable(prec, blocks, zero)
+                print(json.dumps({"probe": "mfma_peak", "instruction": PEAK_PROBES[prec][0],
+                                  "waves_per_simd": blocks // 256, "operands":
+                                  "zero" if zero else "random", "tflops": tf,
+                                  "published_peak_tflops": PEAKS_TFLOPS[prec],
+                                  "frac_of_published": tf / PEAKS_TFLOPS[prec],
+                                  "avg_launch_ms": ms}), flush=True)
 
 
 def cpu_baseline(scene, n_pixels, seed=12345):
@@ -624,6 +666,9 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.mfma_peak:
+        mfma_peak_lines()
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "

@@ -258,6 +258,33 @@ size_t cgh_angular_spectrum_workspace_size(int ny, int nx);  /* 0 for unsupporte
 int cgh_angular_spectrum(const float* field, int ny, int nx, double lambda, double pitch, double z,
                          void* workspace, size_t workspace_bytes, float* out, void* stream);
 
+/* Work counts of a forward pass: of the last cgh_progressive_hologram that used
+ * a workspace (cgh_workspace_stats), or summed over a plan's scenes
+ * (cgh_plan_get_stats). */
+typedef struct cgh_stats_s {
+    long long coef_rows_active;  /* nonzero rows of every layer's and level's coefficient square:
+                                    the K extent of the second contraction                    */
+    long long coef_rows_total;
+    long long k_padded;          /* K the second contraction ran over (segments padded to 16)  */
+    long long k_total;           /* K of the dense form (every row of every level and layer)   */
+    int k_tile;                  /* K tile of the contractions                                 */
+    int split_k;                 /* K-range split of the second contraction                    */
+    double flops_first;          /* algorithmic real flops, first contraction:
+                                    4 * nx * sum over (layer, level) of active rows x columns  */
+    double flops_second;         /* algorithmic real flops, second contraction:
+                                    8 * ny * nx * coef_rows_active                             */
+    double flops_second_issued;  /* 8 * ny * nx * k_padded: the count on the padded K (FP32
+                                    runs three real products per complex product there, i.e.
+                                    3/4 of it on the matrix cores)                          */
+    long long operators[4];      /* operator count of Sec. 3 per progressive step, for one image
+                                    plane (the saliency masks are shared by the layers):
+                                    [0] the approximation, one per point of the (ny/2^L) x
+                                    (nx/2^L) image; [j] the residual-map points of level L-j+1
+                                    whose block is salient (4 per salient detail position);
+                                    entries beyond `levels` are 0                             */
+    long long operators_pointwise; /* ny * nx: one operator per object point                   */
+} cgh_stats;
+
 /* ---------------------------------------------------------- batched plans */
 
 /*
@@ -323,7 +350,7 @@ int cgh_plan_get_info(const cgh_plan* plan, cgh_plan_info* info /* [host] */);
 
 /* Work counts of the plan's last execution, summed over its scenes (the
  * cgh_stats of every scene added up; split_k = 1).  Synchronises `stream`. */
-int cgh_plan_get_stats(const cgh_plan* plan, struct cgh_stats_s* stats /* [host] */, void* stream);
+int cgh_plan_get_stats(const cgh_plan* plan, cgh_stats* stats /* [host] */, void* stream);
 
 /* ------------------------------------------------------------ diagnostics */
 
@@ -356,35 +383,38 @@ int cgh_profile_stages(unsigned mask);
  * reset != 0 clears the totals after reading. */
 int cgh_profile_read(double* ms, long long* launches, int reset);
 
-/* Work counts of the last cgh_progressive_hologram that used `workspace`. */
-typedef struct cgh_stats_s {
-    long long coef_rows_active;  /* nonzero rows of every layer's and level's coefficient square:
-                                    the K extent of the second contraction                    */
-    long long coef_rows_total;
-    long long k_padded;          /* K the second contraction ran over (segments padded to 16)  */
-    long long k_total;           /* K of the dense form (every row of every level and layer)   */
-    int k_tile;                  /* K tile of the contractions                                 */
-    int split_k;                 /* K-range split of the second contraction                    */
-    double flops_first;          /* algorithmic real flops, first contraction:
-                                    4 * nx * sum over (layer, level) of active rows x columns  */
-    double flops_second;         /* algorithmic real flops, second contraction:
-                                    8 * ny * nx * coef_rows_active                             */
-    double flops_second_issued;  /* 8 * ny * nx * k_padded: the count on the padded K (FP32
-                                    runs three real products per complex product there, i.e.
-                                    3/4 of it on the matrix cores)                          */
-    long long operators[4];      /* operator count of Sec. 3 per progressive step, for one image
-                                    plane (the saliency masks are shared by the layers):
-                                    [0] the approximation, one per point of the (ny/2^L) x
-                                    (nx/2^L) image; [j] the residual-map points of level L-j+1
-                                    whose block is salient (4 per salient detail position);
-                                    entries beyond `levels` are 0                             */
-    long long operators_pointwise; /* ny * nx: one operator per object point                   */
-} cgh_stats;
 
 /* Reads the plan back from `workspace` (same problem arguments as the forward
  * call) and fills *stats [host].  Synchronises `stream`. */
 int cgh_workspace_stats(const void* workspace, int ny, int nx, int n_layers, int levels,
                         int precision, cgh_stats* stats, void* stream);
+
+/* Instruction of the matrix-core throughput probe. */
+enum {
+    CGH_PEAK_FP32 = 0, /* v_mfma_f32_32x32x2f32:     4096 flops per instruction  */
+    CGH_PEAK_BF16 = 1, /* v_mfma_f32_32x32x16_bf16: 32768 flops per instruction */
+    CGH_PEAK_FP16 = 2  /* v_mfma_f32_32x32x16_f16:  32768 flops per instruction */
+};
+
+/*
+ * Matrix-core throughput probe (diagnostics; not part of the method): what the
+ * matrix cores of this GPU sustain under dense load, the attainable rate beside
+ * the published peak.  Launches `blocks` workgroups of four waves; each wave
+ * runs iters x 32 MFMAs of `kind` on eight independent register accumulators
+ * (no memory access inside the loop), then every thread writes one float of
+ * its accumulator sum to sink.
+ *  zero_operands  0: pseudo-random operands of magnitude [0.5, 2), four A and
+ *                 four B sets in rotation, so the operand bits change from one
+ *                 MFMA to the next as in a contraction; 1: all-zero operands.
+ *  blocks         1 .. 1048576 (256 = one wave per SIMD on 256 CUs).
+ *  iters          1 .. 16777216.
+ *  sink           [device] blocks*256 floats, overwritten.
+ *  flops          [host] out: real flops of the launch, 2*M*N*K per MFMA.
+ * Errors: CGH_ERROR_INVALID_VALUE for an unknown kind, counts out of range or a
+ * NULL pointer (nothing launched); CGH_ERROR_HIP for a failed launch.
+ */
+int cgh_mfma_peak(int kind, int zero_operands, int blocks, int iters, float* sink, double* flops,
+                  void* stream);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcgh.so")
-SOURCES = ["dwt.hip", "lut.hip", "reduce.hip", "plan.hip", "ntgemm.hip", "dense.hip", "backward.hip", "exact.hip", "literal.hip", "angular.hip", "api.cpp", "batch.cpp"]
+SOURCES = ["dwt.hip", "lut.hip", "reduce.hip", "plan.hip", "ntgemm.hip", "dense.hip", "backward.hip", "exact.hip", "literal.hip", "angular.hip", "peak.hip", "api.cpp", "batch.cpp"]
 ARCH = os.environ.get("CGH_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -21,9 +21,12 @@ HIPCC_FLAGS = [
     "-Wall",
     "-Wno-unused-result",
     "-Wno-unused-const-variable",
-    # keep the compiler from forming packed FP32 VALU instructions
-    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+# Device sources only: keep the compiler from forming packed FP32 VALU
+# instructions.  The feature exists only for the GPU target; the host pass of a
+# .hip file reports it as unknown and ignores it (the .cpp sources hold no
+# device code and do not take it).
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def hipcc():
@@ -41,7 +44,7 @@ def build(verbose=False, jobs=4):
     for src in SOURCES:
         obj = os.path.join(build_dir, src.replace(".", "_") + ".o")
         objs.append(obj)
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        lang = ["-x", "hip"] + DEVICE_FLAGS if src.endswith(".hip") else []
         cmd = [hipcc()] + HIPCC_FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         if len(procs) >= jobs:

@@ -74,6 +74,7 @@ SIGNATURES = {
     "cgh_profile_read": (_c_int, [ctypes.POINTER(_c_double), ctypes.POINTER(ctypes.c_longlong),
                                   _c_int]),
     "cgh_workspace_stats": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp]),
+    "cgh_mfma_peak": (_c_int, [_c_int, _c_int, _c_int, _c_int, _vp, ctypes.POINTER(_c_double), _vp]),
     "cgh_plan_create": (_c_int, [_vp, _c_int, _c_int, _c_double, _c_double, _vp, _c_int, _c_uint,
                                  ctypes.c_char_p, _vp, ctypes.POINTER(_vp)]),
     "cgh_plan_execute": (_c_int, [_vp, _vp]),
@@ -456,6 +457,22 @@ def profile_read(reset=True):
     n = (ctypes.c_longlong * len(STAGES))()
     _check(lib().cgh_profile_read(ms, n, 1 if reset else 0), "cgh_profile_read")
     return {name: (ms[i], n[i]) for i, name in enumerate(STAGES)}
+
+
+PEAK_KINDS = {"fp32": 0, "bf16": 1, "fp16": 2}
+
+
+def mfma_peak(kind, blocks=256, iters=4096, zero_operands=False, sink=None):
+    """Launches the matrix-core throughput probe (cgh_mfma_peak) on the current
+    stream; returns (sink tensor, real flops of the launch)."""
+    torch = _torch()
+    if sink is None:
+        sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    flops = ctypes.c_double(0.0)
+    _check(lib().cgh_mfma_peak(PEAK_KINDS[kind], 1 if zero_operands else 0, blocks, iters,
+                               _dev_tensor(sink, torch.float32, "sink", (blocks * 256,)),
+                               ctypes.byref(flops), _stream()), "cgh_mfma_peak")
+    return sink, flops.value
 
 
 def workspace_stats(workspace, ny, nx, n_layers=1, levels=3, precision="fp32"):

@@ -439,6 +439,21 @@ int cgh_angular_spectrum(const float* field, int ny, int nx, double lambda, doub
     }
 }
 
+int cgh_mfma_peak(int kind, int zero_operands, int blocks, int iters, float* sink, double* flops,
+                  void* stream) {
+    try {
+        if (kind < CGH_PEAK_FP32 || kind > CGH_PEAK_FP16) return CGH_ERROR_INVALID_VALUE;
+        if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 24))
+            return CGH_ERROR_INVALID_VALUE;
+        if (!sink || !flops) return CGH_ERROR_INVALID_VALUE;
+        *flops = cgh::mfma_peak_flops(kind, blocks, iters);
+        return hip_status(cgh::launch_mfma_peak(kind, zero_operands ? 1 : 0, blocks, iters, sink,
+                                                (hipStream_t)stream));
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
 int cgh_profile_enable(int on) {
     Profiler& p = profiler();
     std::lock_guard<std::mutex> g(p.mu);

@@ -119,5 +119,8 @@ hipError_t launch_grad_synthesis(const float* gcoef, const uint8_t* layer, const
                                  hipStream_t s);
 hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double* c,
                        const double* pre_re, const double* pre_im, float* table, hipStream_t s);
+// Matrix-core throughput probe (peak.hip): real flops of a launch, and the launch.
+double mfma_peak_flops(int kind, int blocks, int iters);
+hipError_t launch_mfma_peak(int kind, int zero, int blocks, int iters, float* sink, hipStream_t s);
 
 }  // namespace cgh
