@@ -54,7 +54,10 @@ typedef enum {
     CGH_ERROR_UNSUPPORTED = 3,   /* a valid request this build does not implement */
     CGH_ERROR_OUT_OF_MEMORY = 4, /* plan creation could not allocate */
     CGH_ERROR_WORKSPACE = 5,     /* workspace NULL or smaller than cgh_workspace_size() */
-    CGH_ERROR_HIP = 6            /* a HIP runtime call or launch failed */
+    CGH_ERROR_HIP = 6,           /* a HIP runtime call or launch failed */
+    CGH_ERROR_INTERNAL = 7       /* a launch would not fit the workspace layout the library
+                                    computed itself: a library defect, reported before
+                                    anything is enqueued */
 } cgh_status;
 
 /* Arithmetic of the two dense contractions (the coefficient stage and the
@@ -101,6 +104,24 @@ int cgh_haar_idwt(const float* coeffs, int ny, int nx, int levels, float* x, voi
  * bytes: [host] output.
  */
 int cgh_workspace_size(int ny, int nx, int n_layers, int levels, int precision, size_t* bytes);
+
+/* How a workspace of cgh_workspace_size() bytes is divided (diagnostics). */
+typedef struct {
+    size_t total;           /* cgh_workspace_size()                                        */
+    size_t shared_bytes;    /* region shared by the paths' operand panels and scratch      */
+    size_t partial_bytes;   /* split-K partial holograms                                   */
+    int split_reserved;     /* partial holograms the layout holds room for                 */
+    int split_second;       /* K split of this precision's single-scene second contraction */
+    size_t forward_bytes;   /* forward operand panels (cgh_progressive_hologram, stages)   */
+    size_t backward_bytes;  /* adjoint panels, partials and tables (cgh_hologram_backward) */
+    size_t backprop_bytes;  /* back-propagation panels (cgh_fresnel_backpropagate)         */
+    size_t literal_bytes;   /* cgh_literal_hologram panels                                 */
+    size_t fused_bytes;     /* cgh_fused_hologram panels and reconstruction                */
+} cgh_layout_info;
+
+/* Fills *info [host] for the problem; errors as cgh_workspace_size(). */
+int cgh_workspace_layout(int ny, int nx, int n_layers, int levels, int precision,
+                         cgh_layout_info* info);
 
 /*
  * Progressive saliency-guided hologram (Sec. 2, Eqs. 1-3, steps 1-5):

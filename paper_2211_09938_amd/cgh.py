@@ -33,6 +33,7 @@ STATUS = {
     4: "CGH_ERROR_OUT_OF_MEMORY",
     5: "CGH_ERROR_WORKSPACE",
     6: "CGH_ERROR_HIP",
+    7: "CGH_ERROR_INTERNAL",
 }
 
 _lock = threading.Lock()
@@ -48,6 +49,7 @@ SIGNATURES = {
     "cgh_haar_dwt": (_c_int, [_vp, _c_int, _c_int, _c_int, _vp, _vp]),
     "cgh_haar_idwt": (_c_int, [_vp, _c_int, _c_int, _c_int, _vp, _vp]),
     "cgh_workspace_size": (_c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_sz)]),
+    "cgh_workspace_layout": (_c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, _vp]),
     "cgh_progressive_hologram": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double,
                                           _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp,
                                           _vp]),
@@ -112,6 +114,23 @@ class PlanInfo(ctypes.Structure):
         ("tune_ms_second", _c_double),
         ("device_bytes", _sz),
     ]
+
+class LayoutInfo(ctypes.Structure):
+    """Mirror of cgh_layout_info."""
+
+    _fields_ = [
+        ("total", _sz),
+        ("shared_bytes", _sz),
+        ("partial_bytes", _sz),
+        ("split_reserved", _c_int),
+        ("split_second", _c_int),
+        ("forward_bytes", _sz),
+        ("backward_bytes", _sz),
+        ("backprop_bytes", _sz),
+        ("literal_bytes", _sz),
+        ("fused_bytes", _sz),
+    ]
+
 
 STAGES = ("coef", "lut", "plan", "first", "second", "reduce")
 
@@ -212,6 +231,14 @@ def workspace_size(ny, nx, n_layers=1, levels=3, precision="fp32"):
     _check(lib().cgh_workspace_size(ny, nx, n_layers, levels, _precision(precision), ctypes.byref(out)),
            "cgh_workspace_size")
     return out.value
+
+
+def workspace_layout(ny, nx, n_layers=1, levels=3, precision="fp32"):
+    """How the workspace of a problem is divided (cgh_workspace_layout), as a dict."""
+    info = LayoutInfo()
+    _check(lib().cgh_workspace_layout(ny, nx, n_layers, levels, _precision(precision),
+                                      ctypes.byref(info)), "cgh_workspace_layout")
+    return {name: getattr(info, name) for name, _ in info._fields_}
 
 
 def _workspace(nbytes, device, workspace=None):

@@ -28,6 +28,13 @@ namespace {
 
 using namespace cgh::host;
 
+// The forward pass fits its layout: the operand panels fit the shared region and
+// the second contraction's split-K partials fit the reserved partial holograms.
+bool forward_fits(const cgh::Layout& lo, int ny, int nx, int levels, int layers, int precision) {
+    return shared_fits(lo, lo.fwd_bytes) &&
+           partials_fit(lo, second_split(lo, ny, nx, levels, layers, precision), (size_t)ny * nx);
+}
+
 // One forward pass of the hot path into `out` (validated arguments).  parts
 // selects the approximation / detail levels (progressive stages); with_luts
 // false reuses the fringe tables already in the workspace.
@@ -97,6 +104,7 @@ const char* cgh_status_string(int status) {
         case CGH_ERROR_OUT_OF_MEMORY: return "CGH_ERROR_OUT_OF_MEMORY";
         case CGH_ERROR_WORKSPACE: return "CGH_ERROR_WORKSPACE: workspace missing or too small";
         case CGH_ERROR_HIP: return "CGH_ERROR_HIP: HIP runtime or launch failure";
+        case CGH_ERROR_INTERNAL: return "CGH_ERROR_INTERNAL: a launch does not fit the library's own workspace layout";
         default: return "CGH_ERROR_UNKNOWN";
     }
 }
@@ -142,6 +150,32 @@ int cgh_workspace_size(int ny, int nx, int n_layers, int levels, int precision, 
     return CGH_SUCCESS;
 }
 
+int cgh_workspace_layout(int ny, int nx, int n_layers, int levels, int precision,
+                         cgh_layout_info* info) {
+    try {
+        if (!info) return CGH_ERROR_INVALID_VALUE;
+        size_t total = 0;
+        int st = cgh_workspace_size(ny, nx, n_layers, levels, precision, &total);
+        if (st) return st;
+        std::memset(info, 0, sizeof(*info));
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
+        info->total = lo.total;
+        info->shared_bytes = lo.big_bytes;
+        info->partial_bytes = lo.partial_bytes;
+        info->split_reserved = lo.split_k;
+        info->split_second = second_split(lo, ny, nx, levels, n_layers, precision);
+        info->forward_bytes = lo.fwd_bytes;
+        info->backward_bytes = cgh::backward_bytes(ny, nx, n_layers, levels);
+        info->backprop_bytes = cgh::dense_bytes(ny, nx, lo.split_k);
+        info->literal_bytes = cgh::literal_bytes(ny, nx, n_layers, levels);
+        info->fused_bytes = cgh::fused_bytes(ny, nx);
+        return CGH_SUCCESS;
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
 int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, int n_layers,
                              const double* z, const float* saliency, const float* thresholds,
                              double lambda, double pitch, int ny, int nx, int levels,
@@ -156,6 +190,7 @@ int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, in
         if (!object || !hologram) return CGH_ERROR_INVALID_VALUE;
         const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
         if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        if (!forward_fits(lo, ny, nx, levels, n_layers, precision)) return CGH_ERROR_INTERNAL;
         Optics op;
         make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
         return hip_status(forward(object, layer_index, n_layers, saliency, thr, op, ny, nx, levels,
@@ -182,6 +217,7 @@ int cgh_progressive_stages(const float* object, const uint8_t* layer_index, int 
         if (!object || !stages) return CGH_ERROR_INVALID_VALUE;
         const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
         if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        if (!forward_fits(lo, ny, nx, levels, n_layers, precision)) return CGH_ERROR_INTERNAL;
         Optics op;
         make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
         hipStream_t s = (hipStream_t)stream;
@@ -219,6 +255,9 @@ int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_
         if (!object || !hologram) return CGH_ERROR_INVALID_VALUE;
         const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
         if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        if (!partials_fit(lo, lo.split_k, (size_t)ny * nx) ||
+            !shared_fits(lo, cgh::literal_bytes(ny, nx, n_layers, levels)))
+            return CGH_ERROR_INTERNAL;
         hipStream_t s = (hipStream_t)stream;
         char* ws = static_cast<char*>(workspace);
         Optics op;
@@ -266,6 +305,7 @@ int cgh_fused_hologram(const float* object, const uint8_t* layer_index, int n_la
         if (!object || !hologram) return CGH_ERROR_INVALID_VALUE;
         const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
         if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        if (!shared_fits(lo, cgh::fused_bytes(ny, nx))) return CGH_ERROR_INTERNAL;
         hipStream_t s = (hipStream_t)stream;
         char* ws = static_cast<char*>(workspace);
         Optics op;
@@ -315,6 +355,7 @@ int cgh_exact_hologram(const float* object, const uint8_t* layer_index, int n_la
         if (!object || !hologram) return CGH_ERROR_INVALID_VALUE;
         const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
         if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        if (!shared_fits(lo, (size_t)ny * nx * 4)) return CGH_ERROR_INTERNAL;
         hipStream_t s = (hipStream_t)stream;
         char* ws = static_cast<char*>(workspace);
         uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
@@ -354,6 +395,8 @@ int cgh_hologram_backward(const float* grad_hologram, const uint8_t* layer_index
         if (!grad_hologram || !grad_object) return CGH_ERROR_INVALID_VALUE;
         const cgh::Layout lo = make_layout(ny, nx, n_layers, levels);
         if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        if (!shared_fits(lo, cgh::backward_bytes(ny, nx, n_layers, levels)))
+            return CGH_ERROR_INTERNAL;
 
         hipStream_t s = (hipStream_t)stream;
         char* ws = static_cast<char*>(workspace);
@@ -391,6 +434,9 @@ int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lamb
         if (!field_in || !field_out || field_in == field_out) return CGH_ERROR_INVALID_VALUE;
         const cgh::Layout lo = make_layout(ny, nx, 1, 1);
         if (!workspace || workspace_bytes < lo.total) return CGH_ERROR_WORKSPACE;
+        if (!partials_fit(lo, lo.split_k, (size_t)ny * nx) ||
+            !shared_fits(lo, cgh::dense_bytes(ny, nx, lo.split_k)))
+            return CGH_ERROR_INTERNAL;
         hipStream_t s = (hipStream_t)stream;
         char* ws = static_cast<char*>(workspace);
         const double c = pitch * pitch / (2.0 * lambda * z), one = 1.0, zero = 0.0;

@@ -288,7 +288,7 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
             cgh_plan::Scene rec{};
             rec.s = sc;
             rec.z.assign(sc.z, sc.z + sc.n_layers);
-            rec.lo = make_layout(sc.ny, sc.nx, sc.n_layers, levels, false);
+            rec.lo = make_layout(sc.ny, sc.nx, sc.n_layers, levels, LayoutUse::kBatch);
             p->scenes.push_back(rec);
         }
         if (p->scenes.empty()) {

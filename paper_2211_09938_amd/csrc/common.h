@@ -53,6 +53,9 @@ struct Layout {
     size_t cnt_row, cnt_col, seg_row, tbeg;  // per (layer, level) counts, k' and tile offsets
     size_t hdr, entries;         // device plan header and GEMM problem table
     size_t big;                  // shared region: backward T, or the forward panels
+    size_t big_bytes;            // its size
+    size_t fwd_bytes;            // forward operand panels at the start of `big`
+    size_t partial_bytes;        // size of the split-K partial region
     size_t t;                    // backward / back-propagation intermediate (complex)
     size_t fx, cb, fy, tc;       // forward operand panels (inside `big`)
     size_t fx_ps, cb_ps, fy_ps, tc_ps;  // their plane strides, elements

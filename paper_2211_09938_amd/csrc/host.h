@@ -49,9 +49,16 @@ inline int choose_split(int ny, int nx, int levels, int layers, int tm = cgh::kN
     return split;
 }
 
-// with_partial: reserve split-K partials and the adjoint / back-propagation
-// scratch (single-scene calls); batched plans run the forward pass only.
-inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with_partial = true) {
+// What a workspace layout serves:
+//   kAll      single-scene calls: split-K partials, and a shared region large
+//             enough for every path (forward panels, adjoint, back-propagation,
+//             paper-literal and fused forms);
+//   kForward  the forward pass only (partials as kAll, forward panels);
+//   kBatch    one scene of a batched plan (forward panels, no split-K).
+enum class LayoutUse { kAll, kForward, kBatch };
+
+inline cgh::Layout make_layout(int ny, int nx, int layers, int levels,
+                               LayoutUse use = LayoutUse::kAll) {
     cgh::Layout lo{};
     const size_t plane = (size_t)ny * nx;
     const int n_dl = layers * levels;
@@ -82,26 +89,26 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
     lo.entries = take((size_t)(n_dl + 1) * sizeof(cgh::NtEntry));
     lo.entries_n = n_dl + 1;
     lo.first_tiles_max = z.first_tiles_max;
-    // backward: T (complex, >= one plane for the back-propagation intermediate);
     // forward: the operand panels, 8 bytes per complex element in every precision
-    size_t t_bytes = (size_t)layers * lo.t_layer * 8;
-    if (t_bytes < plane * 8) t_bytes = plane * 8;
     const size_t fx_b = align_up(z.fx_plane * 8), cb_b = align_up(z.cb_plane * 4);
     const size_t fy_b = align_up(z.fy_plane * 8), tc_b = align_up(z.tc_plane * 8);
-    size_t panels = fx_b + cb_b + fy_b + tc_b;
-    // the dense back-propagation panels share the region (one layer, one level)
-    lo.split_k = with_partial ? choose_split(ny, nx, levels, layers) : 1;
-    if (with_partial) {
-        const size_t dense = cgh::dense_bytes(ny, nx, lo.split_k);
-        if (dense > panels) panels = dense;
-        const size_t bw = cgh::backward_bytes(ny, nx, layers, levels);
-        if (bw > panels) panels = bw;
-        const size_t lit = cgh::literal_bytes(ny, nx, layers, levels);
-        if (lit > panels) panels = lit;
-        const size_t fused = cgh::fused_bytes(ny, nx);
-        if (fused > panels) panels = fused;
+    lo.fwd_bytes = fx_b + cb_b + fy_b + tc_b;
+    size_t shared = lo.fwd_bytes;
+    lo.split_k = use == LayoutUse::kBatch ? 1 : choose_split(ny, nx, levels, layers);
+    if (use == LayoutUse::kAll) {
+        // backward / back-propagation intermediate T (complex, >= one plane) and the
+        // other paths' scratch share the region
+        size_t t_bytes = (size_t)layers * lo.t_layer * 8;
+        if (t_bytes < plane * 8) t_bytes = plane * 8;
+        const size_t other[5] = {t_bytes, cgh::dense_bytes(ny, nx, lo.split_k),
+                                 cgh::backward_bytes(ny, nx, layers, levels),
+                                 cgh::literal_bytes(ny, nx, layers, levels),
+                                 cgh::fused_bytes(ny, nx)};
+        for (size_t v : other)
+            if (v > shared) shared = v;
     }
-    lo.big = take(t_bytes > panels ? t_bytes : panels);
+    lo.big = take(shared);
+    lo.big_bytes = shared;
     lo.t = lo.big;
     lo.fx = lo.big;
     lo.cb = lo.fx + fx_b;
@@ -111,10 +118,22 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels, bool with
     lo.cb_ps = z.cb_plane;
     lo.fy_ps = z.fy_plane;
     lo.tc_ps = z.tc_plane;
-    lo.partial = take(lo.split_k > 1 ? (size_t)lo.split_k * plane * 8 : 0);
+    lo.partial_bytes = lo.split_k > 1 ? (size_t)lo.split_k * plane * 8 : 0;
+    lo.partial = take(lo.partial_bytes);
     lo.total = off;
     return lo;
 }
+
+// Launch-time consistency with the layout (a failed check is a library bug and
+// is reported as CGH_ERROR_INTERNAL before anything is enqueued): `split`
+// partial planes of `plane` complex elements fit the reserved partials, and a
+// path's scratch of `bytes` fits the shared region.
+inline bool partials_fit(const cgh::Layout& lo, int split, size_t plane) {
+    if (split < 1) return false;
+    if (split == 1) return true;
+    return split <= lo.split_k && (size_t)split * plane * 8 <= lo.partial_bytes;
+}
+inline bool shared_fits(const cgh::Layout& lo, size_t bytes) { return bytes <= lo.big_bytes; }
 
 // Split of the single-scene second contraction: as many workgroups as can be
 // resident with the precision's kernel and tile shape (FP32: two per CU; the split

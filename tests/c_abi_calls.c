@@ -22,6 +22,7 @@ int cgh_header_calls(void) {
     long long launches[CGH_STAGE_COUNT];
     cgh_stats stats;
     cgh_plan_info info;
+    cgh_layout_info layout;
     cgh_plan* plan = NULL;
     cgh_scene scene = {cf, u8, 1, z, cf, 64, 64, f};
     int st = 0;
@@ -32,6 +33,7 @@ int cgh_header_calls(void) {
     st |= cgh_haar_dwt(cf, 64, 64, 3, f, stream);
     st |= cgh_haar_idwt(cf, 64, 64, 3, f, stream);
     st |= cgh_workspace_size(64, 64, 1, 3, CGH_FP32, &bytes);
+    st |= cgh_workspace_layout(64, 64, 1, 3, CGH_FP16_SPLIT, &layout);
     st |= cgh_progressive_hologram(cf, u8, 1, z, cf, thr, 532e-9, 8e-6, 64, 64, 3, CGH_BF16_SPLIT,
                                    CGH_FLAG_ACCUMULATE, ws, bytes, f, stream);
     st |= cgh_progressive_stages(cf, u8, 1, z, cf, thr, 532e-9, 8e-6, 64, 64, 3, CGH_FP32, 0u, ws,

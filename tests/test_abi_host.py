@@ -14,7 +14,7 @@ from paper_2211_09938_amd import cgh
 
 pytestmark = pytest.mark.skipif(not os.path.exists(cgh.LIB_PATH), reason="libcgh.so not built")
 
-OK, INVALID, SHAPE, UNSUP, OOM, WS, HIP = range(7)
+OK, INVALID, SHAPE, UNSUP, OOM, WS, HIP, INTERNAL = range(8)
 P = ctypes.c_void_p
 BOGUS = P(0x1000)  # never dereferenced: validation fails first
 
@@ -31,7 +31,7 @@ def test_every_declared_function_is_exported():
 
 def test_status_strings():
     lib = cgh.lib()
-    for code in range(7):
+    for code in range(8):
         assert lib.cgh_status_string(code).decode().startswith(cgh.STATUS[code])
     assert lib.cgh_status_string(99) == b"CGH_ERROR_UNKNOWN"
     assert lib.cgh_version() >= 100
@@ -267,3 +267,37 @@ def test_angular_spectrum_validation():
     assert call(z=float("inf")) == INVALID and call(z=float("nan")) == INVALID
     assert call(field=None) == INVALID and call(out=None) == INVALID
     assert call(ws=None) == WS and call(nbytes=ws_bytes(64, 64) - 1) == WS
+
+
+LAYOUT_SHAPES = [(8, 8, 1, 1), (16, 24, 3, 3), (64, 64, 1, 3), (128, 128, 2, 3), (264, 200, 3, 3),
+                 (520, 136, 2, 3), (1024, 1024, 1, 3), (1024, 512, 4, 2), (2048, 2048, 8, 3),
+                 (2048, 2048, 1, 1), (4096, 256, 2, 3), (16384, 16384, 1, 3), (256, 256, 256, 3)]
+
+
+@pytest.mark.parametrize("ny,nx,layers,levels", LAYOUT_SHAPES)
+@pytest.mark.parametrize("prec", ["fp32", "bf16_split", "fp16_split"])
+def test_workspace_layout_holds_every_path(ny, nx, layers, levels, prec):
+    """Every path's scratch fits the shared region and the second contraction's
+    split-K partials fit the reserved partial holograms (a split beyond them once
+    wrote past the workspace); the launch paths check the same conditions and
+    return CGH_ERROR_INTERNAL otherwise."""
+    lay = cgh.workspace_layout(ny, nx, layers, levels, prec)
+    assert lay["total"] == cgh.workspace_size(ny, nx, layers, levels, prec)
+    assert 1 <= lay["split_second"] <= lay["split_reserved"] <= 16
+    plane = ny * nx * 8
+    if lay["split_reserved"] > 1:
+        assert lay["partial_bytes"] >= lay["split_reserved"] * plane
+    else:
+        assert lay["partial_bytes"] == 0
+    for key in ("forward_bytes", "backward_bytes", "literal_bytes", "fused_bytes",
+                "backprop_bytes"):
+        if key == "backprop_bytes" and (layers, levels) != (1, 1):
+            continue  # back-propagation runs on the (1 layer, 1 level) layout
+        assert lay[key] <= lay["shared_bytes"], key
+    assert lay["shared_bytes"] + lay["partial_bytes"] <= lay["total"]
+
+
+def test_workspace_layout_rejects_what_workspace_size_rejects():
+    assert cgh.lib().cgh_workspace_layout(100, 64, 1, 3, 0, cgh.ctypes.byref(cgh.LayoutInfo())) == SHAPE
+    assert cgh.lib().cgh_workspace_layout(64, 64, 1, 3, 0, None) == INVALID
+    assert cgh.workspace_layout(0, 64)["total"] == 0
