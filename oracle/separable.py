@@ -71,3 +71,46 @@ def window(obj, z, lam, pitch, levels=3, saliency_map=None, layer_index=None,
     """Hologram window [y0:y0+h, x0:x0+w] of the progressive hologram, complex128 (h, w)."""
     return windows(obj, z, lam, pitch, levels, saliency_map, layer_index, thresholds,
                    corners=((y0, x0),), h=h, w=w, eq1_prefactor=eq1_prefactor)[0]
+
+
+# ---------------------------------------------------------------- differentiable form, full size
+#
+# The same chain as ``gradient.loss_and_grad`` (single layer at z, Fresnel
+# back-propagation, loss sum (|U| - T)^2), with every 2D kernel sum written as
+# matrix products.  The kernel matrix K[m, q] = k_z(m - q) is symmetric, so
+#
+#   hologram          H   = K_y Ahat K_x^T                      (Ahat real)
+#   back-propagation  U   = s conj(K_y)^T H conj(K_x)            s = 1 / (ny nx)
+#   loss cotangent    g_U = 2 (|U| - T) U / |U|                  (0 where U = 0)
+#   adjoint of U      g_H = s K_y g_U K_x^T
+#   back-projection   R   = Re( K_y^T conj(g_H) K_x )
+#   gradient          dL/dA = S M W (R)                          (self-adjoint)
+#
+# where conj(g_H) is the conjugate of the cotangent because the real loss
+# depends on H through Re(conj(g_H) dH).  Pinned to the direct-sum chain of
+# ``gradient`` on small sides; at 1024 x 1024 it takes seconds.
+
+
+def full_kernel(n, lam, pitch, z):
+    """K[m, q] = k_z(m - q) over a whole side of n pixels, complex128 (n, n)."""
+    return kernel_rows(np.arange(n), n, lam, pitch, z)
+
+
+def loss_and_grad(obj, target, z, lam, pitch, levels=3, saliency_map=None, thresholds=None):
+    """(loss, dL/dA, U) of the single-layer reconstruction loss, all in float64."""
+    from . import gradient
+
+    obj = np.asarray(obj, dtype=np.float64)
+    ny, nx = obj.shape
+    ky = full_kernel(ny, lam, pitch, z)
+    kx = full_kernel(nx, lam, pitch, z)
+    a_hat = progressive.masked_reconstruction(obj, saliency_map, levels, thresholds)
+    h = (np.ascontiguousarray(ky.real) @ a_hat + 1j * (np.ascontiguousarray(ky.imag) @ a_hat))
+    h = h @ np.ascontiguousarray(kx.T)
+    s = 1.0 / float(ny * nx)
+    u = s * (np.ascontiguousarray(np.conj(ky).T) @ h @ np.conj(kx))
+    loss, g_u = gradient.amplitude_loss(u, target)
+    g_h = s * (ky @ g_u @ np.ascontiguousarray(kx.T))
+    r = np.real(np.ascontiguousarray(ky.T) @ np.conj(g_h) @ kx)
+    grad = progressive.masked_reconstruction(r, saliency_map, levels, thresholds)
+    return loss, grad, u

@@ -66,3 +66,25 @@ def test_several_windows_share_one_reconstruction():
     ws = separable.windows(s.obj, s.z, s.lam, s.pitch, 3, sal, s.layer, corners=corners, h=16, w=16)
     for (y0, x0), got in zip(corners, ws):
         assert progressive.rel_l2(got, direct_window(s, y0, x0, 16, 16)) <= 1e-12
+
+
+@pytest.mark.parametrize("shape,levels,fraction", [((32, 32), 3, 0.3), ((24, 40), 2, 0.5),
+                                                  ((48, 16), 3, None)])
+def test_separable_loss_chain_equals_direct_sum_chain(shape, levels, fraction):
+    # the full-size chain (products of kernel matrices) against the chain of direct
+    # 2D sums in oracle.gradient, itself pinned by central finite differences
+    from oracle import gradient
+
+    s = scenes.random_scene(510 + shape[0], *shape, fraction=fraction, levels=levels)
+    target = scenes.blobs(np.random.default_rng(41), *shape, 4, sigma_px=(2, 5), scale_ref=32)
+    sal = None if s.saliency is None else s.saliency.astype(np.float64)
+    ref_loss, ref_grad = gradient.loss_and_grad(s.obj.astype(np.float64), target, s.z[0], s.lam,
+                                                s.pitch, levels, sal, workers=1)
+    loss, grad, u = separable.loss_and_grad(s.obj.astype(np.float64), target, s.z[0], s.lam,
+                                            s.pitch, levels, sal)
+    assert loss == pytest.approx(ref_loss, rel=1e-12)
+    assert progressive.rel_l2(grad, ref_grad) <= 1e-12
+    ref_u = gradient.fresnel_backpropagate(
+        progressive.hologram(s.obj.astype(np.float64), s.z, s.lam, s.pitch, levels, sal,
+                             workers=1), s.lam, s.pitch, s.z[0], workers=1)
+    assert progressive.rel_l2(u, ref_u) <= 1e-12
