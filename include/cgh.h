@@ -55,9 +55,11 @@ typedef enum {
     CGH_ERROR_OUT_OF_MEMORY = 4, /* plan creation could not allocate */
     CGH_ERROR_WORKSPACE = 5,     /* workspace NULL or smaller than cgh_workspace_size() */
     CGH_ERROR_HIP = 6,           /* a HIP runtime call or launch failed */
-    CGH_ERROR_INTERNAL = 7       /* a launch would not fit the workspace layout the library
+    CGH_ERROR_INTERNAL = 7,      /* a launch would not fit the workspace layout the library
                                     computed itself: a library defect, reported before
                                     anything is enqueued */
+    CGH_ERROR_SCRATCH_LIMIT = 8  /* cgh_progressive_hologram_noalloc: the problem needs more
+                                    scratch than CGH_NOALLOC_SCRATCH_BYTES */
 } cgh_status;
 
 /* Arithmetic of the two dense contractions (the coefficient stage and the
@@ -149,6 +151,34 @@ int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, in
                              double lambda, double pitch, int ny, int nx, int levels,
                              int precision, unsigned flags, void* workspace,
                              size_t workspace_bytes, float* hologram, void* stream);
+
+/*
+ * Allocation-free variant of cgh_progressive_hologram, for callers that cannot
+ * allocate device memory or pass a workspace: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same method, kernels
+ * and results as cgh_progressive_hologram (bit-identical for the same
+ * arguments); the scratch comes from a library-resident device array of
+ * CGH_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until the
+ * process ends.  The call allocates and frees nothing.
+ *  - Problems whose forward-pass scratch exceeds CGH_NOALLOC_SCRATCH_BYTES are
+ *    rejected with CGH_ERROR_SCRATCH_LIMIT before anything is enqueued
+ *    (128 MiB holds a 1024 x 1024 single-layer problem, or 512 x 512 with two
+ *    layers; 2048 x 2048 does not fit).
+ *  - Every call on one GPU uses that GPU's single array: calls that overlap on
+ *    one GPU (other streams, other threads, a graph replayed while another
+ *    call runs) race and give undefined results.  Serialise them.  Each call
+ *    clears what it needs cleared; nothing carries over between calls.
+ *  - The array's device address is looked up on a device's first call (with
+ *    that device current); a failure there returns CGH_ERROR_HIP.
+ * Arguments, other errors and ownership as for cgh_progressive_hologram,
+ * without the workspace; profiling (cgh_profile_enable) does not apply.
+ */
+#define CGH_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int cgh_progressive_hologram_noalloc(const float* object, const uint8_t* layer_index,
+                                     int n_layers, const double* z, const float* saliency,
+                                     const float* thresholds, double lambda, double pitch,
+                                     int ny, int nx, int levels, int precision, unsigned flags,
+                                     float* hologram, void* stream);
 
 /*
  * Progressive stage holograms (Sec. 2, steps 2-5; the progressive display of

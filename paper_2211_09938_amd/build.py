@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcgh.so")
-SOURCES = ["dwt.hip", "lut.hip", "reduce.hip", "plan.hip", "ntgemm.hip", "dense.hip", "backward.hip", "exact.hip", "literal.hip", "angular.hip", "peak.hip", "api.cpp", "batch.cpp"]
+SOURCES = ["dwt.hip", "lut.hip", "reduce.hip", "plan.hip", "ntgemm.hip", "dense.hip", "backward.hip", "exact.hip", "literal.hip", "angular.hip", "peak.hip", "noalloc.hip", "api.cpp", "batch.cpp"]
 ARCH = os.environ.get("CGH_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

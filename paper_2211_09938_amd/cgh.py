@@ -34,7 +34,9 @@ STATUS = {
     5: "CGH_ERROR_WORKSPACE",
     6: "CGH_ERROR_HIP",
     7: "CGH_ERROR_INTERNAL",
+    8: "CGH_ERROR_SCRATCH_LIMIT",
 }
+NOALLOC_SCRATCH_BYTES = 128 << 20  # CGH_NOALLOC_SCRATCH_BYTES
 
 _lock = threading.Lock()
 _lib = None
@@ -53,6 +55,9 @@ SIGNATURES = {
     "cgh_progressive_hologram": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double,
                                           _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp,
                                           _vp]),
+    "cgh_progressive_hologram_noalloc": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double,
+                                                  _c_double, _c_int, _c_int, _c_int, _c_int,
+                                                  _c_uint, _vp, _vp]),
     "cgh_progressive_stages": (_c_int, [_vp, _vp, _c_int, _vp, _vp, _vp, _c_double, _c_double,
                                         _c_int, _c_int, _c_int, _c_int, _c_uint, _vp, _sz, _vp,
                                         _vp]),
@@ -307,6 +312,31 @@ def progressive_hologram(obj, z, lam, pitch, levels=3, saliency=None, layer_inde
         p_obj, p_lay, len(zs), _host_doubles(zs), p_sal, _host_floats(thresholds), float(lam),
         float(pitch), ny, nx, levels, prec, flags, ctypes.c_void_p(ws.data_ptr()),
         ws.numel(), p_out, _stream()), "cgh_progressive_hologram")
+    return out
+
+
+def progressive_hologram_noalloc(obj, z, lam, pitch, levels=3, saliency=None, layer_index=None,
+                                 thresholds=None, precision="fp32", eq1_prefactor=False, out=None,
+                                 accumulate=False):
+    """As :func:`progressive_hologram`, through cgh_progressive_hologram_noalloc: the library
+    takes its scratch from its own static device array (no workspace); ``out`` may be given
+    so that nothing is allocated here either."""
+    torch = _torch()
+    ny, nx = obj.shape
+    zs = list(np.atleast_1d(np.asarray(z, dtype=np.float64)))
+    p_obj = _dev_tensor(obj, torch.float32, "object")
+    p_sal = None if saliency is None else _dev_tensor(saliency, torch.float32, "saliency", (ny, nx))
+    p_lay = None if layer_index is None else _dev_tensor(layer_index, torch.uint8, "layer_index", (ny, nx))
+    if out is None:
+        if accumulate:
+            raise ValueError("accumulate needs an existing `out`")
+        out = torch.empty((ny, nx), dtype=torch.complex64, device=obj.device)
+    p_out = _dev_tensor(out, torch.complex64, "out", (ny, nx))
+    flags = (FLAG_ACCUMULATE if accumulate else 0) | (FLAG_EQ1_PREFACTOR if eq1_prefactor else 0)
+    _check(lib().cgh_progressive_hologram_noalloc(
+        p_obj, p_lay, len(zs), _host_doubles(zs), p_sal, _host_floats(thresholds), float(lam),
+        float(pitch), ny, nx, levels, _precision(precision), flags, p_out, _stream()),
+        "cgh_progressive_hologram_noalloc")
     return out
 
 

@@ -41,7 +41,12 @@ bool forward_fits(const cgh::Layout& lo, int ny, int nx, int levels, int layers,
 hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers,
                    const float* saliency, const float* thr, const Optics& op, int ny, int nx,
                    int levels, int precision, const cgh::Layout& lo, char* ws, unsigned parts,
-                   bool with_luts, int acc, float2* out, hipStream_t s) {
+                   bool with_luts, int acc, float2* out, hipStream_t s, bool timers = true) {
+    // stage timing (event pairs from the profiler's pool) unless the caller
+    // must not create anything
+    auto timed = [&](hipStream_t st, int stage, auto&& f) -> hipError_t {
+        return timers ? cgh::host::timed(st, stage, f) : f();
+    };
     uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
     const cgh::NtBuffers nb = nt_buffers(ws, lo);
     const float* coef = reinterpret_cast<const float*>(ws + lo.coef);
@@ -93,6 +98,10 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
 
 }  // namespace
 
+namespace cgh {
+hipError_t noalloc_scratch(void** ptr);  // noalloc.hip
+}
+
 extern "C" {
 
 const char* cgh_status_string(int status) {
@@ -105,6 +114,7 @@ const char* cgh_status_string(int status) {
         case CGH_ERROR_WORKSPACE: return "CGH_ERROR_WORKSPACE: workspace missing or too small";
         case CGH_ERROR_HIP: return "CGH_ERROR_HIP: HIP runtime or launch failure";
         case CGH_ERROR_INTERNAL: return "CGH_ERROR_INTERNAL: a launch does not fit the library's own workspace layout";
+        case CGH_ERROR_SCRATCH_LIMIT: return "CGH_ERROR_SCRATCH_LIMIT: the problem needs more than the allocation-free entry point's static scratch (CGH_NOALLOC_SCRATCH_BYTES)";
         default: return "CGH_ERROR_UNKNOWN";
     }
 }
@@ -197,6 +207,36 @@ int cgh_progressive_hologram(const float* object, const uint8_t* layer_index, in
                                   precision, lo, static_cast<char*>(workspace), cgh::kAllParts,
                                   true, (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0,
                                   reinterpret_cast<float2*>(hologram), (hipStream_t)stream));
+    } catch (...) {
+        return CGH_ERROR_HIP;
+    }
+}
+
+int cgh_progressive_hologram_noalloc(const float* object, const uint8_t* layer_index,
+                                     int n_layers, const double* z, const float* saliency,
+                                     const float* thresholds, double lambda, double pitch,
+                                     int ny, int nx, int levels, int precision, unsigned flags,
+                                     float* hologram, void* stream) {
+    try {
+        float thr[CGH_MAX_LEVELS];
+        int st = check_common(n_layers, layer_index, z, thresholds, lambda, pitch, ny, nx, levels,
+                              precision, flags, thr);
+        if (st) return st;
+        if (ny == 0 || nx == 0) return CGH_SUCCESS;
+        if (!object || !hologram) return CGH_ERROR_INVALID_VALUE;
+        const cgh::Layout lo = make_layout(ny, nx, n_layers, levels, LayoutUse::kForward);
+        if (lo.total > CGH_NOALLOC_SCRATCH_BYTES) return CGH_ERROR_SCRATCH_LIMIT;
+        if (!forward_fits(lo, ny, nx, levels, n_layers, precision)) return CGH_ERROR_INTERNAL;
+        void* ws = nullptr;
+        hipError_t e = cgh::noalloc_scratch(&ws);
+        if (e != hipSuccess) return hip_status(e);
+        Optics op;
+        make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
+        return hip_status(forward(object, layer_index, n_layers, saliency, thr, op, ny, nx, levels,
+                                  precision, lo, static_cast<char*>(ws), cgh::kAllParts, true,
+                                  (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0,
+                                  reinterpret_cast<float2*>(hologram), (hipStream_t)stream,
+                                  false));
     } catch (...) {
         return CGH_ERROR_HIP;
     }

@@ -36,6 +36,8 @@ int cgh_header_calls(void) {
     st |= cgh_workspace_layout(64, 64, 1, 3, CGH_FP16_SPLIT, &layout);
     st |= cgh_progressive_hologram(cf, u8, 1, z, cf, thr, 532e-9, 8e-6, 64, 64, 3, CGH_BF16_SPLIT,
                                    CGH_FLAG_ACCUMULATE, ws, bytes, f, stream);
+    st |= cgh_progressive_hologram_noalloc(cf, u8, 1, z, cf, thr, 532e-9, 8e-6, 64, 64, 3,
+                                           CGH_FP16_SPLIT, 0u, f, stream);
     st |= cgh_progressive_stages(cf, u8, 1, z, cf, thr, 532e-9, 8e-6, 64, 64, 3, CGH_FP32, 0u, ws,
                                  bytes, f, stream);
     st |= cgh_literal_hologram(cf, u8, 1, z, cf, thr, 532e-9, 8e-6, 64, 64, 3, CGH_FP16_SPLIT,
