@@ -159,6 +159,41 @@ def mfma_peak_lines():
                                   "avg_launch_ms": ms}), flush=True)
 
 
+def host_cpu():
+    """CPU model and core counts of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        affinity = None
+    return {"cpu_model": model, "host_cpus": os.cpu_count(), "cpus_in_affinity": affinity,
+            "worker_cap": "the oracle's pool takes the process's CPU affinity, at most 16 "
+                          "processes (one GPU's share of the host); ORACLE_WORKERS overrides"}
+
+
+def crop_reference(scene, size=256, seed=2048):
+    """FP64 window of the hologram (separable oracle) at a seeded offset: the 256 x 256
+    crop the depth workload's parity is stated on (the same offset as its test)."""
+    from oracle import separable
+
+    ny, nx = scene.shape
+    h, w = min(size, ny), min(size, nx)
+    rng = np.random.default_rng(seed)
+    y0, x0 = (int(v) for v in rng.integers(0, [ny - h + 1, nx - w + 1]))
+    sal = None if scene.saliency is None else scene.saliency.astype(np.float64)
+    ref = separable.window(scene.obj.astype(np.float64), scene.z, scene.lam, scene.pitch,
+                           scene.levels, sal, scene.layer, y0=y0, x0=x0, h=h, w=w)
+    return y0, x0, ref
+
+
 def cpu_baseline(scene, n_pixels, seed=12345):
     """FP64 oracle on a seeded pixel sample of the same hologram (host cores only)."""
     from oracle import fresnel, progressive
@@ -182,6 +217,7 @@ def cpu_baseline(scene, n_pixels, seed=12345):
         "value": 1.0 / per_holo,
         "unit": "holograms/s",
         "cores": fresnel.worker_count(),
+        **host_cpu(),
         "kind": "oracle",
         "sample": (f"FP64 direct 2D point sum at {n_pixels} seeded pixels of the same hologram "
                    f"({t2 - t1:.1f} s) plus the masked reconstruction of every layer "
@@ -310,7 +346,10 @@ def run_dense(scene, prec, steps, warmup, form):
         fl_issued += layers * (ISSUE_FACTOR[prec] * 4.0 * r * c * nx
                                + SECOND_ISSUE[prec] * 8.0 * ny * r * nx)
     ms = 1e3 * elapsed / steps
-    achieved = fl / (ms * 1e-3) / 1e12
+    # achieved: the matrix-core flops the two contractions' algorithms perform (three-product
+    # FP32 complex form, three products per real product in the split forms); the method's
+    # count (8 real flops per complex multiply-add) beside it
+    achieved = fl_issued / (ms * 1e-3) / 1e12
     return {
         "value": steps / elapsed,
         "ms_per_step": ms,
@@ -319,7 +358,8 @@ def run_dense(scene, prec, steps, warmup, form):
         "roofline": {"bound": "mfma", "kernel": f"whole {form} step (both contractions dominate)",
                      "achieved": achieved, "peak": PEAKS_TFLOPS[prec], "unit": "TFLOP/s",
                      "frac": achieved / PEAKS_TFLOPS[prec], "traffic": None,
-                     "issued_mfma_frac": fl_issued / (ms * 1e-3) / 1e12 / PEAKS_TFLOPS[prec]},
+                     "flops_per_launch": fl_issued, "flops_4m_per_launch": fl,
+                     "achieved_4m": fl / (ms * 1e-3) / 1e12},
         "_out": out.cpu().numpy(),
     }
 
@@ -475,24 +515,48 @@ def batch_second_kernel(prec, info):
             else "nt_persistent_kernel")
 
 
-def roofline(stats, prec, avg_ms, kernel, traffic=None, issue=None):
-    """Second contraction: algorithmic flops per launch / average launch time."""
-    achieved = stats["flops_second"] / (avg_ms * 1e-3) / 1e12
-    peak = PEAKS_TFLOPS[prec]
+def roofline(stats, prec, avg_ms, kernel, traffic=None, issue=None, attainable=None):
+    """Second contraction: the real flops its algorithm performs per launch over the
+    average launch time, against the published dense peak of its MFMA type.
+
+    The method's count (``flops_4m_per_launch``) is 8 real flops per complex
+    multiply-add, 8 * ny * nx * active coefficient rows.  The kernel performs
+    ``issue`` times that on the matrix cores: 3/4 in the three-product FP32 form,
+    3x in the split forms (hi*hi + hi*lo + lo*hi per real product), so ``achieved``
+    counts issue x the method's flops on the active rows and ``frac`` is a true
+    fraction of the peak.  ``issued_mfma_frac`` adds the zero rows that pad every K
+    segment to 16; ``attainable`` is the register-resident probe's rate for the same
+    instruction on this GPU, measured in the same run.
+    """
     issue = SECOND_ISSUE[prec] if issue is None else issue
-    issued = achieved * issue * stats["flops_second_issued"] / max(1.0, stats["flops_second"])
-    return {
+    t = avg_ms * 1e-3
+    flops = issue * stats["flops_second"]
+    achieved = flops / t / 1e12
+    peak = PEAKS_TFLOPS[prec]
+    issued = issue * stats["flops_second_issued"] / t / 1e12
+    frac = achieved / peak
+    if frac > 1.0:
+        print(f"bench.py: roofline fraction {frac:.3f} > 1 for {kernel}: flop count or timing "
+              "is wrong", file=sys.stderr)
+    out = {
         "bound": "mfma",
         "kernel": kernel,
         "achieved": achieved,
         "peak": peak,
         "unit": "TFLOP/s",
-        "frac": achieved / peak,
+        "frac": frac,
         "traffic": traffic,
-        "flops_per_launch": stats["flops_second"],
+        "flops_per_launch": flops,
         "avg_launch_ms": avg_ms,
         "issued_mfma_frac": issued / peak,
+        "flops_4m_per_launch": stats["flops_second"],
+        "achieved_4m": stats["flops_second"] / t / 1e12,
+        "mfma_flops_per_4m_flop": issue,
     }
+    if attainable is not None:
+        out["attainable"] = attainable
+        out["frac_of_attainable"] = achieved / attainable
+    return out
 
 
 def timed_steps(step, steps):
@@ -564,7 +628,8 @@ def run_single(scene, prec, steps, warmup, workload):
         "stages_ms_per_step": {k: v[0] / max(1, v[1]) for k, v in prof.items()},
         "work": stats,
         "roofline": roofline(stats, prec, sec_ms / max(1, sec_n), kernel,
-                             measured_traffic(workload, prec)),
+                             measured_traffic(workload, prec),
+                             attainable=mfma_attainable(prec)[0]),
         "hbm_roofline": hbm,
         "_out": out.cpu().numpy(),
     }
@@ -752,6 +817,9 @@ def main():
     precs = [args.precision]
     if args.forms == "all":
         precs += [p for p in ("fp32", "bf16_split", "fp16_split") if p != args.precision]
+    crop = None
+    if base is not None and not args.workload.startswith(("literal", "fused")):
+        crop = crop_reference(scene)
     forms = {}
     for prec in precs:
         if batch:
@@ -769,6 +837,12 @@ def main():
             ys, xs, vals = base["_pixels"]
             got = out[ys, xs].astype(np.complex128)
             forms[prec]["rel_l2_vs_oracle"] = float(np.linalg.norm(got - vals) / np.linalg.norm(vals))
+        if crop is not None and out is not None:
+            y0, x0, ref = crop
+            win = out[y0:y0 + ref.shape[0], x0:x0 + ref.shape[1]].astype(np.complex128)
+            forms[prec]["crop_rel_l2_vs_oracle"] = {
+                "value": float(np.linalg.norm(win - ref) / np.linalg.norm(ref)),
+                "window": [y0, x0, ref.shape[0], ref.shape[1]]}
         forms[prec]["dtype"] = DTYPES[prec]
     head = forms[args.precision]
     if batch:
@@ -802,6 +876,8 @@ def main():
     }
     if "rel_l2_vs_oracle" in head:
         line["rel_l2_vs_oracle"] = head["rel_l2_vs_oracle"]
+    if "crop_rel_l2_vs_oracle" in head:
+        line["crop_rel_l2_vs_oracle"] = head["crop_rel_l2_vs_oracle"]
     if batch:
         line["plan"] = head["plan"]
     line["forms"] = {p: {k: v for k, v in f.items() if k != "work"} for p, f in forms.items()}
