@@ -119,6 +119,11 @@ typedef struct {
     size_t backprop_bytes;  /* back-propagation panels (cgh_fresnel_backpropagate)         */
     size_t literal_bytes;   /* cgh_literal_hologram panels                                 */
     size_t fused_bytes;     /* cgh_fused_hologram panels and reconstruction                */
+    size_t lut_x_offset;    /* byte offset of the x fringe tables (float): per layer d, level
+                               l, band b (0 lo, 1 hi), part (0 re, 1 im), table
+                               ((d*levels + l-1)*2 + b)*2 + part of 2*nx floats, entry i
+                               holding the fringe at offset i - nx (Sec. 2 LUT blocks)     */
+    size_t lut_y_offset;    /* the y tables, 2*ny floats each, times the layer's prefactor */
 } cgh_layout_info;
 
 /* Fills *info [host] for the problem; errors as cgh_workspace_size(). */

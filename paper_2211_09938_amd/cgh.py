@@ -134,6 +134,8 @@ class LayoutInfo(ctypes.Structure):
         ("backprop_bytes", _sz),
         ("literal_bytes", _sz),
         ("fused_bytes", _sz),
+        ("lut_x_offset", _sz),
+        ("lut_y_offset", _sz),
     ]
 
 

@@ -64,12 +64,14 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
                                     lo.flags_layer,
                                     reinterpret_cast<unsigned long long*>(ws + lo.ops), s);
     });
+    FringeScale fs;
+    fringe_scale(op, n_layers, precision, fs);
     if (e == hipSuccess && with_luts)
         e = timed(s, CGH_STAGE_LUT, [&] {
             hipError_t r = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
                                             reinterpret_cast<float*>(ws + lo.lut_x), s);
             if (r != hipSuccess) return r;
-            return cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im,
+            return cgh::launch_luts(ny, n_layers, levels, 1, op.c, fs.re, fs.im,
                                     reinterpret_cast<float*>(ws + lo.lut_y), s);
         });
     if (e == hipSuccess)
@@ -77,8 +79,9 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
             const int tiles[4] = {cgh::nt_first_tile_m(precision), cgh::kNtTile,
                                   cgh::nt_second_tile_m(precision), tn2};
             const cgh::NtOutput o{out, split > 1 ? partial : nullptr, acc};
-            hipError_t r = cgh::launch_nt_plan(fl, ny, nx, n_layers, levels, lo.flags_layer,
-                                               precision, tiles, nb, o, s);
+            hipError_t r = cgh::launch_nt_plan(
+                fl, ny, nx, n_layers, levels, lo.flags_layer, precision, tiles, nb, o,
+                reinterpret_cast<const unsigned long long*>(ws + lo.ops) + kAbsmaxWord, fs.e, s);
             if (r != hipSuccess) return r;
             return cgh::launch_nt_materialize(coef, lut_x, lut_y, ny, nx, n_layers, levels,
                                               precision, nb, s);
@@ -180,6 +183,8 @@ int cgh_workspace_layout(int ny, int nx, int n_layers, int levels, int precision
         info->backprop_bytes = cgh::dense_bytes(ny, nx, lo.split_k);
         info->literal_bytes = cgh::literal_bytes(ny, nx, n_layers, levels);
         info->fused_bytes = cgh::fused_bytes(ny, nx);
+        info->lut_x_offset = lo.lut_x;
+        info->lut_y_offset = lo.lut_y;
         return CGH_SUCCESS;
     } catch (...) {
         return CGH_ERROR_HIP;
@@ -302,6 +307,8 @@ int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_
         char* ws = static_cast<char*>(workspace);
         Optics op;
         make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
+        FringeScale fs;
+        fringe_scale(op, n_layers, precision, fs);
         uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
         hipError_t e = cgh::launch_fill_u8(fl, lo.flags_fill, s);
         if (e == hipSuccess)
@@ -313,17 +320,20 @@ int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_
             e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
                                  reinterpret_cast<float*>(ws + lo.lut_x), s);
         if (e == hipSuccess)
-            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im,
+            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, fs.re, fs.im,
                                  reinterpret_cast<float*>(ws + lo.lut_y), s);
         if (e == hipSuccess) {
-            const cgh::LitTables tb{op.c, op.one_re, op.one_im, op.pre_re, op.pre_im};
+            const cgh::LitTables tb{op.c, op.one_re, op.one_im, fs.re, fs.im};
             e = cgh::launch_literal(reinterpret_cast<const float*>(ws + lo.coef),
                                     reinterpret_cast<const float*>(ws + lo.lut_x),
                                     reinterpret_cast<const float*>(ws + lo.lut_y), tb, ny, nx,
                                     n_layers, levels, precision, lo.split_k,
                                     reinterpret_cast<float2*>(ws + lo.partial),
                                     reinterpret_cast<float2*>(hologram),
-                                    (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0, ws + lo.big, s);
+                                    (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0,
+                                    reinterpret_cast<const unsigned long long*>(ws + lo.ops) +
+                                        kAbsmaxWord,
+                                    fs.e, ws + lo.big, s);
         }
         return hip_status(e);
     } catch (...) {
@@ -351,9 +361,15 @@ int cgh_fused_hologram(const float* object, const uint8_t* layer_index, int n_la
         Optics op;
         make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
         float* coef = reinterpret_cast<float*>(ws + lo.coef);
-        hipError_t e = cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers,
-                                            levels, thr, cgh::kAllParts, coef, nullptr, 0,
-                                            nullptr, s);
+        // the coefficient stage also records max |object| (FP16 range scaling)
+        uint8_t* fl = reinterpret_cast<uint8_t*>(ws + lo.flags);
+        auto* ops = reinterpret_cast<unsigned long long*>(ws + lo.ops);
+        FringeScale fs;
+        fringe_scale(op, n_layers, precision, fs);
+        hipError_t e = cgh::launch_fill_u8(fl, lo.flags_fill, s);
+        if (e == hipSuccess)
+            e = cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels, thr,
+                                     cgh::kAllParts, coef, fl, lo.flags_layer, ops, s);
         char* scratch = ws + lo.big;
         float* recon = reinterpret_cast<float*>(scratch + cgh::fused_recon_offset(ny, nx));
         float* lut0_x = reinterpret_cast<float*>(ws + lo.lut0);
@@ -366,14 +382,14 @@ int cgh_fused_hologram(const float* object, const uint8_t* layer_index, int n_la
                 e = cgh::launch_luts(nx, 1, 1, 0, &op.c[d], &op.one_re[d], &op.one_im[d], lut0_x,
                                      s);
             if (e == hipSuccess)
-                e = cgh::launch_luts(ny, 1, 1, 0, &op.c[d], &op.pre_re[d], &op.pre_im[d], lut0_y,
-                                     s);
+                e = cgh::launch_luts(ny, 1, 1, 0, &op.c[d], &fs.re[d], &fs.im[d], lut0_y, s);
             if (e == hipSuccess)
                 e = cgh::launch_fused_layer(recon, lut0_x, lut0_y, ny, nx, precision,
                                             (d > 0 || acc) ? 1 : 0,
                                             reinterpret_cast<float2*>(hologram), scratch,
                                             reinterpret_cast<cgh::NtEntry*>(ws + lo.entries),
-                                            reinterpret_cast<int*>(ws + lo.hdr), s);
+                                            reinterpret_cast<int*>(ws + lo.hdr),
+                                            ops + kAbsmaxWord, fs.e, s);
         }
         return hip_status(e);
     } catch (...) {
@@ -442,17 +458,26 @@ int cgh_hologram_backward(const float* grad_hologram, const uint8_t* layer_index
         char* ws = static_cast<char*>(workspace);
         Optics op;
         make_optics(op, n_layers, z, lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
-        hipError_t e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
-                                        reinterpret_cast<float*>(ws + lo.lut_x), s);
+        FringeScale fs;
+        fringe_scale(op, n_layers, precision, fs);
+        // max-abs word of the cotangent (FP16 range scaling), cleared first
+        auto* absmax = reinterpret_cast<unsigned long long*>(ws + lo.ops) + kAbsmaxWord;
+        hipError_t e = hipSuccess;
+        if (precision == CGH_FP16_SPLIT)
+            e = cgh::launch_fill_u8(reinterpret_cast<uint8_t*>(absmax), 8, s);
         if (e == hipSuccess)
-            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, op.pre_re, op.pre_im,
+            e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
+                                 reinterpret_cast<float*>(ws + lo.lut_x), s);
+        if (e == hipSuccess)
+            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, fs.re, fs.im,
                                  reinterpret_cast<float*>(ws + lo.lut_y), s);
         if (e == hipSuccess)
             e = cgh::launch_backward_nt(reinterpret_cast<const float2*>(grad_hologram),
                                         reinterpret_cast<const float*>(ws + lo.lut_x),
                                         reinterpret_cast<const float*>(ws + lo.lut_y), ny, nx,
                                         n_layers, levels, precision,
-                                        reinterpret_cast<float*>(ws + lo.coef), ws + lo.big, s);
+                                        reinterpret_cast<float*>(ws + lo.coef), ws + lo.big,
+                                        absmax, fs.e, s);
         if (e == hipSuccess)
             e = cgh::launch_grad_synthesis(reinterpret_cast<const float*>(ws + lo.coef), layer_index,
                                            saliency, ny, nx, n_layers, levels, thr, grad_object, s);
@@ -482,13 +507,19 @@ int cgh_fresnel_backpropagate(const float* field_in, int ny, int nx, double lamb
         const double c = pitch * pitch / (2.0 * lambda * z), one = 1.0, zero = 0.0;
         float* lut0_x = reinterpret_cast<float*>(ws + lo.lut0);
         float* lut0_y = lut0_x + 2 * cgh::lut_len(nx);
-        hipError_t e = cgh::launch_luts(nx, 1, 1, 0, &c, &one, &zero, lut0_x, s);
+        // max-abs word of the input field (FP16 range scaling), cleared first
+        auto* absmax = reinterpret_cast<unsigned long long*>(ws + lo.ops) + kAbsmaxWord;
+        hipError_t e = hipSuccess;
+        if (precision == CGH_FP16_SPLIT)
+            e = cgh::launch_fill_u8(reinterpret_cast<uint8_t*>(absmax), 8, s);
+        if (e == hipSuccess) e = cgh::launch_luts(nx, 1, 1, 0, &c, &one, &zero, lut0_x, s);
         if (e == hipSuccess)
             e = cgh::launch_luts(ny, 1, 1, 0, &c, &one, &zero, lut0_y, s);
         if (e == hipSuccess) {
             const cgh::DenseBuffers b = cgh::dense_buffers(
                 ws + lo.big, ny, nx, lo.split_k, reinterpret_cast<float2*>(ws + lo.partial),
-                reinterpret_cast<cgh::NtEntry*>(ws + lo.entries), reinterpret_cast<int*>(ws + lo.hdr));
+                reinterpret_cast<cgh::NtEntry*>(ws + lo.entries), reinterpret_cast<int*>(ws + lo.hdr),
+                absmax);
             e = cgh::launch_dense_backprop(b, lut0_x, lut0_y,
                                            reinterpret_cast<const float2*>(field_in),
                                            reinterpret_cast<float2*>(field_out), ny, nx,

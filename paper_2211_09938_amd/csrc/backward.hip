@@ -61,17 +61,21 @@ __global__ __launch_bounds__(256) void fringe_h_kernel(const float* __restrict__
 }
 
 // Interleaved complex64 [rows][cols] -> operand planes [rows][ld], zero pad.
+// absmax (FP16 range scaling, else null): values scaled by 2^-e, e the exponent of
+// the cotangent's largest component magnitude.
 template <int P>
 __global__ __launch_bounds__(256) void cotangent_panel_kernel(const float2* __restrict__ in,
                                                               int rows, int cols, int ld,
+                                                              const unsigned long long* absmax,
                                                               void* __restrict__ out, size_t ps) {
     const size_t total = (size_t)rows * ld;
+    const float sc = absmax ? pow2f(-range_exp(absmax_value(absmax))) : 1.f;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         int r, c;
         kblk_pos(e, rows, r, c);
         const float2 v = c < cols ? in[(size_t)r * cols + c] : make_float2(0.f, 0.f);
-        put_c<P>(out, ps, e, v.x, v.y);
+        put_c<P>(out, ps, e, v.x * sc, v.y * sc);
     }
 }
 
@@ -88,12 +92,20 @@ struct BwArgs {
     NtEntry* ea;              // step A problems [layers * levels]
     NtEntry* eb;              // step B problems [layers * (2 * levels - 1)]
     int* counts;              // tile totals of step A and step B
+    // FP16 range scaling: G scaled by 2^-e (e from the cotangent's max-abs word),
+    // P = conj(Fx) G (|P| < 2 sqrt 2 x 8 nx) stored times 2^-t, and step B's epilogue
+    // multiplies by 2^(e + t + e_fringe); scale 1 otherwise
+    const unsigned long long* absmax;  // null unless FP16
+    int t_shift, e_fringe;
 };
 
 // One thread per layer writes that layer's problems; every layer has the same
 // shapes, so tile offsets are closed-form.
 __global__ void bw_entries_kernel(BwArgs a) {
     const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    const float a_scale = a.absmax ? pow2f(-a.t_shift) : 1.f;
+    const float b_scale =
+        a.absmax ? pow2f(range_exp(absmax_value(a.absmax)) + a.t_shift + a.e_fringe) : 1.f;
     if (d == 0) {
         a.counts[0] = a.layers * a.tiles_a_layer;
         a.counts[1] = a.layers * a.tiles_b_layer;
@@ -138,6 +150,7 @@ __global__ void bw_entries_kernel(BwArgs a) {
         e.tile_begin = d * a.tiles_a_layer + ta;
         e.tile_m = kNtTile;
         e.tile_n = a.tn_a;
+        e.out_scale = a_scale;
         a.ea[d * L + l - 1] = e;
         ta += nt_tiles(sx, a.ny, kNtTile, a.tn_a);
         pa += (size_t)sx * a.ny;
@@ -173,6 +186,7 @@ __global__ void bw_entries_kernel(BwArgs a) {
             f.tiles_n = (N + kNtTile - 1) / kNtTile;
             f.tile_begin = d * a.tiles_b_layer + tb;
             f.tile_m = f.tile_n = kNtTile;
+            f.out_scale = b_scale;
             a.eb[(size_t)d * (2 * L - 1) + nb] = f;
             ++nb;
             tb += nt_tiles(M, N, kNtTile, kNtTile);
@@ -272,7 +286,9 @@ BwShape bw_shape(int ny, int nx, int layers, int levels, int tn_a = kNtTile) {
 
 template <int P>
 hipError_t backward_nt(const float2* grad_h, const float* lut_x, const float* lut_y, int ny,
-                       int nx, int layers, int levels, float* gcoef, char* base, hipStream_t s) {
+                       int nx, int layers, int levels, float* gcoef, char* base,
+                       unsigned long long* absmax, int e_fringe, hipStream_t s) {
+    constexpr bool F16 = P == P_FP16;
     const int tn_a = nt_table_tile_n(kEpiPanel, P);
     const BwShape z = bw_shape(ny, nx, layers, levels, tn_a);
     BwArgs a{};
@@ -310,10 +326,18 @@ hipError_t backward_nt(const float2* grad_h, const float* lut_x, const float* lu
     a.fxh_ps = (long long)layers * z.rows_x * z.ldx;
     a.fyh_ps = (long long)layers * z.rows_y * z.ldy;
     a.pt_ps = (long long)layers * z.rows_x * z.ldy;
+    a.absmax = F16 ? absmax : nullptr;
+    a.t_shift = F16 ? headroom_shift(32.f * (float)nx) : 0;
+    a.e_fringe = e_fringe;
     const int n_dl = layers * levels;
 
+    if (F16) {
+        hipError_t r = launch_absmax(reinterpret_cast<const float*>(grad_h), 2 * (size_t)ny * nx,
+                                     absmax, s);
+        if (r != hipSuccess) return r;
+    }
     hipLaunchKernelGGL(cotangent_panel_kernel<P>, dim3(grid_1d((size_t)a.g_ps)), dim3(256), 0, s,
-                       grad_h, ny, nx, z.ldx, g, (size_t)a.g_ps);
+                       grad_h, ny, nx, z.ldx, a.absmax, g, (size_t)a.g_ps);
     hipLaunchKernelGGL(fringe_h_kernel<P>, dim3(grid_1d((size_t)nx * z.ldx), n_dl), dim3(256), 0,
                        s, lut_x, nx, levels, z.ldx, fxh, (size_t)a.fxh_ps);
     hipLaunchKernelGGL(fringe_h_kernel<P>, dim3(grid_1d((size_t)ny * z.ldy), n_dl), dim3(256), 0,
@@ -352,13 +376,17 @@ size_t backward_bytes(int ny, int nx, int layers, int levels) {
 
 hipError_t launch_backward_nt(const float2* grad_h, const float* lut_x, const float* lut_y, int ny,
                               int nx, int layers, int levels, int precision, float* gcoef,
-                              void* region, hipStream_t s) {
+                              void* region, unsigned long long* absmax, int e_fringe,
+                              hipStream_t s) {
     char* base = static_cast<char*>(region);
     if (precision == P_BF16)
-        return backward_nt<P_BF16>(grad_h, lut_x, lut_y, ny, nx, layers, levels, gcoef, base, s);
+        return backward_nt<P_BF16>(grad_h, lut_x, lut_y, ny, nx, layers, levels, gcoef, base,
+                                   absmax, e_fringe, s);
     if (precision == P_FP16)
-        return backward_nt<P_FP16>(grad_h, lut_x, lut_y, ny, nx, layers, levels, gcoef, base, s);
-    return backward_nt<P_FP32>(grad_h, lut_x, lut_y, ny, nx, layers, levels, gcoef, base, s);
+        return backward_nt<P_FP16>(grad_h, lut_x, lut_y, ny, nx, layers, levels, gcoef, base,
+                                   absmax, e_fringe, s);
+    return backward_nt<P_FP32>(grad_h, lut_x, lut_y, ny, nx, layers, levels, gcoef, base, absmax,
+                               e_fringe, s);
 }
 
 }  // namespace cgh

@@ -26,6 +26,7 @@ struct cgh_plan {
         size_t ws_off;
         cgh::Layout lo;
         int first_off;
+        int e_fringe = 0;  // FP16 range scaling of the scene's y fringe tables (2^-e)
     };
     int levels = 3, precision = 0;
     unsigned flags = 0;
@@ -91,8 +92,10 @@ hipError_t upload_args(cgh_plan& p, const int* tiles, hipStream_t s) {
     for (size_t i = 0; i < p.scenes.size(); ++i) {
         const cgh_plan::Scene& sc = p.scenes[i];
         const cgh::NtOutput o{reinterpret_cast<float2*>(sc.s.hologram), nullptr, 0};
+        const auto* absmax = reinterpret_cast<const unsigned long long*>(p.mem + sc.ws_off +
+                                                                         sc.lo.ops) + kAbsmaxWord;
         p.h_args[i] = cgh::make_plan_args(sc.s.ny, sc.s.nx, sc.s.n_layers, p.levels, p.precision,
-                                          tiles, p.h_prep[i].b, o);
+                                          tiles, p.h_prep[i].b, o, absmax, sc.e_fringe);
     }
     hipError_t e = hipMemcpyAsync(p.d_args, p.h_args.data(), p.h_args.size() * sizeof(cgh::PlanArgs),
                                   hipMemcpyHostToDevice, s);
@@ -362,6 +365,7 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
         h_luts.reserve(n_luts);
         p->h_prep.resize(n);
         Optics op;
+        FringeScale fs;
         for (int i = 0; i < n; ++i) {
             const cgh_plan::Scene& sc = p->scenes[i];
             const cgh::Layout& lo = sc.lo;
@@ -382,10 +386,12 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
                                           reinterpret_cast<const float*>(ws + lo.lut_y), ny, nx,
                                           nl, lo.flags_layer, nb};
             make_optics(op, nl, sc.z.data(), lambda, pitch, (flags & CGH_FLAG_EQ1_PREFACTOR) != 0);
+            fringe_scale(op, nl, p->precision, fs);
+            p->scenes[i].e_fringe = fs.e;
             for (int d = 0; d < nl; ++d) {
                 h_luts.push_back(cgh::LutJob{nx, d, levels, op.c[d], op.one_re[d], op.one_im[d],
                                              reinterpret_cast<float*>(ws + lo.lut_x)});
-                h_luts.push_back(cgh::LutJob{ny, d, levels, op.c[d], op.pre_re[d], op.pre_im[d],
+                h_luts.push_back(cgh::LutJob{ny, d, levels, op.c[d], fs.re[d], fs.im[d],
                                              reinterpret_cast<float*>(ws + lo.lut_y)});
             }
             p->max_nbx = std::max(p->max_nbx, nx >> levels);

@@ -37,6 +37,40 @@ __host__ __device__ inline size_t flag_level_off(int ny, int nx, int l) {
     return off;
 }
 
+// Range of the FP16 split operands.  FP16 keeps values below 65504 and normal
+// above 2^-14, so its panels hold power-of-two scaled values (exact in FP32):
+// data panels (coefficients, images, fields, cotangents) are scaled by 2^-e
+// with e the exponent of the source's largest magnitude, panels written by a
+// first contraction by 2^-t with t from a static bound of their magnitude, and
+// the FP32 epilogue of the last contraction multiplies by the inverse of the
+// product (a linear map commutes with the scaling, Eq. 3).  BF16 and FP32 keep
+// the FP32 exponent range and use scale 1.
+constexpr float kF16Ceiling = 32768.f;  // panel magnitudes are kept below 2^15
+
+// e with m in [2^e, 2^(e+1)), clamped to [-100, 100]; 0 for 0, inf and NaN.
+__host__ __device__ inline int range_exp(float m) {
+    if (!(m > 0.f) || !(m <= 3.402823466e38f)) return 0;
+    int e = 0;
+    frexpf(m, &e);
+    e -= 1;
+    return e < -100 ? -100 : (e > 100 ? 100 : e);
+}
+// Smallest t >= 0 with bound * 2^-t <= kF16Ceiling.
+__host__ __device__ inline int headroom_shift(float bound) {
+    int t = 0;
+    while (bound > kF16Ceiling) {
+        bound *= 0.5f;
+        ++t;
+    }
+    return t;
+}
+__host__ __device__ inline float pow2f(int e) { return ldexpf(1.0f, e); }
+// Largest magnitude recorded by a max-abs word (float bits of a nonnegative
+// value in the low half of a 64-bit word, raised with atomicMax).
+__device__ inline float absmax_value(const unsigned long long* w) {
+    return w ? __uint_as_float((unsigned)*w) : 0.f;
+}
+
 struct LayerConsts {
     double c[kLayerChunk];       // pitch^2 / (2 lambda z_d): kernel phase in cycles per px^2
     double pre_re[kLayerChunk];  // per-layer complex constant (1, or exp(i k z)/z)
@@ -63,7 +97,7 @@ struct Layout {
     size_t total;
     size_t t_layer;              // complex elements of T per layer
     size_t flags_layer;          // flag bytes per layer
-    size_t ops;                  // 4 x u64 operator counters, right after the flags
+    size_t ops;                  // 4 x u64 operator counters and the max-abs word, after the flags
     size_t flags_fill;           // bytes to clear from `flags` (flags and counters)
     int entries_n;               // problems in the table: one per (layer, level), then one
     int first_tiles_max;
@@ -74,6 +108,8 @@ struct Launch;  // forward declaration for the host dispatcher
 
 // ------------------------------------------------------------ launchers (host)
 hipError_t launch_fill_u8(uint8_t* p, size_t n, hipStream_t s);
+// *word = max(*word, bits of max |x[i]|) over n floats (word cleared by the caller).
+hipError_t launch_absmax(const float* x, size_t n, unsigned long long* word, hipStream_t s);
 // parts: bit l-1 keeps the level-l details, bit `levels` the approximation.
 constexpr unsigned kAllParts = 0xFu;
 hipError_t launch_dwt_mask(const float* obj, const uint8_t* layer, const float* sal, int ny, int nx,

@@ -47,40 +47,49 @@ __global__ __launch_bounds__(256) void toeplitz_panel_kernel(const float* __rest
 }
 
 // Interleaved complex64 [rows][cols] -> K-blocked operand planes [rows][ld], zero pad.
+// absmax (FP16 range scaling, else null): values scaled by 2^-e, e the exponent of
+// the input's largest component magnitude.
 template <int P>
 __global__ __launch_bounds__(256) void complex_panel_kernel(const float2* __restrict__ in,
                                                             int rows, int cols, int ld,
+                                                            const unsigned long long* absmax,
                                                             void* __restrict__ out, size_t ps) {
     const size_t total = (size_t)rows * ld;
+    const float sc = absmax ? pow2f(-range_exp(absmax_value(absmax))) : 1.f;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         int r, c;
         kblk_pos(e, rows, r, c);
         const float2 v = c < cols ? in[(size_t)r * cols + c] : make_float2(0.f, 0.f);
-        put_c<P>(out, ps, e, v.x, v.y);
+        put_c<P>(out, ps, e, v.x * sc, v.y * sc);
     }
 }
 
 // Real image [rows][cols] -> K-blocked operand planes [rows][ld] (zeros for
 // cols <= k < ld).
+// absmax as for complex_panel_kernel.
 template <int P>
 __global__ __launch_bounds__(256) void real_panel_kernel(const float* __restrict__ in, int rows,
                                                          int cols, int ld,
+                                                         const unsigned long long* absmax,
                                                          void* __restrict__ out, size_t ps) {
     const size_t total = (size_t)rows * ld;
+    const float sc = absmax ? pow2f(-range_exp(absmax_value(absmax))) : 1.f;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         int r, c;
         kblk_pos(e, rows, r, c);
-        put_r<P>(out, ps, e, c < cols ? in[(size_t)r * cols + c] : 0.f);
+        put_r<P>(out, ps, e, c < cols ? in[(size_t)r * cols + c] * sc : 0.f);
     }
 }
 
 // Sum of `split` FP32 partials [split][rows][cols] -> K-blocked operand planes [rows][ld].
+// scale: multiplies the sums (a power of two: FP16 range scaling, else 1).
 template <int P>
 __global__ __launch_bounds__(256) void reduce_panel_kernel(const float2* __restrict__ partial,
                                                            int split, int rows, int cols, int ld,
-                                                           void* __restrict__ out, size_t ps) {
+                                                           float scale, void* __restrict__ out,
+                                                           size_t ps) {
     const size_t total = (size_t)rows * ld, plane = (size_t)rows * cols;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
@@ -95,34 +104,48 @@ __global__ __launch_bounds__(256) void reduce_panel_kernel(const float2* __restr
                 im += v.y;
             }
         }
-        put_c<P>(out, ps, e, re, im);
+        put_c<P>(out, ps, e, re * scale, im * scale);
     }
 }
 
 // Writes one problem and its tile count where the contraction kernel reads them.
+// With a max-abs word the problem's output scale becomes
+// base * 2^(exponent of the word's value + shift) (FP16 range scaling).
 __global__ void dense_entry_kernel(NtEntry e, int tiles, NtEntry* __restrict__ dst,
-                                   int* __restrict__ count) {
+                                   int* __restrict__ count, const unsigned long long* absmax,
+                                   int shift, float base) {
     if (threadIdx.x == 0) {
+        if (absmax) e.out_scale = base * pow2f(range_exp(absmax_value(absmax)) + shift);
         *dst = e;
         *count = tiles;
     }
 }
 
+// FP16 range scaling: the field panel is scaled to [1, 2) times its largest
+// component (|H'| < 2 sqrt 2), the step-1 product T = K'_x H' (|T| < 2 sqrt 2 nx)
+// by 2^-t into its panel, and the 1 / (ny nx) factor moves from the K'_y panel
+// (where it would fall below FP16's normal range) into step 2's epilogue, which
+// multiplies by 2^(e + t) / (ny nx).
 template <int P>
 hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const float* lut0_y,
                           const float2* in, float2* out, int ny, int nx, int adjoint, float scale,
                           int split, hipStream_t s) {
+    constexpr bool F16 = P == P_FP16;
     const int ldx = pad_kt(nx), ldy = pad_kt(ny);
     const float im_sign = adjoint ? 1.f : -1.f;
     const size_t kx_ps = (size_t)nx * ldx, ky_ps = (size_t)ny * ldy;
     const size_t h_ps = (size_t)ny * ldx, t_ps = (size_t)nx * ldy;
+    const int t = F16 ? headroom_shift(3.f * (float)nx) : 0;
+    hipError_t e = hipSuccess;
+    if (F16) e = launch_absmax(reinterpret_cast<const float*>(in), 2 * (size_t)ny * nx, b.absmax, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(toeplitz_panel_kernel<P>, dim3(grid_1d(kx_ps)), dim3(256), 0, s, lut0_x,
                        nx, nx, nx, ldx, 1.f, im_sign, b.kx, kx_ps);
     hipLaunchKernelGGL(toeplitz_panel_kernel<P>, dim3(grid_1d(ky_ps)), dim3(256), 0, s, lut0_y,
-                       ny, ny, ny, ldy, scale, im_sign, b.ky, ky_ps);
+                       ny, ny, ny, ldy, F16 ? 1.f : scale, im_sign, b.ky, ky_ps);
     hipLaunchKernelGGL(complex_panel_kernel<P>, dim3(grid_1d(h_ps)), dim3(256), 0, s, in, ny, nx,
-                       ldx, b.h, h_ps);
-    hipError_t e = hipGetLastError();
+                       ldx, F16 ? b.absmax : nullptr, b.h, h_ps);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
 
     const int tn = nt_table_tile_n(kEpiComplex, P);
@@ -143,11 +166,12 @@ hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const floa
     e1.tiles_n = (ny + tn - 1) / tn;
     e1.tile_m = kNtTile;
     e1.tile_n = tn;
+    e1.out_scale = 1.f;
     hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e1, tiles1, b.entries,
-                       b.counts);
+                       b.counts, nullptr, 0, 1.f);
     if ((e = launch_nt_table(kEpiComplex, P, b.entries, 1, b.counts, tiles1, split, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_panel_kernel<P>, dim3(grid_1d(t_ps)), dim3(256), 0, s,
-                       split > 1 ? b.partial : b.c1, split, nx, ny, ldy, b.t, t_ps);
+                       split > 1 ? b.partial : b.c1, split, nx, ny, ldy, pow2f(-t), b.t, t_ps);
 
     NtEntry e2{};
     e2.a = b.ky;
@@ -165,8 +189,9 @@ hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const floa
     e2.tiles_n = (nx + tn - 1) / tn;
     e2.tile_m = kNtTile;
     e2.tile_n = tn;
+    e2.out_scale = 1.f;
     hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e2, tiles2, b.entries + 1,
-                       b.counts + 1);
+                       b.counts + 1, F16 ? b.absmax : nullptr, t, scale);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_nt_table(kEpiComplex, P, b.entries + 1, 1, b.counts + 1, tiles2, split, s)) != hipSuccess)
         return e;
@@ -178,10 +203,17 @@ hipError_t dense_backprop(const DenseBuffers& b, const float* lut0_x, const floa
 // (the layer's prefactor is in g_y).  Step 1 T[x][q] = sum_p A[q][p] K_x[x][p]
 // (real x complex, written transposed as a K-blocked panel); step 2
 // H[y][x] = sum_q K_y[y][q] T[x][q].
+// FP16 range scaling: the reconstruction (|recon| <= (1 + 3L) max |object| <= 10 max
+// |object| for the averaging Haar pair with details masked) is scaled by 2^-e, e the
+// exponent of max |object| (absmax), so |A'| < 20; T = A' K_x^T (|T| < 20 nx) by
+// 2^-t; step 2's epilogue multiplies by 2^(e + t + e_fringe).
 template <int P>
 hipError_t fused_layer(const float* recon, const float* lut0_x, const float* lut0_y, int ny,
                        int nx, int accumulate, float2* out, char* scratch, NtEntry* entries,
-                       int* counts, hipStream_t s) {
+                       int* counts, const unsigned long long* absmax, int e_fringe,
+                       hipStream_t s) {
+    constexpr bool F16 = P == P_FP16;
+    const int ts = F16 ? headroom_shift(20.f * (float)nx) : 0;
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     const int ldx = pad_kt(nx), ldy = pad_kt(ny);
     const size_t kx_ps = (size_t)nx * ldx, ky_ps = (size_t)ny * ldy;
@@ -195,7 +227,7 @@ hipError_t fused_layer(const float* recon, const float* lut0_x, const float* lut
     hipLaunchKernelGGL(toeplitz_panel_kernel<P>, dim3(grid_1d(ky_ps)), dim3(256), 0, s, lut0_y,
                        ny, ny, ny, ldy, 1.f, 1.f, ky, ky_ps);
     hipLaunchKernelGGL(real_panel_kernel<P>, dim3(grid_1d(a_ps)), dim3(256), 0, s, recon, ny, nx,
-                       ldx, a, a_ps);
+                       ldx, F16 ? absmax : nullptr, a, a_ps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 
@@ -215,7 +247,9 @@ hipError_t fused_layer(const float* recon, const float* lut0_x, const float* lut
     e1.out_ld = nx * 16;  // T panel: nx rows
     e1.tiles_n = (nx + kNtTile - 1) / kNtTile;
     e1.tile_m = e1.tile_n = kNtTile;
-    hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e1, tiles1, entries, counts);
+    e1.out_scale = pow2f(-ts);
+    hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e1, tiles1, entries, counts,
+                       nullptr, 0, 1.f);
     if ((e = launch_nt_first_table(P, entries, 1, counts, tiles1, s)) != hipSuccess) return e;
 
     const int tn = nt_table_tile_n(kEpiComplex, P);
@@ -236,8 +270,9 @@ hipError_t fused_layer(const float* recon, const float* lut0_x, const float* lut
     e2.tile_m = kNtTile;
     e2.tile_n = tn;
     e2.accumulate = accumulate;
+    e2.out_scale = 1.f;
     hipLaunchKernelGGL(dense_entry_kernel, dim3(1), dim3(64), 0, s, e2, tiles2, entries + 1,
-                       counts + 1);
+                       counts + 1, F16 ? absmax : nullptr, ts + e_fringe, 1.f);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return launch_nt_table(kEpiComplex, P, entries + 1, 1, counts + 1, tiles2, 1, s);
 }
@@ -252,7 +287,7 @@ size_t dense_bytes(int ny, int nx, int split) {
 }
 
 DenseBuffers dense_buffers(char* base, int ny, int nx, int split, float2* partial,
-                           NtEntry* entries, int* counts) {
+                           NtEntry* entries, int* counts, unsigned long long* absmax) {
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     const size_t ldx = pad_kt(nx), ldy = pad_kt(ny);
     DenseBuffers b{};
@@ -269,6 +304,7 @@ DenseBuffers dense_buffers(char* base, int ny, int nx, int split, float2* partia
     b.partial = partial;
     b.entries = entries;
     b.counts = counts;
+    b.absmax = absmax;
     return b;
 }
 
@@ -295,15 +331,16 @@ size_t fused_bytes(int ny, int nx) {
 
 hipError_t launch_fused_layer(const float* recon, const float* lut0_x, const float* lut0_y,
                               int ny, int nx, int precision, int accumulate, float2* out,
-                              char* scratch, NtEntry* entries, int* counts, hipStream_t s) {
+                              char* scratch, NtEntry* entries, int* counts,
+                              const unsigned long long* absmax, int e_fringe, hipStream_t s) {
     if (precision == P_BF16)
         return fused_layer<P_BF16>(recon, lut0_x, lut0_y, ny, nx, accumulate, out, scratch,
-                                   entries, counts, s);
+                                   entries, counts, absmax, e_fringe, s);
     if (precision == P_FP16)
         return fused_layer<P_FP16>(recon, lut0_x, lut0_y, ny, nx, accumulate, out, scratch,
-                                   entries, counts, s);
+                                   entries, counts, absmax, e_fringe, s);
     return fused_layer<P_FP32>(recon, lut0_x, lut0_y, ny, nx, accumulate, out, scratch, entries,
-                               counts, s);
+                               counts, absmax, e_fringe, s);
 }
 
 }  // namespace cgh

@@ -63,15 +63,16 @@ __device__ __forceinline__ float pooled(const Pool<B>& p, int lev, int j, int i)
 // positions whose block is salient, the operator count of Sec. 3 (one
 // operator per point of the level's residual map that is processed).  The
 // masks are the same for every layer, so they are counted once.
+// Returns the largest |object| value of the block.
 template <int L>
-__device__ __forceinline__ void dwt_mask_block(
+__device__ __forceinline__ float dwt_mask_body(
     const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
     int ny, int nx, int layers, float t1, float t2, float t3, unsigned parts,
     float* __restrict__ coef, uint8_t* __restrict__ flags, size_t flags_layer,
     unsigned long long* __restrict__ ops, int bx, int by) {
     constexpr int B = 1 << L;
     const int nbx = nx >> L;
-    if (bx >= nbx) return;
+    if (bx >= nbx) return 0.f;
     // lowest active lane: writes the row flags once per wave (all lanes share by)
     const bool leader = (int)__lane_id() == __ffsll((long long)__ballot(1)) - 1;
 
@@ -120,6 +121,11 @@ __device__ __forceinline__ void dwt_mask_block(
             }
         }
     }
+    float amax = 0.f;
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int c = 0; c < B; ++c) amax = fmaxf(amax, fabsf(a[r][c]));
     Pool<B> pool;
     if (sal) pool_saliency<L>(sal, nx, by, bx, pool);
     const bool vst = (reinterpret_cast<uintptr_t>(coef) & 15) == 0;  // vector stores
@@ -230,6 +236,26 @@ __device__ __forceinline__ void dwt_mask_block(
         if (leader)
             for (int l = 0; l < L; ++l)
                 if (wave_ops[l]) atomicAdd(&ops[l], 4ull * wave_ops[l]);
+    }
+    return amax;
+}
+
+// ops (optional): ops[0..2] operator counts, ops[4] max |object| as float bits (the
+// range of the FP16 split operands), both zeroed by the caller.
+template <int L>
+__device__ __forceinline__ void dwt_mask_block(
+    const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
+    int ny, int nx, int layers, float t1, float t2, float t3, unsigned parts,
+    float* __restrict__ coef, uint8_t* __restrict__ flags, size_t flags_layer,
+    unsigned long long* __restrict__ ops, int bx, int by) {
+    float amax = dwt_mask_body<L>(obj, layer, sal, ny, nx, layers, t1, t2, t3, parts, coef, flags,
+                                  flags_layer, ops, bx, by);
+    if (ops) {
+        // wave maximum: every lane of the wave is active here (lanes past the row give 0)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+        if (__lane_id() == 0 && amax > 0.f)
+            atomicMax(&ops[4], (unsigned long long)__float_as_uint(amax));
     }
 }
 

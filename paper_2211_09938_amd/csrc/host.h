@@ -15,6 +15,8 @@ namespace cgh {
 namespace host {
 
 constexpr size_t kAlign = 256;  // workspace region alignment (bytes)
+constexpr int kOpsWords = 5;    // operator counters [0..3], max-abs word [4]
+constexpr int kAbsmaxWord = 4;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -75,9 +77,11 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels,
         lo.flags_layer += (size_t)cgh::band_side(ny, l) + cgh::band_side(nx, l);
     }
     const size_t flag_bytes = (size_t)layers * lo.flags_layer;
-    lo.flags = take((flag_bytes + 7) / 8 * 8 + 32);
+    // after the flags: four 64-bit operator counters, then the max-abs word of the
+    // FP16 range scaling (kOpsWords words, cleared with the flags)
+    lo.flags = take((flag_bytes + 7) / 8 * 8 + 8 * kOpsWords);
     lo.ops = lo.flags + (flag_bytes + 7) / 8 * 8;
-    lo.flags_fill = lo.ops + 32 - lo.flags;
+    lo.flags_fill = lo.ops + 8 * kOpsWords - lo.flags;
     const cgh::NtSizes z = cgh::nt_sizes(ny, nx, layers, levels);
     lo.rowlist = take(z.rowlist * 4);
     lo.collist = take(z.collist * 4);
@@ -190,6 +194,26 @@ inline void make_optics(Optics& o, int layers, const double* z, double lambda, d
             o.pre_re[d] = 1.0;
             o.pre_im[d] = 0.0;
         }
+    }
+}
+
+// FP16 split operands: the y fringe tables carry the layer prefactors (magnitude
+// 1, or 1/z_d with the Eq. 1 constant).  They are built from prefactors scaled by
+// 2^-e, e the exponent of the largest magnitude, so that every table entry stays
+// below 2^(levels+1); the last contraction's epilogue multiplies by 2^e.  Other
+// precisions: e = 0 and the prefactors unchanged.
+struct FringeScale {
+    int e = 0;
+    double re[CGH_MAX_LAYERS], im[CGH_MAX_LAYERS];
+};
+
+inline void fringe_scale(const Optics& op, int layers, int precision, FringeScale& f) {
+    double m = 0.0;
+    for (int d = 0; d < layers; ++d) m = std::fmax(m, std::hypot(op.pre_re[d], op.pre_im[d]));
+    f.e = precision == CGH_FP16_SPLIT ? cgh::range_exp((float)m) : 0;
+    for (int d = 0; d < layers; ++d) {
+        f.re[d] = std::ldexp(op.pre_re[d], -f.e);
+        f.im[d] = std::ldexp(op.pre_im[d], -f.e);
     }
 }
 

@@ -32,12 +32,16 @@ inline int grid_1d(size_t n) {
 
 // Residual map (b < L) or approximation image (b == L) of layer d as a
 // K-blocked real panel: rows ny >> b, K = nx >> b padded to 16.
+// absmax (FP16 range scaling, else null): values scaled by 2^-e, e the exponent of
+// max |object| (|residual| <= 3 max |object|).
 template <int P>
 __global__ __launch_bounds__(256) void residual_panel_kernel(const float* __restrict__ coef,
                                                              int ny, int nx, int L, int b,
+                                                             const unsigned long long* absmax,
                                                              void* __restrict__ out, size_t ps) {
     const int rows = ny >> b, cols = nx >> b, ld = pad_kt(cols);
     const size_t total = (size_t)rows * ld;
+    const float sc = absmax ? pow2f(-range_exp(absmax_value(absmax))) : 1.f;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         int r, c;
@@ -56,7 +60,7 @@ __global__ __launch_bounds__(256) void residual_panel_kernel(const float* __rest
                 v = sx * vv + sy * hh + sx * sy * dd;
             }
         }
-        put_r<P>(out, ps, e, v);
+        put_r<P>(out, ps, e, v * sc);
     }
 }
 
@@ -97,11 +101,18 @@ struct LitArgs {
     NtEntry* first;       // [layers * (L + 1)]
     NtEntry* second;      // [1]
     int* counts;          // tile totals of the two contractions
+    // FP16 range scaling: images scaled by 2^-e (|image'| < 6), the first products
+    // (|T| < 6 x 8 nx) by 2^-t, the second epilogue by 2^(e + t + e_fringe)
+    const unsigned long long* absmax;  // null unless FP16
+    int t_shift, e_fringe;
 };
 
 // Problem tables; one thread (at most 256 x 4 problems with closed-form shapes).
 __global__ void literal_entries_kernel(LitArgs a) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const float first_scale = a.absmax ? pow2f(-a.t_shift) : 1.f;
+    const float second_scale =
+        a.absmax ? pow2f(range_exp(absmax_value(a.absmax)) + a.t_shift + a.e_fringe) : 1.f;
     size_t rb_off = 0, fx_off = 0;
     int seg = 0, tiles = 0, t = 0;
     for (int d = 0; d < a.layers; ++d) {
@@ -123,6 +134,7 @@ __global__ void literal_entries_kernel(LitArgs a) {
             e.tiles_n = (a.nx + kNtTile - 1) / kNtTile;
             e.tile_begin = tiles;
             e.tile_m = e.tile_n = kNtTile;
+            e.out_scale = first_scale;
             a.first[t++] = e;
             tiles += nt_tiles(rows, a.nx, kNtTile, kNtTile);
             rb_off += (size_t)rows * kc;
@@ -147,6 +159,7 @@ __global__ void literal_entries_kernel(LitArgs a) {
     e.accumulate = a.accumulate;
     e.tile_m = kNtTile;
     e.tile_n = a.tn2;
+    e.out_scale = second_scale;
     a.second[0] = e;
     a.counts[0] = tiles;
     a.counts[1] = nt_tiles(a.ny, a.nx, kNtTile, a.tn2);
@@ -206,7 +219,9 @@ LitRegions lit_regions(char* base, int ny, int nx, int layers, int L) {
 template <int P>
 hipError_t literal(const float* coef, const float* lut_x, const float* lut_y,
                    const LitTables& tb, int ny, int nx, int layers, int L, int split,
-                   float2* partial, float2* hologram, int accumulate, char* base, hipStream_t s) {
+                   float2* partial, float2* hologram, int accumulate,
+                   const unsigned long long* absmax, int e_fringe, char* base, hipStream_t s) {
+    const unsigned long long* am = P == P_FP16 ? absmax : nullptr;
     const LitShape z = lit_shape(ny, nx, layers, L);
     const LitRegions r = lit_regions(base, ny, nx, layers, L);
     // level-0 (point) tables of every layer; y tables carry the per-layer prefactor
@@ -223,7 +238,7 @@ hipError_t literal(const float* coef, const float* lut_x, const float* lut_y,
         for (int b = L; b >= 0; --b) {
             const int rows = ny >> b, kc = pad_kt(nx >> b);
             hipLaunchKernelGGL(residual_panel_kernel<P>, dim3(grid_1d((size_t)rows * kc)),
-                               dim3(256), 0, s, coef + (size_t)d * ny * nx, ny, nx, L, b,
+                               dim3(256), 0, s, coef + (size_t)d * ny * nx, ny, nx, L, b, am,
                                r.rb + rb_off * es, (size_t)z.rb_ps);
             const float* tx = b == 0 ? l0x + (size_t)d * 2 * lenx
                                      : lut_x + lut_table(d, b, 0, 0, L) * lenx;
@@ -262,6 +277,9 @@ hipError_t literal(const float* coef, const float* lut_x, const float* lut_y,
     a.first = r.entries;
     a.second = r.entries + (size_t)layers * (L + 1);
     a.counts = r.counts;
+    a.absmax = am;
+    a.t_shift = am ? headroom_shift(48.f * (float)nx) : 0;
+    a.e_fringe = e_fringe;
     hipLaunchKernelGGL(literal_entries_kernel, dim3(1), dim3(64), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     e = launch_nt_first_table(P, a.first, layers * (L + 1), a.counts, z.first_tiles, s);
@@ -281,16 +299,17 @@ size_t literal_bytes(int ny, int nx, int layers, int levels) {
 hipError_t launch_literal(const float* coef, const float* lut_x, const float* lut_y,
                           const LitTables& tb, int ny, int nx, int layers, int levels,
                           int precision, int split, float2* partial, float2* hologram,
-                          int accumulate, void* region, hipStream_t s) {
+                          int accumulate, const unsigned long long* absmax, int e_fringe,
+                          void* region, hipStream_t s) {
     char* base = static_cast<char*>(region);
     if (precision == P_BF16)
         return literal<P_BF16>(coef, lut_x, lut_y, tb, ny, nx, layers, levels, split, partial,
-                               hologram, accumulate, base, s);
+                               hologram, accumulate, absmax, e_fringe, base, s);
     if (precision == P_FP16)
         return literal<P_FP16>(coef, lut_x, lut_y, tb, ny, nx, layers, levels, split, partial,
-                               hologram, accumulate, base, s);
+                               hologram, accumulate, absmax, e_fringe, base, s);
     return literal<P_FP32>(coef, lut_x, lut_y, tb, ny, nx, layers, levels, split, partial,
-                           hologram, accumulate, base, s);
+                           hologram, accumulate, absmax, e_fringe, base, s);
 }
 
 }  // namespace cgh

@@ -53,6 +53,8 @@ struct NtEntry {
     int tile_begin;         // exclusive prefix of tiles over the table
     int accumulate;         // second: hologram += result
     int tile_m, tile_n;     // tile shape the table was planned for
+    float out_scale;        // the epilogue multiplies the FP32 products by it (a power of
+                            // two undoing FP16 range scaling, else 1)
 };
 
 // Device-side plan written by the planning kernels (lives in the workspace).
@@ -61,6 +63,7 @@ struct PlanHeader {
     int first_tiles;   // tiles of the first contraction
     int rows_active;   // sum of active row counts
     int second_tiles;  // output tiles of the second contraction
+    float cb_scale;    // scale of the coefficient panel (FP16 range scaling, else 1)
 };
 
 // Element counts (dense upper bounds) of the compacted regions.
@@ -156,6 +159,9 @@ struct NtOutput {
 // Arguments of the planning kernel of one scene (device-side tables).
 struct PlanArgs {
     int ny, nx, layers, levels, esize;
+    int fp16;                            // FP16 split operands: range scaling
+    int e_fringe;                        // exponent the y fringe tables were scaled by (2^-e)
+    const unsigned long long* absmax;    // max |object| of the scene (max-abs word)
     int tm1, tn1, tm2, tn2;  // tile shapes of the first and second contraction
     const int* cnt_row;
     const int* cnt_col;
@@ -176,7 +182,8 @@ struct PlanArgs {
 
 // tiles: {rows, cols} of the first contraction's tile, then of the second's.
 PlanArgs make_plan_args(int ny, int nx, int layers, int levels, int precision, const int* tiles,
-                        const NtBuffers& b, const NtOutput& o);
+                        const NtBuffers& b, const NtOutput& o,
+                        const unsigned long long* absmax = nullptr, int e_fringe = 0);
 
 // One scene of a batched preparation: its flags, coefficients, tables and buffers.
 struct PrepScene {
@@ -198,7 +205,8 @@ hipError_t launch_materialize_batch(const PrepScene* scenes, int n, int levels, 
 // tiles: {rows, cols} of the first contraction's tile, then of the second's.
 hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int levels,
                           size_t flags_layer, int precision, const int* tiles,
-                          const NtBuffers& b, const NtOutput& o, hipStream_t s);
+                          const NtBuffers& b, const NtOutput& o,
+                          const unsigned long long* absmax, int e_fringe, hipStream_t s);
 hipError_t launch_nt_materialize(const float* coef, const float* lut_x, const float* lut_y, int ny,
                                  int nx, int layers, int levels, int precision,
                                  const NtBuffers& b, hipStream_t s);
@@ -259,6 +267,8 @@ struct DenseBuffers {
     float2* partial;    // split-K partials (split x ny x nx)
     NtEntry* entries;   // 2 problem slots
     int* counts;        // 2 tile counts
+    unsigned long long* absmax;  // max-abs word of the input field (FP16 range scaling;
+                                 // cleared by the caller)
 };
 // Bytes of the panel region (plus the unsplit step-1 product) for a split.
 size_t dense_bytes(int ny, int nx, int split);
@@ -270,11 +280,14 @@ size_t dense_bytes(int ny, int nx, int split);
 // entries / counts: 2 slots.
 size_t fused_bytes(int ny, int nx);
 size_t fused_recon_offset(int ny, int nx);
+// absmax: max |object| word of the coefficient stage, e_fringe: the exponent the y
+// table's prefactor was scaled by (FP16 range scaling; ignored otherwise).
 hipError_t launch_fused_layer(const float* recon, const float* lut0_x, const float* lut0_y,
                               int ny, int nx, int precision, int accumulate, float2* out,
-                              char* scratch, NtEntry* entries, int* counts, hipStream_t s);
+                              char* scratch, NtEntry* entries, int* counts,
+                              const unsigned long long* absmax, int e_fringe, hipStream_t s);
 DenseBuffers dense_buffers(char* base, int ny, int nx, int split, float2* partial,
-                           NtEntry* entries, int* counts);
+                           NtEntry* entries, int* counts, unsigned long long* absmax);
 // out = scale * K'_y in K'_x, K' = conj(K) (adjoint == 0) or K (adjoint != 0).
 hipError_t launch_dense_backprop(const DenseBuffers& b, const float* lut0_x, const float* lut0_y,
                                  const float2* in, float2* out, int ny, int nx, int adjoint,
@@ -284,9 +297,12 @@ hipError_t launch_dense_backprop(const DenseBuffers& b, const float* lut0_x, con
 // contractions) into gcoef (per layer an ny x nx plane at Mallat positions);
 // `region` holds backward_bytes() of panels, partials and problem tables.
 size_t backward_bytes(int ny, int nx, int layers, int levels);
+// absmax: a cleared max-abs word for the cotangent and e_fringe the exponent the y
+// tables' prefactors were scaled by (FP16 range scaling; ignored otherwise).
 hipError_t launch_backward_nt(const float2* grad_h, const float* lut_x, const float* lut_y, int ny,
                               int nx, int layers, int levels, int precision, float* gcoef,
-                              void* region, hipStream_t s);
+                              void* region, unsigned long long* absmax, int e_fringe,
+                              hipStream_t s);
 
 // Direct launch of first-contraction problems (A real, B complex, transposed
 // K-blocked panel output) over a table; `tiles` bounds the device tile count.
@@ -300,10 +316,13 @@ struct LitTables {
     const double *c, *one_re, *one_im, *pre_re, *pre_im;
 };
 size_t literal_bytes(int ny, int nx, int layers, int levels);
+// absmax: max |object| word of the coefficient stage; e_fringe as for the backward
+// (FP16 range scaling; ignored otherwise).
 hipError_t launch_literal(const float* coef, const float* lut_x, const float* lut_y,
                           const LitTables& tb, int ny, int nx, int layers, int levels,
                           int precision, int split, float2* partial, float2* hologram,
-                          int accumulate, void* region, hipStream_t s);
+                          int accumulate, const unsigned long long* absmax, int e_fringe,
+                          void* region, hipStream_t s);
 
 // Tiles of a problem with M rows and N columns under a tile shape.
 __host__ __device__ inline int nt_tiles(int M, int N, int tm, int tn) {

@@ -441,6 +441,10 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
                         re[q] = cr[i][j][4 * qd + q];
                         im[q] = ci[i][j][4 * qd + q];
                     }
+                    if constexpr (P == P_FP16) {  // power-of-two range scale: exact
+                        re[q] *= e.out_scale;
+                        im[q] *= e.out_scale;
+                    }
                 }
                 Epi::store4(e, s, split, m0 + wm + 32 * i + 8 * qd + 4 * g,
                             n0 + wn + 32 * j + l32, re, im);
@@ -683,6 +687,10 @@ __device__ __forceinline__ void pp_tile(const NtEntry& e, int m0, int n0, int kb
                 for (int q = 0; q < 4; ++q) {
                     re[q] = cr[i][j][4 * qd + q];
                     im[q] = ci[i][j][4 * qd + q];
+                    if constexpr (P == P_FP16) {  // power-of-two range scale: exact
+                        re[q] *= e.out_scale;
+                        im[q] *= e.out_scale;
+                    }
                 }
                 Epi::store4(e, s, split, m0 + wm + 32 * i + 8 * qd + 4 * g,
                             n0 + wn + 32 * j + l32, re, im);

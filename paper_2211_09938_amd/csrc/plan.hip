@@ -122,6 +122,18 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
         __syncthreads();
     }
     const int kpad = total_k;
+    // FP16 range scaling: coefficients to [1, 2) times their largest magnitude
+    // (|coefficient| <= max |object| for the averaging Haar pair), T_c below 2^15:
+    // |T_c| < 2 x nx columns x 8 (a level's block fringe sums at most 2^3 unit
+    // phasors); the second contraction's epilogue undoes both and the y tables' scale
+    float cb_scale = 1.f, first_scale = 1.f, second_scale = 1.f;
+    if (a.fp16) {
+        const int ea = range_exp(absmax_value(a.absmax));
+        const int t = headroom_shift(16.f * (float)a.nx);
+        cb_scale = pow2f(-ea);
+        first_scale = pow2f(-t);
+        second_scale = pow2f(ea + t + a.e_fringe);
+    }
     // pass 2: the problem table
     const char* cb = static_cast<const char*>(a.cb);
     const char* fx = static_cast<const char*>(a.fx);
@@ -147,6 +159,7 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
         e.accumulate = 0;
         e.tile_m = a.tm1;
         e.tile_n = a.tn1;
+        e.out_scale = first_scale;
         a.first[t] = e;
     }
     if (threadIdx.x == 0) {
@@ -154,6 +167,7 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
         a.hdr->first_tiles = total_t;
         a.hdr->rows_active = total_r;
         a.hdr->second_tiles = nt_tiles(a.ny, a.nx, a.tm2, a.tn2);
+        a.hdr->cb_scale = cb_scale;
         NtEntry e;
         e.a = a.fy;
         e.b = a.tc;
@@ -173,6 +187,7 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
         e.accumulate = a.accumulate;
         e.tile_m = a.tm2;
         e.tile_n = a.tn2;
+        e.out_scale = second_scale;
         a.second[0] = e;
     }
 }
@@ -327,10 +342,12 @@ __device__ __forceinline__ void cb_block(const float* __restrict__ coef,
                                          const int* __restrict__ collist,
                                          const int* __restrict__ cnt_row,
                                          const int* __restrict__ cnt_col, int ny, int nx,
-                                         int levels, void* cb, size_t ps, int dl) {
+                                         int levels, const PlanHeader* __restrict__ hdr,
+                                         void* cb, size_t ps, int dl) {
     const int d = dl / levels, l = dl % levels + 1;
     const int cr = cnt_row[dl], cc = cnt_col[dl], pc = pad_kt(cc);
     if (cr == 0 || pc == 0) return;
+    const float scale = hdr->cb_scale;  // written by the planning kernel
     const int nyl = ny >> l, nxl = nx >> l;
     const int* rl = rowlist + dl_rows_off(ny, levels, d, l);
     const int* cl = collist + dl_cols_off(nx, levels, d, l);
@@ -351,7 +368,7 @@ __device__ __forceinline__ void cb_block(const float* __restrict__ coef,
             if (c < cc) {
                 const int j = cl[c];
                 // the LL quadrant of a level below the top belongs to the coarser levels
-                if (!(l < levels && r < nyl && j < nxl)) v[q] = cd[(size_t)r * nx + j];
+                if (!(l < levels && r < nyl && j < nxl)) v[q] = cd[(size_t)r * nx + j] * scale;
             }
         }
         put_r4<P>(cb, ps, base + e, v);
@@ -382,8 +399,10 @@ __global__ __launch_bounds__(256) void cb_kernel(const float* __restrict__ coef,
                                                  const int* __restrict__ collist,
                                                  const int* __restrict__ cnt_row,
                                                  const int* __restrict__ cnt_col, int ny, int nx,
-                                                 int levels, void* cb, size_t ps) {
-    cb_block<P>(coef, rowlist, collist, cnt_row, cnt_col, ny, nx, levels, cb, ps, blockIdx.y);
+                                                 int levels, const PlanHeader* __restrict__ hdr,
+                                                 void* cb, size_t ps) {
+    cb_block<P>(coef, rowlist, collist, cnt_row, cnt_col, ny, nx, levels, hdr, cb, ps,
+                blockIdx.y);
 }
 
 // Batched panels: grid.z = scene, grid.y = (layer, level), grid.x = chunks; the
@@ -412,7 +431,7 @@ __global__ __launch_bounds__(256) void cb_batch_kernel(const PrepScene* __restri
     const PrepScene& sc = scenes[blockIdx.z];
     if ((int)blockIdx.y >= sc.layers * levels) return;
     cb_block<P>(sc.coef, sc.b.rowlist, sc.b.collist, sc.b.cnt_row, sc.b.cnt_col, sc.ny, sc.nx,
-                levels, sc.b.cb, sc.b.cb_ps, blockIdx.y);
+                levels, sc.b.hdr, sc.b.cb, sc.b.cb_ps, blockIdx.y);
 }
 
 int grid_for(long long elems) {
@@ -425,13 +444,17 @@ int grid_for(long long elems) {
 }  // namespace
 
 PlanArgs make_plan_args(int ny, int nx, int layers, int levels, int precision, const int* tiles,
-                        const NtBuffers& b, const NtOutput& o) {
+                        const NtBuffers& b, const NtOutput& o, const unsigned long long* absmax,
+                        int e_fringe) {
     PlanArgs a{};
     a.ny = ny;
     a.nx = nx;
     a.layers = layers;
     a.levels = levels;
     a.esize = precision == P_FP32 ? 4 : 2;
+    a.fp16 = precision == P_FP16;
+    a.e_fringe = e_fringe;
+    a.absmax = absmax;
     a.tm1 = tiles[0];
     a.tn1 = tiles[1];
     a.tm2 = tiles[2];
@@ -459,13 +482,15 @@ PlanArgs make_plan_args(int ny, int nx, int layers, int levels, int precision, c
 
 hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int levels,
                           size_t flags_layer, int precision, const int* tiles,
-                          const NtBuffers& b, const NtOutput& o, hipStream_t s) {
+                          const NtBuffers& b, const NtOutput& o,
+                          const unsigned long long* absmax, int e_fringe, hipStream_t s) {
     const int n_dl = layers * levels;
     hipLaunchKernelGGL(lists_kernel, dim3(n_dl), dim3(1024), 0, s, flags, ny, nx, levels,
                        flags_layer, b.rowlist, b.collist, b.cnt_row, b.cnt_col);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const PlanArgs a = make_plan_args(ny, nx, layers, levels, precision, tiles, b, o);
+    const PlanArgs a = make_plan_args(ny, nx, layers, levels, precision, tiles, b, o, absmax,
+                                      e_fringe);
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
@@ -486,7 +511,8 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
                        b.collist, b.cnt_row, b.cnt_col, nx, levels, b.fx, b.fx_ps);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(cb_kernel<P>, dim3(grid_for(big_c), n_dl), dim3(256), 0, s, coef,
-                       b.rowlist, b.collist, b.cnt_row, b.cnt_col, ny, nx, levels, b.cb, b.cb_ps);
+                       b.rowlist, b.collist, b.cnt_row, b.cnt_col, ny, nx, levels, b.hdr, b.cb,
+                       b.cb_ps);
     return hipGetLastError();
 }
 

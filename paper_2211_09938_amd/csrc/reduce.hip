@@ -21,7 +21,35 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const float2* __res
     }
 }
 
+// Largest |x[i]| over n floats into *word (float bits, atomicMax; cleared by the
+// caller).  Every lane reaches the wave reduction (no early exit).
+__global__ __launch_bounds__(256) void absmax_kernel(const float* __restrict__ x, size_t n,
+                                                     unsigned long long* __restrict__ word) {
+    float m = 0.f;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t n4 = (reinterpret_cast<uintptr_t>(x) & 15) == 0 ? n / 4 : 0;
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        const float4 v = x4[i];
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+    for (size_t i = 4 * n4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        m = fmaxf(m, fabsf(x[i]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if (__lane_id() == 0 && m > 0.f) atomicMax(word, (unsigned long long)__float_as_uint(m));
+}
+
 }  // namespace
+
+hipError_t launch_absmax(const float* x, size_t n, unsigned long long* word, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n / 4 + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, word);
+    return hipGetLastError();
+}
 
 hipError_t launch_reduce_partial(int ny, int nx, int split, const float2* partial, float2* out,
                                  int accumulate, hipStream_t s) {

@@ -97,7 +97,8 @@ def test_backpropagation_matches_oracle(shape, adjoint):
     assert rel_l2(u.cpu().numpy(), ref) <= LIN_TOL
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", LIN_TOL), ("bf16_split", 1e-3)])
+@pytest.mark.parametrize("precision,tol", [("fp32", LIN_TOL), ("bf16_split", 1e-3),
+                                           ("fp16_split", 1e-3)])
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_backpropagation_at_1024_sampled(precision, tol, adjoint):
     # the reconstruction of the differentiable workload at its size, sampled pixels
@@ -151,3 +152,61 @@ def test_split_precision_backward_and_backprop(precision):
     ref_u = gradient.fresnel_backpropagate(g.astype(np.complex128), s.lam, s.pitch, 0.2)
     assert rel_l2(ga.cpu().numpy(), ref) <= 1e-3
     assert rel_l2(u.cpu().numpy(), ref_u) <= 1e-3
+
+
+# FP16 split (11-bit halves, range-scaled) is as accurate as FP32 here and takes the
+# FP32 chain bar; BF16 split keeps the split forms' 1e-3
+@pytest.mark.parametrize("precision,tol", [("fp32", CHAIN_TOL), ("bf16_split", 1e-3),
+                                           ("fp16_split", CHAIN_TOL)])
+def test_loss_gradient_at_1024_matches_fp64_separable_chain(precision, tol):
+    # the differentiable workload at its own size: 1024 x 1024 amplitudes, 30% saliency,
+    # loss through |Fresnel back-propagation|, against the FP64 chain of kernel-matrix
+    # products (oracle.separable, pinned to the direct-sum chain on small sides)
+    import torch
+
+    from oracle import separable
+
+    s = scenes.differentiable()
+    target = s.extra["target"]
+    z = s.z[0]
+    obj = to_dev(s.obj).requires_grad_(True)
+    h = cgh().hologram_fn(obj, [z], s.lam, s.pitch, 3, to_dev(s.saliency), precision=precision)
+    u = cgh().backprop_fn(h, s.lam, s.pitch, z, precision=precision)
+    loss = ((u.abs() - to_dev(target)) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    ref_loss, ref_grad, ref_u = separable.loss_and_grad(
+        s.obj.astype(np.float64), target, z, s.lam, s.pitch, 3, s.saliency.astype(np.float64))
+    got = obj.grad.cpu().numpy().astype(np.float64)
+    e_u = rel_l2(u.detach().cpu().numpy(), ref_u)
+    e_g = rel_l2(got, ref_grad)
+    e_max = float(np.max(np.abs(got - ref_grad)) / np.max(np.abs(ref_grad)))
+    e_loss = abs(float(loss.detach()) - ref_loss) / ref_loss
+    print(f"grad1024 {precision}: U rel-L2 {e_u:.2e}, loss {e_loss:.2e}, gradient rel-L2 {e_g:.2e},"
+          f" max |diff| / max |grad| {e_max:.2e}")
+    assert e_loss <= tol
+    assert e_u <= tol
+    assert e_g <= tol
+    assert e_max <= 10 * tol
+
+
+@pytest.mark.parametrize("factor", [1e5, 1e-7])
+def test_fp16_split_adjoint_and_backprop_outside_unit_range(factor):
+    # the cotangent and the back-propagated field are arbitrary in magnitude; the FP16
+    # panels are range-scaled by powers of two (exact) and the epilogues undo it
+    import torch
+
+    s = scenes.random_scene(311, 48, 40, planes=2)
+    g = (_cot(7, 48, 40).astype(np.complex128) * factor).astype(np.complex64)
+    ga = cgh().hologram_backward(to_dev(g), s.z, s.lam, s.pitch, 3, to_dev(s.saliency),
+                                 to_dev(s.layer), precision="fp16_split")
+    u = cgh().fresnel_backpropagate(to_dev(g), s.lam, s.pitch, 0.2, precision="fp16_split")
+    torch.cuda.synchronize()
+    ref = gradient.grad_object(g.astype(np.complex128), s.z, s.lam, s.pitch, 3,
+                               s.saliency.astype(np.float64), s.layer)
+    ref_u = gradient.fresnel_backpropagate(g.astype(np.complex128), s.lam, s.pitch, 0.2)
+    e_g = rel_l2(ga.cpu().numpy(), ref)
+    e_u = rel_l2(u.cpu().numpy(), ref_u)
+    print(f"fp16 x{factor:g}: adjoint rel-L2 {e_g:.2e}, back-propagation {e_u:.2e}")
+    assert np.isfinite(ga.cpu().numpy()).all() and np.isfinite(u.cpu().numpy()).all()
+    assert e_g <= 1e-5 and e_u <= 1e-5

@@ -34,7 +34,10 @@ def big_scene(n=16384, seed=601):
     return scenes.Scene(obj, sal, (0.2,), None, name=f"big{n}")
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16_split", 1e-3)])
+# split forms: the model-derived bounds of the forward parity tests (4 x 2^-16 for
+# BF16; the FP32 bar for FP16, whose split error lies below FP32 accumulation)
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16_split", 4 * 2.0 ** -16),
+                                           ("fp16_split", 1e-5)])
 def test_largest_side_16384(precision, tol):
     # bf16_split: the one-workgroup-per-CU split kernel over 8192 tiles without split-K
     t0 = time.time()
