@@ -19,6 +19,8 @@ saliency", arXiv 2211.09938):
 * ``literal``     -- the same hologram computed the way steps 2-5 describe it
                      (image-domain residual maps times shifted block fringes)
                      plus the paper's operator accounting (Sec. 3).
+* ``fringe``      -- the 1D block fringes g_lo, g_hi of the Haar basis blocks (the
+                     factors of the paper's look-up-table blocks, Sec. 2).
 * ``separable``   -- the same hologram over a window as three matrix products
                      (the paraxial kernel factors per axis), for large sizes.
 * ``exact``       -- Eq. 1 with the exact distance and 1/r amplitude, to measure
@@ -35,4 +37,4 @@ reordered beyond the definitions it states.
 """
 
 from . import (haar, saliency, fresnel, progressive, literal, gradient, separable, exact,  # noqa: F401
-               quality, angular)
+               quality, angular, fringe)

@@ -1,0 +1,86 @@
+"""The FP32 fringe tables of the forward pass against their FP64 closed form.
+
+The library computes every table entry from an exact integer m^2, an FP64
+phase in turns reduced to its fractional part, FP64 sincospi and an FP64 block
+sum, rounded once to FP32.  Bar: within one FP32 ulp of the FP64 closed form of
+oracle.fringe (sums of the Fresnel kernel of Eq. 1 over the block), plus an
+absolute allowance for FP64 rounding: of the 2^l phases in turns (m^2 c at
+offset m), of Eq. 1's prefactor phase (z / lambda turns) where the y tables
+carry it, and of the sum; it matters only where a component cancels to near
+zero.  The tables are read back from the workspace of a forward call (their
+offsets come from cgh_workspace_layout).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import fresnel, fringe
+from paper_2211_09938_amd import scenes
+
+from helpers import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def cgh():
+    from paper_2211_09938_amd import cgh as m
+
+    return m
+
+
+def _check(got, ref, level, floor):
+    """Largest |got - ref| / (one FP32 ulp of ref + floor), with its entry."""
+    ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+    diff = np.abs(got.astype(np.float64) - ref)
+    r = diff / (ulp + floor)
+    i = int(np.argmax(r))
+    return float(r[i]), i, float(ref[i]), float(got[i])
+
+
+@pytest.mark.parametrize("ny,nx,planes,levels,precision,eq1", [
+    (2048, 2048, 2, 3, "fp32", False),
+    (136, 200, 3, 3, "fp16_split", True),
+    (64, 96, 1, 2, "bf16_split", False),
+])
+def test_fringe_tables_within_one_ulp_of_fp64(ny, nx, planes, levels, precision, eq1):
+    import torch
+
+    s = scenes.random_scene(700 + planes, ny, nx, planes=planes, levels=levels)
+    ws = torch.empty(cgh().workspace_size(ny, nx, planes, levels, precision), dtype=torch.uint8,
+                     device="cuda")
+    lay = None if s.layer is None else to_dev(s.layer)
+    cgh().progressive_hologram(to_dev(s.obj), s.z, s.lam, s.pitch, levels, to_dev(s.saliency),
+                               lay, precision=precision, eq1_prefactor=eq1, workspace=ws)
+    torch.cuda.synchronize()
+    info = cgh().workspace_layout(ny, nx, planes, levels, precision)
+    raw = ws.cpu().numpy()
+    pre = [complex(fresnel.prefactor(s.lam, z)) if eq1 else 1.0 for z in s.z]
+    # FP16 split: the y tables are built from prefactors scaled by 2^-e (e the exponent
+    # of the largest |prefactor|), undone in the last contraction's epilogue
+    e_f = int(np.floor(np.log2(max(abs(p) for p in pre)))) if precision == "fp16_split" else 0
+    worst, where = 0.0, None
+    for axis, n, off in (("x", nx, info["lut_x_offset"]), ("y", ny, info["lut_y_offset"])):
+        count = planes * levels * 4 * (2 * n)  # floats: (layer, level, band, part) x 2n
+        tabs = raw[off:off + 4 * count].view(np.float32)
+        tabs = tabs.reshape(planes, levels, 2, 2, 2 * n)
+        for d in range(planes):
+            for lev in range(1, levels + 1):
+                for band in (0, 1):
+                    p = 1.0 if axis == "x" else pre[d] * 2.0 ** -e_f
+                    ref = fringe.table(n, lev, band, s.lam, s.pitch, s.z[d], prefactor=p)
+                    # FP64 rounding of the phase in turns (m^2 c up to (2n)^2 c) on each of
+                    # the block's 2^l terms and of the sum; for the y tables with Eq. 1's
+                    # prefactor also of its phase in turns, z / lambda (the library reduces
+                    # it to a fraction on the host, the oracle takes 2 pi z / lambda whole)
+                    c = s.pitch ** 2 / (2 * s.lam * s.z[d])
+                    turns = (2 * n) ** 2 * c + (s.z[d] / s.lam if (eq1 and axis == "y") else 0.0)
+                    floor = abs(p) * (1 << lev) * (2 * np.pi * 2.0 ** -51 * turns + 1e-15)
+                    for part, v in ((0, ref.real), (1, ref.imag)):
+                        w = _check(tabs[d, lev - 1, band, part], v, lev, floor)
+                        if w[0] > worst:
+                            worst = w[0]
+                            where = (axis, d, lev, band, part) + w[1:]
+    print(f"worst at (axis, layer, level, band, part, entry, ref, got) = {where}")
+    print(f"tables {ny}x{nx} x{planes} L{levels} {precision} eq1={eq1}: worst |diff| / bound "
+          f"{worst:.3f}")
+    assert worst <= 1.0
