@@ -721,9 +721,26 @@ __global__ __launch_bounds__(256, 1) void nt_pp_kernel(const NtEntry* __restrict
     pp_tile<P, Epi>(e, m0, n0, kb, ke, s, split, smem);
 }
 
-// Direct schedule: block id = s * count + t.  (Round-robin over the XCDs: the
-// tables of the first contraction mix problems of very different K, which
-// contiguous runs per XCD would leave unbalanced -- measured 1.8x slower.)
+// Tile (mt, nt) of the `local`-th tile in band order: bands of kBandRows row
+// tiles, column-major inside a band, so that a run of consecutive indices
+// covers a near-square block of the output (the last band may be shorter).
+constexpr int kBandRows = 8;
+__device__ __forceinline__ void band_tile(int local, int tiles_m, int tiles_n, int& mt, int& nt) {
+    const int band = local / (kBandRows * tiles_n);
+    const int h = min(kBandRows, tiles_m - band * kBandRows);
+    const int r = local - band * kBandRows * tiles_n;
+    mt = band * kBandRows + r % h;
+    nt = r / h;
+}
+
+// Direct schedule: block id = s * count + t.  A table of several problems runs
+// round-robin over the XCDs (the first contraction's tables mix problems of very
+// different K, which contiguous runs per XCD would leave unbalanced -- measured
+// 1.8x slower).  A single problem (same K in every tile) gives each XCD one
+// contiguous run of (split, tile) indices in band order: an XCD's workgroups
+// then cover a block of about 8 x 8 output tiles and its L2 holds the A and B
+// rows they share, instead of every XCD fetching the whole B panel for two rows
+// of tiles.
 template <int P, bool A_CPLX, class Epi, int TM, int TN>
 __global__ __launch_bounds__(256, direct_occ<P>()) void nt_direct_kernel(
     const NtEntry* __restrict__ entries, int n_entries, const int* __restrict__ tile_count,
@@ -732,8 +749,21 @@ __global__ __launch_bounds__(256, direct_occ<P>()) void nt_direct_kernel(
     __shared__ __attribute__((aligned(16))) unsigned char As[S::A];
     __shared__ __attribute__((aligned(16))) unsigned char Bs[S::B];
     const int count = *tile_count;
+    const int total = count * split;
+    if ((int)blockIdx.x >= total) return;
+    if (n_entries == 1) {
+        const int bid = xcd_run_index(total);
+        const int s = bid / count;
+        const NtEntry e = entries[0];
+        int mt, nt;
+        band_tile(bid - s * count - e.tile_begin, (e.M + TM - 1) / TM, e.tiles_n, mt, nt);
+        const int chunk = pad_kt((e.K + split - 1) / split);
+        const int kb = s * chunk;
+        const int ke = min(e.K, kb + chunk);
+        nt_tile<P, A_CPLX, Epi, TM, TN, kDirectKS>(e, mt * TM, nt * TN, kb, ke, s, split, As, Bs);
+        return;
+    }
     const int bid = blockIdx.x;
-    if (bid >= count * split) return;
     const int s = bid / count;
     run_tile<P, A_CPLX, Epi, TM, TN, kDirectKS>(entries, n_entries, bid - s * count, s, split, As, Bs);
 }

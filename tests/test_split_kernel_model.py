@@ -158,3 +158,23 @@ def test_operand_reads_are_bank_conflict_free():
 @pytest.mark.parametrize("total", list(range(1, 70)) + [256, 511, 4097])
 def test_xcd_renumbering_is_a_bijection(total):
     assert sorted(xcd_run_index(b, total) for b in range(total)) == list(range(total))
+
+
+def band_tile(local, tiles_m, tiles_n, rows=8):
+    """The single-problem direct schedule's band order (ntgemm.hip, band_tile)."""
+    band = local // (rows * tiles_n)
+    h = min(rows, tiles_m - band * rows)
+    r = local - band * rows * tiles_n
+    return band * rows + r % h, r // h
+
+
+@pytest.mark.parametrize("tiles_m,tiles_n", [(16, 32), (1, 1), (3, 5), (8, 16), (17, 9), (128, 128)])
+def test_band_order_is_a_bijection_and_xcd_runs_are_compact(tiles_m, tiles_n):
+    count = tiles_m * tiles_n
+    tiles = [band_tile(t, tiles_m, tiles_n) for t in range(count)]
+    assert sorted(tiles) == [(m, n) for m in range(tiles_m) for n in range(tiles_n)]
+    if (tiles_m, tiles_n) == (16, 32):
+        # 512 tiles of the 2048^2 FP32 second contraction: every XCD an 8 x 8 block
+        for x in range(8):
+            run = {tiles[xcd_run_index(b, count)] for b in range(count) if b % 8 == x}
+            assert len({m for m, _ in run}) == 8 and len({n for _, n in run}) == 8
