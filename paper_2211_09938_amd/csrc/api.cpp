@@ -59,9 +59,10 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
     hipError_t e = timed(s, CGH_STAGE_COEF, [&] {
         hipError_t r = cgh::launch_fill_u8(fl, lo.flags_fill, s);
         if (r != hipSuccess) return r;
+        // sparse coefficient planes: the panel gather consults the occupancy bytes
         return cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels, thr,
                                     parts, reinterpret_cast<float*>(ws + lo.coef), fl,
-                                    lo.flags_layer,
+                                    lo.flags_layer, reinterpret_cast<uint8_t*>(ws + lo.occ),
                                     reinterpret_cast<unsigned long long*>(ws + lo.ops), s);
     });
     FringeScale fs;
@@ -134,7 +135,7 @@ int cgh_haar_dwt(const float* x, int ny, int nx, int levels, float* coeffs, void
         if (!x || !coeffs || (const void*)x == (const void*)coeffs) return CGH_ERROR_INVALID_VALUE;
         const float thr[3] = {0.f, 0.f, 0.f};
         return hip_status(cgh::launch_dwt_mask(x, nullptr, nullptr, ny, nx, 1, levels, thr,
-                                               cgh::kAllParts, coeffs, nullptr, 0, nullptr,
+                                               cgh::kAllParts, coeffs, nullptr, 0, nullptr, nullptr,
                                                (hipStream_t)stream));
     } catch (...) {
         return CGH_ERROR_HIP;
@@ -314,7 +315,7 @@ int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_
         if (e == hipSuccess)
             e = cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels, thr,
                                      cgh::kAllParts, reinterpret_cast<float*>(ws + lo.coef), fl,
-                                     lo.flags_layer,
+                                     lo.flags_layer, nullptr,
                                      reinterpret_cast<unsigned long long*>(ws + lo.ops), s);
         if (e == hipSuccess)
             e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
@@ -369,7 +370,7 @@ int cgh_fused_hologram(const float* object, const uint8_t* layer_index, int n_la
         hipError_t e = cgh::launch_fill_u8(fl, lo.flags_fill, s);
         if (e == hipSuccess)
             e = cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels, thr,
-                                     cgh::kAllParts, coef, fl, lo.flags_layer, ops, s);
+                                     cgh::kAllParts, coef, fl, lo.flags_layer, nullptr, ops, s);
         char* scratch = ws + lo.big;
         float* recon = reinterpret_cast<float*>(scratch + cgh::fused_recon_offset(ny, nx));
         float* lut0_x = reinterpret_cast<float*>(ws + lo.lut0);
@@ -421,7 +422,7 @@ int cgh_exact_hologram(const float* object, const uint8_t* layer_index, int n_la
         hipError_t e = cgh::launch_fill_u8(fl, lo.flags_fill, s);
         if (e == hipSuccess)
             e = cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels, thr,
-                                     cgh::kAllParts, coef, fl, lo.flags_layer,
+                                     cgh::kAllParts, coef, fl, lo.flags_layer, nullptr,
                                      reinterpret_cast<unsigned long long*>(ws + lo.ops), s);
         const int acc = (flags & CGH_FLAG_ACCUMULATE) ? 1 : 0;
         for (int d = 0; d < n_layers && e == hipSuccess; ++d) {

@@ -379,7 +379,8 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
                                      reinterpret_cast<float*>(ws + lo.coef),
                                      reinterpret_cast<uint8_t*>(ws + lo.flags), lo.flags_layer,
                                      lo.flags_fill,
-                                     reinterpret_cast<unsigned long long*>(ws + lo.ops)};
+                                     reinterpret_cast<unsigned long long*>(ws + lo.ops),
+                                     reinterpret_cast<uint8_t*>(ws + lo.occ)};
             p->h_prep[i] = cgh::PrepScene{reinterpret_cast<const uint8_t*>(ws + lo.flags),
                                           reinterpret_cast<const float*>(ws + lo.coef),
                                           reinterpret_cast<const float*>(ws + lo.lut_x),

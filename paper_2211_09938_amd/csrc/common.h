@@ -83,6 +83,7 @@ struct Layout {
     size_t lut_x, lut_y;         // FP32 fringe tables
     size_t lut0;                 // level-0 table pair (x then y) for back-propagation
     size_t flags;                // per layer: rows then cols of every level, bytes
+    size_t occ;                  // per layer: one byte per 2^levels block (coefficients written)
     size_t rowlist, collist;     // active row / column indices per (layer, level)
     size_t cnt_row, cnt_col, seg_row, tbeg;  // per (layer, level) counts, k' and tile offsets
     size_t hdr, entries;         // device plan header and GEMM problem table
@@ -112,10 +113,13 @@ hipError_t launch_fill_u8(uint8_t* p, size_t n, hipStream_t s);
 hipError_t launch_absmax(const float* x, size_t n, unsigned long long* word, hipStream_t s);
 // parts: bit l-1 keeps the level-l details, bit `levels` the approximation.
 constexpr unsigned kAllParts = 0xFu;
+// occ: null (every coefficient plane written in full) or one byte per (layer, block of
+// 2^levels x 2^levels pixels), 1 where the layer has a pixel in the block; then only
+// those blocks' coefficients are written (the rest are zero and left unwritten).
 hipError_t launch_dwt_mask(const float* obj, const uint8_t* layer, const float* sal, int ny, int nx,
                            int layers, int levels, const float* thr, unsigned parts, float* coef,
-                           uint8_t* flags, size_t flags_layer, unsigned long long* ops,
-                           hipStream_t s);
+                           uint8_t* flags, size_t flags_layer, uint8_t* occ,
+                           unsigned long long* ops, hipStream_t s);
 // One scene of a batched preparation (device-resident tables, batched plans).
 struct DwtScene {
     const float* obj;
@@ -127,6 +131,7 @@ struct DwtScene {
     size_t flags_layer;
     size_t flags_fill;  // bytes of flags and operator counters to clear
     unsigned long long* ops;
+    uint8_t* occ;       // (layer, block) occupancy: only occupied blocks' coefficients written
 };
 // One fringe table set (one axis of one layer of one scene), FP32.
 struct LutJob {

@@ -63,18 +63,22 @@ __device__ __forceinline__ float pooled(const Pool<B>& p, int lev, int j, int i)
 // positions whose block is salient, the operator count of Sec. 3 (one
 // operator per point of the level's residual map that is processed).  The
 // masks are the same for every layer, so they are counted once.
-// Returns the largest |object| value of the block.
+// Returns the largest |object| value of the block; with count_ops, wave_ops[l-1]
+// receives the wave's level-l count (the same value in every lane that has a block).
+// occ (optional): one byte per (layer, block), 1 where a pixel of the block belongs to
+// the layer.  With occ the coefficients of the other (layer, block) pairs, all zero,
+// are not written: readers of the coefficient planes consult occ.  Without occ
+// every plane is written in full.
 template <int L>
 __device__ __forceinline__ float dwt_mask_body(
     const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
     int ny, int nx, int layers, float t1, float t2, float t3, unsigned parts,
     float* __restrict__ coef, uint8_t* __restrict__ flags, size_t flags_layer,
-    unsigned long long* __restrict__ ops, int bx, int by) {
+    uint8_t* __restrict__ occ, bool count_ops, unsigned long long (&wave_ops)[3], int bx,
+    int by) {
     constexpr int B = 1 << L;
     const int nbx = nx >> L;
     if (bx >= nbx) return 0.f;
-    // lowest active lane: writes the row flags once per wave (all lanes share by)
-    const bool leader = (int)__lane_id() == __ffsll((long long)__ballot(1)) - 1;
 
     float a[B][B];
     uint8_t li[B][B];
@@ -131,14 +135,42 @@ __device__ __forceinline__ float dwt_mask_body(
     const bool vst = (reinterpret_cast<uintptr_t>(coef) & 15) == 0;  // vector stores
     const float thr[3] = {t1, t2, t3};
     const size_t plane = (size_t)ny * nx;
-    unsigned long long wave_ops[3] = {0ull, 0ull, 0ull};  // same value in every lane
 
+    if (count_ops) {
+        // the masks are shared by the layers: counted once, from the saliency alone
+#pragma unroll
+        for (int lev = 1; lev <= L; ++lev) {
+            const int h = B >> lev;
+#pragma unroll
+            for (int j = 0; j < h; ++j)
+#pragma unroll
+                for (int i = 0; i < h; ++i) {
+                    const bool salient = !sal || pooled<B>(pool, lev, j, i) > thr[lev - 1];
+                    wave_ops[lev - 1] += __popcll(__ballot(salient));
+                }
+        }
+    }
+
+    const size_t blocks = (size_t)(ny >> L) * nbx;
     for (int d = 0; d < layers; ++d) {
         float cur[B][B];
+        bool present = false;
 #pragma unroll
         for (int r = 0; r < B; ++r)
 #pragma unroll
-            for (int c = 0; c < B; ++c) cur[r][c] = (li[r][c] == d) ? a[r][c] : 0.0f;
+            for (int c = 0; c < B; ++c) {
+                present |= li[r][c] == d;
+                cur[r][c] = (li[r][c] == d) ? a[r][c] : 0.0f;
+            }
+        // with occ, a layer without a pixel in the block has only zero coefficients
+        // and no flags: nothing to compute or store
+        if (occ) {
+            occ[(size_t)d * blocks + (size_t)by * nbx + bx] = present ? 1 : 0;
+            if (!present) continue;
+        }
+        // lowest lane working on this layer: writes the row flags once per wave (all
+        // lanes share by)
+        const bool leader = (int)__lane_id() == __ffsll((long long)__ballot(1)) - 1;
         const size_t base = (size_t)d * plane;
         uint8_t* fl = flags ? flags + (size_t)d * flags_layer : nullptr;
 #pragma unroll
@@ -169,7 +201,6 @@ __device__ __forceinline__ float dwt_mask_body(
                     const float vv = (hi[2 * j][i] + hi[2 * j + 1][i]) * 0.5f;
                     const float dd = (hi[2 * j][i] - hi[2 * j + 1][i]) * 0.5f;
                     const bool salient = !sal || pooled<B>(pool, lev, j, i) > thr[lev - 1];
-                    if (ops && d == 0) wave_ops[lev - 1] += __popcll(__ballot(salient));
                     const bool keep = ((parts >> (lev - 1)) & 1u) && salient;
                     v[i] = keep ? vv : 0.0f;
                     hv[i] = keep ? hh : 0.0f;
@@ -226,16 +257,10 @@ __device__ __forceinline__ float dwt_mask_body(
         coef[base + (size_t)by * nx + bx] = av;
         if (fl) {
             uint8_t* frow = fl + flag_level_off(ny, nx, L);
-            const bool any_av = __ballot(av != 0.0f) != 0ull;  // every lane takes part
+            const bool any_av = __ballot(av != 0.0f) != 0ull;  // every lane on this layer
             if (leader && any_av) frow[by] = 1;
             if (av != 0.0f) frow[band_side(ny, L) + bx] = 1;
         }
-    }
-    if (ops) {
-        // the lowest active lane of the wave publishes the wave's counts
-        if (leader)
-            for (int l = 0; l < L; ++l)
-                if (wave_ops[l]) atomicAdd(&ops[l], 4ull * wave_ops[l]);
     }
     return amax;
 }
@@ -247,15 +272,36 @@ __device__ __forceinline__ void dwt_mask_block(
     const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
     int ny, int nx, int layers, float t1, float t2, float t3, unsigned parts,
     float* __restrict__ coef, uint8_t* __restrict__ flags, size_t flags_layer,
-    unsigned long long* __restrict__ ops, int bx, int by) {
+    uint8_t* __restrict__ occ, unsigned long long* __restrict__ ops, int bx, int by) {
+    unsigned long long wave_ops[3] = {0ull, 0ull, 0ull};
     float amax = dwt_mask_body<L>(obj, layer, sal, ny, nx, layers, t1, t2, t3, parts, coef, flags,
-                                  flags_layer, ops, bx, by);
+                                  flags_layer, occ, ops != nullptr, wave_ops, bx, by);
     if (ops) {
-        // wave maximum: every lane of the wave is active here (lanes past the row give 0)
+        // Counts and max |object| gathered over the workgroup first: one atomic per
+        // counter and workgroup (atomics on one address from every wave of every XCD
+        // serialise).  Every lane is active here: lanes past the row hold 0, and lane 0
+        // of a wave that has any block holds the wave's counts.
+        __shared__ unsigned long long s_ops[4][3];
+        __shared__ float s_max[4];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
-        if (__lane_id() == 0 && amax > 0.f)
-            atomicMax(&ops[4], (unsigned long long)__float_as_uint(amax));
+        const int w = threadIdx.x >> 6;
+        if (__lane_id() == 0) {
+            s_max[w] = amax;
+            for (int l = 0; l < 3; ++l) s_ops[w][l] = wave_ops[l];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int nw = blockDim.x >> 6;  // 4: the launches use 256 threads
+            float m = 0.f;
+            for (int k = 0; k < nw; ++k) m = fmaxf(m, s_max[k]);
+            for (int l = 0; l < L; ++l) {
+                unsigned long long c = 0ull;
+                for (int k = 0; k < nw; ++k) c += s_ops[k][l];
+                if (c) atomicAdd(&ops[l], 4ull * c);
+            }
+            if (m > 0.f) atomicMax(&ops[4], (unsigned long long)__float_as_uint(m));
+        }
     }
 }
 
@@ -264,9 +310,9 @@ __global__ __launch_bounds__(256) void dwt_mask_kernel(
     const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
     int ny, int nx, int layers, float t1, float t2, float t3, unsigned parts,
     float* __restrict__ coef, uint8_t* __restrict__ flags, size_t flags_layer,
-    unsigned long long* __restrict__ ops) {
+    uint8_t* __restrict__ occ, unsigned long long* __restrict__ ops) {
     dwt_mask_block<L>(obj, layer, sal, ny, nx, layers, t1, t2, t3, parts, coef, flags,
-                      flags_layer, ops, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+                      flags_layer, occ, ops, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
 }
 
 // Every scene of a batch in one launch: grid.z = scene, x / y sized for the largest.
@@ -276,7 +322,7 @@ __global__ __launch_bounds__(256) void dwt_mask_batch_kernel(const DwtScene* __r
     const DwtScene sc = scenes[blockIdx.z];
     if ((int)blockIdx.y >= (sc.ny >> L)) return;
     dwt_mask_block<L>(sc.obj, sc.layer, sc.sal, sc.ny, sc.nx, sc.layers, t1, t2, t3, kAllParts,
-                      sc.coef, sc.flags, sc.flags_layer, sc.ops,
+                      sc.coef, sc.flags, sc.flags_layer, sc.occ, sc.ops,
                       blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
 }
 
@@ -453,24 +499,27 @@ hipError_t launch_fill_u8(uint8_t* p, size_t n, hipStream_t s) {
 template <int L>
 static void dwt_launch(const float* obj, const uint8_t* layer, const float* sal, int ny, int nx,
                        int layers, const float* thr, unsigned parts, float* coef, uint8_t* flags,
-                       size_t flags_layer, unsigned long long* ops, hipStream_t s) {
+                       size_t flags_layer, uint8_t* occ, unsigned long long* ops, hipStream_t s) {
     const int nbx = nx >> L;
     dim3 grid((nbx + 255) / 256, ny >> L);
     hipLaunchKernelGGL((dwt_mask_kernel<L>), grid, dim3(256), 0, s, obj, layer, sal, ny, nx,
                        layers, thr[0], L >= 2 ? thr[1] : 0.f, L >= 3 ? thr[2] : 0.f, parts, coef,
-                       flags, flags_layer, ops);
+                       flags, flags_layer, occ, ops);
 }
 
 hipError_t launch_dwt_mask(const float* obj, const uint8_t* layer, const float* sal, int ny, int nx,
                            int layers, int levels, const float* thr, unsigned parts, float* coef,
-                           uint8_t* flags, size_t flags_layer, unsigned long long* ops,
-                           hipStream_t s) {
+                           uint8_t* flags, size_t flags_layer, uint8_t* occ,
+                           unsigned long long* ops, hipStream_t s) {
     if (levels == 1)
-        dwt_launch<1>(obj, layer, sal, ny, nx, layers, thr, parts, coef, flags, flags_layer, ops, s);
+        dwt_launch<1>(obj, layer, sal, ny, nx, layers, thr, parts, coef, flags, flags_layer, occ,
+                      ops, s);
     else if (levels == 2)
-        dwt_launch<2>(obj, layer, sal, ny, nx, layers, thr, parts, coef, flags, flags_layer, ops, s);
+        dwt_launch<2>(obj, layer, sal, ny, nx, layers, thr, parts, coef, flags, flags_layer, occ,
+                      ops, s);
     else if (levels == 3)
-        dwt_launch<3>(obj, layer, sal, ny, nx, layers, thr, parts, coef, flags, flags_layer, ops, s);
+        dwt_launch<3>(obj, layer, sal, ny, nx, layers, thr, parts, coef, flags, flags_layer, occ,
+                      ops, s);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -79,6 +79,7 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels,
     const size_t flag_bytes = (size_t)layers * lo.flags_layer;
     // after the flags: four 64-bit operator counters, then the max-abs word of the
     // FP16 range scaling (kOpsWords words, cleared with the flags)
+    lo.occ = take((size_t)layers * (size_t)(ny >> levels) * (size_t)(nx >> levels));
     lo.flags = take((flag_bytes + 7) / 8 * 8 + 8 * kOpsWords);
     lo.ops = lo.flags + (flag_bytes + 7) / 8 * 8;
     lo.flags_fill = lo.ops + 8 * kOpsWords - lo.flags;
@@ -159,6 +160,7 @@ inline cgh::NtBuffers nt_buffers(char* ws, const cgh::Layout& lo) {
     b.cnt_col = reinterpret_cast<int*>(ws + lo.cnt_col);
     b.seg_row = reinterpret_cast<int*>(ws + lo.seg_row);
     b.tbeg = reinterpret_cast<int*>(ws + lo.tbeg);
+    b.occ = reinterpret_cast<const uint8_t*>(ws + lo.occ);
     b.hdr = reinterpret_cast<cgh::PlanHeader*>(ws + lo.hdr);
     b.first = reinterpret_cast<cgh::NtEntry*>(ws + lo.entries);
     b.second = b.first + (lo.entries_n - 1);

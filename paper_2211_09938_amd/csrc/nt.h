@@ -141,6 +141,7 @@ struct NtBuffers {
     int* cnt_col;   // [D*L]
     int* seg_row;   // [D*L]
     int* tbeg;      // [D*L] tile prefix (first contraction, local to the scene)
+    const uint8_t* occ;  // (layer, block) occupancy of the coefficient planes
     PlanHeader* hdr;
     NtEntry* first;   // [D*L] first-contraction problems of this scene
     NtEntry* second;  // [1] second-contraction problem of this scene

@@ -342,13 +342,19 @@ __device__ __forceinline__ void cb_block(const float* __restrict__ coef,
                                          const int* __restrict__ collist,
                                          const int* __restrict__ cnt_row,
                                          const int* __restrict__ cnt_col, int ny, int nx,
-                                         int levels, const PlanHeader* __restrict__ hdr,
+                                         int levels, const uint8_t* __restrict__ occ,
+                                         const PlanHeader* __restrict__ hdr,
                                          void* cb, size_t ps, int dl) {
     const int d = dl / levels, l = dl % levels + 1;
     const int cr = cnt_row[dl], cc = cnt_col[dl], pc = pad_kt(cc);
     if (cr == 0 || pc == 0) return;
     const float scale = hdr->cb_scale;  // written by the planning kernel
     const int nyl = ny >> l, nxl = nx >> l;
+    // the coefficient stage wrote only the blocks that hold a pixel of the layer:
+    // a level-l coefficient at quadrant position (i, j) covers block
+    // (i >> (levels - l), j >> (levels - l)) of 2^levels pixels
+    const int nbx = nx >> levels, sh = levels - l;
+    const uint8_t* oc = occ + (size_t)d * (size_t)(ny >> levels) * nbx;
     const int* rl = rowlist + dl_rows_off(ny, levels, d, l);
     const int* cl = collist + dl_cols_off(nx, levels, d, l);
     const float* cd = coef + (size_t)d * ny * nx;
@@ -360,6 +366,7 @@ __device__ __forceinline__ void cb_block(const float* __restrict__ coef,
         int rr, c0;
         kblk_pos(e, cr, rr, c0);
         const int r = rl[rr];
+        const int brow = (r < nyl ? r : r - nyl) >> sh;
         float v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -367,8 +374,10 @@ __device__ __forceinline__ void cb_block(const float* __restrict__ coef,
             v[q] = 0.f;
             if (c < cc) {
                 const int j = cl[c];
+                const int bcol = (j < nxl ? j : j - nxl) >> sh;
                 // the LL quadrant of a level below the top belongs to the coarser levels
-                if (!(l < levels && r < nyl && j < nxl)) v[q] = cd[(size_t)r * nx + j] * scale;
+                if (!(l < levels && r < nyl && j < nxl) && oc[(size_t)brow * nbx + bcol])
+                    v[q] = cd[(size_t)r * nx + j] * scale;
             }
         }
         put_r4<P>(cb, ps, base + e, v);
@@ -399,9 +408,10 @@ __global__ __launch_bounds__(256) void cb_kernel(const float* __restrict__ coef,
                                                  const int* __restrict__ collist,
                                                  const int* __restrict__ cnt_row,
                                                  const int* __restrict__ cnt_col, int ny, int nx,
-                                                 int levels, const PlanHeader* __restrict__ hdr,
+                                                 int levels, const uint8_t* __restrict__ occ,
+                                                 const PlanHeader* __restrict__ hdr,
                                                  void* cb, size_t ps) {
-    cb_block<P>(coef, rowlist, collist, cnt_row, cnt_col, ny, nx, levels, hdr, cb, ps,
+    cb_block<P>(coef, rowlist, collist, cnt_row, cnt_col, ny, nx, levels, occ, hdr, cb, ps,
                 blockIdx.y);
 }
 
@@ -431,7 +441,7 @@ __global__ __launch_bounds__(256) void cb_batch_kernel(const PrepScene* __restri
     const PrepScene& sc = scenes[blockIdx.z];
     if ((int)blockIdx.y >= sc.layers * levels) return;
     cb_block<P>(sc.coef, sc.b.rowlist, sc.b.collist, sc.b.cnt_row, sc.b.cnt_col, sc.ny, sc.nx,
-                levels, sc.b.hdr, sc.b.cb, sc.b.cb_ps, blockIdx.y);
+                levels, sc.b.occ, sc.b.hdr, sc.b.cb, sc.b.cb_ps, blockIdx.y);
 }
 
 int grid_for(long long elems) {
@@ -511,8 +521,8 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
                        b.collist, b.cnt_row, b.cnt_col, nx, levels, b.fx, b.fx_ps);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(cb_kernel<P>, dim3(grid_for(big_c), n_dl), dim3(256), 0, s, coef,
-                       b.rowlist, b.collist, b.cnt_row, b.cnt_col, ny, nx, levels, b.hdr, b.cb,
-                       b.cb_ps);
+                       b.rowlist, b.collist, b.cnt_row, b.cnt_col, ny, nx, levels, b.occ, b.hdr,
+                       b.cb, b.cb_ps);
     return hipGetLastError();
 }
 
