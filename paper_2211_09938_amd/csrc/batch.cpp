@@ -78,7 +78,7 @@ hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s) {
         e = cgh::launch_dwt_mask_batch(p.d_dwt, n, p.levels, p.thr, p.max_nbx, p.max_nby, s);
     if (e == hipSuccess) e = cgh::launch_luts_batch(p.d_luts, p.n_luts, p.max_len, p.levels, s);
     if (e == hipSuccess) e = cgh::launch_lists_batch(p.d_prep, n, p.levels, p.max_ndl, s);
-    if (e == hipSuccess) e = cgh::launch_plan_batch(p.d_args, n, s);
+    if (e == hipSuccess) e = cgh::launch_plan_batch(p.d_args, n, p.max_ndl, s);
     if (e == hipSuccess)
         e = cgh::launch_materialize_batch(p.d_prep, n, p.levels, p.precision, p.max_ndl, s);
     if (e != hipSuccess) return e;

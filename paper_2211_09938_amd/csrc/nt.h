@@ -199,7 +199,8 @@ struct PrepScene {
 // Batched launches over device tables of n scenes (grid sized for the largest).
 hipError_t launch_lists_batch(const PrepScene* scenes, int n, int levels, int max_ndl,
                               hipStream_t s);
-hipError_t launch_plan_batch(const PlanArgs* args, int n, hipStream_t s);
+// max_ndl: the largest (layer, level) count of the scenes (sizes the workgroup).
+hipError_t launch_plan_batch(const PlanArgs* args, int n, int max_ndl, hipStream_t s);
 hipError_t launch_materialize_batch(const PrepScene* scenes, int n, int levels, int precision,
                                     int max_ndl, hipStream_t s);
 

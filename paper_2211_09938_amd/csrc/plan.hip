@@ -74,7 +74,7 @@ __global__ __launch_bounds__(1024) void lists_batch_kernel(const PrepScene* __re
                 sc.b.cnt_row, sc.b.cnt_col, blockIdx.x, s_wave);
 }
 
-// Inclusive Hillis-Steele scan over the block (blockDim.x == 1024).
+// Inclusive Hillis-Steele scan over the workgroup (blockDim.x <= 1024 threads).
 __device__ int block_scan_incl(int v, int* sh) {
     sh[threadIdx.x] = v;
     __syncthreads();
@@ -95,7 +95,7 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
     const int tn1 = (a.nx + a.tn1 - 1) / a.tn1;
     int total_k = 0, total_t = 0, total_r = 0;
     // pass 1: padded row counts -> k' segment offsets, tile counts -> tile prefix
-    for (int base = 0; base < n_dl; base += 1024) {
+    for (int base = 0; base < n_dl; base += blockDim.x) {
         const int t = base + (int)threadIdx.x;
         int cr = 0, pr = 0, tiles = 0;
         if (t < n_dl) {
@@ -384,64 +384,41 @@ __device__ __forceinline__ void cb_block(const float* __restrict__ coef,
     }
 }
 
+// The three panels of one scene in one launch: grid.z selects the panel (0 Fy_c,
+// 1 Fx_c, 2 Cb_c), grid.y the (layer, level), grid.x strides over its chunks; the
+// three gathers share the machine instead of each ending on a partial wave.
 template <int P>
-__global__ __launch_bounds__(256) void fy_kernel(const float* __restrict__ lut_y,
-                                                 const int* __restrict__ rowlist,
-                                                 const int* __restrict__ cnt_row,
-                                                 const int* __restrict__ seg_row, int ny,
-                                                 int levels, void* fy, size_t ps) {
-    fy_block<P>(lut_y, rowlist, cnt_row, seg_row, ny, levels, fy, ps, blockIdx.y);
+__global__ __launch_bounds__(256) void panels_kernel(const float* __restrict__ coef,
+                                                     const float* __restrict__ lut_x,
+                                                     const float* __restrict__ lut_y, int ny,
+                                                     int nx, int levels, NtBuffers b) {
+    const int dl = blockIdx.y;
+    if (blockIdx.z == 0)
+        fy_block<P>(lut_y, b.rowlist, b.cnt_row, b.seg_row, ny, levels, b.fy, b.fy_ps, dl);
+    else if (blockIdx.z == 1)
+        fx_block<P>(lut_x, b.collist, b.cnt_row, b.cnt_col, nx, levels, b.fx, b.fx_ps, dl);
+    else
+        cb_block<P>(coef, b.rowlist, b.collist, b.cnt_row, b.cnt_col, ny, nx, levels, b.occ,
+                    b.hdr, b.cb, b.cb_ps, dl);
 }
 
+// Batched panels: grid.z = 3 x scene + panel (as panels_kernel), grid.y = (layer, level),
+// grid.x = chunks.
 template <int P>
-__global__ __launch_bounds__(256) void fx_kernel(const float* __restrict__ lut_x,
-                                                 const int* __restrict__ collist,
-                                                 const int* __restrict__ cnt_row,
-                                                 const int* __restrict__ cnt_col, int nx,
-                                                 int levels, void* fx, size_t ps) {
-    fx_block<P>(lut_x, collist, cnt_row, cnt_col, nx, levels, fx, ps, blockIdx.y);
-}
-
-template <int P>
-__global__ __launch_bounds__(256) void cb_kernel(const float* __restrict__ coef,
-                                                 const int* __restrict__ rowlist,
-                                                 const int* __restrict__ collist,
-                                                 const int* __restrict__ cnt_row,
-                                                 const int* __restrict__ cnt_col, int ny, int nx,
-                                                 int levels, const uint8_t* __restrict__ occ,
-                                                 const PlanHeader* __restrict__ hdr,
-                                                 void* cb, size_t ps) {
-    cb_block<P>(coef, rowlist, collist, cnt_row, cnt_col, ny, nx, levels, occ, hdr, cb, ps,
-                blockIdx.y);
-}
-
-// Batched panels: grid.z = scene, grid.y = (layer, level), grid.x = chunks; the
-// three panels of a scene are gathered by one launch each over every scene.
-template <int P>
-__global__ __launch_bounds__(256) void fy_batch_kernel(const PrepScene* __restrict__ scenes,
-                                                       int levels) {
-    const PrepScene& sc = scenes[blockIdx.z];
+__global__ __launch_bounds__(256) void panels_batch_kernel(const PrepScene* __restrict__ scenes,
+                                                           int levels) {
+    const PrepScene& sc = scenes[blockIdx.z / 3];
     if ((int)blockIdx.y >= sc.layers * levels) return;
-    fy_block<P>(sc.lut_y, sc.b.rowlist, sc.b.cnt_row, sc.b.seg_row, sc.ny, levels, sc.b.fy,
-                sc.b.fy_ps, blockIdx.y);
-}
-
-template <int P>
-__global__ __launch_bounds__(256) void fx_batch_kernel(const PrepScene* __restrict__ scenes,
-                                                       int levels) {
-    const PrepScene& sc = scenes[blockIdx.z];
-    if ((int)blockIdx.y >= sc.layers * levels) return;
-    fx_block<P>(sc.lut_x, sc.b.collist, sc.b.cnt_row, sc.b.cnt_col, sc.nx, levels, sc.b.fx,
-                sc.b.fx_ps, blockIdx.y);
-}
-
-template <int P>
-__global__ __launch_bounds__(256) void cb_batch_kernel(const PrepScene* __restrict__ scenes,
-                                                       int levels) {
-    const PrepScene& sc = scenes[blockIdx.z];
-    if ((int)blockIdx.y >= sc.layers * levels) return;
-    cb_block<P>(sc.coef, sc.b.rowlist, sc.b.collist, sc.b.cnt_row, sc.b.cnt_col, sc.ny, sc.nx,
-                levels, sc.b.occ, sc.b.hdr, sc.b.cb, sc.b.cb_ps, blockIdx.y);
+    const int panel = blockIdx.z % 3, dl = blockIdx.y;
+    if (panel == 0)
+        fy_block<P>(sc.lut_y, sc.b.rowlist, sc.b.cnt_row, sc.b.seg_row, sc.ny, levels, sc.b.fy,
+                    sc.b.fy_ps, dl);
+    else if (panel == 1)
+        fx_block<P>(sc.lut_x, sc.b.collist, sc.b.cnt_row, sc.b.cnt_col, sc.nx, levels, sc.b.fx,
+                    sc.b.fx_ps, dl);
+    else
+        cb_block<P>(sc.coef, sc.b.rowlist, sc.b.collist, sc.b.cnt_row, sc.b.cnt_col, sc.ny,
+                    sc.nx, levels, sc.b.occ, sc.b.hdr, sc.b.cb, sc.b.cb_ps, dl);
 }
 
 int grid_for(long long elems) {
@@ -501,7 +478,8 @@ hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int 
     if (e != hipSuccess) return e;
     const PlanArgs a = make_plan_args(ny, nx, layers, levels, precision, tiles, b, o, absmax,
                                       e_fringe);
-    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(1024), 0, s, a);
+    // one wave scans up to 64 (layer, level) pairs without a workgroup barrier's cost
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(n_dl <= 64 ? 64 : 1024), 0, s, a);
     return hipGetLastError();
 }
 
@@ -512,17 +490,13 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
     const long long big_y = (long long)ny * pad_kt(band_side(ny, 1));
     const long long big_x = (long long)nx * pad_kt(band_side(nx, 1));
     const long long big_c = (long long)band_side(ny, 1) * pad_kt(band_side(nx, 1));
-    // fringe panels: one workgroup per 256 rows x 16 K = 4096 elements (grid_for sizes for 2048)
-    hipLaunchKernelGGL(fy_kernel<P>, dim3(grid_for(big_y / 2), n_dl), dim3(256), 0, s, lut_y,
-                       b.rowlist, b.cnt_row, b.seg_row, ny, levels, b.fy, b.fy_ps);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fx_kernel<P>, dim3(grid_for(big_x / 2), n_dl), dim3(256), 0, s, lut_x,
-                       b.collist, b.cnt_row, b.cnt_col, nx, levels, b.fx, b.fx_ps);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(cb_kernel<P>, dim3(grid_for(big_c), n_dl), dim3(256), 0, s, coef,
-                       b.rowlist, b.collist, b.cnt_row, b.cnt_col, ny, nx, levels, b.occ, b.hdr,
-                       b.cb, b.cb_ps);
+    // fringe panels: one workgroup per 256 rows x 16 K = 4096 elements (grid_for sizes for
+    // 2048); the coefficient panel four elements per thread; all three in one launch
+    int gx = grid_for(big_y / 2);
+    if (grid_for(big_x / 2) > gx) gx = grid_for(big_x / 2);
+    if (grid_for(big_c) > gx) gx = grid_for(big_c);
+    hipLaunchKernelGGL(panels_kernel<P>, dim3(gx, n_dl, 3), dim3(256), 0, s, coef, lut_x, lut_y,
+                       ny, nx, levels, b);
     return hipGetLastError();
 }
 
@@ -534,10 +508,8 @@ constexpr int kBatchPanelBlocks = 64;
 template <int P>
 static void materialize_batch(const PrepScene* scenes, int n, int levels, int max_ndl,
                               hipStream_t s) {
-    const dim3 grid(kBatchPanelBlocks, max_ndl, n);
-    hipLaunchKernelGGL(fy_batch_kernel<P>, grid, dim3(256), 0, s, scenes, levels);
-    hipLaunchKernelGGL(fx_batch_kernel<P>, grid, dim3(256), 0, s, scenes, levels);
-    hipLaunchKernelGGL(cb_batch_kernel<P>, grid, dim3(256), 0, s, scenes, levels);
+    hipLaunchKernelGGL(panels_batch_kernel<P>, dim3(kBatchPanelBlocks, max_ndl, 3 * n),
+                       dim3(256), 0, s, scenes, levels);
 }
 
 hipError_t launch_lists_batch(const PrepScene* scenes, int n, int levels, int max_ndl,
@@ -546,8 +518,8 @@ hipError_t launch_lists_batch(const PrepScene* scenes, int n, int levels, int ma
     return hipGetLastError();
 }
 
-hipError_t launch_plan_batch(const PlanArgs* args, int n, hipStream_t s) {
-    hipLaunchKernelGGL(plan_batch_kernel, dim3(n), dim3(1024), 0, s, args);
+hipError_t launch_plan_batch(const PlanArgs* args, int n, int max_ndl, hipStream_t s) {
+    hipLaunchKernelGGL(plan_batch_kernel, dim3(n), dim3(max_ndl <= 64 ? 64 : 1024), 0, s, args);
     return hipGetLastError();
 }
 
