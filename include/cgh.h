@@ -318,17 +318,20 @@ int cgh_angular_spectrum(const float* field, int ny, int nx, double lambda, doub
  * a workspace (cgh_workspace_stats), or summed over a plan's scenes
  * (cgh_plan_get_stats). */
 typedef struct cgh_stats_s {
-    long long coef_rows_active;  /* nonzero rows of every layer's and level's coefficient square:
-                                    the K extent of the second contraction                    */
-    long long coef_rows_total;
+    long long k_active;          /* active K of the second contraction: for every layer and
+                                    level, the nonzero rows of its coefficient square, or its
+                                    nonzero columns where the level is contracted columns-first
+                                    (Eq. 3 in the other order; taken where the padded column
+                                    count is the smaller)                                      */
     long long k_padded;          /* K the second contraction ran over (segments padded to 16)  */
     long long k_total;           /* K of the dense form (every row of every level and layer)   */
     int k_tile;                  /* K tile of the contractions                                 */
     int split_k;                 /* K-range split of the second contraction                    */
-    double flops_first;          /* algorithmic real flops, first contraction:
-                                    4 * nx * sum over (layer, level) of active rows x columns  */
+    double flops_first;          /* algorithmic real flops, first contraction: 4 x the sum over
+                                    (layer, level) of active rows x active columns x nx
+                                    (rows-first) or x ny (columns-first)                       */
     double flops_second;         /* algorithmic real flops, second contraction:
-                                    8 * ny * nx * coef_rows_active                             */
+                                    8 * ny * nx * k_active                                     */
     double flops_second_issued;  /* 8 * ny * nx * k_padded: the count on the padded K (FP32
                                     runs three real products per complex product there, i.e.
                                     3/4 of it on the matrix cores)                          */

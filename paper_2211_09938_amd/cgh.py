@@ -146,8 +146,7 @@ class Stats(ctypes.Structure):
     """Mirror of cgh_stats."""
 
     _fields_ = [
-        ("coef_rows_active", ctypes.c_longlong),
-        ("coef_rows_total", ctypes.c_longlong),
+        ("k_active", ctypes.c_longlong),
         ("k_padded", ctypes.c_longlong),
         ("k_total", ctypes.c_longlong),
         ("k_tile", ctypes.c_int),

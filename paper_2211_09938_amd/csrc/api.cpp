@@ -629,28 +629,28 @@ int cgh_workspace_stats(const void* workspace, int ny, int nx, int n_layers, int
         hipStream_t s = (hipStream_t)stream;
         const char* ws = static_cast<const char*>(workspace);
         const int n_dl = n_layers * levels;
-        std::vector<int> cr(n_dl), cc(n_dl);
+        std::vector<int> cr(n_dl), cc(n_dl), orient(n_dl);
         cgh::PlanHeader hdr{};
         unsigned long long ops[4] = {0, 0, 0, 0};
         hipError_t e = hipMemcpyAsync(cr.data(), ws + lo.cnt_row, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipMemcpyAsync(ops, ws + lo.ops, sizeof(ops), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipMemcpyAsync(cc.data(), ws + lo.cnt_col, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(orient.data(), ws + lo.orient, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipMemcpyAsync(&hdr, ws + lo.hdr, sizeof(hdr), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_status(e);
         double rc = 0.0;
-        for (int k = 0; k < n_dl; ++k) rc += (double)cr[k] * (double)cc[k];
+        for (int k = 0; k < n_dl; ++k) rc += (double)cr[k] * (double)cc[k] * (orient[k] ? ny : nx);
         long long total = 0;
         for (int l = 1; l <= levels; ++l) total += cgh::band_side(ny, l);
         total *= n_layers;
-        stats->coef_rows_active = hdr.rows_active;
-        stats->coef_rows_total = total;
+        stats->k_active = hdr.k_active;
         stats->k_padded = hdr.kpad;
         stats->k_total = total;
         stats->k_tile = cgh::kKT;
         stats->split_k = second_split(lo, ny, nx, levels, n_layers, precision);
-        stats->flops_first = 4.0 * (double)nx * rc;
-        stats->flops_second = 8.0 * (double)ny * (double)nx * (double)hdr.rows_active;
+        stats->flops_first = 4.0 * rc;
+        stats->flops_second = 8.0 * (double)ny * (double)nx * (double)hdr.k_active;
         stats->flops_second_issued = 8.0 * (double)ny * (double)nx * (double)hdr.kpad;
         stats->operators[0] = (long long)(ny >> levels) * (nx >> levels);
         for (int j = 1; j <= levels; ++j) stats->operators[j] = (long long)ops[levels - j];

@@ -486,17 +486,20 @@ int cgh_plan_get_stats(const cgh_plan* plan, cgh_stats* stats, void* stream) {
         std::vector<cgh::PlanHeader> hdrs(n);
         hipError_t e = hipMemcpyAsync(hdrs.data(), plan->hdrs, n * sizeof(cgh::PlanHeader),
                                       hipMemcpyDeviceToHost, s);
-        std::vector<std::vector<int>> cr(n), cc(n);
+        std::vector<std::vector<int>> cr(n), cc(n), orient(n);
         std::vector<unsigned long long> ops(4 * (size_t)n, 0ull);
         for (int i = 0; i < n && e == hipSuccess; ++i) {
             const auto& sc = plan->scenes[i];
             const int n_dl = sc.s.n_layers * plan->levels;
             cr[i].resize(n_dl);
             cc[i].resize(n_dl);
+            orient[i].resize(n_dl);
             const char* ws = plan->mem + sc.ws_off;
             e = hipMemcpyAsync(cr[i].data(), ws + sc.lo.cnt_row, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(cc[i].data(), ws + sc.lo.cnt_col, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(orient[i].data(), ws + sc.lo.orient, n_dl * sizeof(int), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(ops.data() + 4 * i, ws + sc.lo.ops, 4 * sizeof(unsigned long long),
                                    hipMemcpyDeviceToHost, s);
@@ -507,16 +510,16 @@ int cgh_plan_get_stats(const cgh_plan* plan, cgh_stats* stats, void* stream) {
             const auto& sc = plan->scenes[i];
             const double ny = sc.s.ny, nx = sc.s.nx;
             double rc = 0.0;
-            for (size_t k = 0; k < cr[i].size(); ++k) rc += (double)cr[i][k] * cc[i][k];
+            for (size_t k = 0; k < cr[i].size(); ++k)
+                rc += (double)cr[i][k] * cc[i][k] * (orient[i][k] ? ny : nx);
             long long total = 0;
             for (int l = 1; l <= plan->levels; ++l) total += cgh::band_side(sc.s.ny, l);
             total *= sc.s.n_layers;
-            stats->coef_rows_active += hdrs[i].rows_active;
-            stats->coef_rows_total += total;
+            stats->k_active += hdrs[i].k_active;
             stats->k_padded += hdrs[i].kpad;
             stats->k_total += total;
-            stats->flops_first += 4.0 * nx * rc;
-            stats->flops_second += 8.0 * ny * nx * hdrs[i].rows_active;
+            stats->flops_first += 4.0 * rc;
+            stats->flops_second += 8.0 * ny * nx * hdrs[i].k_active;
             stats->flops_second_issued += 8.0 * ny * nx * hdrs[i].kpad;
             const int L = plan->levels;
             stats->operators[0] += (long long)(sc.s.ny >> L) * (sc.s.nx >> L);

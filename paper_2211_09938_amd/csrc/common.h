@@ -85,7 +85,8 @@ struct Layout {
     size_t flags;                // per layer: rows then cols of every level, bytes
     size_t occ;                  // per layer: one byte per 2^levels block (coefficients written)
     size_t rowlist, collist;     // active row / column indices per (layer, level)
-    size_t cnt_row, cnt_col, seg_row, tbeg;  // per (layer, level) counts, k' and tile offsets
+    size_t cnt_row, cnt_col, seg_row, orient, tbeg;  // per (layer, level) counts, k' offsets,
+                                                      // contraction order, tile offsets
     size_t hdr, entries;         // device plan header and GEMM problem table
     size_t big;                  // shared region: backward T, or the forward panels
     size_t big_bytes;            // its size

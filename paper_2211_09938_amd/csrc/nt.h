@@ -59,9 +59,10 @@ struct NtEntry {
 
 // Device-side plan written by the planning kernels (lives in the workspace).
 struct PlanHeader {
-    int kpad;          // K of the second contraction (sum of padded row counts)
+    int kpad;          // K of the second contraction (sum of padded segment lengths)
     int first_tiles;   // tiles of the first contraction
-    int rows_active;   // sum of active row counts
+    int k_active;      // active K of the second contraction: per (layer, level) its
+                       // active rows, or its active columns where those go first
     int second_tiles;  // output tiles of the second contraction
     float cb_scale;    // scale of the coefficient panel (FP16 range scaling, else 1)
 };
@@ -76,6 +77,27 @@ struct NtSizes {
     int first_tiles_max;  // upper bound over every tile shape
 };
 
+// Each (layer, level) square is contracted rows-first (T = Cb Fx^T: K' = its padded
+// active rows) or columns-first (T' = Cb^T Fy^T: K' = its padded active columns),
+// whichever gives the second contraction the shorter K' segment.  The per-(layer,
+// level) regions of the first contraction's operands are sized for either order:
+// its fringe operand holds nx x pad(columns) or ny x pad(rows) elements, its
+// coefficient operand rows x pad(columns) or columns x pad(rows).
+__host__ __device__ inline size_t dl_first_fringe_elems(int ny, int nx, int l) {
+    const size_t r = (size_t)nx * pad_kt(band_side(nx, l)), c = (size_t)ny * pad_kt(band_side(ny, l));
+    return r > c ? r : c;
+}
+__host__ __device__ inline size_t dl_coef_elems(int ny, int nx, int l) {
+    const int syl = band_side(ny, l), sxl = band_side(nx, l);
+    const size_t r = (size_t)syl * pad_kt(sxl), c = (size_t)sxl * pad_kt(syl);
+    return r > c ? r : c;
+}
+// The order of one (layer, level): columns-first iff its padded column count is
+// the smaller (K' never exceeds the rows-first bound kmax).
+__host__ __device__ inline bool columns_first(int rows, int cols) {
+    return pad_kt(cols) < pad_kt(rows);
+}
+
 inline NtSizes nt_sizes(int ny, int nx, int layers, int levels) {
     NtSizes z{};
     size_t sy = 0, sx = 0, fx = 0, cb = 0, kmax = 0;
@@ -84,10 +106,13 @@ inline NtSizes nt_sizes(int ny, int nx, int layers, int levels) {
         const int syl = band_side(ny, l), sxl = band_side(nx, l);
         sy += syl;
         sx += sxl;
-        fx += (size_t)nx * pad_kt(sxl);
-        cb += (size_t)syl * pad_kt(sxl);
+        fx += dl_first_fringe_elems(ny, nx, l);
+        cb += dl_coef_elems(ny, nx, l);
         kmax += pad_kt(syl);
-        tiles += ((syl + 63) / 64) * ((nx + 63) / 64);  // bound for the smallest tile shape
+        // bound for the smallest tile shape, in either order
+        const int tr = ((syl + 63) / 64) * ((nx + 63) / 64);
+        const int tc = ((sxl + 63) / 64) * ((ny + 63) / 64);
+        tiles += tr > tc ? tr : tc;
     }
     z.rowlist = sy * layers;
     z.collist = sx * layers;
@@ -114,10 +139,10 @@ __host__ __device__ inline size_t dl_cols_off(int nx, int levels, int d, int l) 
     }
     return (size_t)d * per + off;
 }
-__host__ __device__ inline size_t dl_fx_off(int nx, int levels, int d, int l) {
+__host__ __device__ inline size_t dl_fx_off(int ny, int nx, int levels, int d, int l) {
     size_t per = 0, off = 0;
     for (int k = 1; k <= levels; ++k) {
-        const size_t v = (size_t)nx * pad_kt(band_side(nx, k));
+        const size_t v = dl_first_fringe_elems(ny, nx, k);
         if (k < l) off += v;
         per += v;
     }
@@ -126,7 +151,7 @@ __host__ __device__ inline size_t dl_fx_off(int nx, int levels, int d, int l) {
 __host__ __device__ inline size_t dl_cb_off(int ny, int nx, int levels, int d, int l) {
     size_t per = 0, off = 0;
     for (int k = 1; k <= levels; ++k) {
-        const size_t v = (size_t)band_side(ny, k) * pad_kt(band_side(nx, k));
+        const size_t v = dl_coef_elems(ny, nx, k);
         if (k < l) off += v;
         per += v;
     }
@@ -139,7 +164,8 @@ struct NtBuffers {
     int* collist;
     int* cnt_row;   // [D*L]
     int* cnt_col;   // [D*L]
-    int* seg_row;   // [D*L]
+    int* seg_row;   // [D*L] k' offset of the (layer, level) segment
+    int* orient;    // [D*L] 1: contracted columns-first (set by the planning kernel)
     int* tbeg;      // [D*L] tile prefix (first contraction, local to the scene)
     const uint8_t* occ;  // (layer, block) occupancy of the coefficient planes
     PlanHeader* hdr;
@@ -167,13 +193,14 @@ struct PlanArgs {
     const int* cnt_row;
     const int* cnt_col;
     int* seg_row;
+    int* orient;
     int* tbeg;
     PlanHeader* hdr;
     NtEntry* first;
     NtEntry* second;
     const void* cb;
     const void* fx;
-    const void* fy;
+    void* fy;
     void* tc;
     long long cb_ps, fx_ps, fy_ps, tc_ps;
     float2* hologram;

@@ -4,8 +4,10 @@
 //            coefficient square (deterministic wave-ballot compaction);
 //  * plan:   padded counts, k' segment offsets and the GEMM problem table;
 //  * panels: K-contiguous operand panels in the operand precision --
-//            Fy_c[y][k'] and Fx_c[x][c'] gathered from the 1D fringe tables,
-//            Cb_c[r'][c'] gathered from the masked Mallat coefficients.
+//            the fringe operands (Fy_c[y][k'], Fx_c[x][c'], or their roles swapped
+//            where a (layer, level) is contracted columns-first) gathered from the
+//            1D fringe tables, Cb_c[r'][c'] (or its transpose) gathered from the
+//            masked Mallat coefficients.
 #include "nt.h"
 #include "split.h"
 
@@ -92,69 +94,85 @@ __device__ int block_scan_incl(int v, int* sh) {
 
 __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last) {
     const int n_dl = a.layers * a.levels;
-    const int tn1 = (a.nx + a.tn1 - 1) / a.tn1;
-    int total_k = 0, total_t = 0, total_r = 0;
-    // pass 1: padded row counts -> k' segment offsets, tile counts -> tile prefix
+    int total_k = 0, total_t = 0, total_a = 0;
+    // pass 1: the order of each (layer, level) (rows-first, or columns-first where
+    // that gives the shorter padded K' segment: Eq. 3's sum is the same in either
+    // order), its K' segment -> k' offsets, its first-contraction tiles -> tile prefix
     for (int base = 0; base < n_dl; base += blockDim.x) {
         const int t = base + (int)threadIdx.x;
-        int cr = 0, pr = 0, tiles = 0;
+        int seg = 0, tiles = 0, act = 0;
         if (t < n_dl) {
-            cr = a.cnt_row[t];
-            pr = pad_kt(cr);
-            tiles = cr > 0 ? ((cr + a.tm1 - 1) / a.tm1) * tn1 : 0;
+            const int cr = a.cnt_row[t], cc = a.cnt_col[t];
+            const bool cf = columns_first(cr, cc);
+            act = cf ? cc : cr;
+            seg = pad_kt(act);
+            // rows-first: cr x nx outputs; columns-first: cc x ny
+            const int outer = cf ? a.ny : a.nx;
+            tiles = act > 0 ? ((act + a.tm1 - 1) / a.tm1) * ((outer + a.tn1 - 1) / a.tn1) : 0;
+            a.orient[t] = cf ? 1 : 0;
         }
-        const int ik = block_scan_incl(pr, sh);
+        const int ik = block_scan_incl(seg, sh);
         const int it = block_scan_incl(tiles, sh);
-        const int ir = block_scan_incl(cr, sh);
+        const int ia = block_scan_incl(act, sh);
         if (t < n_dl) {
-            a.seg_row[t] = total_k + ik - pr;
+            a.seg_row[t] = total_k + ik - seg;
             a.tbeg[t] = total_t + it - tiles;
         }
         if (threadIdx.x == blockDim.x - 1) {
             last[0] = ik;
             last[1] = it;
-            last[2] = ir;
+            last[2] = ia;
         }
         __syncthreads();
         total_k += last[0];
         total_t += last[1];
-        total_r += last[2];
+        total_a += last[2];
         __syncthreads();
     }
     const int kpad = total_k;
     // FP16 range scaling: coefficients to [1, 2) times their largest magnitude
-    // (|coefficient| <= max |object| for the averaging Haar pair), T_c below 2^15:
-    // |T_c| < 2 x nx columns x 8 (a level's block fringe sums at most 2^3 unit
-    // phasors); the second contraction's epilogue undoes both and the y tables' scale
+    // (|coefficient| <= max |object| for the averaging Haar pair), the first
+    // contraction's outputs below 2^15: a level-l fringe entry is a sum of 2^l unit
+    // phasors (times the y tables' layer constant, scaled into [1, 2)), and a row
+    // or column of a level's square has at most 2 n / 2^l active entries, so
+    // |T| < 2 x 2 nx and |T'| < 2 x 2 x 2 ny, both below 16 max(ny, nx); the second
+    // contraction's epilogue undoes the three scales
     float cb_scale = 1.f, first_scale = 1.f, second_scale = 1.f;
     if (a.fp16) {
         const int ea = range_exp(absmax_value(a.absmax));
-        const int t = headroom_shift(16.f * (float)a.nx);
+        const int t = headroom_shift(16.f * (float)(a.ny > a.nx ? a.ny : a.nx));
         cb_scale = pow2f(-ea);
         first_scale = pow2f(-t);
         second_scale = pow2f(ea + t + a.e_fringe);
     }
-    // pass 2: the problem table
+    // pass 2: the problem table.  Rows-first: T = Cb_c Fx_c^T (cr x nx, K = padded
+    // columns) into the B operand of the second contraction; columns-first:
+    // T' = Cb_c^T Fy_c^T (cc x ny, K = padded rows) into its A operand.
     const char* cb = static_cast<const char*>(a.cb);
     const char* fx = static_cast<const char*>(a.fx);
+    char* fy = static_cast<char*>(a.fy);
     char* tc = static_cast<char*>(a.tc);
     for (int t = threadIdx.x; t < n_dl; t += blockDim.x) {
         const int d = t / a.levels, l = t % a.levels + 1;
+        const int cr = a.cnt_row[t], cc = a.cnt_col[t];
+        const bool cf = columns_first(cr, cc);
+        const int outer = cf ? a.ny : a.nx;
         NtEntry e;
         e.a = cb + dl_cb_off(a.ny, a.nx, a.levels, d, l) * a.esize;
-        e.b = fx + dl_fx_off(a.nx, a.levels, d, l) * a.esize;
-        e.out = tc + (size_t)a.seg_row[t] * a.nx * a.esize;  // K block seg/16 of T_c
+        e.b = fx + dl_fx_off(a.ny, a.nx, a.levels, d, l) * a.esize;
+        // K block seg/16 of the operand panel the result feeds
+        e.out = (cf ? fy : tc) + (size_t)a.seg_row[t] * outer * a.esize;
         e.partial = nullptr;
         e.a_ps = a.cb_ps;
         e.b_ps = a.fx_ps;
-        e.out_ps = a.tc_ps;
-        e.M = a.cnt_row[t];
-        e.N = a.nx;
-        e.K = pad_kt(a.cnt_col[t]);
+        e.out_ps = cf ? a.fy_ps : a.tc_ps;
+        e.M = cf ? cc : cr;
+        e.N = outer;
+        e.K = pad_kt(cf ? cr : cc);
         e.lda = e.M * 16;
-        e.ldb = a.nx * 16;
-        e.out_ld = a.nx * 16;
-        e.tiles_n = tn1;
+        e.ldb = outer * 16;
+        e.out_ld = outer * 16;
+        e.tiles_n = (outer + a.tn1 - 1) / a.tn1;
         e.tile_begin = a.tbeg[t];
         e.accumulate = 0;
         e.tile_m = a.tm1;
@@ -165,7 +183,7 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
     if (threadIdx.x == 0) {
         a.hdr->kpad = kpad;
         a.hdr->first_tiles = total_t;
-        a.hdr->rows_active = total_r;
+        a.hdr->k_active = total_a;
         a.hdr->second_tiles = nt_tiles(a.ny, a.nx, a.tm2, a.tn2);
         a.hdr->cb_scale = cb_scale;
         NtEntry e;
@@ -305,101 +323,115 @@ __device__ __forceinline__ void fringe_tiles(const float* __restrict__ lutl, int
     }
 }
 
+// Fringe operand of the second contraction for one (layer, level): rows-first, the
+// y fringes of its active rows (Fy_c, ny rows) at its k' segment of the A panel;
+// columns-first, the x fringes of its active columns (nx rows) at its segment of
+// the B panel (the first contraction fills the other operand's segment).
 template <int P>
-__device__ __forceinline__ void fy_block(const float* __restrict__ lut_y,
-                                         const int* __restrict__ rowlist,
-                                         const int* __restrict__ cnt_row,
-                                         const int* __restrict__ seg_row, int ny, int levels,
-                                         void* fy, size_t ps, int dl) {
+__device__ __forceinline__ void second_fringe_block(const float* __restrict__ lut_x,
+                                                    const float* __restrict__ lut_y,
+                                                    const NtBuffers& b, int ny, int nx,
+                                                    int levels, int dl) {
     const int d = dl / levels, l = dl % levels + 1;
-    const int cr = cnt_row[dl], pr = pad_kt(cr);
-    if (pr == 0) return;
-    const int len = lut_len(ny);
-    // the segment starts on a K-block boundary: its blocks follow in storage order
-    fringe_tiles<P>(lut_y + lut_table(d, l, 0, 0, levels) * len, len,
-                    rowlist + dl_rows_off(ny, levels, d, l), cr, ny >> l, l, ny, pr, fy, ps,
-                    (size_t)seg_row[dl] * ny);
+    const int cr = b.cnt_row[dl], cc = b.cnt_col[dl];
+    if (cr == 0 || cc == 0) return;
+    const size_t seg = (size_t)b.seg_row[dl];
+    if (b.orient[dl]) {
+        const int len = lut_len(nx);
+        fringe_tiles<P>(lut_x + lut_table(d, l, 0, 0, levels) * len, len,
+                        b.collist + dl_cols_off(nx, levels, d, l), cc, nx >> l, l, nx,
+                        pad_kt(cc), b.tc, b.tc_ps, seg * nx);
+    } else {
+        const int len = lut_len(ny);
+        fringe_tiles<P>(lut_y + lut_table(d, l, 0, 0, levels) * len, len,
+                        b.rowlist + dl_rows_off(ny, levels, d, l), cr, ny >> l, l, ny,
+                        pad_kt(cr), b.fy, b.fy_ps, seg * ny);
+    }
 }
 
+// Fringe operand of the first contraction: rows-first, the x fringes of the active
+// columns (Fx_c, nx rows); columns-first, the y fringes of the active rows (ny rows).
 template <int P>
-__device__ __forceinline__ void fx_block(const float* __restrict__ lut_x,
-                                         const int* __restrict__ collist,
-                                         const int* __restrict__ cnt_row,
-                                         const int* __restrict__ cnt_col, int nx, int levels,
-                                         void* fx, size_t ps, int dl) {
+__device__ __forceinline__ void first_fringe_block(const float* __restrict__ lut_x,
+                                                   const float* __restrict__ lut_y,
+                                                   const NtBuffers& b, int ny, int nx,
+                                                   int levels, int dl) {
     const int d = dl / levels, l = dl % levels + 1;
-    const int cc = cnt_col[dl], pc = pad_kt(cc);
-    if (pc == 0 || cnt_row[dl] == 0) return;
-    const int len = lut_len(nx);
-    fringe_tiles<P>(lut_x + lut_table(d, l, 0, 0, levels) * len, len,
-                    collist + dl_cols_off(nx, levels, d, l), cc, nx >> l, l, nx, pc, fx, ps,
-                    dl_fx_off(nx, levels, d, l));
+    const int cr = b.cnt_row[dl], cc = b.cnt_col[dl];
+    if (cr == 0 || cc == 0) return;
+    const size_t base = dl_fx_off(ny, nx, levels, d, l);
+    if (b.orient[dl]) {
+        const int len = lut_len(ny);
+        fringe_tiles<P>(lut_y + lut_table(d, l, 0, 0, levels) * len, len,
+                        b.rowlist + dl_rows_off(ny, levels, d, l), cr, ny >> l, l, ny,
+                        pad_kt(cr), b.fx, b.fx_ps, base);
+    } else {
+        const int len = lut_len(nx);
+        fringe_tiles<P>(lut_x + lut_table(d, l, 0, 0, levels) * len, len,
+                        b.collist + dl_cols_off(nx, levels, d, l), cc, nx >> l, l, nx,
+                        pad_kt(cc), b.fx, b.fx_ps, base);
+    }
 }
 
+// Coefficient operand of the first contraction: Cb_c (active rows x padded active
+// columns) rows-first, its transpose (active columns x padded active rows)
+// columns-first; K-blocked, four consecutive k' per thread.
 template <int P>
-__device__ __forceinline__ void cb_block(const float* __restrict__ coef,
-                                         const int* __restrict__ rowlist,
-                                         const int* __restrict__ collist,
-                                         const int* __restrict__ cnt_row,
-                                         const int* __restrict__ cnt_col, int ny, int nx,
-                                         int levels, const uint8_t* __restrict__ occ,
-                                         const PlanHeader* __restrict__ hdr,
-                                         void* cb, size_t ps, int dl) {
+__device__ __forceinline__ void cb_block(const float* __restrict__ coef, const NtBuffers& b,
+                                         int ny, int nx, int levels, int dl) {
     const int d = dl / levels, l = dl % levels + 1;
-    const int cr = cnt_row[dl], cc = cnt_col[dl], pc = pad_kt(cc);
-    if (cr == 0 || pc == 0) return;
-    const float scale = hdr->cb_scale;  // written by the planning kernel
+    const int cr = b.cnt_row[dl], cc = b.cnt_col[dl];
+    if (cr == 0 || cc == 0) return;
+    const bool cf = b.orient[dl] != 0;
+    const int rows = cf ? cc : cr, kn = cf ? cr : cc, kp = pad_kt(kn);
+    const float scale = b.hdr->cb_scale;  // written by the planning kernel
     const int nyl = ny >> l, nxl = nx >> l;
     // the coefficient stage wrote only the blocks that hold a pixel of the layer:
     // a level-l coefficient at quadrant position (i, j) covers block
     // (i >> (levels - l), j >> (levels - l)) of 2^levels pixels
     const int nbx = nx >> levels, sh = levels - l;
-    const uint8_t* oc = occ + (size_t)d * (size_t)(ny >> levels) * nbx;
-    const int* rl = rowlist + dl_rows_off(ny, levels, d, l);
-    const int* cl = collist + dl_cols_off(nx, levels, d, l);
+    const uint8_t* oc = b.occ + (size_t)d * (size_t)(ny >> levels) * nbx;
+    const int* rl = b.rowlist + dl_rows_off(ny, levels, d, l);
+    const int* cl = b.collist + dl_cols_off(nx, levels, d, l);
     const float* cd = coef + (size_t)d * ny * nx;
     const size_t base = dl_cb_off(ny, nx, levels, d, l);
-    const long long total4 = (long long)cr * pc / 4;
+    const long long total4 = (long long)rows * kp / 4;
     for (long long e4 = (long long)blockIdx.x * blockDim.x + threadIdx.x; e4 < total4;
          e4 += (long long)gridDim.x * blockDim.x) {
         const size_t e = (size_t)e4 * 4;
-        int rr, c0;
-        kblk_pos(e, cr, rr, c0);
-        const int r = rl[rr];
-        const int brow = (r < nyl ? r : r - nyl) >> sh;
+        int pr, k0;
+        kblk_pos(e, rows, pr, k0);
         float v[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int c = c0 + q;
+            const int k = k0 + q;
             v[q] = 0.f;
-            if (c < cc) {
-                const int j = cl[c];
+            if (k < kn) {
+                const int r = rl[cf ? k : pr], j = cl[cf ? pr : k];
+                const int brow = (r < nyl ? r : r - nyl) >> sh;
                 const int bcol = (j < nxl ? j : j - nxl) >> sh;
                 // the LL quadrant of a level below the top belongs to the coarser levels
                 if (!(l < levels && r < nyl && j < nxl) && oc[(size_t)brow * nbx + bcol])
                     v[q] = cd[(size_t)r * nx + j] * scale;
             }
         }
-        put_r4<P>(cb, ps, base + e, v);
+        put_r4<P>(b.cb, b.cb_ps, base + e, v);
     }
 }
 
-// The three panels of one scene in one launch: grid.z selects the panel (0 Fy_c,
-// 1 Fx_c, 2 Cb_c), grid.y the (layer, level), grid.x strides over its chunks; the
-// three gathers share the machine instead of each ending on a partial wave.
+// The three panels of one scene in one launch: grid.z selects the panel (0 the
+// second contraction's fringe operand, 1 the first contraction's, 2 the coefficient
+// operand), grid.y the (layer, level), grid.x strides over its chunks; the three
+// gathers share the machine instead of each ending on a partial wave.
 template <int P>
 __global__ __launch_bounds__(256) void panels_kernel(const float* __restrict__ coef,
                                                      const float* __restrict__ lut_x,
                                                      const float* __restrict__ lut_y, int ny,
                                                      int nx, int levels, NtBuffers b) {
     const int dl = blockIdx.y;
-    if (blockIdx.z == 0)
-        fy_block<P>(lut_y, b.rowlist, b.cnt_row, b.seg_row, ny, levels, b.fy, b.fy_ps, dl);
-    else if (blockIdx.z == 1)
-        fx_block<P>(lut_x, b.collist, b.cnt_row, b.cnt_col, nx, levels, b.fx, b.fx_ps, dl);
-    else
-        cb_block<P>(coef, b.rowlist, b.collist, b.cnt_row, b.cnt_col, ny, nx, levels, b.occ,
-                    b.hdr, b.cb, b.cb_ps, dl);
+    if (blockIdx.z == 0) second_fringe_block<P>(lut_x, lut_y, b, ny, nx, levels, dl);
+    else if (blockIdx.z == 1) first_fringe_block<P>(lut_x, lut_y, b, ny, nx, levels, dl);
+    else cb_block<P>(coef, b, ny, nx, levels, dl);
 }
 
 // Batched panels: grid.z = 3 x scene + panel (as panels_kernel), grid.y = (layer, level),
@@ -410,15 +442,9 @@ __global__ __launch_bounds__(256) void panels_batch_kernel(const PrepScene* __re
     const PrepScene& sc = scenes[blockIdx.z / 3];
     if ((int)blockIdx.y >= sc.layers * levels) return;
     const int panel = blockIdx.z % 3, dl = blockIdx.y;
-    if (panel == 0)
-        fy_block<P>(sc.lut_y, sc.b.rowlist, sc.b.cnt_row, sc.b.seg_row, sc.ny, levels, sc.b.fy,
-                    sc.b.fy_ps, dl);
-    else if (panel == 1)
-        fx_block<P>(sc.lut_x, sc.b.collist, sc.b.cnt_row, sc.b.cnt_col, sc.nx, levels, sc.b.fx,
-                    sc.b.fx_ps, dl);
-    else
-        cb_block<P>(sc.coef, sc.b.rowlist, sc.b.collist, sc.b.cnt_row, sc.b.cnt_col, sc.ny,
-                    sc.nx, levels, sc.b.occ, sc.b.hdr, sc.b.cb, sc.b.cb_ps, dl);
+    if (panel == 0) second_fringe_block<P>(sc.lut_x, sc.lut_y, sc.b, sc.ny, sc.nx, levels, dl);
+    else if (panel == 1) first_fringe_block<P>(sc.lut_x, sc.lut_y, sc.b, sc.ny, sc.nx, levels, dl);
+    else cb_block<P>(sc.coef, sc.b, sc.ny, sc.nx, levels, dl);
 }
 
 int grid_for(long long elems) {
@@ -449,6 +475,7 @@ PlanArgs make_plan_args(int ny, int nx, int layers, int levels, int precision, c
     a.cnt_row = b.cnt_row;
     a.cnt_col = b.cnt_col;
     a.seg_row = b.seg_row;
+    a.orient = b.orient;
     a.tbeg = b.tbeg;
     a.hdr = b.hdr;
     a.first = b.first;
@@ -489,7 +516,7 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
     const int n_dl = layers * levels;
     const long long big_y = (long long)ny * pad_kt(band_side(ny, 1));
     const long long big_x = (long long)nx * pad_kt(band_side(nx, 1));
-    const long long big_c = (long long)band_side(ny, 1) * pad_kt(band_side(nx, 1));
+    const long long big_c = (long long)dl_coef_elems(ny, nx, 1);
     // fringe panels: one workgroup per 256 rows x 16 K = 4096 elements (grid_for sizes for
     // 2048); the coefficient panel four elements per thread; all three in one launch
     int gx = grid_for(big_y / 2);

@@ -162,7 +162,7 @@ def single_with_rows(s, precision):
                      device="cuda")
     h = m.progressive_hologram(d["obj"], s.z, s.lam, s.pitch, 3, d["saliency"],
                                d.get("layer_index"), precision=precision, workspace=ws)
-    rows = m.workspace_stats(ws, ny, nx, len(s.z), 3, precision)["coef_rows_active"]
+    rows = m.workspace_stats(ws, ny, nx, len(s.z), 3, precision)["k_active"]
     torch.cuda.synchronize()
     return h.cpu().numpy(), rows
 

@@ -72,7 +72,7 @@ def test_last_stage_equals_single_call_and_stages_differ():
     ws = torch.empty(m.workspace_size(ny, nx, 2, 3, "fp32"), dtype=torch.uint8, device="cuda")
     h = m.progressive_hologram(to_dev(s.obj), s.z, s.lam, s.pitch, 3, to_dev(s.saliency),
                                to_dev(s.layer), workspace=ws)
-    rows = m.workspace_stats(ws, ny, nx, 2, 3, "fp32")["coef_rows_active"]
+    rows = m.workspace_stats(ws, ny, nx, 2, 3, "fp32")["k_active"]
     torch.cuda.synchronize()
     err = rel_l2(st[3], h.cpu().numpy())
     assert err <= 2.0 * np.sqrt(rows) * 2.0 ** -24
