@@ -40,6 +40,8 @@ struct cgh_plan {
     int n_first = 0;
     cgh::PlanHeader* hdrs = nullptr;
     int* first_off = nullptr;
+    int* scene_units = nullptr;  // [n + 1] prefix of the scenes' panel work units
+    long long units_bound = 0;   // upper bound of their total (sizes the panel grid)
     int* counts = nullptr;
     int* queues = nullptr;
     int tiles[4] = {cgh::kNtTile, cgh::kNtTile, cgh::kNtTile, cgh::kNtTile};
@@ -80,10 +82,11 @@ hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s) {
     if (e == hipSuccess) e = cgh::launch_lists_batch(p.d_prep, n, p.levels, p.max_ndl, s);
     if (e == hipSuccess) e = cgh::launch_plan_batch(p.d_args, n, p.max_ndl, s);
     if (e == hipSuccess)
-        e = cgh::launch_materialize_batch(p.d_prep, n, p.levels, p.precision, p.max_ndl, s);
+        e = cgh::launch_batch_prefix(p.hdrs, n, p.first_off, p.first, p.second, p.counts,
+                                     p.queues, p.scene_units, s);
     if (e != hipSuccess) return e;
-    return cgh::launch_batch_prefix(p.hdrs, n, p.first_off, p.first, p.second, p.counts,
-                                    p.queues, s);
+    return cgh::launch_materialize_batch(p.d_prep, n, p.levels, p.precision, p.scene_units,
+                                         p.units_bound, s);
 }
 
 // Planning arguments of every scene for the given tile shapes (synchronous).
@@ -325,8 +328,8 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
         const size_t prep_b = align_up((size_t)n * sizeof(cgh::PrepScene));
         const size_t luts_b = align_up((size_t)n_luts * sizeof(cgh::LutJob));
         const size_t args_b = align_up((size_t)n * sizeof(cgh::PlanArgs));
-        p->bytes = off + first_b + second_b + hdr_b + off_b + align_up(4 * sizeof(int)) + dwt_b +
-                   prep_b + luts_b + args_b;
+        p->bytes = off + first_b + second_b + hdr_b + 2 * off_b + align_up(4 * sizeof(int)) +
+                   dwt_b + prep_b + luts_b + args_b;
 
         const char* fail = std::getenv("CGH_TEST_FAIL_ALLOC");  // host-forced failure for tests
         if (fail && fail[0] == '1') {
@@ -347,6 +350,8 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
         p->hdrs = reinterpret_cast<cgh::PlanHeader*>(m);
         m += hdr_b;
         p->first_off = reinterpret_cast<int*>(m);
+        m += off_b;
+        p->scene_units = reinterpret_cast<int*>(m);
         m += off_b;
         p->counts = reinterpret_cast<int*>(m);
         p->queues = p->counts + 2;
@@ -400,6 +405,7 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
             p->max_ndl = std::max(p->max_ndl, nl * levels);
             p->max_len = std::max(p->max_len, cgh::lut_len(std::max(nx, ny)));
             p->max_fill = std::max(p->max_fill, lo.flags_fill);
+            p->units_bound += cgh::panel_units_bound(ny, nx, nl, levels);
         }
 
         hipStream_t s = (hipStream_t)stream;

@@ -87,6 +87,7 @@ struct Layout {
     size_t rowlist, collist;     // active row / column indices per (layer, level)
     size_t cnt_row, cnt_col, seg_row, orient, tbeg;  // per (layer, level) counts, k' offsets,
                                                       // contraction order, tile offsets
+    size_t units;                                    // panel work-unit table (3 D L + 1 ints)
     size_t hdr, entries;         // device plan header and GEMM problem table
     size_t big;                  // shared region: backward T, or the forward panels
     size_t big_bytes;            // its size

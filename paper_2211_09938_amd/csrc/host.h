@@ -90,6 +90,7 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels,
     lo.cnt_col = take((size_t)n_dl * 4);
     lo.seg_row = take((size_t)n_dl * 4);
     lo.orient = take((size_t)n_dl * 4);
+    lo.units = take((size_t)(3 * n_dl + 1) * 4);
     lo.tbeg = take((size_t)n_dl * 4);
     lo.hdr = take(sizeof(cgh::PlanHeader));
     lo.entries = take((size_t)(n_dl + 1) * sizeof(cgh::NtEntry));
@@ -161,6 +162,7 @@ inline cgh::NtBuffers nt_buffers(char* ws, const cgh::Layout& lo) {
     b.cnt_col = reinterpret_cast<int*>(ws + lo.cnt_col);
     b.seg_row = reinterpret_cast<int*>(ws + lo.seg_row);
     b.orient = reinterpret_cast<int*>(ws + lo.orient);
+    b.units = reinterpret_cast<int*>(ws + lo.units);
     b.tbeg = reinterpret_cast<int*>(ws + lo.tbeg);
     b.occ = reinterpret_cast<const uint8_t*>(ws + lo.occ);
     b.hdr = reinterpret_cast<cgh::PlanHeader*>(ws + lo.hdr);

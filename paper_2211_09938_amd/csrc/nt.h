@@ -65,6 +65,7 @@ struct PlanHeader {
                        // active rows, or its active columns where those go first
     int second_tiles;  // output tiles of the second contraction
     float cb_scale;    // scale of the coefficient panel (FP16 range scaling, else 1)
+    int panel_units;   // work units of the operand-panel gather
 };
 
 // Element counts (dense upper bounds) of the compacted regions.
@@ -96,6 +97,34 @@ __host__ __device__ inline size_t dl_coef_elems(int ny, int nx, int l) {
 // the smaller (K' never exceeds the rows-first bound kmax).
 __host__ __device__ inline bool columns_first(int rows, int cols) {
     return pad_kt(cols) < pad_kt(rows);
+}
+
+// Work units of the operand-panel gather of one (layer, level) with `rows` active
+// rows and `cols` active columns: [0] tasks of the second contraction's fringe
+// operand, [1] of the first contraction's (a task is kFringeRows rows x one
+// 16-wide K block), [2] units of kCbUnit coefficient-operand elements.
+constexpr int kFringeRows = 256;
+constexpr int kCbUnit = 1024;  // 256 threads x 4 elements
+__host__ __device__ inline void dl_panel_units(int ny, int nx, int rows, int cols, int u[3]) {
+    u[0] = u[1] = u[2] = 0;
+    if (rows == 0 || cols == 0) return;
+    const bool cf = columns_first(rows, cols);
+    const int n2 = cf ? nx : ny, k2 = cf ? cols : rows;  // the K' side
+    const int n1 = cf ? ny : nx, k1 = cf ? rows : cols;  // the first contraction's K side
+    u[0] = (n2 + kFringeRows - 1) / kFringeRows * (pad_kt(k2) / kKT);
+    u[1] = (n1 + kFringeRows - 1) / kFringeRows * (pad_kt(k1) / kKT);
+    u[2] = (int)(((long long)k2 * pad_kt(k1) + kCbUnit - 1) / kCbUnit);
+}
+
+// Upper bound of a scene's panel work units (every row and column active).
+inline long long panel_units_bound(int ny, int nx, int layers, int levels) {
+    long long t = 0;
+    for (int l = 1; l <= levels; ++l) {
+        int u[3];
+        dl_panel_units(ny, nx, band_side(ny, l), band_side(nx, l), u);
+        t += (long long)u[0] + u[1] + u[2];
+    }
+    return t * layers;
 }
 
 inline NtSizes nt_sizes(int ny, int nx, int layers, int levels) {
@@ -166,6 +195,9 @@ struct NtBuffers {
     int* cnt_col;   // [D*L]
     int* seg_row;   // [D*L] k' offset of the (layer, level) segment
     int* orient;    // [D*L] 1: contracted columns-first (set by the planning kernel)
+    int* units;     // [3*D*L+1] start of the panel work units of kind k of (layer,
+                    // level) t at entry k D L + t, then the total (planning kernel;
+                    // the batched panel gather numbers its work by it)
     int* tbeg;      // [D*L] tile prefix (first contraction, local to the scene)
     const uint8_t* occ;  // (layer, block) occupancy of the coefficient planes
     PlanHeader* hdr;
@@ -194,6 +226,7 @@ struct PlanArgs {
     const int* cnt_col;
     int* seg_row;
     int* orient;
+    int* units;
     int* tbeg;
     PlanHeader* hdr;
     NtEntry* first;
@@ -228,8 +261,11 @@ hipError_t launch_lists_batch(const PrepScene* scenes, int n, int levels, int ma
                               hipStream_t s);
 // max_ndl: the largest (layer, level) count of the scenes (sizes the workgroup).
 hipError_t launch_plan_batch(const PlanArgs* args, int n, int max_ndl, hipStream_t s);
+// scene_units: as written by launch_batch_prefix; units_bound: an estimate of the
+// batch's panel work units (sizes the grid).
 hipError_t launch_materialize_batch(const PrepScene* scenes, int n, int levels, int precision,
-                                    int max_ndl, hipStream_t s);
+                                    const int* scene_units, long long units_bound,
+                                    hipStream_t s);
 
 // tiles: {rows, cols} of the first contraction's tile, then of the second's.
 hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int levels,
@@ -266,9 +302,11 @@ hipError_t launch_nt_persistent(bool second, int precision, int tile_m, int tile
                                 int* queue, int grid, hipStream_t s);
 // Adds each scene's tile offset to its problems in the batched tables, writes
 // the two tile totals to counts[0..1] and zeroes queues[0..1].
+// Also writes scene_units[0..n]: the exclusive prefix of the scenes' panel work
+// units (the batched panel gather splits that range over its workgroups).
 hipError_t launch_batch_prefix(const PlanHeader* hdrs, int n_scenes, const int* first_off,
                                NtEntry* first, NtEntry* second, int* counts, int* queues,
-                               hipStream_t s);
+                               int* scene_units, hipStream_t s);
 // Direct launch over a table of complex x complex problems (A and B complex,
 // tile 128 x nt_table_tile_n(epi, precision); `tiles` bounds the device tile
 // count, split-K when split > 1 into each problem's partial buffer).  Epilogues:

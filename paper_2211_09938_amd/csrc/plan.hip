@@ -94,13 +94,13 @@ __device__ int block_scan_incl(int v, int* sh) {
 
 __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last) {
     const int n_dl = a.layers * a.levels;
-    int total_k = 0, total_t = 0, total_a = 0;
+    int total_k = 0, total_t = 0, total_a = 0, total_u0 = 0, total_u1 = 0, total_u2 = 0;
     // pass 1: the order of each (layer, level) (rows-first, or columns-first where
     // that gives the shorter padded K' segment: Eq. 3's sum is the same in either
     // order), its K' segment -> k' offsets, its first-contraction tiles -> tile prefix
     for (int base = 0; base < n_dl; base += blockDim.x) {
         const int t = base + (int)threadIdx.x;
-        int seg = 0, tiles = 0, act = 0;
+        int seg = 0, tiles = 0, act = 0, pu[3] = {0, 0, 0};
         if (t < n_dl) {
             const int cr = a.cnt_row[t], cc = a.cnt_col[t];
             const bool cf = columns_first(cr, cc);
@@ -110,25 +110,48 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
             const int outer = cf ? a.ny : a.nx;
             tiles = act > 0 ? ((act + a.tm1 - 1) / a.tm1) * ((outer + a.tn1 - 1) / a.tn1) : 0;
             a.orient[t] = cf ? 1 : 0;
+            dl_panel_units(a.ny, a.nx, cr, cc, pu);
         }
         const int ik = block_scan_incl(seg, sh);
         const int it = block_scan_incl(tiles, sh);
         const int ia = block_scan_incl(act, sh);
+        const int iu0 = block_scan_incl(pu[0], sh);
+        const int iu1 = block_scan_incl(pu[1], sh);
+        const int iu2 = block_scan_incl(pu[2], sh);
         if (t < n_dl) {
             a.seg_row[t] = total_k + ik - seg;
             a.tbeg[t] = total_t + it - tiles;
+            // kind-local starts; the kinds' bases are added once their totals are known
+            a.units[t] = total_u0 + iu0 - pu[0];
+            a.units[n_dl + t] = total_u1 + iu1 - pu[1];
+            a.units[2 * n_dl + t] = total_u2 + iu2 - pu[2];
         }
         if (threadIdx.x == blockDim.x - 1) {
             last[0] = ik;
             last[1] = it;
             last[2] = ia;
+            last[3] = iu0;
+            last[4] = iu1;
+            last[5] = iu2;
         }
         __syncthreads();
         total_k += last[0];
         total_t += last[1];
         total_a += last[2];
+        total_u0 += last[3];
+        total_u1 += last[4];
+        total_u2 += last[5];
         __syncthreads();
     }
+    // the unit table in kind-major order (every (layer, level)'s second-contraction
+    // fringe tasks, then the first contraction's, then the coefficient units): the
+    // workgroups resident at one time then write one panel (each thread adds the
+    // bases to the entries it wrote above)
+    for (int t = threadIdx.x; t < n_dl; t += blockDim.x) {
+        a.units[n_dl + t] += total_u0;
+        a.units[2 * n_dl + t] += total_u0 + total_u1;
+    }
+    const int total_u = total_u0 + total_u1 + total_u2;
     const int kpad = total_k;
     // FP16 range scaling: coefficients to [1, 2) times their largest magnitude
     // (|coefficient| <= max |object| for the averaging Haar pair), the first
@@ -186,6 +209,8 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
         a.hdr->k_active = total_a;
         a.hdr->second_tiles = nt_tiles(a.ny, a.nx, a.tm2, a.tn2);
         a.hdr->cb_scale = cb_scale;
+        a.hdr->panel_units = total_u;
+        a.units[3 * n_dl] = total_u;
         NtEntry e;
         e.a = a.fy;
         e.b = a.tc;
@@ -212,50 +237,57 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
 
 __global__ __launch_bounds__(1024) void plan_kernel(PlanArgs a) {
     __shared__ int sh[1024];
-    __shared__ int last[3];
+    __shared__ int last[6];
     plan_block(a, sh, last);
 }
 
 // Batched: one workgroup per scene.
 __global__ __launch_bounds__(1024) void plan_batch_kernel(const PlanArgs* __restrict__ args) {
     __shared__ int sh[1024];
-    __shared__ int last[3];
+    __shared__ int last[6];
     const PlanArgs a = args[blockIdx.x];
     plan_block(a, sh, last);
 }
 
 // Merges the per-scene problem tables of a batch: scene i's first-contraction
 // entries (first_off[i] .. first_off[i+1]) and its second-contraction entry get
-// the tile offset of every scene before it; writes the batch tile totals and
-// clears the two work-queue counters.
+// the tile offset of every scene before it; writes the batch tile totals, clears
+// the two work-queue counters, and writes the prefix of the scenes' panel work
+// units (scene_units[n_scenes] = their total).
 __global__ __launch_bounds__(1024) void batch_prefix_kernel(const PlanHeader* __restrict__ hdrs,
                                                             int n_scenes,
                                                             const int* __restrict__ first_off,
                                                             NtEntry* __restrict__ first,
                                                             NtEntry* __restrict__ second,
                                                             int* __restrict__ counts,
-                                                            int* __restrict__ queues) {
+                                                            int* __restrict__ queues,
+                                                            int* __restrict__ scene_units) {
     __shared__ int sh[1024];
-    __shared__ int last[2];
-    int run1 = 0, run2 = 0;
+    __shared__ int last[3];
+    int run1 = 0, run2 = 0, run3 = 0;
     for (int base = 0; base < n_scenes; base += 1024) {
         const int i = base + (int)threadIdx.x;
         const int v1 = i < n_scenes ? hdrs[i].first_tiles : 0;
         const int v2 = i < n_scenes ? hdrs[i].second_tiles : 0;
+        const int v3 = i < n_scenes ? hdrs[i].panel_units : 0;
         const int c1 = block_scan_incl(v1, sh);
         const int c2 = block_scan_incl(v2, sh);
+        const int c3 = block_scan_incl(v3, sh);
         if (i < n_scenes) {
             const int o1 = run1 + c1 - v1;
             for (int e = first_off[i]; e < first_off[i + 1]; ++e) first[e].tile_begin += o1;
             second[i].tile_begin = run2 + c2 - v2;
+            scene_units[i] = run3 + c3 - v3;
         }
         if (threadIdx.x == blockDim.x - 1) {
             last[0] = c1;
             last[1] = c2;
+            last[2] = c3;
         }
         __syncthreads();
         run1 += last[0];
         run2 += last[1];
+        run3 += last[2];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -263,195 +295,272 @@ __global__ __launch_bounds__(1024) void batch_prefix_kernel(const PlanHeader* __
         counts[1] = run2;
         queues[0] = 0;
         queues[1] = 0;
+        scene_units[n_scenes] = run3;
     }
 }
 
-// Fringe panels through LDS.  Column k' of a panel is a contiguous slice of a 1D
-// fringe table (row y reads entry y - j 2^l + n for the k'-th active row j).  A
-// workgroup takes 256 rows x one 16-wide K block: it reads the table with the
-// lanes along the rows (one contiguous run per k'), keeps the tile in LDS (row
-// pitch 17 floats: the LDS stores of each table read hit 64 different banks; the
-// chunk reads that follow can pair up on a bank), and writes the tile's K-blocked
-// storage -- 256 rows x 16 elements, contiguous -- with consecutive lanes on
-// consecutive 4-element chunks.
-constexpr int kFringeRows = 256, kFringePitch = 17;
+// Fringe operands through LDS.  Column k' of a fringe operand is a contiguous slice
+// of a 1D fringe table (row y reads entry y - j 2^l + n for the k'-th active row or
+// column j).  A task is kFringeRows rows x one 16-wide K block: the workgroup reads
+// the table with the lanes along the rows (one contiguous run per k'), keeps the
+// tile in LDS (row pitch 17 floats: the LDS stores of each table read hit 64
+// different banks; the chunk reads that follow can pair up on a bank), and writes
+// the tile's K-blocked storage -- 256 rows x 16 elements, contiguous -- with
+// consecutive lanes on consecutive 4-element chunks.
+constexpr int kFringePitch = 17;
 
 template <int P>
-__device__ __forceinline__ void fringe_tiles(const float* __restrict__ lutl, int len,
-                                             const int* __restrict__ list, int count, int half,
-                                             int l, int n, int padded, void* panel, size_t ps,
-                                             size_t base) {
-    __shared__ float lre[kFringeRows * kFringePitch], lim[kFringeRows * kFringePitch];
+__device__ __forceinline__ void fringe_task(const float* __restrict__ lutl, int len,
+                                            const int* __restrict__ list, int count, int half,
+                                            int l, int n, void* panel, size_t ps, size_t base,
+                                            int task, float* lre, float* lim) {
     const int tid = threadIdx.x;
     const int ytiles = (n + kFringeRows - 1) / kFringeRows;
-    const int tasks = ytiles * (padded / 16);
-    for (int task = blockIdx.x; task < tasks; task += gridDim.x) {
-        const int kb = task / ytiles, y0 = (task - kb * ytiles) * kFringeRows;
-        const int y = y0 + tid;
-#pragma unroll 4
-        for (int q = 0; q < 16; ++q) {
-            const int i = 16 * kb + q;
-            float re = 0.f, im = 0.f;
-            if (i < count && y < n) {
-                const int r = list[i];
-                const int band = r >= half, j = r - band * half;
-                const float* tb = lutl + (size_t)band * 2 * len;
-                const int idx = y - (j << l) + n;
-                re = tb[idx];
-                im = tb[len + idx];
-            }
-            lre[tid * kFringePitch + q] = re;
-            lim[tid * kFringePitch + q] = im;
-        }
-        __syncthreads();
-        // chunk c = 4 elements: row c / 4 of the tile, k' 4 (c % 4) .. + 3
-        const size_t tile = base + ((size_t)kb * n + y0) * 16;
+    const int kb = task / ytiles, y0 = (task - kb * ytiles) * kFringeRows;
+    // every read is issued before the first is used: clamped, in-bounds addresses
+    // (rows past n are never stored; k' past count store zero) instead of a branch
+    // around each read, which serialised a thread's 32 reads into 16 round trips
+    const int y = min(y0 + tid, n - 1);
+    // the K block's 16 list entries: one load across the wave, then each is
+    // broadcast from its lane (a read per entry waited for its value first)
+    const int mine = list[min(16 * kb + (tid & 15), count - 1)];
+    float re[16], im[16];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-            const int c = s4 * kFringeRows + tid, row = c >> 2, k4 = (c & 3) * 4;
-            if (y0 + row < n) {
-                float re[4], im[4];
+    for (int q = 0; q < 16; ++q) {
+        const int r = __builtin_amdgcn_readlane(mine, q);
+        const int band = r >= half, j = r - band * half;
+        const float* tb = lutl + (size_t)band * 2 * len;
+        const int idx = y - (j << l) + n;
+        re[q] = tb[idx];
+        im[q] = tb[len + idx];
+    }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    re[q] = lre[row * kFringePitch + k4 + q];
-                    im[q] = lim[row * kFringePitch + k4 + q];
-                }
-                put_c4<P>(panel, ps, tile + 4 * (size_t)c, re, im);
+    for (int q = 0; q < 16; ++q) {
+        const bool live = 16 * kb + q < count;
+        lre[tid * kFringePitch + q] = live ? re[q] : 0.f;
+        lim[tid * kFringePitch + q] = live ? im[q] : 0.f;
+    }
+    __syncthreads();
+    // chunk c = 4 elements: row c / 4 of the tile, k' 4 (c % 4) .. + 3
+    const size_t tile = base + ((size_t)kb * n + y0) * 16;
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+        const int c = s4 * kFringeRows + tid, row = c >> 2, k4 = (c & 3) * 4;
+        if (y0 + row < n) {
+            float vr[4], vi[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                vr[q] = lre[row * kFringePitch + k4 + q];
+                vi[q] = lim[row * kFringePitch + k4 + q];
             }
+            put_c4<P>(panel, ps, tile + 4 * (size_t)c, vr, vi);
         }
-        __syncthreads();
     }
+    __syncthreads();
 }
 
-// Fringe operand of the second contraction for one (layer, level): rows-first, the
-// y fringes of its active rows (Fy_c, ny rows) at its k' segment of the A panel;
-// columns-first, the x fringes of its active columns (nx rows) at its segment of
-// the B panel (the first contraction fills the other operand's segment).
-template <int P>
-__device__ __forceinline__ void second_fringe_block(const float* __restrict__ lut_x,
-                                                    const float* __restrict__ lut_y,
-                                                    const NtBuffers& b, int ny, int nx,
-                                                    int levels, int dl) {
-    const int d = dl / levels, l = dl % levels + 1;
-    const int cr = b.cnt_row[dl], cc = b.cnt_col[dl];
-    if (cr == 0 || cc == 0) return;
-    const size_t seg = (size_t)b.seg_row[dl];
-    if (b.orient[dl]) {
-        const int len = lut_len(nx);
-        fringe_tiles<P>(lut_x + lut_table(d, l, 0, 0, levels) * len, len,
-                        b.collist + dl_cols_off(nx, levels, d, l), cc, nx >> l, l, nx,
-                        pad_kt(cc), b.tc, b.tc_ps, seg * nx);
-    } else {
-        const int len = lut_len(ny);
-        fringe_tiles<P>(lut_y + lut_table(d, l, 0, 0, levels) * len, len,
-                        b.rowlist + dl_rows_off(ny, levels, d, l), cr, ny >> l, l, ny,
-                        pad_kt(cr), b.fy, b.fy_ps, seg * ny);
-    }
+// One (layer, level) as the planning kernel left it.
+struct DlPlan {
+    int d, l, cr, cc, cf, seg;
+};
+
+__device__ __forceinline__ DlPlan load_dl(const NtBuffers& b, int levels, int dl) {
+    DlPlan g;
+    g.d = dl / levels;
+    g.l = dl - g.d * levels + 1;
+    g.cr = b.cnt_row[dl];
+    g.cc = b.cnt_col[dl];
+    g.cf = b.orient[dl];
+    g.seg = b.seg_row[dl];
+    return g;
 }
 
-// Fringe operand of the first contraction: rows-first, the x fringes of the active
-// columns (Fx_c, nx rows); columns-first, the y fringes of the active rows (ny rows).
-template <int P>
-__device__ __forceinline__ void first_fringe_block(const float* __restrict__ lut_x,
-                                                   const float* __restrict__ lut_y,
-                                                   const NtBuffers& b, int ny, int nx,
-                                                   int levels, int dl) {
-    const int d = dl / levels, l = dl % levels + 1;
-    const int cr = b.cnt_row[dl], cc = b.cnt_col[dl];
-    if (cr == 0 || cc == 0) return;
-    const size_t base = dl_fx_off(ny, nx, levels, d, l);
-    if (b.orient[dl]) {
-        const int len = lut_len(ny);
-        fringe_tiles<P>(lut_y + lut_table(d, l, 0, 0, levels) * len, len,
-                        b.rowlist + dl_rows_off(ny, levels, d, l), cr, ny >> l, l, ny,
-                        pad_kt(cr), b.fx, b.fx_ps, base);
-    } else {
-        const int len = lut_len(nx);
-        fringe_tiles<P>(lut_x + lut_table(d, l, 0, 0, levels) * len, len,
-                        b.collist + dl_cols_off(nx, levels, d, l), cc, nx >> l, l, nx,
-                        pad_kt(cc), b.fx, b.fx_ps, base);
-    }
+// A fringe operand of one (layer, level): its table, list and destination.
+struct FringeOp {
+    const float* lut;
+    const int* list;
+    void* panel;
+    size_t ps, base;
+    int len, count, half, n;
+};
+
+// The x fringes of the active columns (nx rows) or the y fringes of the active rows.
+__device__ __forceinline__ FringeOp fringe_op(const PrepScene& sc, int levels, const DlPlan& g,
+                                              bool x_axis, void* panel, size_t ps, size_t base) {
+    FringeOp f;
+    f.n = x_axis ? sc.nx : sc.ny;
+    f.len = lut_len(f.n);
+    f.lut = (x_axis ? sc.lut_x : sc.lut_y) + lut_table(g.d, g.l, 0, 0, levels) * f.len;
+    f.list = x_axis ? sc.b.collist + dl_cols_off(sc.nx, levels, g.d, g.l)
+                    : sc.b.rowlist + dl_rows_off(sc.ny, levels, g.d, g.l);
+    f.count = x_axis ? g.cc : g.cr;
+    f.half = f.n >> g.l;
+    f.panel = panel;
+    f.ps = ps;
+    f.base = base;
+    return f;
 }
 
-// Coefficient operand of the first contraction: Cb_c (active rows x padded active
-// columns) rows-first, its transpose (active columns x padded active rows)
-// columns-first; K-blocked, four consecutive k' per thread.
+// The second contraction's fringe operand: rows-first, the y fringes of the active
+// rows (Fy_c, ny rows) at the level's k' segment of the A panel; columns-first,
+// the x fringes of the active columns (nx rows) at its segment of the B panel (the
+// first contraction fills the other operand's segment).
+__device__ __forceinline__ FringeOp second_fringe(const PrepScene& sc, int levels,
+                                                  const DlPlan& g) {
+    const size_t seg = (size_t)g.seg;
+    return g.cf ? fringe_op(sc, levels, g, true, sc.b.tc, sc.b.tc_ps, seg * sc.nx)
+                : fringe_op(sc, levels, g, false, sc.b.fy, sc.b.fy_ps, seg * sc.ny);
+}
+// The first contraction's fringe operand: rows-first, the x fringes of the active
+// columns (Fx_c, nx rows); columns-first, the y fringes of the active rows.
+__device__ __forceinline__ FringeOp first_fringe(const PrepScene& sc, int levels,
+                                                 const DlPlan& g) {
+    const size_t base = dl_fx_off(sc.ny, sc.nx, levels, g.d, g.l);
+    return fringe_op(sc, levels, g, !g.cf, sc.b.fx, sc.b.fx_ps, base);
+}
+
 template <int P>
-__device__ __forceinline__ void cb_block(const float* __restrict__ coef, const NtBuffers& b,
-                                         int ny, int nx, int levels, int dl) {
-    const int d = dl / levels, l = dl % levels + 1;
-    const int cr = b.cnt_row[dl], cc = b.cnt_col[dl];
-    if (cr == 0 || cc == 0) return;
-    const bool cf = b.orient[dl] != 0;
-    const int rows = cf ? cc : cr, kn = cf ? cr : cc, kp = pad_kt(kn);
-    const float scale = b.hdr->cb_scale;  // written by the planning kernel
+__device__ __forceinline__ void run_fringe_task(const FringeOp& f, int l, int task, float* lre,
+                                                float* lim) {
+    fringe_task<P>(f.lut, f.len, f.list, f.count, f.half, l, f.n, f.panel, f.ps, f.base, task,
+                   lre, lim);
+}
+
+// Chunk e4 (four consecutive k' of one row, in storage order) of the coefficient
+// operand of the first contraction: Cb_c (active rows x padded active columns)
+// rows-first, its transpose (active columns x padded active rows) columns-first.
+template <int P>
+__device__ __forceinline__ void cb_chunk(const PrepScene& sc, int levels, const DlPlan& g,
+                                         float scale, long long e4) {
+    const NtBuffers& b = sc.b;
+    const int ny = sc.ny, nx = sc.nx, l = g.l;
+    const bool cf = g.cf != 0;
+    const int rows = cf ? g.cc : g.cr, kn = cf ? g.cr : g.cc;
     const int nyl = ny >> l, nxl = nx >> l;
     // the coefficient stage wrote only the blocks that hold a pixel of the layer:
     // a level-l coefficient at quadrant position (i, j) covers block
     // (i >> (levels - l), j >> (levels - l)) of 2^levels pixels
     const int nbx = nx >> levels, sh = levels - l;
-    const uint8_t* oc = b.occ + (size_t)d * (size_t)(ny >> levels) * nbx;
-    const int* rl = b.rowlist + dl_rows_off(ny, levels, d, l);
-    const int* cl = b.collist + dl_cols_off(nx, levels, d, l);
-    const float* cd = coef + (size_t)d * ny * nx;
-    const size_t base = dl_cb_off(ny, nx, levels, d, l);
-    const long long total4 = (long long)rows * kp / 4;
-    for (long long e4 = (long long)blockIdx.x * blockDim.x + threadIdx.x; e4 < total4;
-         e4 += (long long)gridDim.x * blockDim.x) {
-        const size_t e = (size_t)e4 * 4;
-        int pr, k0;
-        kblk_pos(e, rows, pr, k0);
-        float v[4];
+    const uint8_t* oc = b.occ + (size_t)g.d * (size_t)(ny >> levels) * nbx;
+    const int* rl = b.rowlist + dl_rows_off(ny, levels, g.d, l);
+    const int* cl = b.collist + dl_cols_off(nx, levels, g.d, l);
+    const float* cd = sc.coef + (size_t)g.d * ny * nx;
+    const size_t e = (size_t)e4 * 4;
+    int pr, k0;
+    kblk_pos(e, rows, pr, k0);
+    // reads issued together on clamped, in-bounds indices; the selects below zero
+    // the padding k', the low-low quadrant of a level below the top (it belongs to
+    // the coarser levels) and blocks without the layer
+    int r[4], j[4];
+    float c[4];
+    uint8_t o[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = k0 + q;
-            v[q] = 0.f;
-            if (k < kn) {
-                const int r = rl[cf ? k : pr], j = cl[cf ? pr : k];
-                const int brow = (r < nyl ? r : r - nyl) >> sh;
-                const int bcol = (j < nxl ? j : j - nxl) >> sh;
-                // the LL quadrant of a level below the top belongs to the coarser levels
-                if (!(l < levels && r < nyl && j < nxl) && oc[(size_t)brow * nbx + bcol])
-                    v[q] = cd[(size_t)r * nx + j] * scale;
-            }
-        }
-        put_r4<P>(b.cb, b.cb_ps, base + e, v);
+    for (int q = 0; q < 4; ++q) {
+        const int k = min(k0 + q, kn - 1);
+        r[q] = rl[cf ? k : pr];
+        j[q] = cl[cf ? pr : k];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int brow = (r[q] < nyl ? r[q] : r[q] - nyl) >> sh;
+        const int bcol = (j[q] < nxl ? j[q] : j[q] - nxl) >> sh;
+        o[q] = oc[(size_t)brow * nbx + bcol];
+        c[q] = cd[(size_t)r[q] * nx + j[q]];
+    }
+    float v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool keep = k0 + q < kn && !(l < levels && r[q] < nyl && j[q] < nxl) && o[q];
+        v[q] = keep ? c[q] * scale : 0.f;
+    }
+    put_r4<P>(b.cb, b.cb_ps, dl_cb_off(ny, nx, levels, g.d, l) + e, v);
+}
+
+__device__ __forceinline__ long long cb_chunks(const DlPlan& g) {
+    return g.cf ? (long long)g.cc * pad_kt(g.cr) / 4 : (long long)g.cr * pad_kt(g.cc) / 4;
+}
+
+// The operand panels of one scene in one launch: grid.z selects the panel (0 the
+// second contraction's fringe operand, 1 the first contraction's, 2 the coefficient
+// operand), grid.y the (layer, level), grid.x strides over its tasks or chunks.
+// The dispatcher hands out the workgroups in that order, so those resident at one
+// time write neighbouring parts of one panel.  grid.x is at most kPanelBlocks: the
+// grid is sized for dense upper bounds, and a workgroup with nothing to do still
+// holds its LDS until its counts arrive (512 per (layer, level) and panel measured
+// 85 us at 2048^2 x 8 layers, 128 measured 63 us, 32 measured 82 us).
+template <int P>
+__global__ __launch_bounds__(256) void panels_kernel(PrepScene sc, int levels) {
+    __shared__ float lre[kFringeRows * kFringePitch], lim[kFringeRows * kFringePitch];
+    const DlPlan g = load_dl(sc.b, levels, blockIdx.y);
+    if (g.cr == 0 || g.cc == 0) return;
+    if (blockIdx.z < 2) {
+        const FringeOp f = blockIdx.z == 0 ? second_fringe(sc, levels, g)
+                                           : first_fringe(sc, levels, g);
+        const int tasks = (f.n + kFringeRows - 1) / kFringeRows * (pad_kt(f.count) / kKT);
+        for (int t = blockIdx.x; t < tasks; t += gridDim.x)
+            run_fringe_task<P>(f, g.l, t, lre, lim);
+    } else {
+        const float scale = sc.b.hdr->cb_scale;  // written by the planning kernel
+        const long long total4 = cb_chunks(g);
+        for (long long e4 = (long long)blockIdx.x * blockDim.x + threadIdx.x; e4 < total4;
+             e4 += (long long)gridDim.x * blockDim.x)
+            cb_chunk<P>(sc, levels, g, scale, e4);
     }
 }
 
-// The three panels of one scene in one launch: grid.z selects the panel (0 the
-// second contraction's fringe operand, 1 the first contraction's, 2 the coefficient
-// operand), grid.y the (layer, level), grid.x strides over its chunks; the three
-// gathers share the machine instead of each ending on a partial wave.
-template <int P>
-__global__ __launch_bounds__(256) void panels_kernel(const float* __restrict__ coef,
-                                                     const float* __restrict__ lut_x,
-                                                     const float* __restrict__ lut_y, int ny,
-                                                     int nx, int levels, NtBuffers b) {
-    const int dl = blockIdx.y;
-    if (blockIdx.z == 0) second_fringe_block<P>(lut_x, lut_y, b, ny, nx, levels, dl);
-    else if (blockIdx.z == 1) first_fringe_block<P>(lut_x, lut_y, b, ny, nx, levels, dl);
-    else cb_block<P>(coef, b, ny, nx, levels, dl);
+// Number of entries of the non-decreasing a[0..n) that are <= v (a prefix of it),
+// counted by the whole workgroup.
+__device__ __forceinline__ int count_le(const int* __restrict__ a, int n, int v) {
+    int count = 0;
+    for (int base = 0; base < n; base += blockDim.x) {
+        const int i = base + (int)threadIdx.x;
+        const int c = __syncthreads_count(i < n && a[i] <= v);
+        count += c;
+        if (c < (int)blockDim.x) break;
+    }
+    return count;
 }
 
-// Batched panels: grid.z = 3 x scene + panel (as panels_kernel), grid.y = (layer, level),
-// grid.x = chunks.
+// Batched panels.  Every scene's planning kernel numbers its panel work in a unit
+// table, kind-major (entry k D L + t starts kind k of (layer, level) t: every
+// (layer, level)'s second-contraction fringe tasks, then the first contraction's,
+// then the coefficient units of kCbUnit elements), and scene_units numbers the
+// scenes' units one after the other.  Workgroup w takes units w, w + grid,
+// w + 2 grid, ...: no workgroup is launched for an empty scene, (layer, level) or
+// panel (a dense grid of upper bounds over 64 scenes of uneven size launched
+// about 150 thousand mostly idle workgroups), and the ones resident at one time
+// take neighbouring units.
 template <int P>
 __global__ __launch_bounds__(256) void panels_batch_kernel(const PrepScene* __restrict__ scenes,
-                                                           int levels) {
-    const PrepScene& sc = scenes[blockIdx.z / 3];
-    if ((int)blockIdx.y >= sc.layers * levels) return;
-    const int panel = blockIdx.z % 3, dl = blockIdx.y;
-    if (panel == 0) second_fringe_block<P>(sc.lut_x, sc.lut_y, sc.b, sc.ny, sc.nx, levels, dl);
-    else if (panel == 1) first_fringe_block<P>(sc.lut_x, sc.lut_y, sc.b, sc.ny, sc.nx, levels, dl);
-    else cb_block<P>(sc.coef, sc.b, sc.ny, sc.nx, levels, dl);
+                                                           int n_scenes, int levels,
+                                                           const int* __restrict__ scene_units) {
+    __shared__ float lre[kFringeRows * kFringePitch], lim[kFringeRows * kFringePitch];
+    const int total = scene_units[n_scenes];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int i = count_le(scene_units, n_scenes, u) - 1;
+        const PrepScene& sc = scenes[i];
+        const int v = u - scene_units[i], n_dl = sc.layers * levels;
+        const int p = count_le(sc.b.units, 3 * n_dl, v) - 1;
+        const int kind = p / n_dl, dl = p - kind * n_dl, local = v - sc.b.units[p];
+        const DlPlan g = load_dl(sc.b, levels, dl);
+        if (kind < 2) {
+            const FringeOp f = kind == 0 ? second_fringe(sc, levels, g)
+                                         : first_fringe(sc, levels, g);
+            run_fringe_task<P>(f, g.l, local, lre, lim);
+        } else {
+            const long long e4 = (long long)local * (kCbUnit / 4) + threadIdx.x;
+            if (e4 < cb_chunks(g)) cb_chunk<P>(sc, levels, g, sc.b.hdr->cb_scale, e4);
+        }
+    }
 }
 
-int grid_for(long long elems) {
-    long long g = (elems + 256 * 8 - 1) / (256 * 8);
-    if (g < 1) g = 1;
-    if (g > 512) g = 512;
-    return (int)g;
+// Workgroups per (layer, level) and panel of the single-scene launch.
+constexpr int kPanelBlocks = 128;
+// Workgroups of the batched launch: four per CU (the LDS tile bounds residency).
+constexpr int kPanelGrid = 1024;
+
+int panel_grid(long long units_bound) {
+    return (int)(units_bound < 1 ? 1 : (units_bound < kPanelGrid ? units_bound : kPanelGrid));
 }
 
 }  // namespace
@@ -476,6 +585,7 @@ PlanArgs make_plan_args(int ny, int nx, int layers, int levels, int precision, c
     a.cnt_col = b.cnt_col;
     a.seg_row = b.seg_row;
     a.orient = b.orient;
+    a.units = b.units;
     a.tbeg = b.tbeg;
     a.hdr = b.hdr;
     a.first = b.first;
@@ -513,30 +623,36 @@ hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int 
 template <int P>
 static hipError_t materialize(const float* coef, const float* lut_x, const float* lut_y, int ny,
                               int nx, int layers, int levels, const NtBuffers& b, hipStream_t s) {
-    const int n_dl = layers * levels;
-    const long long big_y = (long long)ny * pad_kt(band_side(ny, 1));
-    const long long big_x = (long long)nx * pad_kt(band_side(nx, 1));
-    const long long big_c = (long long)dl_coef_elems(ny, nx, 1);
-    // fringe panels: one workgroup per 256 rows x 16 K = 4096 elements (grid_for sizes for
-    // 2048); the coefficient panel four elements per thread; all three in one launch
-    int gx = grid_for(big_y / 2);
-    if (grid_for(big_x / 2) > gx) gx = grid_for(big_x / 2);
-    if (grid_for(big_c) > gx) gx = grid_for(big_c);
-    hipLaunchKernelGGL(panels_kernel<P>, dim3(gx, n_dl, 3), dim3(256), 0, s, coef, lut_x, lut_y,
-                       ny, nx, levels, b);
+    PrepScene sc{};
+    sc.coef = coef;
+    sc.lut_x = lut_x;
+    sc.lut_y = lut_y;
+    sc.ny = ny;
+    sc.nx = nx;
+    sc.layers = layers;
+    sc.b = b;
+    // workgroups per (layer, level) and panel: the largest dense task or chunk
+    // count of one (layer, level), capped
+    long long most = 1;
+    for (int l = 1; l <= levels; ++l) {
+        int u[3];
+        dl_panel_units(ny, nx, band_side(ny, l), band_side(nx, l), u);
+        const long long fringe = u[0] > u[1] ? u[0] : u[1];
+        const long long chunks = ((long long)u[2] * kCbUnit / 4 + 255) / 256;
+        if (fringe > most) most = fringe;
+        if (chunks > most) most = chunks;
+    }
+    const int gx = (int)(most < kPanelBlocks ? most : kPanelBlocks);
+    hipLaunchKernelGGL(panels_kernel<P>, dim3(gx, layers * levels, 3), dim3(256), 0, s, sc,
+                       levels);
     return hipGetLastError();
 }
 
-// Workgroups per (scene, layer, level) of the batched panel kernels: the scenes
-// already give the launch its parallelism (a grid sized for the largest scene
-// left most workgroups idle: measured 30% slower preparation on the 64-scene batch).
-constexpr int kBatchPanelBlocks = 64;
-
 template <int P>
-static void materialize_batch(const PrepScene* scenes, int n, int levels, int max_ndl,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(panels_batch_kernel<P>, dim3(kBatchPanelBlocks, max_ndl, 3 * n),
-                       dim3(256), 0, s, scenes, levels);
+static void materialize_batch(const PrepScene* scenes, int n, int levels, const int* scene_units,
+                              long long units_bound, hipStream_t s) {
+    hipLaunchKernelGGL(panels_batch_kernel<P>, dim3(panel_grid(units_bound)), dim3(256), 0, s,
+                       scenes, n, levels, scene_units);
 }
 
 hipError_t launch_lists_batch(const PrepScene* scenes, int n, int levels, int max_ndl,
@@ -551,18 +667,19 @@ hipError_t launch_plan_batch(const PlanArgs* args, int n, int max_ndl, hipStream
 }
 
 hipError_t launch_materialize_batch(const PrepScene* scenes, int n, int levels, int precision,
-                                    int max_ndl, hipStream_t s) {
-    if (precision == P_BF16) materialize_batch<P_BF16>(scenes, n, levels, max_ndl, s);
-    else if (precision == P_FP16) materialize_batch<P_FP16>(scenes, n, levels, max_ndl, s);
-    else materialize_batch<P_FP32>(scenes, n, levels, max_ndl, s);
+                                    const int* scene_units, long long units_bound,
+                                    hipStream_t s) {
+    if (precision == P_BF16) materialize_batch<P_BF16>(scenes, n, levels, scene_units, units_bound, s);
+    else if (precision == P_FP16) materialize_batch<P_FP16>(scenes, n, levels, scene_units, units_bound, s);
+    else materialize_batch<P_FP32>(scenes, n, levels, scene_units, units_bound, s);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_prefix(const PlanHeader* hdrs, int n_scenes, const int* first_off,
                                NtEntry* first, NtEntry* second, int* counts, int* queues,
-                               hipStream_t s) {
+                               int* scene_units, hipStream_t s) {
     hipLaunchKernelGGL(batch_prefix_kernel, dim3(1), dim3(1024), 0, s, hdrs, n_scenes, first_off,
-                       first, second, counts, queues);
+                       first, second, counts, queues, scene_units);
     return hipGetLastError();
 }
 
