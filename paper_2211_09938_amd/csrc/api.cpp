@@ -92,8 +92,12 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
             return cgh::launch_nt_first(n_layers, levels, precision, nb, lo.first_tiles_max, s);
         });
     if (e == hipSuccess)
-        e = timed(s, CGH_STAGE_SECOND,
-                  [&] { return cgh::launch_nt_second(ny, nx, precision, split, nb, s); });
+        e = timers ? cgh::host::kernel_timed(CGH_STAGE_SECOND,
+                                             [&](hipEvent_t t0, hipEvent_t t1) {
+                                                 return cgh::launch_nt_second(
+                                                     ny, nx, precision, split, nb, s, t0, t1);
+                                             })
+                   : cgh::launch_nt_second(ny, nx, precision, split, nb, s);
     if (e == hipSuccess && split > 1)
         e = timed(s, CGH_STAGE_REDUCE,
                   [&] { return cgh::launch_reduce_partial(ny, nx, split, partial, out, acc, s); });
