@@ -69,11 +69,9 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
     fringe_scale(op, n_layers, precision, fs);
     if (e == hipSuccess && with_luts)
         e = timed(s, CGH_STAGE_LUT, [&] {
-            hipError_t r = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
-                                            reinterpret_cast<float*>(ws + lo.lut_x), s);
-            if (r != hipSuccess) return r;
-            return cgh::launch_luts(ny, n_layers, levels, 1, op.c, fs.re, fs.im,
-                                    reinterpret_cast<float*>(ws + lo.lut_y), s);
+            return cgh::launch_luts_xy(nx, ny, n_layers, levels, op.c, op.one_re, op.one_im,
+                                       reinterpret_cast<float*>(ws + lo.lut_x), fs.re, fs.im,
+                                       reinterpret_cast<float*>(ws + lo.lut_y), s);
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_PLAN, [&] {
@@ -92,12 +90,8 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
             return cgh::launch_nt_first(n_layers, levels, precision, nb, lo.first_tiles_max, s);
         });
     if (e == hipSuccess)
-        e = timers ? cgh::host::kernel_timed(CGH_STAGE_SECOND,
-                                             [&](hipEvent_t t0, hipEvent_t t1) {
-                                                 return cgh::launch_nt_second(
-                                                     ny, nx, precision, split, nb, s, t0, t1);
-                                             })
-                   : cgh::launch_nt_second(ny, nx, precision, split, nb, s);
+        e = timed(s, CGH_STAGE_SECOND,
+                  [&] { return cgh::launch_nt_second(ny, nx, precision, split, nb, s); });
     if (e == hipSuccess && split > 1)
         e = timed(s, CGH_STAGE_REDUCE,
                   [&] { return cgh::launch_reduce_partial(ny, nx, split, partial, out, acc, s); });
@@ -322,11 +316,9 @@ int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_
                                      lo.flags_layer, nullptr,
                                      reinterpret_cast<unsigned long long*>(ws + lo.ops), s);
         if (e == hipSuccess)
-            e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
-                                 reinterpret_cast<float*>(ws + lo.lut_x), s);
-        if (e == hipSuccess)
-            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, fs.re, fs.im,
-                                 reinterpret_cast<float*>(ws + lo.lut_y), s);
+            e = cgh::launch_luts_xy(nx, ny, n_layers, levels, op.c, op.one_re, op.one_im,
+                                    reinterpret_cast<float*>(ws + lo.lut_x), fs.re, fs.im,
+                                    reinterpret_cast<float*>(ws + lo.lut_y), s);
         if (e == hipSuccess) {
             const cgh::LitTables tb{op.c, op.one_re, op.one_im, fs.re, fs.im};
             e = cgh::launch_literal(reinterpret_cast<const float*>(ws + lo.coef),
@@ -471,11 +463,9 @@ int cgh_hologram_backward(const float* grad_hologram, const uint8_t* layer_index
         if (precision == CGH_FP16_SPLIT)
             e = cgh::launch_fill_u8(reinterpret_cast<uint8_t*>(absmax), 8, s);
         if (e == hipSuccess)
-            e = cgh::launch_luts(nx, n_layers, levels, 1, op.c, op.one_re, op.one_im,
-                                 reinterpret_cast<float*>(ws + lo.lut_x), s);
-        if (e == hipSuccess)
-            e = cgh::launch_luts(ny, n_layers, levels, 1, op.c, fs.re, fs.im,
-                                 reinterpret_cast<float*>(ws + lo.lut_y), s);
+            e = cgh::launch_luts_xy(nx, ny, n_layers, levels, op.c, op.one_re, op.one_im,
+                                    reinterpret_cast<float*>(ws + lo.lut_x), fs.re, fs.im,
+                                    reinterpret_cast<float*>(ws + lo.lut_y), s);
         if (e == hipSuccess)
             e = cgh::launch_backward_nt(reinterpret_cast<const float2*>(grad_hologram),
                                         reinterpret_cast<const float*>(ws + lo.lut_x),

@@ -314,39 +314,6 @@ inline hipError_t timed(hipStream_t s, int stage, F&& f) {
     return e;
 }
 
-// A stage of one kernel launched with hipExtLaunchKernel: f(start, stop) passes the
-// pair to the launch, which stamps the kernel's own start and end into them, so the
-// stage's time is the kernel's alone and no marker is queued beside it.  Both are
-// null when the stage is not being timed.
-template <class F>
-inline hipError_t kernel_timed(int stage, F&& f) {
-    Profiler& p = profiler();
-    hipEvent_t a = nullptr, b = nullptr;
-    {
-        std::lock_guard<std::mutex> g(p.mu);
-        if (p.on && ((p.mask >> stage) & 1u)) {
-            a = p.take();
-            b = p.take();
-            if (!a || !b) {
-                if (a) p.pool.push_back(a);
-                if (b) p.pool.push_back(b);
-                a = b = nullptr;
-            }
-        }
-    }
-    const hipError_t e = f(a, b);
-    if (a) {
-        std::lock_guard<std::mutex> g(p.mu);
-        if (e == hipSuccess) {
-            p.pending.push_back({stage, a, b});
-        } else {
-            p.pool.push_back(a);
-            p.pool.push_back(b);
-        }
-    }
-    return e;
-}
-
 
 }  // namespace host
 }  // namespace cgh

@@ -61,6 +61,26 @@ __global__ __launch_bounds__(256) void lut_kernel(int n_pix, int d0, int levels,
               blockIdx.y, table);
 }
 
+// Both axes' level tables of up to kLayerChunk layers in one launch: grid.z =
+// 2 x layer + axis (0: x, 1: y); the axes share the phase constant and differ in
+// their layer constants and lengths.
+struct AxisConsts {
+    double c[kLayerChunk];
+    double pre_re[2][kLayerChunk];
+    double pre_im[2][kLayerChunk];
+};
+
+__global__ __launch_bounds__(256) void lut_xy_kernel(int nx, int ny, int d0, int levels,
+                                                     AxisConsts ac, float* __restrict__ table_x,
+                                                     float* __restrict__ table_y) {
+    const int axis = blockIdx.z & 1, dl = blockIdx.z >> 1;
+    const int n_pix = axis ? ny : nx;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= lut_len(n_pix)) return;
+    lut_entry(n_pix, d0 + dl, levels, 1, ac.c[dl], ac.pre_re[axis][dl], ac.pre_im[axis][dl], idx,
+              blockIdx.y, axis ? table_y : table_x);
+}
+
 // Every (scene, layer, axis) table set of a batch: grid.z = job.
 __global__ __launch_bounds__(256) void lut_batch_kernel(const LutJob* __restrict__ jobs,
                                                         int job0) {
@@ -99,6 +119,31 @@ hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double
         }
         dim3 grid((len + 255) / 256, combos, nd);
         hipLaunchKernelGGL(lut_kernel, grid, dim3(256), 0, s, n_pix, d0, levels, lmin, lc, table);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_luts_xy(int nx, int ny, int layers, int levels, const double* c,
+                          const double* x_re, const double* x_im, float* table_x,
+                          const double* y_re, const double* y_im, float* table_y,
+                          hipStream_t s) {
+    const int len = lut_len(nx > ny ? nx : ny);
+    for (int d0 = 0; d0 < layers; d0 += kLayerChunk) {
+        const int nd = (layers - d0 < kLayerChunk) ? layers - d0 : kLayerChunk;
+        AxisConsts ac;
+        for (int k = 0; k < kLayerChunk; ++k) {
+            const int d = d0 + (k < nd ? k : 0);
+            ac.c[k] = c[d];
+            ac.pre_re[0][k] = x_re[d];
+            ac.pre_im[0][k] = x_im[d];
+            ac.pre_re[1][k] = y_re[d];
+            ac.pre_im[1][k] = y_im[d];
+        }
+        dim3 grid((len + 255) / 256, 2 * levels, 2 * nd);
+        hipLaunchKernelGGL(lut_xy_kernel, grid, dim3(256), 0, s, nx, ny, d0, levels, ac, table_x,
+                           table_y);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -293,9 +293,8 @@ hipError_t launch_nt_ring_table(int precision, const NtEntry* entries, int n_ent
                                 const int* tile_count, int max_tiles, hipStream_t s);
 hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffers& b,
                            int max_tiles, hipStream_t s);
-// t0, t1: optional events that receive the kernel's own start and end time.
 hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBuffers& b,
-                            hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                            hipStream_t s);
 // Persistent launch over a batched table: `grid` workgroups pull tiles from
 // *queue (zeroed by the caller) until *tile_count is reached.
 hipError_t launch_nt_persistent(bool second, int precision, int tile_m, int tile_n,

@@ -23,8 +23,6 @@
 // The single-scene second contraction of the split forms has a kernel of its
 // own (nt_pp_kernel, one workgroup per CU, operands global -> LDS by direct
 // loads into a three-stage ring); see its comment.
-#include <hip/hip_ext.h>
-
 #include "nt.h"
 #include "split.h"
 
@@ -825,26 +823,19 @@ hipError_t first_direct(int layers, int levels, const NtBuffers& b, int max_tile
     return hipGetLastError();
 }
 
-// The second contraction's launches take an optional event pair: the extended
-// launch stamps the kernel's own start and end into them (no separate marker on
-// the stream), which is how stage timing measures this kernel.
 template <int P, int TN>
-hipError_t second_direct(int ny, int nx, int split, const NtBuffers& b, hipStream_t s,
-                         hipEvent_t t0, hipEvent_t t1) {
+hipError_t second_direct(int ny, int nx, int split, const NtBuffers& b, hipStream_t s) {
     const int tiles = nt_tiles(ny, nx, 128, TN);
-    hipExtLaunchKernelGGL((nt_direct_kernel<P, true, SecondEpi, 128, TN>), dim3(tiles * split),
-                          dim3(256), 0, s, t0, t1, 0, (const NtEntry*)b.second, 1,
-                          (const int*)&b.hdr->second_tiles, split);
+    hipLaunchKernelGGL((nt_direct_kernel<P, true, SecondEpi, 128, TN>), dim3(tiles * split),
+                       dim3(256), 0, s, b.second, 1, &b.hdr->second_tiles, split);
     return hipGetLastError();
 }
 
 template <int P>
-hipError_t second_pp(int ny, int nx, int split, const NtBuffers& b, hipStream_t s,
-                     hipEvent_t t0, hipEvent_t t1) {
+hipError_t second_pp(int ny, int nx, int split, const NtBuffers& b, hipStream_t s) {
     const int tiles = nt_tiles(ny, nx, PpShape::TM, PpShape::TN);
-    hipExtLaunchKernelGGL((nt_pp_kernel<P, SecondEpi>), dim3(tiles * split), dim3(256), 0, s, t0,
-                          t1, 0, (const NtEntry*)b.second, 1, (const int*)&b.hdr->second_tiles,
-                          split);
+    hipLaunchKernelGGL((nt_pp_kernel<P, SecondEpi>), dim3(tiles * split), dim3(256), 0, s,
+                       b.second, 1, &b.hdr->second_tiles, split);
     return hipGetLastError();
 }
 
@@ -880,10 +871,10 @@ hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffer
 }
 
 hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBuffers& b,
-                            hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-    if (precision == P_BF16) return second_pp<P_BF16>(ny, nx, split, b, s, t0, t1);
-    if (precision == P_FP16) return second_pp<P_FP16>(ny, nx, split, b, s, t0, t1);
-    return second_direct<P_FP32, 64>(ny, nx, split, b, s, t0, t1);
+                            hipStream_t s) {
+    if (precision == P_BF16) return second_pp<P_BF16>(ny, nx, split, b, s);
+    if (precision == P_FP16) return second_pp<P_FP16>(ny, nx, split, b, s);
+    return second_direct<P_FP32, 64>(ny, nx, split, b, s);
 }
 
 namespace {

@@ -115,16 +115,19 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
         const int ik = block_scan_incl(seg, sh);
         const int it = block_scan_incl(tiles, sh);
         const int ia = block_scan_incl(act, sh);
-        const int iu0 = block_scan_incl(pu[0], sh);
-        const int iu1 = block_scan_incl(pu[1], sh);
-        const int iu2 = block_scan_incl(pu[2], sh);
+        // the unit table only where a batched gather reads it (a.units is uniform)
+        const int iu0 = a.units ? block_scan_incl(pu[0], sh) : 0;
+        const int iu1 = a.units ? block_scan_incl(pu[1], sh) : 0;
+        const int iu2 = a.units ? block_scan_incl(pu[2], sh) : 0;
         if (t < n_dl) {
             a.seg_row[t] = total_k + ik - seg;
             a.tbeg[t] = total_t + it - tiles;
-            // kind-local starts; the kinds' bases are added once their totals are known
-            a.units[t] = total_u0 + iu0 - pu[0];
-            a.units[n_dl + t] = total_u1 + iu1 - pu[1];
-            a.units[2 * n_dl + t] = total_u2 + iu2 - pu[2];
+            if (a.units) {
+                // kind-local starts; the kinds' bases are added once their totals are known
+                a.units[t] = total_u0 + iu0 - pu[0];
+                a.units[n_dl + t] = total_u1 + iu1 - pu[1];
+                a.units[2 * n_dl + t] = total_u2 + iu2 - pu[2];
+            }
         }
         if (threadIdx.x == blockDim.x - 1) {
             last[0] = ik;
@@ -147,7 +150,7 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
     // fringe tasks, then the first contraction's, then the coefficient units): the
     // workgroups resident at one time then write one panel (each thread adds the
     // bases to the entries it wrote above)
-    for (int t = threadIdx.x; t < n_dl; t += blockDim.x) {
+    for (int t = threadIdx.x; a.units && t < n_dl; t += blockDim.x) {
         a.units[n_dl + t] += total_u0;
         a.units[2 * n_dl + t] += total_u0 + total_u1;
     }
@@ -210,7 +213,7 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
         a.hdr->second_tiles = nt_tiles(a.ny, a.nx, a.tm2, a.tn2);
         a.hdr->cb_scale = cb_scale;
         a.hdr->panel_units = total_u;
-        a.units[3 * n_dl] = total_u;
+        if (a.units) a.units[3 * n_dl] = total_u;
         NtEntry e;
         e.a = a.fy;
         e.b = a.tc;
@@ -613,8 +616,9 @@ hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int 
                        flags_layer, b.rowlist, b.collist, b.cnt_row, b.cnt_col);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const PlanArgs a = make_plan_args(ny, nx, layers, levels, precision, tiles, b, o, absmax,
-                                      e_fringe);
+    PlanArgs a = make_plan_args(ny, nx, layers, levels, precision, tiles, b, o, absmax,
+                                e_fringe);
+    a.units = nullptr;  // the single-scene gather does not number its work
     // one wave scans up to 64 (layer, level) pairs without a workgroup barrier's cost
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(n_dl <= 64 ? 64 : 1024), 0, s, a);
     return hipGetLastError();
