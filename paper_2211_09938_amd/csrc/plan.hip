@@ -487,10 +487,11 @@ __device__ __forceinline__ long long cb_chunks(const DlPlan& g) {
 // second contraction's fringe operand, 1 the first contraction's, 2 the coefficient
 // operand), grid.y the (layer, level), grid.x strides over its tasks or chunks.
 // The dispatcher hands out the workgroups in that order, so those resident at one
-// time write neighbouring parts of one panel.  grid.x is at most kPanelBlocks: the
-// grid is sized for dense upper bounds, and a workgroup with nothing to do still
-// holds its LDS until its counts arrive (512 per (layer, level) and panel measured
-// 85 us at 2048^2 x 8 layers, 128 measured 63 us, 32 measured 82 us).
+// time write neighbouring parts of one panel.  The grid is sized for dense upper
+// bounds, and a workgroup with nothing to do still holds its LDS until its counts
+// arrive, so grid.x shares about kPanelGridTotal workgroups among the (layer, level)
+// and panel pairs (at 2048^2 x 8 layers, 24 pairs: 512 per pair measured 85 us, 128
+// measured 63 us, 32 measured 82 us).
 template <int P>
 __global__ __launch_bounds__(256) void panels_kernel(PrepScene sc, int levels) {
     __shared__ float lre[kFringeRows * kFringePitch], lim[kFringeRows * kFringePitch];
@@ -557,8 +558,9 @@ __global__ __launch_bounds__(256) void panels_batch_kernel(const PrepScene* __re
     }
 }
 
-// Workgroups per (layer, level) and panel of the single-scene launch.
-constexpr int kPanelBlocks = 128;
+// Workgroups of the single-scene launch, shared among its (layer, level) and panel
+// pairs (each pair between 32 and 512).
+constexpr int kPanelGridTotal = 9216;
 // Workgroups of the batched launch: four per CU (the LDS tile bounds residency).
 constexpr int kPanelGrid = 1024;
 
@@ -635,8 +637,8 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
     sc.nx = nx;
     sc.layers = layers;
     sc.b = b;
-    // workgroups per (layer, level) and panel: the largest dense task or chunk
-    // count of one (layer, level), capped
+    // workgroups per (layer, level) and panel: the share of kPanelGridTotal, at most
+    // the largest dense task or chunk count of one (layer, level)
     long long most = 1;
     for (int l = 1; l <= levels; ++l) {
         int u[3];
@@ -646,7 +648,9 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
         if (fringe > most) most = fringe;
         if (chunks > most) most = chunks;
     }
-    const int gx = (int)(most < kPanelBlocks ? most : kPanelBlocks);
+    int share = kPanelGridTotal / (3 * layers * levels);
+    share = share < 32 ? 32 : (share > 512 ? 512 : share);
+    const int gx = (int)(most < share ? most : share);
     hipLaunchKernelGGL(panels_kernel<P>, dim3(gx, layers * levels, 3), dim3(256), 0, s, sc,
                        levels);
     return hipGetLastError();
