@@ -54,6 +54,7 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
     const float* lut_y = reinterpret_cast<const float*>(ws + lo.lut_y);
     float2* partial = reinterpret_cast<float2*>(ws + lo.partial);
     const int tn2 = cgh::nt_second_tile_n(precision);
+    const int tn1 = cgh::nt_first_tile_n(ny, nx, n_layers, levels, precision);
     const int split = second_split(lo, ny, nx, levels, n_layers, precision);
 
     hipError_t e = timed(s, CGH_STAGE_COEF, [&] {
@@ -75,7 +76,7 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_PLAN, [&] {
-            const int tiles[4] = {cgh::nt_first_tile_m(precision), cgh::kNtTile,
+            const int tiles[4] = {cgh::nt_first_tile_m(precision), tn1,
                                   cgh::nt_second_tile_m(precision), tn2};
             const cgh::NtOutput o{out, split > 1 ? partial : nullptr, acc};
             hipError_t r = cgh::launch_nt_plan(
@@ -87,7 +88,8 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_FIRST, [&] {
-            return cgh::launch_nt_first(n_layers, levels, precision, nb, lo.first_tiles_max, s);
+            return cgh::launch_nt_first(n_layers, levels, precision, nb, lo.first_tiles_max, tn1,
+                                        s);
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_SECOND,

@@ -282,6 +282,9 @@ hipError_t launch_nt_materialize(const float* coef, const float* lut_x, const fl
 // three-product complex form, two workgroups per CU), 256 x 128 for the split
 // forms (one workgroup per CU, two LDS stages).
 int nt_first_tile_m(int precision);
+// Columns of the first contraction's tile for a single scene: 64 on scenes small enough
+// that 128-column tiles would leave most compute units idle, else 128.
+int nt_first_tile_n(int ny, int nx, int layers, int levels, int precision);
 int nt_second_tile_m(int precision);
 int nt_second_tile_n(int precision);
 // The split forms' ring kernel over a table of second contractions (a batch of
@@ -292,7 +295,7 @@ int nt_ring_tile_n();
 hipError_t launch_nt_ring_table(int precision, const NtEntry* entries, int n_entries,
                                 const int* tile_count, int max_tiles, hipStream_t s);
 hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffers& b,
-                           int max_tiles, hipStream_t s);
+                           int max_tiles, int tile_n, hipStream_t s);
 hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBuffers& b,
                             hipStream_t s);
 // Persistent launch over a batched table: `grid` workgroups pull tiles from

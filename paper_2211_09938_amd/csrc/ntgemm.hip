@@ -810,16 +810,20 @@ hipError_t persistent_shape(int tm, int tn, const NtEntry* entries, int n_entrie
     return hipErrorInvalidValue;
 }
 
+template <int P, int TM, int TN>
+void first_direct_shape(int layers, int levels, const NtBuffers& b, int max_tiles, hipStream_t s) {
+    hipLaunchKernelGGL((nt_direct_kernel<P, false, FirstEpi<P>, TM, TN>), dim3(max_tiles),
+                       dim3(256), 0, s, b.first, layers * levels, &b.hdr->first_tiles, 1);
+}
+
 template <int P>
 hipError_t first_direct(int layers, int levels, const NtBuffers& b, int max_tiles, int tile_m,
-                        hipStream_t s) {
+                        int tile_n, hipStream_t s) {
     if (max_tiles <= 0) return hipSuccess;
-    if (tile_m == 64)
-        hipLaunchKernelGGL((nt_direct_kernel<P, false, FirstEpi<P>, 64, 128>), dim3(max_tiles),
-                           dim3(256), 0, s, b.first, layers * levels, &b.hdr->first_tiles, 1);
-    else
-        hipLaunchKernelGGL((nt_direct_kernel<P, false, FirstEpi<P>, 128, 128>), dim3(max_tiles),
-                           dim3(256), 0, s, b.first, layers * levels, &b.hdr->first_tiles, 1);
+    if (tile_m == 64 && tile_n == 64) first_direct_shape<P, 64, 64>(layers, levels, b, max_tiles, s);
+    else if (tile_m == 64) first_direct_shape<P, 64, 128>(layers, levels, b, max_tiles, s);
+    else if (tile_n == 64) first_direct_shape<P, 128, 64>(layers, levels, b, max_tiles, s);
+    else first_direct_shape<P, 128, 128>(layers, levels, b, max_tiles, s);
     return hipGetLastError();
 }
 
@@ -842,6 +846,21 @@ hipError_t second_pp(int ny, int nx, int split, const NtBuffers& b, hipStream_t 
 }  // namespace
 
 int nt_first_tile_m(int precision) { return precision == P_FP32 ? 64 : 128; }
+
+// 128-column tiles unless the scene is small: at most 512 tiles (two workgroups per
+// CU) even with every row and column active, in either contraction order; 64-column
+// tiles then give the launch twice the workgroups.
+int nt_first_tile_n(int ny, int nx, int layers, int levels, int precision) {
+    const int tm = nt_first_tile_m(precision);
+    long long tiles = 0;
+    for (int l = 1; l <= levels; ++l) {
+        const long long syl = band_side(ny, l), sxl = band_side(nx, l);
+        const long long r = (syl + tm - 1) / tm * ((nx + 127) / 128);
+        const long long c = (sxl + tm - 1) / tm * ((ny + 127) / 128);
+        tiles += r > c ? r : c;
+    }
+    return tiles * layers < 512 ? 64 : 128;
+}
 int nt_ring_tile_m() { return PpShape::TM; }
 int nt_ring_tile_n() { return PpShape::TN; }
 
@@ -863,11 +882,11 @@ int nt_second_tile_m(int precision) { return precision == P_FP32 ? 128 : PpShape
 int nt_second_tile_n(int precision) { return precision == P_FP32 ? 64 : 128; }
 
 hipError_t launch_nt_first(int layers, int levels, int precision, const NtBuffers& b,
-                           int max_tiles, hipStream_t s) {
+                           int max_tiles, int tile_n, hipStream_t s) {
     const int tm = nt_first_tile_m(precision);
-    if (precision == P_BF16) return first_direct<P_BF16>(layers, levels, b, max_tiles, tm, s);
-    if (precision == P_FP16) return first_direct<P_FP16>(layers, levels, b, max_tiles, tm, s);
-    return first_direct<P_FP32>(layers, levels, b, max_tiles, tm, s);
+    if (precision == P_BF16) return first_direct<P_BF16>(layers, levels, b, max_tiles, tm, tile_n, s);
+    if (precision == P_FP16) return first_direct<P_FP16>(layers, levels, b, max_tiles, tm, tile_n, s);
+    return first_direct<P_FP32>(layers, levels, b, max_tiles, tm, tile_n, s);
 }
 
 hipError_t launch_nt_second(int ny, int nx, int precision, int split, const NtBuffers& b,
