@@ -57,22 +57,30 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
     const int tn1 = cgh::nt_first_tile_n(ny, nx, n_layers, levels, precision);
     const int split = second_split(lo, ny, nx, levels, n_layers, precision);
 
-    hipError_t e = timed(s, CGH_STAGE_COEF, [&] {
-        hipError_t r = cgh::launch_fill_u8(fl, lo.flags_fill, s);
-        if (r != hipSuccess) return r;
-        // sparse coefficient planes: the panel gather consults the occupancy bytes
-        return cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels, thr,
-                                    parts, reinterpret_cast<float*>(ws + lo.coef), fl,
-                                    lo.flags_layer, reinterpret_cast<uint8_t*>(ws + lo.occ),
-                                    reinterpret_cast<unsigned long long*>(ws + lo.ops), s);
-    });
     FringeScale fs;
     fringe_scale(op, n_layers, precision, fs);
-    if (e == hipSuccess && with_luts)
+    // The fringe tables do not depend on the object: their launch comes first and also
+    // clears the flags and counters that the coefficient stage sets (one launch fewer).
+    // Without it a fill clears them.
+    hipError_t e = hipSuccess;
+    if (with_luts)
         e = timed(s, CGH_STAGE_LUT, [&] {
             return cgh::launch_luts_xy(nx, ny, n_layers, levels, op.c, op.one_re, op.one_im,
                                        reinterpret_cast<float*>(ws + lo.lut_x), fs.re, fs.im,
-                                       reinterpret_cast<float*>(ws + lo.lut_y), s);
+                                       reinterpret_cast<float*>(ws + lo.lut_y), fl, lo.flags_fill,
+                                       s);
+        });
+    if (e == hipSuccess)
+        e = timed(s, CGH_STAGE_COEF, [&] {
+            if (!with_luts) {
+                const hipError_t r = cgh::launch_fill_u8(fl, lo.flags_fill, s);
+                if (r != hipSuccess) return r;
+            }
+            // sparse coefficient planes: the panel gather consults the occupancy bytes
+            return cgh::launch_dwt_mask(object, layer_index, saliency, ny, nx, n_layers, levels,
+                                        thr, parts, reinterpret_cast<float*>(ws + lo.coef), fl,
+                                        lo.flags_layer, reinterpret_cast<uint8_t*>(ws + lo.occ),
+                                        reinterpret_cast<unsigned long long*>(ws + lo.ops), s);
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_PLAN, [&] {
@@ -320,7 +328,7 @@ int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_
         if (e == hipSuccess)
             e = cgh::launch_luts_xy(nx, ny, n_layers, levels, op.c, op.one_re, op.one_im,
                                     reinterpret_cast<float*>(ws + lo.lut_x), fs.re, fs.im,
-                                    reinterpret_cast<float*>(ws + lo.lut_y), s);
+                                    reinterpret_cast<float*>(ws + lo.lut_y), nullptr, 0, s);
         if (e == hipSuccess) {
             const cgh::LitTables tb{op.c, op.one_re, op.one_im, fs.re, fs.im};
             e = cgh::launch_literal(reinterpret_cast<const float*>(ws + lo.coef),
@@ -467,7 +475,7 @@ int cgh_hologram_backward(const float* grad_hologram, const uint8_t* layer_index
         if (e == hipSuccess)
             e = cgh::launch_luts_xy(nx, ny, n_layers, levels, op.c, op.one_re, op.one_im,
                                     reinterpret_cast<float*>(ws + lo.lut_x), fs.re, fs.im,
-                                    reinterpret_cast<float*>(ws + lo.lut_y), s);
+                                    reinterpret_cast<float*>(ws + lo.lut_y), nullptr, 0, s);
         if (e == hipSuccess)
             e = cgh::launch_backward_nt(reinterpret_cast<const float2*>(grad_hologram),
                                         reinterpret_cast<const float*>(ws + lo.lut_x),

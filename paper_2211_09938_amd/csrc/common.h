@@ -165,11 +165,12 @@ hipError_t launch_grad_synthesis(const float* gcoef, const uint8_t* layer, const
                                  hipStream_t s);
 hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double* c,
                        const double* pre_re, const double* pre_im, float* table, hipStream_t s);
-// The level tables of both axes (as two launch_luts calls with lmin 1) in one launch.
+// The level tables of both axes (as two launch_luts calls with lmin 1) in one launch;
+// clear (optional, 8-byte aligned, clear_bytes a multiple of 8) is zeroed by the same grid.
 hipError_t launch_luts_xy(int nx, int ny, int layers, int levels, const double* c,
                           const double* x_re, const double* x_im, float* table_x,
                           const double* y_re, const double* y_im, float* table_y,
-                          hipStream_t s);
+                          uint8_t* clear, size_t clear_bytes, hipStream_t s);
 // Matrix-core throughput probe (peak.hip): real flops of a launch, and the launch.
 double mfma_peak_flops(int kind, int blocks, int iters);
 hipError_t launch_mfma_peak(int kind, int zero, int blocks, int iters, float* sink, hipStream_t s);

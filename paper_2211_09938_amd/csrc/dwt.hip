@@ -69,7 +69,7 @@ __device__ __forceinline__ float pooled(const Pool<B>& p, int lev, int j, int i)
 // the layer.  With occ the coefficients of the other (layer, block) pairs, all zero,
 // are not written: readers of the coefficient planes consult occ.  Without occ
 // every plane is written in full.
-template <int L>
+template <int L, bool MASK>
 __device__ __forceinline__ float dwt_mask_body(
     const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
     int ny, int nx, int layers, float t1, float t2, float t3, unsigned parts,
@@ -152,7 +152,22 @@ __device__ __forceinline__ float dwt_mask_body(
     }
 
     const size_t blocks = (size_t)(ny >> L) * nbx;
+    // MASK (at most 32 layers): bit (index mod 32) of every pixel's layer, a superset of the
+    // layers the block holds; a layer no lane of the wave has costs only its occupancy byte.
+    unsigned pres = 0u;
+    if constexpr (MASK) {
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int c = 0; c < B; ++c) pres |= 1u << (li[r][c] & 31u);
+    }
     for (int d = 0; d < layers; ++d) {
+        if constexpr (MASK) {
+            if (__ballot((pres >> d) & 1u) == 0ull) {
+                if (occ) occ[(size_t)d * blocks + (size_t)by * nbx + bx] = 0;
+                continue;
+            }
+        }
         float cur[B][B];
         bool present = false;
 #pragma unroll
@@ -267,14 +282,14 @@ __device__ __forceinline__ float dwt_mask_body(
 
 // ops (optional): ops[0..2] operator counts, ops[4] max |object| as float bits (the
 // range of the FP16 split operands), both zeroed by the caller.
-template <int L>
+template <int L, bool MASK>
 __device__ __forceinline__ void dwt_mask_block(
     const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
     int ny, int nx, int layers, float t1, float t2, float t3, unsigned parts,
     float* __restrict__ coef, uint8_t* __restrict__ flags, size_t flags_layer,
     uint8_t* __restrict__ occ, unsigned long long* __restrict__ ops, int bx, int by) {
     unsigned long long wave_ops[3] = {0ull, 0ull, 0ull};
-    float amax = dwt_mask_body<L>(obj, layer, sal, ny, nx, layers, t1, t2, t3, parts, coef, flags,
+    float amax = dwt_mask_body<L, MASK>(obj, layer, sal, ny, nx, layers, t1, t2, t3, parts, coef, flags,
                                   flags_layer, occ, ops != nullptr, wave_ops, bx, by);
     if (ops) {
         // Counts and max |object| gathered over the workgroup first: one atomic per
@@ -305,13 +320,13 @@ __device__ __forceinline__ void dwt_mask_block(
     }
 }
 
-template <int L>
+template <int L, bool MASK>
 __global__ __launch_bounds__(256) void dwt_mask_kernel(
     const float* __restrict__ obj, const uint8_t* __restrict__ layer, const float* __restrict__ sal,
     int ny, int nx, int layers, float t1, float t2, float t3, unsigned parts,
     float* __restrict__ coef, uint8_t* __restrict__ flags, size_t flags_layer,
     uint8_t* __restrict__ occ, unsigned long long* __restrict__ ops) {
-    dwt_mask_block<L>(obj, layer, sal, ny, nx, layers, t1, t2, t3, parts, coef, flags,
+    dwt_mask_block<L, MASK>(obj, layer, sal, ny, nx, layers, t1, t2, t3, parts, coef, flags,
                       flags_layer, occ, ops, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
 }
 
@@ -321,7 +336,7 @@ __global__ __launch_bounds__(256) void dwt_mask_batch_kernel(const DwtScene* __r
                                                              float t1, float t2, float t3) {
     const DwtScene sc = scenes[blockIdx.z];
     if ((int)blockIdx.y >= (sc.ny >> L)) return;
-    dwt_mask_block<L>(sc.obj, sc.layer, sc.sal, sc.ny, sc.nx, sc.layers, t1, t2, t3, kAllParts,
+    dwt_mask_block<L, false>(sc.obj, sc.layer, sc.sal, sc.ny, sc.nx, sc.layers, t1, t2, t3, kAllParts,
                       sc.coef, sc.flags, sc.flags_layer, sc.occ, sc.ops,
                       blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
 }
@@ -502,9 +517,16 @@ static void dwt_launch(const float* obj, const uint8_t* layer, const float* sal,
                        size_t flags_layer, uint8_t* occ, unsigned long long* ops, hipStream_t s) {
     const int nbx = nx >> L;
     dim3 grid((nbx + 255) / 256, ny >> L);
-    hipLaunchKernelGGL((dwt_mask_kernel<L>), grid, dim3(256), 0, s, obj, layer, sal, ny, nx,
-                       layers, thr[0], L >= 2 ? thr[1] : 0.f, L >= 3 ? thr[2] : 0.f, parts, coef,
-                       flags, flags_layer, occ, ops);
+    // the layer mask needs at most 32 layers, and occupancy bytes to record absent layers
+    // (without them every plane is written in full)
+    if (layers <= 32 && occ)
+        hipLaunchKernelGGL((dwt_mask_kernel<L, true>), grid, dim3(256), 0, s, obj, layer, sal, ny,
+                           nx, layers, thr[0], L >= 2 ? thr[1] : 0.f, L >= 3 ? thr[2] : 0.f, parts,
+                           coef, flags, flags_layer, occ, ops);
+    else
+        hipLaunchKernelGGL((dwt_mask_kernel<L, false>), grid, dim3(256), 0, s, obj, layer, sal, ny,
+                           nx, layers, thr[0], L >= 2 ? thr[1] : 0.f, L >= 3 ? thr[2] : 0.f, parts,
+                           coef, flags, flags_layer, occ, ops);
 }
 
 hipError_t launch_dwt_mask(const float* obj, const uint8_t* layer, const float* sal, int ny, int nx,

@@ -70,9 +70,18 @@ struct AxisConsts {
     double pre_im[2][kLayerChunk];
 };
 
+// clear (optional): n8 eight-byte words zeroed by the grid beside the tables (the
+// coefficient stage's flags, which it only sets, and which it runs after).
 __global__ __launch_bounds__(256) void lut_xy_kernel(int nx, int ny, int d0, int levels,
                                                      AxisConsts ac, float* __restrict__ table_x,
-                                                     float* __restrict__ table_y) {
+                                                     float* __restrict__ table_y,
+                                                     uint2* __restrict__ clear, size_t n8) {
+    if (clear) {
+        const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        const size_t stride = (size_t)gridDim.x * gridDim.y * gridDim.z * blockDim.x;
+        for (size_t i = wg * blockDim.x + threadIdx.x; i < n8; i += stride)
+            clear[i] = make_uint2(0u, 0u);
+    }
     const int axis = blockIdx.z & 1, dl = blockIdx.z >> 1;
     const int n_pix = axis ? ny : nx;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -128,7 +137,9 @@ hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double
 hipError_t launch_luts_xy(int nx, int ny, int layers, int levels, const double* c,
                           const double* x_re, const double* x_im, float* table_x,
                           const double* y_re, const double* y_im, float* table_y,
-                          hipStream_t s) {
+                          uint8_t* clear, size_t clear_bytes, hipStream_t s) {
+    if (clear && ((reinterpret_cast<uintptr_t>(clear) & 7) || (clear_bytes & 7)))
+        return hipErrorInvalidValue;
     const int len = lut_len(nx > ny ? nx : ny);
     for (int d0 = 0; d0 < layers; d0 += kLayerChunk) {
         const int nd = (layers - d0 < kLayerChunk) ? layers - d0 : kLayerChunk;
@@ -142,8 +153,9 @@ hipError_t launch_luts_xy(int nx, int ny, int layers, int levels, const double* 
             ac.pre_im[1][k] = y_im[d];
         }
         dim3 grid((len + 255) / 256, 2 * levels, 2 * nd);
+        uint2* c8 = d0 == 0 ? reinterpret_cast<uint2*>(clear) : nullptr;
         hipLaunchKernelGGL(lut_xy_kernel, grid, dim3(256), 0, s, nx, ny, d0, levels, ac, table_x,
-                           table_y);
+                           table_y, c8, c8 ? clear_bytes / 8 : (size_t)0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
