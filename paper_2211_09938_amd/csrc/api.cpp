@@ -67,8 +67,8 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
         e = timed(s, CGH_STAGE_LUT, [&] {
             return cgh::launch_luts_xy(nx, ny, n_layers, levels, op.c, op.one_re, op.one_im,
                                        reinterpret_cast<float*>(ws + lo.lut_x), fs.re, fs.im,
-                                       reinterpret_cast<float*>(ws + lo.lut_y), fl, lo.flags_fill,
-                                       s);
+                                       reinterpret_cast<float*>(ws + lo.lut_y), ws + lo.gen_x,
+                                       ws + lo.gen_y, precision, fl, lo.flags_fill, s);
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_COEF, [&] {
@@ -92,7 +92,7 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
                 reinterpret_cast<const unsigned long long*>(ws + lo.ops) + kAbsmaxWord, fs.e, s);
             if (r != hipSuccess) return r;
             return cgh::launch_nt_materialize(coef, lut_x, lut_y, ny, nx, n_layers, levels,
-                                              precision, nb, s);
+                                              precision, nb, !cgh::nt_first_generates(tn1), s);
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_FIRST, [&] {
@@ -328,7 +328,8 @@ int cgh_literal_hologram(const float* object, const uint8_t* layer_index, int n_
         if (e == hipSuccess)
             e = cgh::launch_luts_xy(nx, ny, n_layers, levels, op.c, op.one_re, op.one_im,
                                     reinterpret_cast<float*>(ws + lo.lut_x), fs.re, fs.im,
-                                    reinterpret_cast<float*>(ws + lo.lut_y), nullptr, 0, s);
+                                    reinterpret_cast<float*>(ws + lo.lut_y), nullptr, nullptr,
+                                    0, nullptr, 0, s);
         if (e == hipSuccess) {
             const cgh::LitTables tb{op.c, op.one_re, op.one_im, fs.re, fs.im};
             e = cgh::launch_literal(reinterpret_cast<const float*>(ws + lo.coef),
@@ -475,7 +476,8 @@ int cgh_hologram_backward(const float* grad_hologram, const uint8_t* layer_index
         if (e == hipSuccess)
             e = cgh::launch_luts_xy(nx, ny, n_layers, levels, op.c, op.one_re, op.one_im,
                                     reinterpret_cast<float*>(ws + lo.lut_x), fs.re, fs.im,
-                                    reinterpret_cast<float*>(ws + lo.lut_y), nullptr, 0, s);
+                                    reinterpret_cast<float*>(ws + lo.lut_y), nullptr, nullptr,
+                                    0, nullptr, 0, s);
         if (e == hipSuccess)
             e = cgh::launch_backward_nt(reinterpret_cast<const float2*>(grad_hologram),
                                         reinterpret_cast<const float*>(ws + lo.lut_x),

@@ -25,6 +25,15 @@ __host__ __device__ inline size_t lut_table(int d, int l, int band, int part, in
     return ((size_t)(d * levels + (l - 1)) * 2 + band) * 2 + part;
 }
 
+// Operand-format fringe tables (the first contraction generates its fringe operand from
+// them): per (layer d, level l >= 1) three bands of lut_len entries of 8 bytes -- band 0,
+// band 1 (as the FP32 tables), then zeros; an entry holds both parts, FP32 (re, im) or
+// for the split forms the words hi | lo << 16 of re and of im.  Returns the index of
+// (d, l)'s band 0 in units of lut_len entries.
+__host__ __device__ inline size_t gen_table(int d, int l, int levels) {
+    return (size_t)(d * levels + (l - 1)) * 3;
+}
+
 // Offsets (in rows of s(l) for T, in bytes for flags) of level l inside one layer.
 __host__ __device__ inline size_t t_level_rows(int ny, int l) {
     size_t rows = 0;
@@ -82,6 +91,8 @@ struct Layout {
     size_t coef;                 // masked Mallat coefficients, D * ny * nx floats
     size_t lut_x, lut_y;         // FP32 fringe tables
     size_t lut0;                 // level-0 table pair (x then y) for back-propagation
+    size_t gen_x, gen_y;         // level tables in the operand format of the precision
+    size_t koff_row, koff_col;   // beside the lists: offsets into the operand-format tables
     size_t flags;                // per layer: rows then cols of every level, bytes
     size_t occ;                  // per layer: one byte per 2^levels block (coefficients written)
     size_t rowlist, collist;     // active row / column indices per (layer, level)
@@ -166,11 +177,14 @@ hipError_t launch_grad_synthesis(const float* gcoef, const uint8_t* layer, const
 hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double* c,
                        const double* pre_re, const double* pre_im, float* table, hipStream_t s);
 // The level tables of both axes (as two launch_luts calls with lmin 1) in one launch;
-// clear (optional, 8-byte aligned, clear_bytes a multiple of 8) is zeroed by the same grid.
+// gen_x, gen_y (optional): the same tables in the operand format of precision gen_prec
+// (gen_table), zero band included; clear
+// (optional, 8-byte aligned, clear_bytes a multiple of 8) is zeroed by the same grid.
 hipError_t launch_luts_xy(int nx, int ny, int layers, int levels, const double* c,
                           const double* x_re, const double* x_im, float* table_x,
                           const double* y_re, const double* y_im, float* table_y,
-                          uint8_t* clear, size_t clear_bytes, hipStream_t s);
+                          void* gen_x, void* gen_y, int gen_prec, uint8_t* clear,
+                          size_t clear_bytes, hipStream_t s);
 // Matrix-core throughput probe (peak.hip): real flops of a launch, and the launch.
 double mfma_peak_flops(int kind, int blocks, int iters);
 hipError_t launch_mfma_peak(int kind, int zero, int blocks, int iters, float* sink, hipStream_t s);

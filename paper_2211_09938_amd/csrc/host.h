@@ -70,6 +70,10 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels,
     lo.lut_x = take((size_t)layers * levels * 4 * cgh::lut_len(nx) * 4);
     lo.lut_y = take((size_t)layers * levels * 4 * cgh::lut_len(ny) * 4);
     lo.lut0 = take((size_t)(2 * cgh::lut_len(nx) + 2 * cgh::lut_len(ny)) * 4);
+    // the level tables again in the operand format (8 bytes per entry, both parts, and a
+    // zero band)
+    lo.gen_x = take((size_t)layers * levels * 3 * cgh::lut_len(nx) * 8);
+    lo.gen_y = take((size_t)layers * levels * 3 * cgh::lut_len(ny) * 8);
     lo.t_layer = 0;
     lo.flags_layer = 0;
     for (int l = 1; l <= levels; ++l) {
@@ -86,6 +90,8 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels,
     const cgh::NtSizes z = cgh::nt_sizes(ny, nx, layers, levels);
     lo.rowlist = take(z.rowlist * 4);
     lo.collist = take(z.collist * 4);
+    lo.koff_row = take(z.rowlist * 4);
+    lo.koff_col = take(z.collist * 4);
     lo.cnt_row = take((size_t)n_dl * 4);
     lo.cnt_col = take((size_t)n_dl * 4);
     lo.seg_row = take((size_t)n_dl * 4);
@@ -176,6 +182,10 @@ inline cgh::NtBuffers nt_buffers(char* ws, const cgh::Layout& lo) {
     b.cb_ps = lo.cb_ps;
     b.fy_ps = lo.fy_ps;
     b.tc_ps = lo.tc_ps;
+    b.gen_x = ws + lo.gen_x;
+    b.gen_y = ws + lo.gen_y;
+    b.koff_row = reinterpret_cast<int*>(ws + lo.koff_row);
+    b.koff_col = reinterpret_cast<int*>(ws + lo.koff_col);
     return b;
 }
 

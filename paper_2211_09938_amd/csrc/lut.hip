@@ -15,15 +15,19 @@
 // sincospi.  The sum is rounded once, to FP32 (the panel kernels round to the
 // operand precision).
 #include "common.h"
+#include "split.h"
 
 namespace cgh {
 
 namespace {
 
-// Entry idx of table (level lev(combo), band(combo)) of layer d.
+// Entry idx of table (level lev(combo), band(combo)) of layer d.  gen (optional, level
+// tables): the same entry in the operand format of precision gen_prec, both parts in
+// one 8-byte word pair -- FP32 (re, im), split forms (hi | lo << 16) of re, then of im.
 __device__ __forceinline__ void lut_entry(int n_pix, int d, int levels, int lmin, double c,
                                           double pre_re, double pre_im, int idx, int combo,
-                                          float* __restrict__ table) {
+                                          float* __restrict__ table, uint2* __restrict__ gen = nullptr,
+                                          int gen_prec = P_FP32) {
     const int len = lut_len(n_pix);
     const int lev = (lmin == 0) ? 0 : 1 + combo / 2;
     const int band = (lmin == 0) ? 0 : combo % 2;
@@ -48,8 +52,28 @@ __device__ __forceinline__ void lut_entry(int n_pix, int d, int levels, int lmin
     }
     const size_t t_re = (lmin == 0) ? (size_t)(d * 2 + 0) : lut_table(d, lev, band, 0, levels);
     const size_t t_im = (lmin == 0) ? (size_t)(d * 2 + 1) : lut_table(d, lev, band, 1, levels);
-    table[t_re * len + idx] = (float)re;
-    table[t_im * len + idx] = (float)im;
+    const float fre = (float)re, fim = (float)im;
+    table[t_re * len + idx] = fre;
+    table[t_im * len + idx] = fim;
+    if (gen && lmin != 0) {
+        uint2 w;
+        if (gen_prec == P_FP32) {
+            w = make_uint2(__float_as_uint(fre), __float_as_uint(fim));
+        } else {
+            uint16_t rh, rl, ih, il;
+            if (gen_prec == P_BF16) {
+                split16<P_BF16>(fre, rh, rl);
+                split16<P_BF16>(fim, ih, il);
+            } else {
+                split16<P_FP16>(fre, rh, rl);
+                split16<P_FP16>(fim, ih, il);
+            }
+            w = make_uint2(rh | ((unsigned)rl << 16), ih | ((unsigned)il << 16));
+        }
+        const size_t g = gen_table(d, lev, levels) * len + idx;
+        gen[g + (size_t)band * len] = w;
+        if (band == 1) gen[g + 2 * (size_t)len] = make_uint2(0u, 0u);  // the zero band
+    }
 }
 
 __global__ __launch_bounds__(256) void lut_kernel(int n_pix, int d0, int levels, int lmin,
@@ -75,6 +99,8 @@ struct AxisConsts {
 __global__ __launch_bounds__(256) void lut_xy_kernel(int nx, int ny, int d0, int levels,
                                                      AxisConsts ac, float* __restrict__ table_x,
                                                      float* __restrict__ table_y,
+                                                     uint2* __restrict__ gen_x,
+                                                     uint2* __restrict__ gen_y, int gen_prec,
                                                      uint2* __restrict__ clear, size_t n8) {
     if (clear) {
         const size_t wg = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -87,7 +113,7 @@ __global__ __launch_bounds__(256) void lut_xy_kernel(int nx, int ny, int d0, int
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= lut_len(n_pix)) return;
     lut_entry(n_pix, d0 + dl, levels, 1, ac.c[dl], ac.pre_re[axis][dl], ac.pre_im[axis][dl], idx,
-              blockIdx.y, axis ? table_y : table_x);
+              blockIdx.y, axis ? table_y : table_x, axis ? gen_y : gen_x, gen_prec);
 }
 
 // Every (scene, layer, axis) table set of a batch: grid.z = job.
@@ -137,7 +163,8 @@ hipError_t launch_luts(int n_pix, int layers, int levels, int lmin, const double
 hipError_t launch_luts_xy(int nx, int ny, int layers, int levels, const double* c,
                           const double* x_re, const double* x_im, float* table_x,
                           const double* y_re, const double* y_im, float* table_y,
-                          uint8_t* clear, size_t clear_bytes, hipStream_t s) {
+                          void* gen_x, void* gen_y, int gen_prec, uint8_t* clear,
+                          size_t clear_bytes, hipStream_t s) {
     if (clear && ((reinterpret_cast<uintptr_t>(clear) & 7) || (clear_bytes & 7)))
         return hipErrorInvalidValue;
     const int len = lut_len(nx > ny ? nx : ny);
@@ -155,7 +182,8 @@ hipError_t launch_luts_xy(int nx, int ny, int layers, int levels, const double* 
         dim3 grid((len + 255) / 256, 2 * levels, 2 * nd);
         uint2* c8 = d0 == 0 ? reinterpret_cast<uint2*>(clear) : nullptr;
         hipLaunchKernelGGL(lut_xy_kernel, grid, dim3(256), 0, s, nx, ny, d0, levels, ac, table_x,
-                           table_y, c8, c8 ? clear_bytes / 8 : (size_t)0);
+                           table_y, static_cast<uint2*>(gen_x), static_cast<uint2*>(gen_y),
+                           gen_prec, c8, c8 ? clear_bytes / 8 : (size_t)0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -55,6 +55,14 @@ struct NtEntry {
     int tile_m, tile_n;     // tile shape the table was planned for
     float out_scale;        // the epilogue multiplies the FP32 products by it (a power of
                             // two undoing FP16 range scaling, else 1)
+    // First contraction: where its B operand (the fringes of the active rows or columns
+    // it sums over) comes from for kernels that generate it instead of reading the
+    // panel at b.  g_lut: the (layer, level)'s operand-format tables (gen_table), and
+    // element (n, k'), k' < g_count, is their entry n + N + g_koff[k']; rows n >= N and
+    // k' >= g_count are zero (the zero band).
+    const void* g_lut;
+    const int* g_koff;
+    int g_count;
 };
 
 // Device-side plan written by the planning kernels (lives in the workspace).
@@ -206,6 +214,12 @@ struct NtBuffers {
     // panels (element type by precision), plane strides in elements
     void* fx; void* cb; void* fy; void* tc;
     size_t fx_ps, cb_ps, fy_ps, tc_ps;
+    // the scene's level fringe tables (x, y) in the operand format (gen_table), and
+    // beside the lists each active row's / column's offset into them (gen_koff)
+    const void* gen_x;
+    const void* gen_y;
+    int* koff_row;
+    int* koff_col;
 };
 
 // Output of the second contraction of one scene.
@@ -236,6 +250,10 @@ struct PlanArgs {
     void* fy;
     void* tc;
     long long cb_ps, fx_ps, fy_ps, tc_ps;
+    const int* koff_row;
+    const int* koff_col;
+    const void* gen_x;
+    const void* gen_y;
     float2* hologram;
     float2* partial;
     int accumulate;
@@ -272,9 +290,11 @@ hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int 
                           size_t flags_layer, int precision, const int* tiles,
                           const NtBuffers& b, const NtOutput& o,
                           const unsigned long long* absmax, int e_fringe, hipStream_t s);
+// first_panel: also gather the first contraction's fringe operand (when the first
+// contraction does not generate it, see nt_first_generates).
 hipError_t launch_nt_materialize(const float* coef, const float* lut_x, const float* lut_y, int ny,
                                  int nx, int layers, int levels, int precision,
-                                 const NtBuffers& b, hipStream_t s);
+                                 const NtBuffers& b, bool first_panel, hipStream_t s);
 // Direct launches over one scene's table (split-K for the second).
 // Row tile of the single-scene first contraction: 64 for FP32 (measured 10%
 // faster there: the active row counts of a level are often far below 128), 128
@@ -285,6 +305,9 @@ int nt_first_tile_m(int precision);
 // Columns of the first contraction's tile for a single scene: 64 on scenes small enough
 // that 128-column tiles would leave most compute units idle, else 128.
 int nt_first_tile_n(int ny, int nx, int layers, int levels, int precision);
+// Whether the single-scene first contraction with tile_n-column tiles generates its fringe
+// operand from the operand-format tables (else the panel gather writes it).
+constexpr bool nt_first_generates(int tile_n) { return tile_n == 128; }
 int nt_second_tile_m(int precision);
 int nt_second_tile_n(int precision);
 // The split forms' ring kernel over a table of second contractions (a batch of

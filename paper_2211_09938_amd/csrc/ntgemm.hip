@@ -62,6 +62,8 @@ typedef const u32x4 __attribute__((address_space(1)))* gptr_u32x4;
 __device__ __forceinline__ u32x4 gload16(const unsigned char* base, size_t byte_off) {
     return *(gptr_u32x4)(base + byte_off);
 }
+typedef const int __attribute__((address_space(1)))* gptr_int;
+__device__ __forceinline__ int gload_int(const int* base, int i) { return ((gptr_int)base)[i]; }
 
 __device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
@@ -203,8 +205,9 @@ struct RealEpi {
     }
 };
 
-// One output tile (m0, n0) of problem e over K tiles [kb, ke).
-template <int P, bool A_CPLX, class Epi, int TM, int TN, int KS>
+// One output tile (m0, n0) of problem e over K tiles [kb, ke).  GEN: the B operand is
+// generated from the fringe tables (NtEntry::g_lut) instead of read from its panel.
+template <int P, bool A_CPLX, class Epi, int TM, int TN, int KS, bool GEN = false>
 __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb, int ke, int s,
                                         int split, unsigned char* As, unsigned char* Bs) {
     using F = Fmt<P, KS>;
@@ -252,6 +255,82 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
     // a staged tile may run past the K range (ke is a multiple of 16 only):
     // chunks starting at or beyond ke read as zero
     constexpr int KPC = 16 / F::ES;  // k per 16-byte chunk
+
+    // GEN: thread = (row pair gp, rows n = n0 + 2 gp and n + 1 of the B tile; KPT
+    // consecutive k' from gk).  Entries (n, k') and (n + 1, k') of the operand-format
+    // tables are adjacent and the first is even (n, N and every offset even), so each k'
+    // is one aligned 16-byte read, and the lanes of a wave read one contiguous run.  The
+    // offsets of a K tile are read one tile ahead of the table reads that need them, so
+    // that waiting for them never waits for the loads in flight behind them.
+    constexpr int RP = TN / 2;
+    constexpr int KPT = GEN ? F::KB * RP / 256 : 2;
+    static_assert(!GEN || KPT == 2 || KPT == 4, "generated B: 2 or 4 k' per thread");
+    const int gp = tid % RP, gk = (tid / RP) * KPT;
+    u32x4 gv[KPT];
+    int gkoff[KPT];
+    auto gen_list = [&](int kt) {
+        const int k = kb + kt * F::KB + gk;
+#pragma unroll
+        for (int q = 0; q < KPT; ++q)
+            gkoff[q] = gload_int(e.g_koff, max(min(k + q, e.g_count - 1), 0));
+    };
+    auto gen_load = [&](int kt) {
+        const int k = kb + kt * F::KB + gk;
+        const int n = n0 + 2 * gp, N = e.N;
+        const unsigned char* tb = static_cast<const unsigned char*>(e.g_lut);
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            // k' past the list: the zero band; rows past N: its first entries
+            const int off = (k + q < e.g_count && k + q < ke) ? gkoff[q] : 3 * N;
+            const int idx = n < N ? n + N + off : 4 * N;
+            // in [2, 6N - 2] for every offset; clamped all the same
+            gv[q] = gload16(tb, (size_t)(min(max(idx, 0), 6 * N - 2) >> 1) * 16);
+        }
+        gen_list(kt + 1);
+    };
+    auto gen_stash = [&]() {
+        // word w of entry pair q: 0 row n re, 1 row n im, 2 row n+1 re, 3 row n+1 im
+        auto word = [&](int q, int w) -> unsigned { return gv[q][w]; };
+        unsigned char* row = Bs + (2 * gp) * F::PITCH + gk * F::ES;
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            unsigned char* pr = row + rr * F::PITCH;
+            if constexpr (P == P_FP32) {
+                // planes re, im: KPT floats each
+#pragma unroll
+                for (int part = 0; part < 2; ++part) {
+                    if constexpr (KPT == 4)
+                        *reinterpret_cast<u32x4*>(pr + part * BPLANE) =
+                            u32x4{word(0, 2 * rr + part), word(1, 2 * rr + part),
+                                  word(2, 2 * rr + part), word(3, 2 * rr + part)};
+                    else
+                        *reinterpret_cast<u32x2*>(pr + part * BPLANE) =
+                            u32x2{word(0, 2 * rr + part), word(1, 2 * rr + part)};
+                }
+            } else {
+                // an entry word is hi | lo << 16; planes re hi, re lo, im hi, im lo hold
+                // KPT halves each
+#pragma unroll
+                for (int part = 0; part < 2; ++part) {
+                    unsigned hi[KPT / 2], lo[KPT / 2];
+#pragma unroll
+                    for (int q = 0; q < KPT; q += 2) {
+                        const unsigned a = word(q, 2 * rr + part), b = word(q + 1, 2 * rr + part);
+                        hi[q / 2] = (a & 0xffffu) | (b << 16);
+                        lo[q / 2] = (a >> 16) | (b & 0xffff0000u);
+                    }
+                    unsigned char* ph = pr + (2 * part) * BPLANE;
+                    if constexpr (KPT == 4) {
+                        *reinterpret_cast<u32x2*>(ph) = u32x2{hi[0], hi[1]};
+                        *reinterpret_cast<u32x2*>(ph + BPLANE) = u32x2{lo[0], lo[1]};
+                    } else {
+                        *reinterpret_cast<unsigned*>(ph) = hi[0];
+                        *reinterpret_cast<unsigned*>(ph + BPLANE) = lo[0];
+                    }
+                }
+            }
+        }
+    };
     auto load = [&](int kt) {
         const int k0 = kb + kt * F::KB;
 #pragma unroll
@@ -267,17 +346,21 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
                 ra[u] = u32x4{0u, 0u, 0u, 0u};
             }
         }
+        if constexpr (GEN) {
+            gen_load(kt);
+        } else {
 #pragma unroll
-        for (int u = 0; u < QB; ++u) {
-            const int q = tid + 256 * u;
-            const int c = (q >> 3) % F::CPR, rl = (q & 7) + 8 * (q / (8 * F::CPR));
-            const int row = rl % TN, plane = rl / TN;
-            const int n = n0 + row;
-            if (n < e.N && (F::KB == kKT || k0 + c * KPC < ke)) {
-                const size_t el = (size_t)plane * e.b_ps + kblk_off(n, k0 + c * KPC, e.ldb);
-                rb[u] = gload16(Bb, el * F::ES);
-            } else {
-                rb[u] = u32x4{0u, 0u, 0u, 0u};
+            for (int u = 0; u < QB; ++u) {
+                const int q = tid + 256 * u;
+                const int c = (q >> 3) % F::CPR, rl = (q & 7) + 8 * (q / (8 * F::CPR));
+                const int row = rl % TN, plane = rl / TN;
+                const int n = n0 + row;
+                if (n < e.N && (F::KB == kKT || k0 + c * KPC < ke)) {
+                    const size_t el = (size_t)plane * e.b_ps + kblk_off(n, k0 + c * KPC, e.ldb);
+                    rb[u] = gload16(Bb, el * F::ES);
+                } else {
+                    rb[u] = u32x4{0u, 0u, 0u, 0u};
+                }
             }
         }
     };
@@ -289,12 +372,16 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
             const int row = rl % TM, plane = rl / TM;
             *reinterpret_cast<u32x4*>(As + plane * APLANE + row * F::PITCH + c * 16) = ra[u];
         }
+        if constexpr (GEN) {
+            gen_stash();
+        } else {
 #pragma unroll
-        for (int u = 0; u < QB; ++u) {
-            const int q = tid + 256 * u;
-            const int c = (q >> 3) % F::CPR, rl = (q & 7) + 8 * (q / (8 * F::CPR));
-            const int row = rl % TN, plane = rl / TN;
-            *reinterpret_cast<u32x4*>(Bs + plane * BPLANE + row * F::PITCH + c * 16) = rb[u];
+            for (int u = 0; u < QB; ++u) {
+                const int q = tid + 256 * u;
+                const int c = (q >> 3) % F::CPR, rl = (q & 7) + 8 * (q / (8 * F::CPR));
+                const int row = rl % TN, plane = rl / TN;
+                *reinterpret_cast<u32x4*>(Bs + plane * BPLANE + row * F::PITCH + c * 16) = rb[u];
+            }
         }
     };
 
@@ -302,6 +389,7 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
     // is free); stash the next tile and start loading the one after it; the
     // MFMAs on the registers (they cover the LDS writes and the global loads);
     // barrier (the next tile is visible).
+    if constexpr (GEN) gen_list(0);
     if (nk > 0) {
         load(0);
         stash();
@@ -460,7 +548,7 @@ struct Smem {
 };
 
 // Resolves tile t of the table and runs it (K range of split s).
-template <int P, bool A_CPLX, class Epi, int TM, int TN, int KS>
+template <int P, bool A_CPLX, class Epi, int TM, int TN, int KS, bool GEN = false>
 __device__ __forceinline__ void run_tile(const NtEntry* __restrict__ entries, int n_entries,
                                          int t, int s, int split, unsigned char* As,
                                          unsigned char* Bs) {
@@ -471,7 +559,7 @@ __device__ __forceinline__ void run_tile(const NtEntry* __restrict__ entries, in
     const int chunk = pad_kt((e.K + split - 1) / split);
     const int kb = s * chunk;
     const int ke = min(e.K, kb + chunk);
-    nt_tile<P, A_CPLX, Epi, TM, TN, KS>(e, m0, n0, kb, ke, s, split, As, Bs);
+    nt_tile<P, A_CPLX, Epi, TM, TN, KS, GEN>(e, m0, n0, kb, ke, s, split, As, Bs);
 }
 
 // Workgroups reach the 8 XCDs round-robin (block b on XCD b % 8).  Renumbered
@@ -740,7 +828,7 @@ __device__ __forceinline__ void band_tile(int local, int tiles_m, int tiles_n, i
 // then cover a block of about 8 x 8 output tiles and its L2 holds the A and B
 // rows they share, instead of every XCD fetching the whole B panel for two rows
 // of tiles.
-template <int P, bool A_CPLX, class Epi, int TM, int TN>
+template <int P, bool A_CPLX, class Epi, int TM, int TN, bool GEN = false>
 __global__ __launch_bounds__(256, direct_occ<P>()) void nt_direct_kernel(
     const NtEntry* __restrict__ entries, int n_entries, const int* __restrict__ tile_count,
     int split) {
@@ -759,12 +847,14 @@ __global__ __launch_bounds__(256, direct_occ<P>()) void nt_direct_kernel(
         const int chunk = pad_kt((e.K + split - 1) / split);
         const int kb = s * chunk;
         const int ke = min(e.K, kb + chunk);
-        nt_tile<P, A_CPLX, Epi, TM, TN, kDirectKS>(e, mt * TM, nt * TN, kb, ke, s, split, As, Bs);
+        nt_tile<P, A_CPLX, Epi, TM, TN, kDirectKS, GEN>(e, mt * TM, nt * TN, kb, ke, s, split, As,
+                                                        Bs);
         return;
     }
     const int bid = blockIdx.x;
     const int s = bid / count;
-    run_tile<P, A_CPLX, Epi, TM, TN, kDirectKS>(entries, n_entries, bid - s * count, s, split, As, Bs);
+    run_tile<P, A_CPLX, Epi, TM, TN, kDirectKS, GEN>(entries, n_entries, bid - s * count, s, split,
+                                                     As, Bs);
 }
 
 // Persistent schedule: pull tiles from *queue until *tile_count is reached;
@@ -812,8 +902,11 @@ hipError_t persistent_shape(int tm, int tn, const NtEntry* entries, int n_entrie
 
 template <int P, int TM, int TN>
 void first_direct_shape(int layers, int levels, const NtBuffers& b, int max_tiles, hipStream_t s) {
-    hipLaunchKernelGGL((nt_direct_kernel<P, false, FirstEpi<P>, TM, TN>), dim3(max_tiles),
-                       dim3(256), 0, s, b.first, layers * levels, &b.hdr->first_tiles, 1);
+    // 128-column tiles generate the fringe operand from the tables (its panel is not
+    // gathered); the 64-column tiles of small scenes read the gathered panel
+    hipLaunchKernelGGL((nt_direct_kernel<P, false, FirstEpi<P>, TM, TN, nt_first_generates(TN)>),
+                       dim3(max_tiles), dim3(256), 0, s, b.first, layers * levels,
+                       &b.hdr->first_tiles, 1);
 }
 
 template <int P>

@@ -16,8 +16,15 @@ namespace cgh {
 namespace {
 
 // Appends, in index order, every i in [0, n) with f[i] != 0 to out; returns the count.
+// koff (optional): beside each i, the offset of its fringe in the (layer, level)'s
+// operand-format tables of an axis of N points at level l (gen_koff).
+__device__ __forceinline__ int gen_koff(int i, int N, int l) {
+    const int half = N >> l;
+    return i >= half ? 2 * N - ((i - half) << l) : -(i << l);
+}
 __device__ int block_compact(const uint8_t* __restrict__ f, int n, int* __restrict__ out,
-                             int* s_wave) {
+                             int* s_wave, int* __restrict__ koff = nullptr, int N = 0,
+                             int l = 0) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     int running = 0;
     for (int base = 0; base < n; base += blockDim.x) {
@@ -32,7 +39,10 @@ __device__ int block_compact(const uint8_t* __restrict__ f, int n, int* __restri
             if (k < w) off += s_wave[k];
             tot += s_wave[k];
         }
-        if (pred) out[running + off + pre] = i;
+        if (pred) {
+            out[running + off + pre] = i;
+            if (koff) koff[running + off + pre] = gen_koff(i, N, l);
+        }
         running += tot;
         __syncthreads();
     }
@@ -43,12 +53,16 @@ __device__ __forceinline__ void lists_block(const uint8_t* __restrict__ flags, i
                                             int levels, size_t flags_layer,
                                             int* __restrict__ rowlist, int* __restrict__ collist,
                                             int* __restrict__ cnt_row, int* __restrict__ cnt_col,
-                                            int dl, int* s_wave) {
+                                            int dl, int* s_wave, int* __restrict__ koff_row = nullptr,
+                                            int* __restrict__ koff_col = nullptr) {
     const int d = dl / levels, l = dl % levels + 1;
     const uint8_t* fr = flags + (size_t)d * flags_layer + flag_level_off(ny, nx, l);
     const int sy = band_side(ny, l), sx = band_side(nx, l);
-    const int nr = block_compact(fr, sy, rowlist + dl_rows_off(ny, levels, d, l), s_wave);
-    const int nc = block_compact(fr + sy, sx, collist + dl_cols_off(nx, levels, d, l), s_wave);
+    const size_t ro = dl_rows_off(ny, levels, d, l), co = dl_cols_off(nx, levels, d, l);
+    const int nr = block_compact(fr, sy, rowlist + ro, s_wave, koff_row ? koff_row + ro : nullptr,
+                                 ny, l);
+    const int nc = block_compact(fr + sy, sx, collist + co, s_wave,
+                                 koff_col ? koff_col + co : nullptr, nx, l);
     if (threadIdx.x == 0) {
         cnt_row[dl] = nr;
         cnt_col[dl] = nc;
@@ -60,10 +74,12 @@ __global__ __launch_bounds__(1024) void lists_kernel(const uint8_t* __restrict__
                                                      int* __restrict__ rowlist,
                                                      int* __restrict__ collist,
                                                      int* __restrict__ cnt_row,
-                                                     int* __restrict__ cnt_col) {
+                                                     int* __restrict__ cnt_col,
+                                                     int* __restrict__ koff_row,
+                                                     int* __restrict__ koff_col) {
     __shared__ int s_wave[16];
     lists_block(flags, ny, nx, levels, flags_layer, rowlist, collist, cnt_row, cnt_col,
-                blockIdx.x, s_wave);
+                blockIdx.x, s_wave, koff_row, koff_col);
 }
 
 // Batched: grid.y = scene, grid.x sized for the scene with the most (layer, level) pairs.
@@ -204,6 +220,13 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
         e.tile_m = a.tm1;
         e.tile_n = a.tn1;
         e.out_scale = first_scale;
+        // the same operand from its table: rows-first the x fringes of the active columns,
+        // columns-first the y fringes of the active rows
+        e.g_lut = static_cast<const char*>(cf ? a.gen_y : a.gen_x) +
+                  gen_table(d, l, a.levels) * lut_len(outer) * 8;
+        e.g_koff = cf ? a.koff_row + dl_rows_off(a.ny, a.levels, d, l)
+                      : a.koff_col + dl_cols_off(a.nx, a.levels, d, l);
+        e.g_count = cf ? cr : cc;
         a.first[t] = e;
     }
     if (threadIdx.x == 0) {
@@ -234,6 +257,9 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
         e.tile_m = a.tm2;
         e.tile_n = a.tn2;
         e.out_scale = second_scale;
+        e.g_lut = nullptr;
+        e.g_koff = nullptr;
+        e.g_count = 0;
         a.second[0] = e;
     }
 }
@@ -484,8 +510,9 @@ __device__ __forceinline__ long long cb_chunks(const DlPlan& g) {
 }
 
 // The operand panels of one scene in one launch: grid.z selects the panel (0 the
-// second contraction's fringe operand, 1 the first contraction's, 2 the coefficient
-// operand), grid.y the (layer, level), grid.x strides over its tasks or chunks.
+// second contraction's fringe operand, 1 the coefficient operand, 2 the first
+// contraction's fringe operand where that contraction does not generate it from the
+// tables itself), grid.y the (layer, level), grid.x strides over its tasks or chunks.
 // The dispatcher hands out the workgroups in that order, so those resident at one
 // time write neighbouring parts of one panel.  The grid is sized for dense upper
 // bounds, and a workgroup with nothing to do still holds its LDS until its counts
@@ -497,7 +524,7 @@ __global__ __launch_bounds__(256) void panels_kernel(PrepScene sc, int levels) {
     __shared__ float lre[kFringeRows * kFringePitch], lim[kFringeRows * kFringePitch];
     const DlPlan g = load_dl(sc.b, levels, blockIdx.y);
     if (g.cr == 0 || g.cc == 0) return;
-    if (blockIdx.z < 2) {
+    if (blockIdx.z != 1) {
         const FringeOp f = blockIdx.z == 0 ? second_fringe(sc, levels, g)
                                            : first_fringe(sc, levels, g);
         const int tasks = (f.n + kFringeRows - 1) / kFringeRows * (pad_kt(f.count) / kKT);
@@ -603,6 +630,10 @@ PlanArgs make_plan_args(int ny, int nx, int layers, int levels, int precision, c
     a.fx_ps = (long long)b.fx_ps;
     a.fy_ps = (long long)b.fy_ps;
     a.tc_ps = (long long)b.tc_ps;
+    a.koff_row = b.koff_row;
+    a.koff_col = b.koff_col;
+    a.gen_x = b.gen_x;
+    a.gen_y = b.gen_y;
     a.hologram = o.hologram;
     a.partial = o.partial;
     a.accumulate = o.accumulate;
@@ -615,7 +646,8 @@ hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int 
                           const unsigned long long* absmax, int e_fringe, hipStream_t s) {
     const int n_dl = layers * levels;
     hipLaunchKernelGGL(lists_kernel, dim3(n_dl), dim3(1024), 0, s, flags, ny, nx, levels,
-                       flags_layer, b.rowlist, b.collist, b.cnt_row, b.cnt_col);
+                       flags_layer, b.rowlist, b.collist, b.cnt_row, b.cnt_col, b.koff_row,
+                       b.koff_col);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     PlanArgs a = make_plan_args(ny, nx, layers, levels, precision, tiles, b, o, absmax,
@@ -628,7 +660,8 @@ hipError_t launch_nt_plan(const uint8_t* flags, int ny, int nx, int layers, int 
 
 template <int P>
 static hipError_t materialize(const float* coef, const float* lut_x, const float* lut_y, int ny,
-                              int nx, int layers, int levels, const NtBuffers& b, hipStream_t s) {
+                              int nx, int layers, int levels, const NtBuffers& b, bool first_panel,
+                              hipStream_t s) {
     PrepScene sc{};
     sc.coef = coef;
     sc.lut_x = lut_x;
@@ -648,10 +681,11 @@ static hipError_t materialize(const float* coef, const float* lut_x, const float
         if (fringe > most) most = fringe;
         if (chunks > most) most = chunks;
     }
-    int share = kPanelGridTotal / (3 * layers * levels);
+    const int kinds = first_panel ? 3 : 2;
+    int share = kPanelGridTotal / (kinds * layers * levels);
     share = share < 32 ? 32 : (share > 512 ? 512 : share);
     const int gx = (int)(most < share ? most : share);
-    hipLaunchKernelGGL(panels_kernel<P>, dim3(gx, layers * levels, 3), dim3(256), 0, s, sc,
+    hipLaunchKernelGGL(panels_kernel<P>, dim3(gx, layers * levels, kinds), dim3(256), 0, s, sc,
                        levels);
     return hipGetLastError();
 }
@@ -693,10 +727,12 @@ hipError_t launch_batch_prefix(const PlanHeader* hdrs, int n_scenes, const int* 
 
 hipError_t launch_nt_materialize(const float* coef, const float* lut_x, const float* lut_y, int ny,
                                  int nx, int layers, int levels, int precision,
-                                 const NtBuffers& b, hipStream_t s) {
-    if (precision == P_BF16) return materialize<P_BF16>(coef, lut_x, lut_y, ny, nx, layers, levels, b, s);
-    if (precision == P_FP16) return materialize<P_FP16>(coef, lut_x, lut_y, ny, nx, layers, levels, b, s);
-    return materialize<P_FP32>(coef, lut_x, lut_y, ny, nx, layers, levels, b, s);
+                                 const NtBuffers& b, bool first_panel, hipStream_t s) {
+    if (precision == P_BF16)
+        return materialize<P_BF16>(coef, lut_x, lut_y, ny, nx, layers, levels, b, first_panel, s);
+    if (precision == P_FP16)
+        return materialize<P_FP16>(coef, lut_x, lut_y, ny, nx, layers, levels, b, first_panel, s);
+    return materialize<P_FP32>(coef, lut_x, lut_y, ny, nx, layers, levels, b, first_panel, s);
 }
 
 }  // namespace cgh
