@@ -90,8 +90,8 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels,
     const cgh::NtSizes z = cgh::nt_sizes(ny, nx, layers, levels);
     lo.rowlist = take(z.rowlist * 4);
     lo.collist = take(z.collist * 4);
-    lo.koff_row = take(z.rowlist * 4);
-    lo.koff_col = take(z.collist * 4);
+    lo.koff_row = take(cgh::dl_koff_off(ny, levels, layers, 1) * 4);
+    lo.koff_col = take(cgh::dl_koff_off(nx, levels, layers, 1) * 4);
     lo.cnt_row = take((size_t)n_dl * 4);
     lo.cnt_col = take((size_t)n_dl * 4);
     lo.seg_row = take((size_t)n_dl * 4);

@@ -163,6 +163,17 @@ inline NtSizes nt_sizes(int ny, int nx, int layers, int levels) {
 }
 
 // Dense offsets of (layer d, level l) inside the per-(d, l) regions.
+// Offsets of (layer d, level l) in the per-axis table-offset arrays (koff_row over ny,
+// koff_col over nx): one segment per (layer, level), the level's side padded to 16, so
+// that a K tile's 16 offsets are one aligned run.
+__host__ __device__ inline size_t dl_koff_off(int n, int levels, int d, int l) {
+    size_t per = 0, at = 0;
+    for (int k = 1; k <= levels; ++k) {
+        if (k == l) at = per;
+        per += (size_t)pad_kt(band_side(n, k));
+    }
+    return (size_t)d * per + at;
+}
 __host__ __device__ inline size_t dl_rows_off(int ny, int levels, int d, int l) {
     size_t per = 0;
     for (int k = 1; k <= levels; ++k) per += band_side(ny, k);

@@ -262,29 +262,34 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
     // is one aligned 16-byte read, and the lanes of a wave read one contiguous run.  The
     // offsets of a K tile are read one tile ahead of the table reads that need them, so
     // that waiting for them never waits for the loads in flight behind them.
-    constexpr int RP = TN / 2;
-    constexpr int KPT = GEN ? F::KB * RP / 256 : 2;
-    static_assert(!GEN || KPT == 2 || KPT == 4, "generated B: 2 or 4 k' per thread");
-    const int gp = tid % RP, gk = (tid / RP) * KPT;
+    // Lanes: tid = 16 a + 4 b + c takes row pair 4 a + c and k' group b (4 k' each), so
+    // that the LDS stores of 8 (16) consecutive lanes spread over the banks (row pairs
+    // 2 rows apart share banks every 4 pairs; the groups shift them by 16 (8) bytes).
+    static_assert(!GEN || TN == 128, "generated B: 128-column tiles");
+    constexpr int KPT = 4;
+    const int gp = 4 * (tid >> 4) + (tid & 3), gk = 4 * ((tid >> 2) & 3);
     u32x4 gv[KPT];
     int gkoff[KPT];
+    // the offset segment of a (layer, level) is padded to 16: a K tile's offsets are in
+    // bounds (past g_count they are not used) and the 4 of a group are one aligned read
     auto gen_list = [&](int kt) {
-        const int k = kb + kt * F::KB + gk;
+        const int k = max(min(kb + kt * F::KB, ke - F::KB), 0) + gk;
+        const u32x4 v = gload16(reinterpret_cast<const unsigned char*>(e.g_koff), (size_t)k * 4);
 #pragma unroll
-        for (int q = 0; q < KPT; ++q)
-            gkoff[q] = gload_int(e.g_koff, max(min(k + q, e.g_count - 1), 0));
+        for (int q = 0; q < 4; ++q) gkoff[q] = (int)v[q];
     };
     auto gen_load = [&](int kt) {
         const int k = kb + kt * F::KB + gk;
         const int n = n0 + 2 * gp, N = e.N;
+        const int live = min(e.g_count, ke) - k;  // k' + q live for q < live
         const unsigned char* tb = static_cast<const unsigned char*>(e.g_lut);
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
-            // k' past the list: the zero band; rows past N: its first entries
-            const int off = (k + q < e.g_count && k + q < ke) ? gkoff[q] : 3 * N;
+            // k' past the list read the zero band, rows past N its first entries: every
+            // index is even and in [2, 6N - 2] (offsets in [2^l - N, 2N], 3N)
+            const int off = q < live ? gkoff[q] : 3 * N;
             const int idx = n < N ? n + N + off : 4 * N;
-            // in [2, 6N - 2] for every offset; clamped all the same
-            gv[q] = gload16(tb, (size_t)(min(max(idx, 0), 6 * N - 2) >> 1) * 16);
+            gv[q] = gload16(tb, (unsigned)idx * 8u);
         }
         gen_list(kt + 1);
     };

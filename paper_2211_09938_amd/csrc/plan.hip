@@ -58,11 +58,12 @@ __device__ __forceinline__ void lists_block(const uint8_t* __restrict__ flags, i
     const int d = dl / levels, l = dl % levels + 1;
     const uint8_t* fr = flags + (size_t)d * flags_layer + flag_level_off(ny, nx, l);
     const int sy = band_side(ny, l), sx = band_side(nx, l);
-    const size_t ro = dl_rows_off(ny, levels, d, l), co = dl_cols_off(nx, levels, d, l);
-    const int nr = block_compact(fr, sy, rowlist + ro, s_wave, koff_row ? koff_row + ro : nullptr,
+    const int nr = block_compact(fr, sy, rowlist + dl_rows_off(ny, levels, d, l), s_wave,
+                                 koff_row ? koff_row + dl_koff_off(ny, levels, d, l) : nullptr,
                                  ny, l);
-    const int nc = block_compact(fr + sy, sx, collist + co, s_wave,
-                                 koff_col ? koff_col + co : nullptr, nx, l);
+    const int nc = block_compact(fr + sy, sx, collist + dl_cols_off(nx, levels, d, l), s_wave,
+                                 koff_col ? koff_col + dl_koff_off(nx, levels, d, l) : nullptr,
+                                 nx, l);
     if (threadIdx.x == 0) {
         cnt_row[dl] = nr;
         cnt_col[dl] = nc;
@@ -224,8 +225,8 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
         // columns-first the y fringes of the active rows
         e.g_lut = static_cast<const char*>(cf ? a.gen_y : a.gen_x) +
                   gen_table(d, l, a.levels) * lut_len(outer) * 8;
-        e.g_koff = cf ? a.koff_row + dl_rows_off(a.ny, a.levels, d, l)
-                      : a.koff_col + dl_cols_off(a.nx, a.levels, d, l);
+        e.g_koff = cf ? a.koff_row + dl_koff_off(a.ny, a.levels, d, l)
+                      : a.koff_col + dl_koff_off(a.nx, a.levels, d, l);
         e.g_count = cf ? cr : cc;
         a.first[t] = e;
     }

@@ -18,7 +18,7 @@ import pytest
 from oracle import haar, progressive, saliency
 from paper_2211_09938_amd import scenes
 
-from helpers import gpu_hologram, oracle_hologram, rel_l2, to_dev
+from helpers import gpu_hologram, oracle_hologram, rel_l2, sample_pixels, to_dev
 
 pytestmark = pytest.mark.gpu
 os.environ.setdefault("ORACLE_WORKERS", "8")
@@ -146,3 +146,31 @@ def test_columns_first_only_scene(precision):
     err = rel_l2(h, oracle_hologram(s))
     print(f"column-only 264x96 {precision}: rel-L2 {err:.3e}")
     assert err <= (FP32_TOL if precision == "fp32" else SPLIT_MODEL[precision])
+
+
+def first_dense_tiles(ny, nx, planes, tm, levels=3):
+    """Tiles of the first contraction with every row and column active, in the order
+    with more of them, at tm x 128 tiles (the library's bound for choosing 128-column
+    tiles, with which the first contraction generates its fringe operand from the
+    operand-format tables instead of reading a gathered panel)."""
+    t = 0
+    for l in range(1, levels + 1):
+        sy, sx = ny >> (l - 1), nx >> (l - 1)
+        t += max(-(-sy // tm) * -(-nx // 128), -(-sx // tm) * -(-ny // 128))
+    return t * planes
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", FP32_TOL),
+                                           ("bf16_split", SPLIT_MODEL["bf16_split"]),
+                                           ("fp16_split", SPLIT_MODEL["fp16_split"])])
+def test_generated_fringe_operand_on_ragged_tiles(precision, tol):
+    # 1000 x 1096 (neither a multiple of 128) in 6 planes: 128-column tiles whose last
+    # column of tiles runs past the image, and both contraction orders
+    ny, nx, planes = 1000, 1096, 6
+    assert first_dense_tiles(ny, nx, planes, 64 if precision == "fp32" else 128) >= 512
+    s = scenes.random_scene(1096, ny, nx, planes=planes, fraction=0.3)
+    h = gpu_hologram(s, precision=precision)
+    ys, xs = sample_pixels(ny, nx, seed=11, n_random=128, crop=8)
+    err = rel_l2(h[ys, xs], oracle_hologram(s, pixels=(ys, xs)))
+    print(f"1000x1096x6 {precision}: rel-L2 {err:.3e} on {len(ys)} pixels")
+    assert err <= tol
