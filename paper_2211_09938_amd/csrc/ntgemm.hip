@@ -256,7 +256,7 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
     // chunks starting at or beyond ke read as zero
     constexpr int KPC = 16 / F::ES;  // k per 16-byte chunk
 
-    // GEN: thread = (row pair gp, rows n = n0 + 2 gp and n + 1 of the B tile; KPT
+    // GEN: thread = (row pair gp, rows n = n0 + 2 gp and n + 1 of the B tile; 4
     // consecutive k' from gk).  Entries (n, k') and (n + 1, k') of the operand-format
     // tables are adjacent and the first is even (n, N and every offset even), so each k'
     // is one aligned 16-byte read, and the lanes of a wave read one contiguous run.  The
@@ -301,37 +301,27 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
         for (int rr = 0; rr < 2; ++rr) {
             unsigned char* pr = row + rr * F::PITCH;
             if constexpr (P == P_FP32) {
-                // planes re, im: KPT floats each
+                // planes re, im: 4 floats each
 #pragma unroll
-                for (int part = 0; part < 2; ++part) {
-                    if constexpr (KPT == 4)
-                        *reinterpret_cast<u32x4*>(pr + part * BPLANE) =
-                            u32x4{word(0, 2 * rr + part), word(1, 2 * rr + part),
-                                  word(2, 2 * rr + part), word(3, 2 * rr + part)};
-                    else
-                        *reinterpret_cast<u32x2*>(pr + part * BPLANE) =
-                            u32x2{word(0, 2 * rr + part), word(1, 2 * rr + part)};
-                }
+                for (int part = 0; part < 2; ++part)
+                    *reinterpret_cast<u32x4*>(pr + part * BPLANE) =
+                        u32x4{word(0, 2 * rr + part), word(1, 2 * rr + part),
+                              word(2, 2 * rr + part), word(3, 2 * rr + part)};
             } else {
                 // an entry word is hi | lo << 16; planes re hi, re lo, im hi, im lo hold
-                // KPT halves each
+                // 4 halves each
 #pragma unroll
                 for (int part = 0; part < 2; ++part) {
-                    unsigned hi[KPT / 2], lo[KPT / 2];
+                    unsigned hi[2], lo[2];
 #pragma unroll
-                    for (int q = 0; q < KPT; q += 2) {
+                    for (int q = 0; q < 4; q += 2) {
                         const unsigned a = word(q, 2 * rr + part), b = word(q + 1, 2 * rr + part);
                         hi[q / 2] = (a & 0xffffu) | (b << 16);
                         lo[q / 2] = (a >> 16) | (b & 0xffff0000u);
                     }
                     unsigned char* ph = pr + (2 * part) * BPLANE;
-                    if constexpr (KPT == 4) {
-                        *reinterpret_cast<u32x2*>(ph) = u32x2{hi[0], hi[1]};
-                        *reinterpret_cast<u32x2*>(ph + BPLANE) = u32x2{lo[0], lo[1]};
-                    } else {
-                        *reinterpret_cast<unsigned*>(ph) = hi[0];
-                        *reinterpret_cast<unsigned*>(ph + BPLANE) = lo[0];
-                    }
+                    *reinterpret_cast<u32x2*>(ph) = u32x2{hi[0], hi[1]};
+                    *reinterpret_cast<u32x2*>(ph + BPLANE) = u32x2{lo[0], lo[1]};
                 }
             }
         }

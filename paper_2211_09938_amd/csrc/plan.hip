@@ -518,8 +518,8 @@ __device__ __forceinline__ long long cb_chunks(const DlPlan& g) {
 // time write neighbouring parts of one panel.  The grid is sized for dense upper
 // bounds, and a workgroup with nothing to do still holds its LDS until its counts
 // arrive, so grid.x shares about kPanelGridTotal workgroups among the (layer, level)
-// and panel pairs (at 2048^2 x 8 layers, 24 pairs: 512 per pair measured 85 us, 128
-// measured 63 us, 32 measured 82 us).
+// and panel pairs (at 2048^2 x 8 layers with all three panels, 72 pairs: 512 per pair
+// measured 85 us, 128 measured 63 us, 32 measured 82 us).
 template <int P>
 __global__ __launch_bounds__(256) void panels_kernel(PrepScene sc, int levels) {
     __shared__ float lre[kFringeRows * kFringePitch], lim[kFringeRows * kFringePitch];
