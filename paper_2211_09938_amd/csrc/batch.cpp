@@ -69,11 +69,13 @@ constexpr int kCandidates[4][2] = {{128, 128}, {64, 128}, {128, 64}, {64, 64}};
 struct Events {
     hipEvent_t a = nullptr, b = nullptr, c = nullptr;
 };
+// (a: before the operand-panel gather, whose work depends on the first contraction's
+// tile shape; b: between the contractions; c: after the second)
 
 // Every per-scene stage of the batch as one launch over all scenes, then the
 // merge of the problem tables.  The planning arguments (tile shapes included)
 // are the ones last uploaded by upload_args.
-hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s) {
+hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s, const Events* ev = nullptr) {
     const int n = (int)p.scenes.size();
     hipError_t e = cgh::launch_prep_fill(p.d_dwt, n, p.max_fill, s);
     if (e == hipSuccess)
@@ -84,6 +86,7 @@ hipError_t enqueue_prep(const cgh_plan& p, hipStream_t s) {
     if (e == hipSuccess)
         e = cgh::launch_batch_prefix(p.hdrs, n, p.first_off, p.first, p.second, p.counts,
                                      p.queues, p.scene_units, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev->a, s);
     if (e != hipSuccess) return e;
     return cgh::launch_materialize_batch(p.d_prep, n, p.levels, p.precision, p.scene_units,
                                          p.units_bound, s);
@@ -132,10 +135,11 @@ hipError_t enqueue_second(const cgh_plan& p, hipStream_t s, const int* tiles) {
 
 // Enqueues the whole batch on `s` with the given tile shapes (the planning
 // arguments must have been uploaded for them); records ev (if given) before the
-// first contraction, between the two, and after the second.
+// operand-panel gather (with 128-column first tiles the first contraction generates its
+// fringe operand and the gather does less), between the contractions, and after the
+// second.
 hipError_t enqueue(const cgh_plan& p, hipStream_t s, const int* tiles, const Events* ev) {
-    hipError_t e = enqueue_prep(p, s);
-    if (e == hipSuccess && ev) e = hipEventRecord(ev->a, s);
+    hipError_t e = enqueue_prep(p, s, ev);
     if (e == hipSuccess) e = enqueue_first(p, s, tiles);
     if (e == hipSuccess && ev) e = hipEventRecord(ev->b, s);
     if (e == hipSuccess) e = enqueue_second(p, s, tiles);
@@ -396,9 +400,11 @@ int cgh_plan_create(const cgh_scene* scenes, int n_scenes, int levels, double la
             p->scenes[i].e_fringe = fs.e;
             for (int d = 0; d < nl; ++d) {
                 h_luts.push_back(cgh::LutJob{nx, d, levels, op.c[d], op.one_re[d], op.one_im[d],
-                                             reinterpret_cast<float*>(ws + lo.lut_x)});
+                                             reinterpret_cast<float*>(ws + lo.lut_x),
+                                             ws + lo.gen_x, p->precision});
                 h_luts.push_back(cgh::LutJob{ny, d, levels, op.c[d], fs.re[d], fs.im[d],
-                                             reinterpret_cast<float*>(ws + lo.lut_y)});
+                                             reinterpret_cast<float*>(ws + lo.lut_y),
+                                             ws + lo.gen_y, p->precision});
             }
             p->max_nbx = std::max(p->max_nbx, nx >> levels);
             p->max_nby = std::max(p->max_nby, ny >> levels);

@@ -151,6 +151,8 @@ struct LutJob {
     int n_pix, d, levels;
     double c, pre_re, pre_im;
     float* table;  // the scene's table region of that axis
+    void* gen;     // its operand-format tables (gen_table), or null
+    int gen_prec;  // their precision
 };
 hipError_t launch_prep_fill(const DwtScene* scenes, int n, size_t max_fill, hipStream_t s);
 hipError_t launch_dwt_mask_batch(const DwtScene* scenes, int n, int levels, const float* thr,

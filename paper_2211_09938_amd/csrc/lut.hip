@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void lut_batch_kernel(const LutJob* __restrict
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= lut_len(j.n_pix)) return;
     lut_entry_bands(j.n_pix, j.d, j.levels, 1 + blockIdx.y, j.c, j.pre_re, j.pre_im, idx, j.table,
-                    nullptr, P_FP32);
+                    static_cast<uint2*>(j.gen), j.gen_prec);
 }
 
 }  // namespace

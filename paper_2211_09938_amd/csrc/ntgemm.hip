@@ -854,7 +854,7 @@ __global__ __launch_bounds__(256, direct_occ<P>()) void nt_direct_kernel(
 
 // Persistent schedule: pull tiles from *queue until *tile_count is reached;
 // every workgroup exits once the counter passes the end of the table.
-template <int P, bool A_CPLX, class Epi, int TM, int TN>
+template <int P, bool A_CPLX, class Epi, int TM, int TN, bool GEN = false>
 __global__ __launch_bounds__(256, persist_occ<P>()) void nt_persistent_kernel(
     const NtEntry* __restrict__ entries, int n_entries, const int* __restrict__ tile_count,
     int* __restrict__ queue) {
@@ -869,7 +869,7 @@ __global__ __launch_bounds__(256, persist_occ<P>()) void nt_persistent_kernel(
         const int t = s_next;
         __syncthreads();
         if (t >= count) break;
-        run_tile<P, A_CPLX, Epi, TM, TN, kPersistKS>(entries, n_entries, t, 0, 1, As, Bs);
+        run_tile<P, A_CPLX, Epi, TM, TN, kPersistKS, GEN>(entries, n_entries, t, 0, 1, As, Bs);
     }
 }
 
@@ -880,8 +880,10 @@ hipError_t persistent(const NtEntry* entries, int n_entries, const int* count, i
         hipLaunchKernelGGL((nt_persistent_kernel<P, true, SecondEpi, TM, TN>), dim3(grid),
                            dim3(256), 0, s, entries, n_entries, count, queue);
     else
-        hipLaunchKernelGGL((nt_persistent_kernel<P, false, FirstEpi<P>, TM, TN>), dim3(grid),
-                           dim3(256), 0, s, entries, n_entries, count, queue);
+        // as the single-scene launch: 128-column tiles generate the fringe operand
+        hipLaunchKernelGGL((nt_persistent_kernel<P, false, FirstEpi<P>, TM, TN,
+                                                 nt_first_generates(TN)>),
+                           dim3(grid), dim3(256), 0, s, entries, n_entries, count, queue);
     return hipGetLastError();
 }
 

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(1024) void lists_batch_kernel(const PrepScene* __re
     const PrepScene& sc = scenes[blockIdx.y];
     if ((int)blockIdx.x >= sc.layers * levels) return;
     lists_block(sc.flags, sc.ny, sc.nx, levels, sc.flags_layer, sc.b.rowlist, sc.b.collist,
-                sc.b.cnt_row, sc.b.cnt_col, blockIdx.x, s_wave);
+                sc.b.cnt_row, sc.b.cnt_col, blockIdx.x, s_wave, sc.b.koff_row, sc.b.koff_col);
 }
 
 // Inclusive Hillis-Steele scan over the workgroup (blockDim.x <= 1024 threads).
@@ -128,6 +128,7 @@ __device__ __forceinline__ void plan_block(const PlanArgs& a, int* sh, int* last
             tiles = act > 0 ? ((act + a.tm1 - 1) / a.tm1) * ((outer + a.tn1 - 1) / a.tn1) : 0;
             a.orient[t] = cf ? 1 : 0;
             dl_panel_units(a.ny, a.nx, cr, cc, pu);
+            if (nt_first_generates(a.tn1)) pu[1] = 0;  // generated by the first contraction
         }
         const int ik = block_scan_incl(seg, sh);
         const int it = block_scan_incl(tiles, sh);
