@@ -278,22 +278,25 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
 #pragma unroll
         for (int q = 0; q < 4; ++q) gkoff[q] = (int)v[q];
     };
+    // rows past N (the last column tile of a ragged N) read row N - 2 and store zero
+    const int gn_tab = min(n0 + 2 * gp, e.N - 2) + e.N;
+    const bool grow_zero = n0 + TN > e.N && n0 + 2 * gp >= e.N;
     auto gen_load = [&](int kt) {
-        const int k = kb + kt * F::KB + gk;
-        const int n = n0 + 2 * gp, N = e.N;
-        const int live = min(e.g_count, ke) - k;  // k' + q live for q < live
         const unsigned char* tb = static_cast<const unsigned char*>(e.g_lut);
 #pragma unroll
         for (int q = 0; q < KPT; ++q) {
-            // k' past the list read the zero band, rows past N its first entries: every
-            // index is even and in [2, 6N - 2] (offsets in [2^l - N, 2N], 3N)
-            const int off = q < live ? gkoff[q] : 3 * N;
-            const int idx = n < N ? n + N + off : 4 * N;
+            // offsets in [2^l - N, 2N] and 3N (k' past the list: the zero band), so every
+            // index is even and in [2, 6N - 2]
+            const int idx = gn_tab + gkoff[q];
             gv[q] = gload16(tb, (unsigned)idx * 8u);
         }
         gen_list(kt + 1);
     };
     auto gen_stash = [&]() {
+        if (grow_zero) {
+#pragma unroll
+            for (int q = 0; q < KPT; ++q) gv[q] = u32x4{0u, 0u, 0u, 0u};
+        }
         // word w of entry pair q: 0 row n re, 1 row n im, 2 row n+1 re, 3 row n+1 im
         auto word = [&](int q, int w) -> unsigned { return gv[q][w]; };
         unsigned char* row = Bs + (2 * gp) * F::PITCH + gk * F::ES;
@@ -315,9 +318,11 @@ __device__ __forceinline__ void nt_tile(const NtEntry& e, int m0, int n0, int kb
                     unsigned hi[2], lo[2];
 #pragma unroll
                     for (int q = 0; q < 4; q += 2) {
+                        // v_perm_b32 bytes 0-3 from a, 4-7 from b: hi = a.lo16 | b.lo16 << 16,
+                        // lo = a.hi16 | b.hi16 << 16
                         const unsigned a = word(q, 2 * rr + part), b = word(q + 1, 2 * rr + part);
-                        hi[q / 2] = (a & 0xffffu) | (b << 16);
-                        lo[q / 2] = (a >> 16) | (b & 0xffff0000u);
+                        hi[q / 2] = __builtin_amdgcn_perm(b, a, 0x05040100u);
+                        lo[q / 2] = __builtin_amdgcn_perm(b, a, 0x07060302u);
                     }
                     unsigned char* ph = pr + (2 * part) * BPLANE;
                     *reinterpret_cast<u32x2*>(ph) = u32x2{hi[0], hi[1]};

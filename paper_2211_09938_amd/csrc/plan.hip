@@ -17,7 +17,8 @@ namespace {
 
 // Appends, in index order, every i in [0, n) with f[i] != 0 to out; returns the count.
 // koff (optional): beside each i, the offset of its fringe in the (layer, level)'s
-// operand-format tables of an axis of N points at level l (gen_koff).
+// operand-format tables of an axis of N points at level l (gen_koff), and 3N (the zero
+// band) from the count up to the next multiple of 16.
 __device__ __forceinline__ int gen_koff(int i, int N, int l) {
     const int half = N >> l;
     return i >= half ? 2 * N - ((i - half) << l) : -(i << l);
@@ -46,6 +47,10 @@ __device__ int block_compact(const uint8_t* __restrict__ f, int n, int* __restri
         running += tot;
         __syncthreads();
     }
+    // the offsets up to the next multiple of 16 point at the zero band (the K padding)
+    if (koff)
+        for (int i = running + (int)threadIdx.x; i < pad_kt(running); i += blockDim.x)
+            koff[i] = 3 * N;
     return running;
 }
 
