@@ -96,8 +96,12 @@ hipError_t forward(const float* object, const uint8_t* layer_index, int n_layers
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_FIRST, [&] {
-            return cgh::launch_nt_first(n_layers, levels, precision, nb, lo.first_tiles_max, tn1,
-                                        s);
+            // workgroups past the planned tile count exit at once: launch the bound for
+            // this tile shape, not the layout's bound over every shape
+            const long long bound = cgh::nt_first_tiles_bound(
+                ny, nx, n_layers, levels, cgh::nt_first_tile_m(precision), tn1);
+            const int grid = (int)std::min<long long>(lo.first_tiles_max, bound);
+            return cgh::launch_nt_first(n_layers, levels, precision, nb, grid, tn1, s);
         });
     if (e == hipSuccess)
         e = timed(s, CGH_STAGE_SECOND,

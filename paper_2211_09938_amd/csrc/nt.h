@@ -316,6 +316,9 @@ int nt_first_tile_m(int precision);
 // Columns of the first contraction's tile for a single scene: 64 on scenes small enough
 // that 128-column tiles would leave most compute units idle, else 128.
 int nt_first_tile_n(int ny, int nx, int layers, int levels, int precision);
+// Tiles of the first contraction at tm x tn tiles with every row and column active, in
+// the order with more of them per (layer, level): a bound of the planned tile count.
+long long nt_first_tiles_bound(int ny, int nx, int layers, int levels, int tm, int tn);
 // Whether the single-scene first contraction with tile_n-column tiles generates its fringe
 // operand from the operand-format tables (else the panel gather writes it).
 constexpr bool nt_first_generates(int tile_n) { return tile_n == 128; }

@@ -945,16 +945,21 @@ int nt_first_tile_m(int precision) { return precision == P_FP32 ? 64 : 128; }
 // 128-column tiles unless the scene is small: at most 512 tiles (two workgroups per
 // CU) even with every row and column active, in either contraction order; 64-column
 // tiles then give the launch twice the workgroups.
-int nt_first_tile_n(int ny, int nx, int layers, int levels, int precision) {
-    const int tm = nt_first_tile_m(precision);
+long long nt_first_tiles_bound(int ny, int nx, int layers, int levels, int tm, int tn) {
     long long tiles = 0;
     for (int l = 1; l <= levels; ++l) {
         const long long syl = band_side(ny, l), sxl = band_side(nx, l);
-        const long long r = (syl + tm - 1) / tm * ((nx + 127) / 128);
-        const long long c = (sxl + tm - 1) / tm * ((ny + 127) / 128);
+        const long long r = (syl + tm - 1) / tm * ((nx + tn - 1) / tn);
+        const long long c = (sxl + tm - 1) / tm * ((ny + tn - 1) / tn);
         tiles += r > c ? r : c;
     }
-    return tiles * layers < 512 ? 64 : 128;
+    return tiles * layers;
+}
+
+int nt_first_tile_n(int ny, int nx, int layers, int levels, int precision) {
+    return nt_first_tiles_bound(ny, nx, layers, levels, nt_first_tile_m(precision), 128) < 512
+               ? 64
+               : 128;
 }
 int nt_ring_tile_m() { return PpShape::TM; }
 int nt_ring_tile_n() { return PpShape::TN; }
