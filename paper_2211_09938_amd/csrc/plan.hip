@@ -15,14 +15,17 @@ namespace cgh {
 
 namespace {
 
-// Appends, in index order, every i in [0, n) with f[i] != 0 to out; returns the count.
-// koff (optional): beside each i, the offset of its fringe in the (layer, level)'s
-// operand-format tables of an axis of N points at level l (gen_koff), and 3N (the zero
-// band) from the count up to the next multiple of 16.
+// Offset of active row / column i's fringe in its (layer, level)'s operand-format tables
+// (an axis of N points at level l): entry n + N + offset is the fringe at point n, in
+// band 1 (table offset 2N) for i in the second half of the level's square.
 __device__ __forceinline__ int gen_koff(int i, int N, int l) {
     const int half = N >> l;
     return i >= half ? 2 * N - ((i - half) << l) : -(i << l);
 }
+
+// Appends, in index order, every i in [0, n) with f[i] != 0 to out; returns the count.
+// koff (optional): beside each i its gen_koff, and 3N (the zero band) from the count up
+// to the next multiple of 16.
 __device__ int block_compact(const uint8_t* __restrict__ f, int n, int* __restrict__ out,
                              int* s_wave, int* __restrict__ koff = nullptr, int N = 0,
                              int l = 0) {
