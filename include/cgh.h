@@ -124,6 +124,21 @@ typedef struct {
                                ((d*levels + l-1)*2 + b)*2 + part of 2*nx floats, entry i
                                holding the fringe at offset i - nx (Sec. 2 LUT blocks)     */
     size_t lut_y_offset;    /* the y tables, 2*ny floats each, times the layer's prefactor */
+    size_t gen_x_offset;    /* the x level tables in the operand format of the call's
+                               precision, written by the forward pass: per (layer d, level l)
+                               three bands of 2*nx entries of 8 bytes, starting at entry
+                               (d*levels + l-1)*3*2*nx -- band 0 (lo), band 1 (hi), zeros;
+                               an entry is (re, im) as FP32, or for the split forms the words
+                               hi | lo << 16 of re and of im (hi = RNE16(v), lo =
+                               RNE16(v - hi))                                              */
+    size_t gen_y_offset;    /* the y tables in that format, 2*ny entries per band          */
+    size_t koff_row_offset; /* per (layer, level), beside each active coefficient row i of
+                               the forward pass its offset into the y operand-format tables
+                               (i < ny/2^l: -i*2^l; else 2*ny - (i - ny/2^l)*2^l), ints, and
+                               3*ny up to the next multiple of 16 rows; one segment per
+                               (layer, level) of the level's side ny/2^(l-1) rounded up to 16,
+                               layer-major                                                 */
+    size_t koff_col_offset; /* the same for the active columns, over nx                    */
 } cgh_layout_info;
 
 /* Fills *info [host] for the problem; errors as cgh_workspace_size(). */

@@ -136,6 +136,10 @@ class LayoutInfo(ctypes.Structure):
         ("fused_bytes", _sz),
         ("lut_x_offset", _sz),
         ("lut_y_offset", _sz),
+        ("gen_x_offset", _sz),
+        ("gen_y_offset", _sz),
+        ("koff_row_offset", _sz),
+        ("koff_col_offset", _sz),
     ]
 
 

@@ -198,6 +198,10 @@ int cgh_workspace_layout(int ny, int nx, int n_layers, int levels, int precision
         info->fused_bytes = cgh::fused_bytes(ny, nx);
         info->lut_x_offset = lo.lut_x;
         info->lut_y_offset = lo.lut_y;
+        info->gen_x_offset = lo.gen_x;
+        info->gen_y_offset = lo.gen_y;
+        info->koff_row_offset = lo.koff_row;
+        info->koff_col_offset = lo.koff_col;
         return CGH_SUCCESS;
     } catch (...) {
         return CGH_ERROR_HIP;

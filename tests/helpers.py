@@ -2,7 +2,7 @@
 
 import numpy as np
 
-from oracle import fresnel, progressive
+from oracle import fresnel, haar, progressive, saliency
 
 
 def to_dev(a, dtype=None):
@@ -51,3 +51,31 @@ def sample_pixels(ny, nx, seed, n_random=192, crop=16):
 
 def rel_l2(a, b):
     return progressive.rel_l2(a, b)
+
+
+def support_indices(scene, levels=3):
+    """Nonzero rows and columns (index arrays) of every (layer, level) square of the
+    oracle's masked Mallat coefficients, layer-major.  A level-l square spans rows
+    [0, 2 ny/2^l) and columns [0, 2 nx/2^l); below the top level its low-low quadrant
+    belongs to the coarser levels."""
+    ny, nx = scene.obj.shape
+    sal = None if scene.saliency is None else scene.saliency.astype(np.float64)
+    masks = None if sal is None else saliency.detail_masks(sal, levels)
+    out = []
+    for a in progressive.layer_split(scene.obj.astype(np.float64), scene.layer, len(scene.z)):
+        c = haar.analysis(a, levels)
+        if masks is not None:
+            c = saliency.apply_masks(c, masks, levels)
+        for l in range(1, levels + 1):
+            h, w = ny >> l, nx >> l
+            sq = c[:2 * h, :2 * w].copy()
+            if l < levels:
+                sq[:h, :w] = 0.0
+            nz = sq != 0.0
+            out.append((np.flatnonzero(nz.any(axis=1)), np.flatnonzero(nz.any(axis=0))))
+    return out
+
+
+def support(scene, levels=3):
+    """Counts of support_indices: (active rows, active columns) per (layer, level)."""
+    return [(len(r), len(c)) for r, c in support_indices(scene, levels)]

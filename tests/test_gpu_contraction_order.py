@@ -15,10 +15,9 @@ import os
 import numpy as np
 import pytest
 
-from oracle import haar, progressive, saliency
 from paper_2211_09938_amd import scenes
 
-from helpers import gpu_hologram, oracle_hologram, rel_l2, sample_pixels, to_dev
+from helpers import gpu_hologram, oracle_hologram, rel_l2, sample_pixels, support, to_dev
 
 pytestmark = pytest.mark.gpu
 os.environ.setdefault("ORACLE_WORKERS", "8")
@@ -29,29 +28,6 @@ SPLIT_MODEL = {"bf16_split": 4 * 2.0 ** -16, "fp16_split": 1e-5}
 
 def pad16(v):
     return (v + 15) // 16 * 16
-
-
-def support(scene, levels=3):
-    """Nonzero rows and columns of every (layer, level) square of the oracle's
-    masked Mallat coefficients.  A level-l square spans rows [0, 2 ny/2^l) and
-    columns [0, 2 nx/2^l); below the top level its low-low quadrant belongs to
-    the coarser levels."""
-    ny, nx = scene.obj.shape
-    sal = None if scene.saliency is None else scene.saliency.astype(np.float64)
-    masks = None if sal is None else saliency.detail_masks(sal, levels)
-    out = []
-    for a in progressive.layer_split(scene.obj.astype(np.float64), scene.layer, len(scene.z)):
-        c = haar.analysis(a, levels)
-        if masks is not None:
-            c = saliency.apply_masks(c, masks, levels)
-        for l in range(1, levels + 1):
-            h, w = ny >> l, nx >> l
-            sq = c[:2 * h, :2 * w].copy()
-            if l < levels:
-                sq[:h, :w] = 0.0
-            nz = sq != 0.0
-            out.append((int(nz.any(axis=1).sum()), int(nz.any(axis=0).sum())))
-    return out
 
 
 def expected_k(scene):

@@ -17,6 +17,7 @@ import pytest
 from oracle import fresnel, fringe
 from paper_2211_09938_amd import scenes
 
+import helpers
 from helpers import to_dev
 
 pytestmark = pytest.mark.gpu
@@ -84,3 +85,93 @@ def test_fringe_tables_within_one_ulp_of_fp64(ny, nx, planes, levels, precision,
     print(f"tables {ny}x{nx} x{planes} L{levels} {precision} eq1={eq1}: worst |diff| / bound "
           f"{worst:.3f}")
     assert worst <= 1.0
+
+
+def _bf16_rne(v):
+    """Round-to-nearest-even bf16 of float32 values, as bits."""
+    u = v.astype(np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint32)
+
+
+def _split_words(v, precision):
+    """hi | lo << 16 with hi = RNE16(v), lo = RNE16(v - hi) (FP32 difference)."""
+    v = v.astype(np.float32)
+    if precision == "fp16_split":
+        hi = v.astype(np.float16)
+        lo = (v - hi.astype(np.float32)).astype(np.float16)
+        return hi.view(np.uint16).astype(np.uint32) | (lo.view(np.uint16).astype(np.uint32) << 16)
+    hb = _bf16_rne(v)
+    hf = (hb << 16).astype(np.uint32).view(np.float32)
+    lb = _bf16_rne(v - hf)
+    return hb | (lb << 16)
+
+
+def _koff_offset(n, levels, d, l):
+    """Start of (layer d, level l)'s segment of a table-offset array: the level sides
+    n / 2^(l-1) rounded up to 16, layer-major."""
+    pad = lambda v: (v + 15) // 16 * 16
+    per = sum(pad(n >> (k - 1)) for k in range(1, levels + 1))
+    return d * per + sum(pad(n >> (k - 1)) for k in range(1, l))
+
+
+@pytest.mark.parametrize("ny,nx,planes,precision", [
+    (200, 328, 3, "fp32"),
+    (200, 328, 3, "bf16_split"),
+    (136, 200, 2, "fp16_split"),
+])
+def test_operand_format_tables_and_offsets(ny, nx, planes, precision):
+    """The tables the first contraction generates its fringe operand from: every entry
+    is the FP32 table entry in the operand format (bit for bit), the third band is zero,
+    and beside each active row / column of the oracle's coefficient support (dyadic
+    object: exact) sits its table offset, then 3N up to the next multiple of 16."""
+    import torch
+
+    levels = 3
+    s = scenes.random_scene(900 + planes, ny, nx, planes=planes, levels=levels)
+    s.obj = scenes.dyadic(np.random.default_rng(900 + planes), ny, nx).astype(np.float32)
+    ws = torch.empty(cgh().workspace_size(ny, nx, planes, levels, precision), dtype=torch.uint8,
+                     device="cuda")
+    lay = None if s.layer is None else to_dev(s.layer)
+    cgh().progressive_hologram(to_dev(s.obj), s.z, s.lam, s.pitch, levels, to_dev(s.saliency),
+                               lay, precision=precision, workspace=ws)
+    torch.cuda.synchronize()
+    info = cgh().workspace_layout(ny, nx, planes, levels, precision)
+    raw = ws.cpu().numpy()
+    for n, lut_off, gen_off in ((nx, info["lut_x_offset"], info["gen_x_offset"]),
+                                (ny, info["lut_y_offset"], info["gen_y_offset"])):
+        tabs = raw[lut_off:lut_off + planes * levels * 4 * 2 * n * 4].view(np.float32)
+        tabs = tabs.reshape(planes, levels, 2, 2, 2 * n)
+        gen = raw[gen_off:gen_off + planes * levels * 3 * 2 * n * 8].view(np.uint32)
+        gen = gen.reshape(planes, levels, 3, 2 * n, 2)
+        for d in range(planes):
+            for lev in range(levels):
+                for band in (0, 1):
+                    re, im = tabs[d, lev, band, 0], tabs[d, lev, band, 1]
+                    if precision == "fp32":
+                        want = np.stack([re.view(np.uint32), im.view(np.uint32)], axis=1)
+                    else:
+                        want = np.stack([_split_words(re, precision),
+                                         _split_words(im, precision)], axis=1)
+                    assert np.array_equal(gen[d, lev, band], want), (n, d, lev, band)
+                assert not gen[d, lev, 2].any(), (n, d, lev)
+    sup = helpers.support_indices(s, levels)
+
+    def koff_array(name, n):  # the whole array: every layer's segments
+        off = info[name]
+        return raw[off:off + 4 * _koff_offset(n, levels, planes, 1)].view(np.int32)
+
+    koff_r, koff_c = koff_array("koff_row_offset", ny), koff_array("koff_col_offset", nx)
+    checked = 0
+    for d in range(planes):
+        for l in range(1, levels + 1):
+            rows, cols = sup[d * levels + l - 1]
+            for idx, n, arr in ((rows, ny, koff_r), (cols, nx, koff_c)):
+                half = n >> l
+                want = np.where(idx >= half, 2 * n - ((idx - half) << l), -(idx << l))
+                pad = (len(idx) + 15) // 16 * 16
+                seg = arr[_koff_offset(n, levels, d, l):][:pad]
+                assert np.array_equal(seg[:len(idx)], want), (d, l, n)
+                assert (seg[len(idx):pad] == 3 * n).all(), (d, l, n)
+                checked += len(idx)
+    print(f"{ny}x{nx}x{planes} {precision}: operand-format tables bit-exact, {checked} offsets")
+    assert checked > 0
