@@ -62,8 +62,6 @@ typedef const u32x4 __attribute__((address_space(1)))* gptr_u32x4;
 __device__ __forceinline__ u32x4 gload16(const unsigned char* base, size_t byte_off) {
     return *(gptr_u32x4)(base + byte_off);
 }
-typedef const int __attribute__((address_space(1)))* gptr_int;
-__device__ __forceinline__ int gload_int(const int* base, int i) { return ((gptr_int)base)[i]; }
 
 __device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
