@@ -58,8 +58,8 @@ struct NtEntry {
     // First contraction: where its B operand (the fringes of the active rows or columns
     // it sums over) comes from for kernels that generate it instead of reading the
     // panel at b.  g_lut: the (layer, level)'s operand-format tables (gen_table), and
-    // element (n, k'), k' < g_count, is their entry n + N + g_koff[k']; rows n >= N and
-    // k' >= g_count are zero (the zero band).
+    // element (n, k') is their entry n + N + g_koff[k'] (g_koff holds 3N, the zero band,
+    // from g_count to the next multiple of 16); rows n >= N are zero.
     const void* g_lut;
     const int* g_koff;
     int g_count;
@@ -319,8 +319,9 @@ int nt_first_tile_n(int ny, int nx, int layers, int levels, int precision);
 // Tiles of the first contraction at tm x tn tiles with every row and column active, in
 // the order with more of them per (layer, level): a bound of the planned tile count.
 long long nt_first_tiles_bound(int ny, int nx, int layers, int levels, int tm, int tn);
-// Whether the single-scene first contraction with tile_n-column tiles generates its fringe
-// operand from the operand-format tables (else the panel gather writes it).
+// Whether the first contraction (single-scene or batched) with tile_n-column tiles
+// generates its fringe operand from the operand-format tables (else the panel gather
+// writes it).
 constexpr bool nt_first_generates(int tile_n) { return tile_n == 128; }
 int nt_second_tile_m(int precision);
 int nt_second_tile_n(int precision);
