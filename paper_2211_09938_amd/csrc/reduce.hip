@@ -21,6 +21,26 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(const float2* __res
     }
 }
 
+// Two complex values per lane (16-byte loads and stores: n even, partial and out 16-byte
+// aligned): the same sums as reduce_partial_kernel.
+__global__ __launch_bounds__(256) void reduce_partial2_kernel(const float4* __restrict__ partial,
+                                                              int split, size_t n2, int accumulate,
+                                                              float4* __restrict__ out) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n2; i += stride) {
+        float4 v = accumulate ? out[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int s = 0; s < split; ++s) {
+            const float4 p = partial[(size_t)s * n2 + i];
+            v.x += p.x;
+            v.y += p.y;
+            v.z += p.z;
+            v.w += p.w;
+        }
+        out[i] = v;
+    }
+}
+
 // Largest |x[i]| over n floats into *word (float bits, atomicMax; cleared by the
 // caller).  Every lane reaches the reductions (no early exit); one atomic per
 // workgroup, few workgroups: atomics on one address serialise (one per wave of a
@@ -63,6 +83,15 @@ hipError_t launch_reduce_partial(int ny, int nx, int split, const float2* partia
                                  int accumulate, hipStream_t s) {
     if (split <= 1) return hipSuccess;
     const size_t n = (size_t)ny * nx;
+    if (n % 2 == 0 && ((reinterpret_cast<uintptr_t>(partial) | reinterpret_cast<uintptr_t>(out)) & 15) == 0) {
+        const size_t n2 = n / 2;
+        size_t blocks = (n2 + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(reduce_partial2_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<const float4*>(partial), split, n2, accumulate,
+                           reinterpret_cast<float4*>(out));
+        return hipGetLastError();
+    }
     size_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(reduce_partial_kernel, dim3((unsigned)blocks), dim3(256), 0, s, partial,
