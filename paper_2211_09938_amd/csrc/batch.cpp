@@ -110,6 +110,8 @@ hipError_t upload_args(cgh_plan& p, const int* tiles, hipStream_t s) {
 }
 
 hipError_t enqueue_first(const cgh_plan& p, hipStream_t s, const int* tiles) {
+    // only the generating shapes: the plan's layout has no fringe panel for this operand
+    if (!cgh::nt_first_generates(tiles[1])) return hipErrorInvalidValue;
     return cgh::launch_nt_persistent(false, p.precision, tiles[0], tiles[1], p.first, p.n_first,
                                      p.counts, p.queues, p.grid, s);
 }
@@ -192,7 +194,9 @@ bool cache_lookup(const char* path, const std::string& key, bool split_form, int
             found |= q == 1 && split_form && t[2] == cgh::nt_ring_tile_m() && t[3] == cgh::nt_ring_tile_n();
             ok &= found;
         }
-        if (!ok) continue;
+        // the batch's first contraction generates its fringe operand: 128-column tiles
+        // only (a plan holds no room for that operand's panel)
+        if (!ok || !cgh::nt_first_generates(t[1])) continue;
         for (int q = 0; q < 4; ++q) tiles[q] = t[q];
         return true;
     }
@@ -210,7 +214,9 @@ void cache_store(const char* path, const std::string& key, const int* tiles, dou
 }
 
 // Times every candidate shape on this batch and keeps the fastest per contraction;
-// the split forms also time the ring kernel for the second contraction.
+// the split forms also time the ring kernel for the second contraction.  The first
+// contraction takes the candidates' row counts with 128-column tiles only: with them it
+// generates its fringe operand, and a plan holds no room for that operand's panel.
 hipError_t autotune(cgh_plan& p, hipStream_t s) {
     Events ev;
     hipError_t e = hipEventCreate(&ev.a);
@@ -219,7 +225,7 @@ hipError_t autotune(cgh_plan& p, hipStream_t s) {
     double best1 = 1e30, best2 = 1e30;
     for (const auto& c : kCandidates) {
         if (e != hipSuccess) break;
-        const int tiles[4] = {c[0], c[1], c[0], c[1]};
+        const int tiles[4] = {c[0], 128, c[0], c[1]};
         e = upload_args(p, tiles, s);
         double t1 = 1e30, t2 = 1e30;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // first run warms up
@@ -233,7 +239,7 @@ hipError_t autotune(cgh_plan& p, hipStream_t s) {
                 t2 = std::min(t2, (double)m2);
             }
         }
-        if (t1 < best1) { best1 = t1; p.tiles[0] = c[0]; p.tiles[1] = c[1]; }
+        if (t1 < best1) { best1 = t1; p.tiles[0] = tiles[0]; p.tiles[1] = tiles[1]; }
         if (t2 < best2) { best2 = t2; p.tiles[2] = c[0]; p.tiles[3] = c[1]; }
     }
     if (e == hipSuccess && p.precision != CGH_FP32) {

@@ -102,8 +102,11 @@ inline cgh::Layout make_layout(int ny, int nx, int layers, int levels,
     lo.entries = take((size_t)(n_dl + 1) * sizeof(cgh::NtEntry));
     lo.entries_n = n_dl + 1;
     lo.first_tiles_max = z.first_tiles_max;
-    // forward: the operand panels, 8 bytes per complex element in every precision
-    const size_t fx_b = align_up(z.fx_plane * 8), cb_b = align_up(z.cb_plane * 4);
+    // forward: the operand panels, 8 bytes per complex element in every precision (a
+    // batched plan has no first-contraction fringe panel: its first contraction generates
+    // that operand from the tables)
+    const size_t fx_b = use == LayoutUse::kBatch ? 0 : align_up(z.fx_plane * 8);
+    const size_t cb_b = align_up(z.cb_plane * 4);
     const size_t fy_b = align_up(z.fy_plane * 8), tc_b = align_up(z.tc_plane * 8);
     lo.fwd_bytes = fx_b + cb_b + fy_b + tc_b;
     size_t shared = lo.fwd_bytes;

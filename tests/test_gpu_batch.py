@@ -244,3 +244,34 @@ def test_cached_ring_tile_for_second_contraction(precision, tmp_path):
     h = plan.holograms[2].cpu().numpy()
     assert rel_l2(h[ys, xs], oracle_hologram(s, pixels=(ys, xs))) <= 1e-3
     plan.close()
+
+
+def test_first_contraction_tiles_generate_their_operand(tmp_path):
+    """A plan's first contraction always runs 128-column tiles, with which it generates
+    its fringe operand from the tables (a plan holds no panel for that operand): the
+    tuner picks among those, and a cache entry naming a 64-column first tile is rejected
+    with a fresh tuning."""
+    import re
+
+    import torch
+
+    batch = make_batch(seed=19, n=6)
+    cache = str(tmp_path / "tune.jsonl")
+    devs = [dev_scene(s) for s in batch]
+    plan = cgh().Plan(devs, scenes.WAVELENGTH, scenes.PITCH, precision="bf16_split",
+                      tune_cache=cache)
+    assert plan.info()["first_tile"][1] == 128
+    plan.close()
+    with open(cache) as f:
+        line = f.read().strip()
+    with open(cache, "w") as f:
+        f.write(re.sub(r'"first": \[\d+, \d+\]', '"first": [64, 64]', line) + "\n")
+    plan = cgh().Plan(devs, scenes.WAVELENGTH, scenes.PITCH, precision="bf16_split",
+                      tune_cache=cache)
+    info = plan.info()
+    assert not info["from_cache"] and info["first_tile"][1] == 128
+    plan.execute()
+    torch.cuda.synchronize()
+    for s, h in zip(batch, plan.holograms):
+        assert rel_l2(h.cpu().numpy(), single(s, "bf16_split")) <= 1e-6
+    plan.close()
